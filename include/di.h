@@ -1,0 +1,176 @@
+/*
+ * di.h -- C ABI of the MI355X D-iteration library (libdi.so).
+ *
+ * The library solves the PageRank-type linear system of Section 1 of
+ * "Revisiting the D-iteration method: runtime comparison" (Hong, Burnside,
+ * Raoult, 2012):
+ *
+ *     X = P.X + B,   P[i][j] = d / out_j for every link j -> i,
+ *
+ * where out_j counts every link leaving j (a self-loop included) and a
+ * dangling node (out_j = 0) has a zero column (Section 2.4). Its hot path is
+ * the DI-SOP fluid diffusion of Sections 2.3 and 2.5.5: a fluid vector F
+ * starts at B and a history H at 0; each cycle computes r = sum_i |F_i| and
+ * diffuses every node with |F_i| > 0 and |F_i| >= (r/L)*out_i (L = number
+ * of links): H_i += transit, F_i = 0, and transit*d/out_i goes to every
+ * out-neighbour j != i, where transit = F_i, or F_i*out_i/(out_i - d) for a
+ * node with a self-loop (Section 2.5.4). H converges to X, and
+ * F = B - (I - P).H holds after every cycle, so sum_i |F_i| is exactly the
+ * L1 residual |B + P.H - H|_1.
+ *
+ * On the GPU a cycle is frontier-synchronous: the selected set and the
+ * diffused amounts are fixed from F at the start of the cycle, and fluid
+ * that arrives during the cycle waits for the next one. Any diffusion order
+ * converges to the same X; only the trajectory differs from the paper's
+ * sequential sweep.
+ *
+ * Conventions for every call:
+ *   - Returns a di_status; nothing throws or aborts across the ABI. On a
+ *     status other than DI_OK / DI_PENDING, di_last_error() returns a
+ *     message for the calling thread.
+ *   - Input arrays are read during the call and never kept; the caller
+ *     keeps ownership. Handles belong to the library until *_destroy.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device allocations (e.g. torch tensors on cuda:0) on the device that
+ *     was current when the graph was created.
+ *   - Node ids are int32 in [0, n); n < 2^31; links m < 2^33.
+ *   - There is no CPU fallback: without a usable gfx950 device, calls that
+ *     compute return DI_E_DEVICE.
+ */
+#ifndef DI_H
+#define DI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum di_status {
+  DI_OK = 0,
+  DI_PENDING = 1,      /* (reserved for asynchronous calls) */
+  DI_E_INVAL = -1,     /* bad argument (null pointer, d outside (0,1), ...) */
+  DI_E_UNSORTED = -2,  /* links not sorted by (origin, destination) */
+  DI_E_DUP = -3,       /* the same link listed twice */
+  DI_E_RANGE = -4,     /* node id outside [0, n) */
+  DI_E_NOMEM = -5,     /* host or device allocation failed */
+  DI_E_NOCONV = -6,    /* max_cycles reached before the tolerance */
+  DI_E_DEVICE = -7,    /* no usable GPU, or a HIP call failed */
+  DI_E_BUSY = -8,      /* (reserved) */
+  DI_E_NOTFOUND = -9   /* (reserved) */
+} di_status;
+
+/* di_opts.method */
+enum { DI_SOP = 0, DI_CYC = 1 };
+/* di_opts.precision */
+enum { DI_FP64 = 0, DI_FP32_REFINE = 1, DI_FP32 = 2 };
+/* di_opts.stop */
+enum { DI_STOP_RESID = 0, DI_STOP_PAPER = 1 };
+/* di_opts.flags */
+#define DI_FLAG_KERNEL_TIMING 1u /* time every push launch with HIP events */
+
+/* di_graph_create flags */
+#define DI_BUILD_CSC 1u /* also keep in-links (rows of P) on the device */
+
+typedef struct di_graph di_graph;
+
+typedef struct di_opts {
+  int32_t method;     /* DI_SOP (default) or DI_CYC (select every |F_i| > 0) */
+  int32_t precision;  /* DI_FP64 (default), DI_FP32_REFINE, DI_FP32 */
+  int32_t stop;       /* DI_STOP_RESID (default): stop when sum|F| <= tol;
+                         DI_STOP_PAPER: stop after a cycle when
+                         sum F / (1 - d - d*e) <= tol, e = fluid absorbed by
+                         dangling nodes (the paper's rule, target 1/N) */
+  int32_t max_cycles; /* <= 0: 100000 */
+  uint32_t flags;     /* DI_FLAG_* */
+  int32_t reserved0;
+  double inner_tol;   /* DI_FP32_REFINE: relative residual reduction asked
+                         of each FP32 pass (<= 0: 1e-5) */
+  void* stream;       /* hipStream_t for the *_dev calls; NULL = the
+                         default (null) stream */
+} di_opts;
+
+typedef struct di_stats {
+  int32_t cycles;           /* diffusion cycles run */
+  int32_t fallback_cycles;  /* DI-CYC cycles run after a DI-SOP cycle that
+                               selected nothing (rounding at a tie) */
+  int32_t refinements;      /* FP64 residual passes (DI_FP32_REFINE) */
+  int32_t push_launches;    /* push kernels timed (DI_FLAG_KERNEL_TIMING) */
+  int64_t edges_pushed;     /* link operations: pushes along links j != i */
+  double nb_iter;           /* edges_pushed / L: cost in units of one
+                               matrix-vector product */
+  double resid_l1;          /* final |B + P.X - X|_1 (sum |F|, or the FP64
+                               residual pass in DI_FP32_REFINE) */
+  double err_bound;         /* resid_l1 / (1 - d) >= |X - X_exact|_1 */
+  double paper_err;         /* last sum F / (1 - d - d*e) */
+  double e;                 /* fluid absorbed by dangling nodes */
+  double seconds;           /* device time of the solve (first cycle to
+                               stop), excluding host<->device copies */
+  double push_seconds;      /* summed push-kernel time (with timing flag) */
+  double bytes_moved;       /* algorithmic bytes of the whole solve */
+  double push_bytes;        /* algorithmic bytes of the push kernels */
+} di_stats;
+
+/* Fills *opts with the defaults listed in di_opts. */
+void di_opts_default(di_opts* opts);
+
+/* Builds a graph from its link list, origin src[e] -> destination dst[e],
+ * e in [0, m), sorted by (origin, destination) as in the input format of
+ * Section 2.1. Self-loops are allowed (p_ii = d/out_i). The link list is
+ * validated on the host before any device work:
+ *   DI_E_INVAL if n < 0, m < 0 or an array is NULL while m > 0,
+ *   DI_E_RANGE if an id is outside [0, n),
+ *   DI_E_UNSORTED if the list is not sorted by (origin, destination),
+ *   DI_E_DUP if a link appears twice.
+ * On success the device holds the out-link lists (CSR, self-loops removed,
+ * int64 offsets + int32 ids), a per-node word with out_i and the self-loop
+ * bit, and, with DI_BUILD_CSC, the in-link lists (CSC, self-loops kept).
+ * Arrays are host memory; they are copied. */
+di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                          uint32_t flags, di_graph** out);
+
+/* Frees the graph and its device memory. NULL is ignored. */
+void di_graph_destroy(di_graph* g);
+
+/* n, links L, dangling nodes and self-loops of a graph (any pointer may be
+ * NULL). */
+di_status di_graph_info(const di_graph* g, int64_t* n, int64_t* m, int64_t* n_dangling,
+                        int64_t* n_loops);
+
+/* Solves X = P.X + B by DI-SOP until |B + P.X - X|_1 <= tol.
+ * B: n doubles (host), all finite; NULL means the PageRank right-hand side
+ *    B = (1-d)/n for every node.
+ * X: n doubles (host), caller-allocated, receives the solution (H).
+ * d in (0, 1); tol > 0 (tol >= 0 with DI_STOP_PAPER).
+ * opts may be NULL (defaults); stats may be NULL.
+ * Returns DI_E_NOCONV (X and stats still filled) after max_cycles. */
+di_status di_solve(const di_graph* g, const double* B, double d, double tol, const di_opts* opts,
+                   double* X, di_stats* stats);
+
+/* As di_solve with B and X in device memory (n doubles each); the work is
+ * queued on opts->stream and the call returns once it has finished. */
+di_status di_solve_dev(const di_graph* g, const double* B_dev, double d, double tol,
+                       const di_opts* opts, double* X_dev, di_stats* stats);
+
+/* Runs exactly `cycles` frontier-synchronous FP64 cycles of DI-SOP
+ * (method DI_SOP) or DI-CYC (DI_CYC) on the state (F, H) in place, with no
+ * stop test. F and H are device arrays of n doubles. Because
+ * F = B - (I - P).H is preserved, (F, H) is an exact checkpoint of a solve:
+ * calling this again resumes it. *e_inout (host, may be NULL) is the
+ * absorbed-fluid total, updated. */
+di_status di_cycles_dev(const di_graph* g, double d, int32_t method, double* F_dev,
+                        double* H_dev, int32_t cycles, double* e_inout, void* stream,
+                        di_stats* stats);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char* di_last_error(void);
+
+/* ABI version: (major << 16) | minor. */
+int32_t di_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DI_H */

@@ -1,0 +1,242 @@
+"""ctypes binding of libdi (include/di.h), with the same names as the C ABI.
+
+Argument marshalling only: every step of a solve runs in libdi's HIP
+kernels. PyTorch tensors may be passed to the *_dev calls (their data_ptr()
+and the current HIP stream are forwarded). Loading fails loudly when
+libdi.so has not been built; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdi.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "di.h")
+
+DI_OK, DI_PENDING = 0, 1
+DI_E_INVAL, DI_E_UNSORTED, DI_E_DUP, DI_E_RANGE = -1, -2, -3, -4
+DI_E_NOMEM, DI_E_NOCONV, DI_E_DEVICE, DI_E_BUSY, DI_E_NOTFOUND = -5, -6, -7, -8, -9
+DI_SOP, DI_CYC = 0, 1
+DI_FP64, DI_FP32_REFINE, DI_FP32 = 0, 1, 2
+DI_STOP_RESID, DI_STOP_PAPER = 0, 1
+DI_FLAG_KERNEL_TIMING = 1
+DI_BUILD_CSC = 1
+
+STATUS_NAMES = {
+    0: "DI_OK", 1: "DI_PENDING", -1: "DI_E_INVAL", -2: "DI_E_UNSORTED", -3: "DI_E_DUP",
+    -4: "DI_E_RANGE", -5: "DI_E_NOMEM", -6: "DI_E_NOCONV", -7: "DI_E_DEVICE", -8: "DI_E_BUSY",
+    -9: "DI_E_NOTFOUND",
+}
+
+
+class di_opts(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("stop", ctypes.c_int32),
+        ("max_cycles", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("reserved0", ctypes.c_int32),
+        ("inner_tol", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class di_stats(ctypes.Structure):
+    _fields_ = [
+        ("cycles", ctypes.c_int32),
+        ("fallback_cycles", ctypes.c_int32),
+        ("refinements", ctypes.c_int32),
+        ("push_launches", ctypes.c_int32),
+        ("edges_pushed", ctypes.c_int64),
+        ("nb_iter", ctypes.c_double),
+        ("resid_l1", ctypes.c_double),
+        ("err_bound", ctypes.c_double),
+        ("paper_err", ctypes.c_double),
+        ("e", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("push_seconds", ctypes.c_double),
+        ("bytes_moved", ctypes.c_double),
+        ("push_bytes", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class DIError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdi (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing. Build it with `python -c \"import __graft_entry__ as g; g.build()\"` "
+            "(hipcc, gfx950); there is no CPU fallback.")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.di_opts_default.argtypes = [P(di_opts)]
+    L.di_opts_default.restype = None
+    L.di_graph_create.argtypes = [i64, i64, vp, vp, u32, P(vp)]
+    L.di_graph_create.restype = i32
+    L.di_graph_destroy.argtypes = [vp]
+    L.di_graph_destroy.restype = None
+    L.di_graph_info.argtypes = [vp, P(i64), P(i64), P(i64), P(i64)]
+    L.di_graph_info.restype = i32
+    L.di_solve.argtypes = [vp, vp, dbl, dbl, P(di_opts), vp, P(di_stats)]
+    L.di_solve.restype = i32
+    L.di_solve_dev.argtypes = [vp, vp, dbl, dbl, P(di_opts), vp, P(di_stats)]
+    L.di_solve_dev.restype = i32
+    L.di_cycles_dev.argtypes = [vp, dbl, i32, vp, vp, i32, P(dbl), vp, P(di_stats)]
+    L.di_cycles_dev.restype = i32
+    L.di_last_error.argtypes = []
+    L.di_last_error.restype = ctypes.c_char_p
+    L.di_version.argtypes = []
+    L.di_version.restype = i32
+    _lib = L
+    return L
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions include/di.h declares."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(di_[a-z0-9_]+)\s*\(", text)))
+
+
+def di_last_error() -> str:
+    return lib().di_last_error().decode(errors="replace")
+
+
+def di_version() -> int:
+    return lib().di_version()
+
+
+def di_opts_default() -> di_opts:
+    o = di_opts()
+    lib().di_opts_default(ctypes.byref(o))
+    return o
+
+
+def _check(status: int, allow=(DI_OK,)) -> int:
+    if status not in allow:
+        raise DIError(status, di_last_error())
+    return status
+
+
+def _ptr(x):
+    """Data pointer of a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return ctypes.c_void_p(x.data_ptr())
+    return ctypes.c_void_p(x.ctypes.data)
+
+
+def _current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def di_graph_create(n: int, src, dst, flags: int = 0):
+    """Returns (status, handle). src/dst: int32 host arrays."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    if src.shape != dst.shape:
+        raise ValueError("src and dst differ in length")
+    h = ctypes.c_void_p()
+    st = lib().di_graph_create(int(n), int(src.size), src.ctypes.data, dst.ctypes.data,
+                               int(flags), ctypes.byref(h))
+    return st, h
+
+
+def di_graph_destroy(h) -> None:
+    if h:
+        lib().di_graph_destroy(h)
+
+
+def di_graph_info(h):
+    n, m, nd, nl = (ctypes.c_int64() for _ in range(4))
+    _check(lib().di_graph_info(h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(nd), ctypes.byref(nl)))
+    return n.value, m.value, nd.value, nl.value
+
+
+def di_solve(h, B, d: float, tol: float, opts: di_opts | None, X) -> tuple[int, di_stats]:
+    """Host arrays: B (n float64, or None for (1-d)/n), X (n float64, written)."""
+    st = di_stats()
+    status = lib().di_solve(h, _ptr(B), float(d), float(tol),
+                            ctypes.byref(opts) if opts is not None else None, _ptr(X), ctypes.byref(st))
+    return status, st
+
+
+def di_solve_dev(h, B_dev, d: float, tol: float, opts: di_opts | None, X_dev) -> tuple[int, di_stats]:
+    """Device tensors: B_dev (n float64 or None), X_dev (n float64). The
+    current torch stream is used unless opts.stream is set."""
+    if opts is None:
+        opts = di_opts_default()
+    if not opts.stream:
+        opts.stream = _current_stream()
+    st = di_stats()
+    status = lib().di_solve_dev(h, _ptr(B_dev), float(d), float(tol), ctypes.byref(opts), _ptr(X_dev),
+                                ctypes.byref(st))
+    return status, st
+
+
+def di_cycles_dev(h, d: float, method: int, F_dev, H_dev, cycles: int, e: float = 0.0, stream=None):
+    """Runs `cycles` FP64 cycles in place on device tensors F, H.
+    Returns (status, e, stats)."""
+    st = di_stats()
+    e_c = ctypes.c_double(e)
+    status = lib().di_cycles_dev(h, float(d), int(method), _ptr(F_dev), _ptr(H_dev), int(cycles),
+                                 ctypes.byref(e_c), stream if stream is not None else _current_stream(),
+                                 ctypes.byref(st))
+    return status, e_c.value, st
+
+
+class Graph:
+    """Owning wrapper of a di_graph handle."""
+
+    def __init__(self, n: int, src, dst, csc: bool = False):
+        status, h = di_graph_create(n, src, dst, DI_BUILD_CSC if csc else 0)
+        _check(status)
+        self.handle = h
+        self.n, self.L, self.n_dangling, self.n_loops = di_graph_info(h)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            di_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(g: Graph, B=None, d: float = 0.85, tol: float = 1e-9, **opt_fields):
+    """Host convenience: returns (X as float64 numpy array, stats dict).
+    Raises DIError unless the status is DI_OK."""
+    o = di_opts_default()
+    for k, v in opt_fields.items():
+        setattr(o, k, v)
+    X = np.empty(g.n, dtype=np.float64)
+    Bh = None if B is None else np.ascontiguousarray(B, dtype=np.float64)
+    status, st = di_solve(g.handle, Bh, d, tol, o, X)
+    _check(status)
+    return X, st.as_dict()
