@@ -68,10 +68,16 @@ enum { DI_FP64 = 0, DI_FP32_REFINE = 1, DI_FP32 = 2 };
 /* di_opts.stop */
 enum { DI_STOP_RESID = 0, DI_STOP_PAPER = 1 };
 /* di_opts.flags */
-#define DI_FLAG_KERNEL_TIMING 1u /* time every push launch with HIP events */
+#define DI_FLAG_KERNEL_TIMING 1u /* time every pull/push launch with HIP events */
 
-/* di_graph_create flags */
-#define DI_BUILD_CSC 1u /* also keep in-links (rows of P) on the device */
+/* di_opts.kernel: how a cycle moves the claimed fluid along the links */
+enum {
+  DI_KERNEL_AUTO = 0, /* the library's choice (currently DI_KERNEL_PULL) */
+  DI_KERNEL_PULL = 1, /* every node sums what its in-links send (CSC);
+                         no atomics, bit-reproducible */
+  DI_KERNEL_PUSH = 2  /* every diffused node adds to its out-neighbours
+                         (CSR) with device-scope float atomics */
+};
 
 typedef struct di_graph di_graph;
 
@@ -84,7 +90,7 @@ typedef struct di_opts {
                          dangling nodes (the paper's rule, target 1/N) */
   int32_t max_cycles; /* <= 0: 100000 */
   uint32_t flags;     /* DI_FLAG_* */
-  int32_t reserved0;
+  int32_t kernel;     /* DI_KERNEL_* (default DI_KERNEL_AUTO) */
   double inner_tol;   /* DI_FP32_REFINE: relative residual reduction asked
                          of each FP32 pass (<= 0: 1e-5) */
   void* stream;       /* hipStream_t for the *_dev calls; NULL = the
@@ -96,7 +102,7 @@ typedef struct di_stats {
   int32_t fallback_cycles;  /* DI-CYC cycles run after a DI-SOP cycle that
                                selected nothing (rounding at a tie) */
   int32_t refinements;      /* FP64 residual passes (DI_FP32_REFINE) */
-  int32_t push_launches;    /* push kernels timed (DI_FLAG_KERNEL_TIMING) */
+  int32_t move_launches;    /* pull/push launches timed (DI_FLAG_KERNEL_TIMING) */
   int64_t edges_pushed;     /* link operations: pushes along links j != i */
   double nb_iter;           /* edges_pushed / L: cost in units of one
                                matrix-vector product */
@@ -107,9 +113,10 @@ typedef struct di_stats {
   double e;                 /* fluid absorbed by dangling nodes */
   double seconds;           /* device time of the solve (first cycle to
                                stop), excluding host<->device copies */
-  double push_seconds;      /* summed push-kernel time (with timing flag) */
+  double move_seconds;      /* summed time of the pull/push kernel that moves
+                               the fluid (with DI_FLAG_KERNEL_TIMING) */
   double bytes_moved;       /* algorithmic bytes of the whole solve */
-  double push_bytes;        /* algorithmic bytes of the push kernels */
+  double move_bytes;        /* algorithmic bytes of those pull/push launches */
 } di_stats;
 
 /* Fills *opts with the defaults listed in di_opts. */
@@ -123,10 +130,12 @@ void di_opts_default(di_opts* opts);
  *   DI_E_RANGE if an id is outside [0, n),
  *   DI_E_UNSORTED if the list is not sorted by (origin, destination),
  *   DI_E_DUP if a link appears twice.
+ * flags must be 0 (reserved).
  * On success the device holds the out-link lists (CSR, self-loops removed,
- * int64 offsets + int32 ids), a per-node word with out_i and the self-loop
- * bit, and, with DI_BUILD_CSC, the in-link lists (CSC, self-loops kept).
- * Arrays are host memory; they are copied. */
+ * int64 offsets + int32 ids), the in-link lists (CSC, self-loops removed),
+ * a per-node word with out_i and the self-loop bit, and the pull work
+ * items (runs of rows with at most 2048 in-links; longer in-link lists are
+ * split). Arrays are host memory; they are copied. */
 di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                           uint32_t flags, di_graph** out);
 

@@ -49,16 +49,20 @@ void free_workspace(Workspace* ws);
 namespace {
 
 void free_graph_device(di_graph* g) {
-  (void)hipFree(g->row_ptr);
-  (void)hipFree(g->col);
-  (void)hipFree(g->info);
-  (void)hipFree(g->csc_ptr);
-  (void)hipFree(g->csc_idx);
+  void* ptrs[] = {g->row_ptr, g->col,   g->info,   g->csc_ptr,   g->csc_idx,
+                  g->it_r0,   g->it_r1, g->it_l0,  g->it_l1,     g->it_seg,
+                  g->heavy_row, g->heavy_seg, g->hb_h0, g->hb_h1};
+  for (void* p : ptrs) (void)hipFree(p);
   g->row_ptr = nullptr;
   g->col = nullptr;
   g->info = nullptr;
   g->csc_ptr = nullptr;
   g->csc_idx = nullptr;
+  g->it_r0 = g->it_r1 = g->it_l0 = g->it_l1 = nullptr;
+  g->it_seg = nullptr;
+  g->heavy_row = nullptr;
+  g->heavy_seg = nullptr;
+  g->hb_h0 = g->hb_h1 = nullptr;
 }
 
 template <typename V>
@@ -114,6 +118,10 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
     }
     if (m > 0 && (!src || !dst)) {
       di::set_error("di_graph_create: src or dst is NULL");
+      return DI_E_INVAL;
+    }
+    if (flags != 0) {
+      di::set_error("di_graph_create: flags must be 0");
       return DI_E_INVAL;
     }
     // validation, in one pass, before any device work
@@ -183,16 +191,88 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
     if (st == DI_OK) st = upload(&g->info, info);
     std::vector<int64_t>().swap(row_ptr);
     std::vector<int32_t>().swap(col);
-    if (st == DI_OK && (flags & DI_BUILD_CSC)) {
+    if (st == DI_OK) {
+      // in-links without self-loops (rows of P), ascending origin per row
       std::vector<int64_t> cptr((size_t)n + 1, 0);
-      for (int64_t e = 0; e < m; ++e) cptr[dst[e] + 1] += 1;
-      for (int64_t i = 0; i < n; ++i) cptr[i + 1] += cptr[i];
-      std::vector<int32_t> cidx((size_t)m);
-      std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
-      for (int64_t e = 0; e < m; ++e) cidx[fill[dst[e]]++] = src[e];
+      for (int64_t e = 0; e < m; ++e)
+        if (src[e] != dst[e]) cptr[dst[e] + 1] += 1;
+      int64_t max_in = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        max_in = std::max(max_in, cptr[i + 1]);
+        cptr[i + 1] += cptr[i];
+      }
+      g->max_in = max_in;
+      std::vector<int32_t> cidx((size_t)Lp);
+      {
+        std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+        for (int64_t e = 0; e < m; ++e)
+          if (src[e] != dst[e]) cidx[fill[dst[e]]++] = src[e];
+      }
+      // pull work items: runs of whole rows with at most kPullChunk in-links
+      // and kPullMaxRows rows; a row with more in-links is split into
+      // segments of kPullChunk links, summed separately
+      std::vector<int64_t> r0v, r1v, l0v, l1v, hseg;
+      std::vector<int32_t> segv, hrow;
+      int64_t nseg = 0, open_r0 = -1, cur_links = 0, cur_rows = 0;
+      auto flush = [&](int64_t end_row) {
+        if (open_r0 < 0) return;
+        r0v.push_back(open_r0);
+        r1v.push_back(end_row);
+        l0v.push_back(cptr[open_r0]);
+        l1v.push_back(cptr[end_row]);
+        segv.push_back(-1);
+        open_r0 = -1;
+        cur_links = cur_rows = 0;
+      };
+      for (int64_t j = 0; j < n; ++j) {
+        const int64_t deg = cptr[j + 1] - cptr[j];
+        if (deg > di::kPullChunk) {
+          flush(j);
+          hrow.push_back((int32_t)j);
+          hseg.push_back(nseg);
+          for (int64_t lo = cptr[j]; lo < cptr[j + 1]; lo += di::kPullChunk) {
+            r0v.push_back(j);
+            r1v.push_back(j + 1);
+            l0v.push_back(lo);
+            l1v.push_back(std::min<int64_t>(lo + di::kPullChunk, cptr[j + 1]));
+            segv.push_back((int32_t)nseg++);
+          }
+          continue;
+        }
+        if (open_r0 >= 0 && (cur_links + deg > di::kPullChunk || cur_rows >= di::kPullMaxRows))
+          flush(j);
+        if (open_r0 < 0) open_r0 = j;
+        cur_links += deg;
+        cur_rows += 1;
+      }
+      flush(n);
+      hseg.push_back(nseg);
+      // group heavy rows into finalize batches of at most kFinalSegBatch
+      // segments (a row with more segments is a batch of its own)
+      std::vector<int64_t> hb0, hb1;
+      for (int64_t h = 0; h < (int64_t)hrow.size();) {
+        int64_t e = h + 1;
+        if (hseg[h + 1] - hseg[h] <= di::kFinalSegBatch)
+          while (e < (int64_t)hrow.size() && hseg[e + 1] - hseg[h] <= di::kFinalSegBatch) ++e;
+        hb0.push_back(h);
+        hb1.push_back(e);
+        h = e;
+      }
+      g->n_hbatch = (int64_t)hb0.size();
+      g->n_items = (int64_t)r0v.size();
+      g->n_heavy = (int64_t)hrow.size();
+      g->n_segs = nseg;
       st = upload(&g->csc_ptr, cptr);
       if (st == DI_OK) st = upload(&g->csc_idx, cidx);
-      g->has_csc = st == DI_OK;
+      if (st == DI_OK) st = upload(&g->it_r0, r0v);
+      if (st == DI_OK) st = upload(&g->it_r1, r1v);
+      if (st == DI_OK) st = upload(&g->it_l0, l0v);
+      if (st == DI_OK) st = upload(&g->it_l1, l1v);
+      if (st == DI_OK) st = upload(&g->it_seg, segv);
+      if (st == DI_OK) st = upload(&g->heavy_row, hrow);
+      if (st == DI_OK) st = upload(&g->heavy_seg, hseg);
+      if (st == DI_OK) st = upload(&g->hb_h0, hb0);
+      if (st == DI_OK) st = upload(&g->hb_h1, hb1);
     }
     if (st != DI_OK) {
       free_graph_device(g);

@@ -15,44 +15,49 @@ namespace di {
 
 // ---- launch geometry ------------------------------------------------------
 constexpr int kSelectBlock = 256;     // threads per select block
-constexpr int kSelectPerThread = 4;   // consecutive nodes per select thread
+constexpr int kSelectPerThread = 2;   // nodes per select thread (block-strided)
 constexpr int kSelectNodes = kSelectBlock * kSelectPerThread;
+constexpr int kPullBlock = 256;       // threads per pull block
+constexpr int kPullChunk = 2048;      // in-links per pull work item (LDS staged)
+constexpr int kPullMaxRows = 2048;    // rows per pull work item
+constexpr int kPullLongRow = 32;      // rows with more in-links: summed by a wave
+constexpr int kPullMaxGrid = 2048;    // pull blocks (grid-stride over items)
 constexpr int kPushBlock = 256;       // threads per push block
-constexpr int kPushTile = 1024;       // frontier links per push tile
 constexpr int kReduceBlock = 256;     // threads per reduction block
-constexpr int kMaxParts = 256;        // reduction blocks (partial sums)
-constexpr int kMaxPushGrid = 4096;    // push blocks (grid-stride over tiles)
+constexpr int kReduceGrid = 1024;     // reduction blocks (push direction)
+constexpr int kFinalBlock = 1024;     // threads of the single finalize block
+constexpr int kFinalSegBatch = 4096;  // heavy-row segment sums staged per pass
 
 // Per-node word: out-degree (self-loop included) in bits 0..30, self-loop
 // flag in bit 31.
 constexpr uint32_t kLoopBit = 0x80000000u;
 constexpr uint32_t kOutMask = 0x7fffffffu;
 
-// Frontier counter: selected nodes with out-links in bits 0..30, their
-// links (self-loops excluded) in bits 31..63. One 64-bit atomic reserves
-// both ranges, so link offsets grow with frontier positions.
-constexpr int kPackShift = 31;
-constexpr uint64_t kPackNodeMask = (1ull << kPackShift) - 1;
-
-// Device control block of one solve. Three rotating slots keep the counters
-// of cycles c-1, c and c+1 apart (slot c % 3).
+// Device control block of one solve. During the cycles only the
+// single-block finalize kernel writes it; the other kernels read it.
 struct Ctl {
-  double e;               // fluid absorbed by dangling nodes (atomics)
-  double e_snap;          // e at the start of the current cycle
-  double final_r;         // sum |F| at the stop test that ended the solve
-  double paper_err;       // last sum F / (1 - d - d e)
-  double r_last;          // r of the last diffusion cycle
-  double r_first;         // r of the first cycle
-  unsigned long long packed[3];  // frontier counter per slot
-  unsigned int sel[3];           // diffused nodes (dangling ones too) per slot
-  int cycles;             // cycles run
-  int fallback;           // DI-CYC cycles run after an empty DI-SOP cycle
-  int done;               // 0 running, 1 converged, 2 stopped at max_cycles,
-                          // 3 non-finite fluid
-  int cur;                // index of the current cycle (-1 before the first)
-  unsigned long long edges_total;  // link operations so far
-  unsigned long long front_total;  // frontier entries so far
-  unsigned long long sel_total;    // diffused nodes so far
+  double r;          // sum |F| after the last cycle: r of the next selection
+  double psum;       // sum F after the last cycle
+  double e;          // fluid absorbed by dangling nodes
+  double final_r;    // sum |F| when the solve stopped
+  double paper_err;  // last sum F / (1 - d - d e)
+  double r_first;    // r used by the first cycle
+  double r_last;     // r used by the last cycle
+  int cycles;        // cycles run
+  int fallback;      // DI-CYC cycles run after an empty DI-SOP cycle
+  int done;          // 0 running, 1 converged, 2 max_cycles, 3 non-finite
+  int cyc_mode;      // next cycle selects every |F_i| > 0
+  unsigned long long edges_total;  // link operations (pushes along j != i)
+  unsigned long long front_total;  // diffused nodes with links to push
+  unsigned long long sel_total;    // diffused nodes
+};
+
+// Per select block: what its nodes did in the cycle.
+struct SelStat {
+  unsigned long long ops;  // link operations
+  double e;                // fluid absorbed by dangling nodes
+  unsigned int sel;        // diffused nodes
+  unsigned int nfront;     // diffused nodes with links to push
 };
 
 enum Prec { kF64 = 0, kF32 = 1 };
@@ -60,19 +65,20 @@ enum Prec { kF64 = 0, kF32 = 1 };
 // Buffers of one solve; pooled per graph so repeated solves do not allocate.
 struct Workspace {
   int prec = kF64;
-  int64_t n = 0;
-  void* F = nullptr;           // fluid, n values of the fluid type
-  void* H = nullptr;           // history, n values
-  int64_t* fr_start = nullptr; // frontier: first link offset of each entry
-  int64_t* fr_base = nullptr;  // frontier: CSR offset of the node's links
-  void* fr_s = nullptr;        // frontier: amount sent along each link
-  int32_t* tile_first = nullptr;  // frontier entry holding link b*kPushTile
-  double* part_abs = nullptr;  // per-block sum |F|
-  double* part_sum = nullptr;  // per-block sum F
+  void* F = nullptr;            // fluid, n values of the fluid type
+  void* H = nullptr;            // history, n values
+  void* sent = nullptr;         // pull: amount each node sends per link
+  int64_t* fr_lstart = nullptr; // push: per-block frontier, local link offset
+  int64_t* fr_base = nullptr;   // push: CSR offset of the entry's links
+  void* fr_s = nullptr;         // push: amount sent along each link
+  SelStat* blk_stat = nullptr;  // per select block
+  double* blk_pabs = nullptr;   // per pull/reduce block: sum |F|
+  double* blk_psum = nullptr;   // per pull/reduce block: sum F
+  double* seg_val = nullptr;    // pull: partial sums of split in-link lists
   Ctl* ctl = nullptr;
-  Ctl* host_ctl = nullptr;     // pinned copy for the stop check
-  double* X64 = nullptr;       // FP64 solution (refinement)
-  double* R64 = nullptr;       // FP64 residual / scratch (refinement)
+  Ctl* host_ctl = nullptr;      // pinned copy for the stop check
+  double* X64 = nullptr;        // host entry points: device copy of X
+  double* B64 = nullptr;        // host entry points: device copy of B
   std::vector<hipEvent_t> events;
 };
 
@@ -81,19 +87,38 @@ struct Workspace {
 struct di_graph {
   int64_t n = 0;
   int64_t L = 0;           // links, self-loops included
-  int64_t Lp = 0;          // links pushed by a diffusion (self-loops removed)
+  int64_t Lp = 0;          // links without self-loops
   int64_t n_dangling = 0;
   int64_t n_loops = 0;
   int64_t max_out = 0;
+  int64_t max_in = 0;
   int device = 0;
-  bool has_csc = false;
-  // out-links (columns of P): CSR without self-loops
+  // out-links (columns of P) without self-loops: CSR
   int64_t* row_ptr = nullptr;  // n + 1
   int32_t* col = nullptr;      // Lp
   uint32_t* info = nullptr;    // n: out-degree | self-loop bit
-  // in-links (rows of P), self-loops kept
+  // in-links (rows of P) without self-loops: CSC
   int64_t* csc_ptr = nullptr;  // n + 1
-  int32_t* csc_idx = nullptr;  // L
+  int32_t* csc_idx = nullptr;  // Lp
+  // pull work items: light items cover rows [r0, r1) and their in-links
+  // [l0, l1); a segment item (seg >= 0) covers links [l0, l1) of one heavy
+  // row and writes seg_val[seg]
+  int64_t n_items = 0;
+  int64_t* it_r0 = nullptr;
+  int64_t* it_r1 = nullptr;
+  int64_t* it_l0 = nullptr;
+  int64_t* it_l1 = nullptr;
+  int32_t* it_seg = nullptr;
+  // heavy rows (more than kPullChunk in-links): row id and segment range
+  int64_t n_heavy = 0;
+  int64_t n_segs = 0;
+  int32_t* heavy_row = nullptr;   // n_heavy
+  int64_t* heavy_seg = nullptr;   // n_heavy + 1
+  // batches of heavy rows for the finalize kernel: rows [hb_h0, hb_h1) with
+  // at most kFinalSegBatch segments, or a single row with more
+  int64_t n_hbatch = 0;
+  int64_t* hb_h0 = nullptr;
+  int64_t* hb_h1 = nullptr;
   std::mutex mu;
   std::vector<di::Workspace*> pool;
 };
@@ -121,8 +146,11 @@ void set_error(const std::string& msg);
   } while (0)
 
 di_status check_device(int* device_out);
+void free_workspace(Workspace* ws);
 
 // ---- kernel launchers (di_kernels.hip) ------------------------------------
+enum Direction { kPull = 0, kPush = 1 };
+
 struct CycleArgs {
   const di_graph* g;
   Workspace* ws;
@@ -130,27 +158,28 @@ struct CycleArgs {
   double tol;
   int method;      // DI_SOP or DI_CYC
   int stop;        // DI_STOP_RESID or DI_STOP_PAPER
-  int max_cycles;  // the stop test of cycle max_cycles ends the solve
-  int nparts;      // reduction blocks
-  int push_grid;   // push blocks
+  int max_cycles;  // the solve stops after this many cycles
+  int direction;   // kPull or kPush
   hipStream_t stream;
 };
 
-// The device keeps the cycle index (Ctl::cur), so every cycle is the same
-// three launches: reduce, select, push.
+int select_grid(int64_t n);
+int pull_grid(const di_graph* g);
+int reduce_grid(int64_t n);
+
 hipError_t launch_reset_ctl(const CycleArgs& a);
+// F = B (or the uniform value), H = 0, per-block sum |F| / sum F partials,
+// then the finalize kernel's stop test before the first cycle.
 template <typename T>
-hipError_t launch_init(const CycleArgs& a, const double* B, double b_uniform);
+hipError_t launch_start(const CycleArgs& a, const double* B, double b_uniform);
+// As launch_start for a state (F, H) already in the workspace buffers.
 template <typename T>
-hipError_t launch_reduce(const CycleArgs& a);
+hipError_t launch_start_state(const CycleArgs& a);
+// One cycle: select (+claim), pull or push (+reduce), finalize. With
+// non-null events, the pull (or push) launch is bracketed by them.
 template <typename T>
-hipError_t launch_select(const CycleArgs& a);
-template <typename T>
-hipError_t launch_push(const CycleArgs& a);
+hipError_t launch_cycle(const CycleArgs& a, hipEvent_t ev_before_main, hipEvent_t ev_after_main);
 template <typename T>
 hipError_t launch_h_to_x(const CycleArgs& a, double* X);
-
-int reduce_parts(int64_t n);
-int push_grid(int64_t Lp);
 
 }  // namespace di

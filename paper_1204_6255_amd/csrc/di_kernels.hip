@@ -1,23 +1,25 @@
 // HIP kernels of one frontier-synchronous D-iteration cycle on gfx950.
 //
-// A cycle is three launches on one stream:
-//   k_reduce  r = sum_i |F_i| (and sum_i F_i) as per-block FP64 partials;
-//             block 0 advances the device cycle counter and clears the
-//             cycle's frontier counters;
-//   k_select  every block sums the partials in the same fixed order (so all
-//             blocks agree on r bit for bit), runs the stop test, applies
-//             the selection rule of DI-SOP (Sections 2.3 and 2.5.5) and, for
-//             each selected node, the claim of Section 2.5.4 (H_i += transit,
-//             F_i = 0, dangling fluid absorbed); nodes with links to push are
-//             compacted into the frontier with a wave64 scan and one 64-bit
-//             atomic per block;
-//   k_push    edge-balanced push: tile b covers frontier links
-//             [b*kPushTile, (b+1)*kPushTile); the tile's frontier entries are
-//             staged in LDS, each lane finds its entry by binary search and
-//             adds the entry's amount to F[col] with a device-scope float
-//             atomic. Index reads are coalesced within each out-link list.
-// Every kernel returns at once when the solve is done, so the host can queue
-// cycles ahead of the stop test.
+// Every cycle runs the selection rule of DI-SOP (Sections 2.3 and 2.5.5)
+// against r = sum_i |F_i| of the fluid at the start of the cycle, claims the
+// selected nodes (Section 2.5.4: H_i += transit, F_i = 0, dangling fluid
+// absorbed), and then moves the claimed fluid along the links. Fluid that
+// arrives during the cycle waits for the next one, so the selected set and
+// the moved amounts depend only on the state at the start of the cycle.
+//
+// The move has two implementations with identical results:
+//   pull  each node sums sent[i] over its in-links (CSC without self-loops),
+//         staged through LDS in work items of at most kPullChunk links;
+//         in-link lists longer than that are split into segments whose sums
+//         the finalize kernel adds. No atomics; the result is deterministic.
+//   push  each selected node's out-links (CSR) receive transit*d/out_i by
+//         device-scope float atomics; a select block's frontier is pushed
+//         by the push block of the same index, link-balanced through LDS.
+// A single-block finalize kernel then sums the per-block partials in a fixed
+// order into r (the residual |B + P.H - H|_1 = sum |F|), accumulates the
+// statistics and runs the stop test. Only it writes the control block while
+// cycles run; every kernel returns at once after the stop, so the host may
+// queue cycles ahead of the test.
 
 #include "di_internal.h"
 
@@ -30,42 +32,24 @@ __device__ inline double to_d(float x) { return (double)x; }
 __device__ inline void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
-// Butterfly sum over the 64 lanes of a wave; every lane gets the total and
+// Butterfly sum over the 64 lanes of a wave: every lane gets the total, and
 // the order of additions is fixed.
-__device__ inline double wave_sum(double v) {
+template <typename V>
+__device__ inline V wave_sum(V v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-__device__ inline unsigned int wave_sum_u32(unsigned int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum of the first `count` entries of parts (count <= blockDim.x, blockDim.x
-// a multiple of 64 and at most 1024) in a fixed order: the same value in
-// every block. lds needs blockDim.x / 64 doubles. Called by all threads.
-__device__ double block_sum_fixed(const double* parts, int count, double* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double v = (int)threadIdx.x < count ? parts[threadIdx.x] : 0.0;
-  v = wave_sum(v);
-  if (lane == 0) lds[wave] = v;
-  __syncthreads();
-  double total = 0.0;
-  for (int w = 0; w < nw; ++w) total += lds[w];
-  __syncthreads();
-  return total;
-}
-
-// Block sum of a per-thread double; the result is valid in thread 0.
-__device__ double block_sum(double v, double* lds) {
+// Block sum (blockDim.x a multiple of 64, at most 1024); the result is
+// valid in thread 0. Fixed order. lds holds blockDim.x / 64 values.
+template <typename V>
+__device__ V block_sum(V v, V* lds) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   v = wave_sum(v);
   if (lane == 0) lds[wave] = v;
   __syncthreads();
-  double total = 0.0;
+  V total = 0;
   if (threadIdx.x == 0)
     for (int w = 0; w < nw; ++w) total += lds[w];
   __syncthreads();
@@ -74,139 +58,119 @@ __device__ double block_sum(double v, double* lds) {
 
 __global__ void k_reset_ctl(Ctl* ctl) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->r = 0.0;
+    ctl->psum = 0.0;
     ctl->e = 0.0;
-    ctl->e_snap = 0.0;
     ctl->final_r = 0.0;
     ctl->paper_err = 0.0;
-    ctl->r_last = 0.0;
     ctl->r_first = 0.0;
-    for (int s = 0; s < 3; ++s) {
-      ctl->packed[s] = 0;
-      ctl->sel[s] = 0;
-    }
+    ctl->r_last = 0.0;
     ctl->cycles = 0;
     ctl->fallback = 0;
     ctl->done = 0;
-    ctl->cur = -1;
+    ctl->cyc_mode = 0;
     ctl->edges_total = 0;
     ctl->front_total = 0;
     ctl->sel_total = 0;
   }
 }
 
+// F = B, H = 0, and per-block partial sums of |F| and F over all nodes.
 template <typename T>
-__global__ void k_init(T* __restrict__ F, T* __restrict__ H, const double* __restrict__ B,
-                       double b_uniform, int64_t n) {
+__global__ __launch_bounds__(kReduceBlock) void k_start(T* __restrict__ F, T* __restrict__ H,
+                                                        const double* __restrict__ B,
+                                                        double b_uniform, int64_t n,
+                                                        double* __restrict__ blk_pabs,
+                                                        double* __restrict__ blk_psum) {
+  __shared__ double lds[kReduceBlock / 64];
+  double pa = 0.0, ps = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    F[i] = B ? (T)B[i] : (T)b_uniform;
+    const T f = B ? (T)B[i] : (T)b_uniform;
+    F[i] = f;
     H[i] = (T)0;
+    pa += fabs(to_d(f));
+    ps += to_d(f);
+  }
+  pa = block_sum(pa, lds);
+  ps = block_sum(ps, lds);
+  if (threadIdx.x == 0) {
+    blk_pabs[blockIdx.x] = pa;
+    blk_psum[blockIdx.x] = ps;
   }
 }
 
+// Per-block partial sums of |F| and F (push direction, after the push).
 template <typename T>
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(const T* __restrict__ F, int64_t n,
-                                                         double* __restrict__ part_abs,
-                                                         double* __restrict__ part_sum,
-                                                         Ctl* __restrict__ ctl) {
+                                                         double* __restrict__ blk_pabs,
+                                                         double* __restrict__ blk_psum,
+                                                         const Ctl* __restrict__ ctl) {
   __shared__ double lds[kReduceBlock / 64];
   if (ctl->done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const int c = ctl->cur + 1;
-    ctl->cur = c;
-    ctl->packed[c % 3] = 0;
-    ctl->sel[c % 3] = 0;
-    ctl->e_snap = ctl->e;
-  }
-  double sa = 0.0, ss = 0.0;
+  double pa = 0.0, ps = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double f = to_d(F[i]);
-    sa += fabs(f);
-    ss += f;
+    pa += fabs(f);
+    ps += f;
   }
-  sa = block_sum(sa, lds);
-  ss = block_sum(ss, lds);
+  pa = block_sum(pa, lds);
+  ps = block_sum(ps, lds);
   if (threadIdx.x == 0) {
-    part_abs[blockIdx.x] = sa;
-    part_sum[blockIdx.x] = ss;
+    blk_pabs[blockIdx.x] = pa;
+    blk_psum[blockIdx.x] = ps;
   }
 }
 
-template <typename T>
+// Selection and claim. Thread t of block b owns the nodes
+// b*kSelectNodes + t + m*kSelectBlock, m < kSelectPerThread (coalesced).
+// PULL: writes sent[i] (0 for nodes not diffused) for every node.
+// PUSH: writes the block's frontier (nodes with links to push) at
+//       [b*kSelectNodes, ...) with block-local link offsets that grow with
+//       the entry index.
+template <typename T, bool PULL>
 __global__ __launch_bounds__(kSelectBlock) void k_select(
     T* __restrict__ F, T* __restrict__ H, const uint32_t* __restrict__ info,
-    const int64_t* __restrict__ row_ptr, int64_t n, int64_t L, double d, double tol, int method,
-    int stop, int max_cycles, const double* __restrict__ part_abs,
-    const double* __restrict__ part_sum, int nparts, int64_t* __restrict__ fr_start,
-    int64_t* __restrict__ fr_base, T* __restrict__ fr_s, int32_t* __restrict__ tile_first,
-    Ctl* __restrict__ ctl) {
-  __shared__ double s_red[kSelectBlock / 64];
-  __shared__ unsigned long long s_scan[kSelectBlock / 64];
-  __shared__ unsigned int s_cnt[kSelectBlock / 64];
-  __shared__ unsigned long long s_base;
+    const int64_t* __restrict__ row_ptr, int64_t n, int64_t L, double d,
+    T* __restrict__ sent, int64_t* __restrict__ fr_lstart, int64_t* __restrict__ fr_base,
+    T* __restrict__ fr_s, SelStat* __restrict__ blk_stat, const Ctl* __restrict__ ctl) {
   constexpr int M = kSelectPerThread;
-
+  constexpr int NW = kSelectBlock / 64;
+  __shared__ unsigned long long s_ops[NW];
+  __shared__ double s_e[NW];
+  __shared__ unsigned int s_sel[NW], s_front[NW];
   if (ctl->done) return;
-  const int cycle = ctl->cur;
-  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
-  const double r = block_sum_fixed(part_abs, nparts, s_red);
-  bool stop_now = false;
-  if (stop == DI_STOP_RESID) {
-    stop_now = r <= tol;
-  } else if (cycle > 0) {
-    const double psum = block_sum_fixed(part_sum, nparts, s_red);
-    const double perr = psum / (1.0 - d - d * ctl->e_snap);
-    if (leader) ctl->paper_err = perr;
-    stop_now = perr <= tol;
-  }
-  if (!isfinite(r)) {
-    if (leader) {
-      ctl->final_r = r;
-      ctl->done = 3;
-    }
-    return;
-  }
-  if (stop_now || cycle >= max_cycles) {
-    if (leader) {
-      ctl->final_r = r;
-      ctl->done = stop_now ? 1 : 2;
-    }
-    return;
-  }
-  bool cyc = method == DI_CYC;
-  if (!cyc && cycle > 0 && ctl->sel[(cycle + 2) % 3] == 0) {
-    cyc = true;  // the previous cycle selected nothing: one DI-CYC cycle
-    if (leader) ctl->fallback += 1;
-  }
-  if (leader) {
-    ctl->cycles = cycle + 1;
-    ctl->r_last = r;
-    if (cycle == 0) ctl->r_first = r;
-  }
-  const int slot = cycle % 3;
+  const double r = ctl->r;
+  const bool cyc = ctl->cyc_mode != 0;
   const double rl = r / (double)L;
 
-  const int64_t base = (int64_t)blockIdx.x * kSelectNodes + (int64_t)threadIdx.x * M;
+  const int64_t base = (int64_t)blockIdx.x * kSelectNodes + threadIdx.x;
+  double f[M];
+  uint32_t w[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int64_t i = base + (int64_t)m * kSelectBlock;
+    f[m] = i < n ? to_d(F[i]) : 0.0;
+    w[m] = i < n ? info[i] : 0u;
+  }
   int npush[M];
-  double sent[M];
-  unsigned long long mine = 0;
-  unsigned int my_sel = 0;
+  double snd[M];
+  unsigned int my_sel = 0, my_front = 0;
+  unsigned long long my_ops = 0;
   double my_e = 0.0;
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     npush[m] = 0;
-    sent[m] = 0.0;
-    const int64_t i = base + m;
+    snd[m] = 0.0;
+    const int64_t i = base + (int64_t)m * kSelectBlock;
     if (i < n) {
-      const double f = to_d(F[i]);
-      const uint32_t w = info[i];
-      const int out = (int)(w & kOutMask);
-      const bool loop = (w & kLoopBit) != 0;
-      const double a = fabs(f);
+      const int out = (int)(w[m] & kOutMask);
+      const bool loop = (w[m] & kLoopBit) != 0;
+      const double a = fabs(f[m]);
       const double thr = (cyc || out == 0) ? 0.0 : rl * (double)out;
       if (a > 0.0 && a >= thr) {
-        const double t = loop ? f * (double)out / ((double)out - d) : f;
+        const double t = loop ? f[m] * (double)out / ((double)out - d) : f[m];
         H[i] = (T)(to_d(H[i]) + t);
         F[i] = (T)0;
         ++my_sel;
@@ -216,106 +180,355 @@ __global__ __launch_bounds__(kSelectBlock) void k_select(
           const int np = out - (loop ? 1 : 0);
           if (np > 0) {
             npush[m] = np;
-            sent[m] = t * d / (double)out;
-            mine += 1ull + ((unsigned long long)np << kPackShift);
+            snd[m] = t * d / (double)out;
+            my_ops += (unsigned long long)np;
+            ++my_front;
           }
         }
       }
+      if (PULL) sent[i] = (T)snd[m];
     }
   }
-
-  // exclusive scan of the packed (entries, links) counts in node order
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  unsigned long long incl = mine;
+  if (!PULL) {
+    // block-local exclusive scan of (entries, links) over (thread, m) order
+    unsigned int cnt_incl = my_front;
+    unsigned long long lnk_incl = my_ops;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned long long u = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += u;
-  }
-  if (lane == 63) s_scan[wave] = incl;
-  const unsigned int wsel = wave_sum_u32(my_sel);
-  if (lane == 0) s_cnt[wave] = wsel;
-  __syncthreads();
-  unsigned long long before = 0, total = 0;
-  unsigned int sel_total = 0;
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned int u = __shfl_up(cnt_incl, off, 64);
+      const unsigned long long v = __shfl_up(lnk_incl, off, 64);
+      if (lane >= off) {
+        cnt_incl += u;
+        lnk_incl += v;
+      }
+    }
+    if (lane == 63) {
+      s_front[wave] = cnt_incl;
+      s_ops[wave] = lnk_incl;
+    }
+    __syncthreads();
+    unsigned int cnt_before = 0;
+    unsigned long long lnk_before = 0;
+    for (int q = 0; q < wave; ++q) {
+      cnt_before += s_front[q];
+      lnk_before += s_ops[q];
+    }
+    __syncthreads();
+    unsigned int k = cnt_before + cnt_incl - my_front;
+    unsigned long long lo = lnk_before + lnk_incl - my_ops;
+    const int64_t fbase = (int64_t)blockIdx.x * kSelectNodes;
 #pragma unroll
-  for (int w = 0; w < kSelectBlock / 64; ++w) {
-    if (w < wave) before += s_scan[w];
-    total += s_scan[w];
-    sel_total += s_cnt[w];
-  }
-  if (threadIdx.x == 0) {
-    s_base = total ? atomicAdd(&ctl->packed[slot], total) : 0ull;
-    if (sel_total) atomicAdd(&ctl->sel[slot], sel_total);
-  }
-  __syncthreads();
-  unsigned long long pos = s_base + before + incl - mine;
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    if (npush[m] > 0) {
-      const int64_t k = (int64_t)(pos & kPackNodeMask);
-      const int64_t es = (int64_t)(pos >> kPackShift);
-      fr_start[k] = es;
-      fr_base[k] = row_ptr[base + m];
-      fr_s[k] = (T)sent[m];
-      const int64_t b_lo = (es + kPushTile - 1) / kPushTile;
-      const int64_t b_hi = (es + npush[m] - 1) / kPushTile;
-      for (int64_t b = b_lo; b <= b_hi; ++b) tile_first[b] = (int32_t)k;
-      pos += 1ull + ((unsigned long long)npush[m] << kPackShift);
+    for (int m = 0; m < M; ++m) {
+      if (npush[m] > 0) {
+        fr_lstart[fbase + k] = (int64_t)lo;
+        fr_base[fbase + k] = row_ptr[base + (int64_t)m * kSelectBlock];
+        fr_s[fbase + k] = (T)snd[m];
+        ++k;
+        lo += (unsigned long long)npush[m];
+      }
     }
   }
-  const double e_blk = block_sum(my_e, s_red);
-  if (threadIdx.x == 0 && e_blk != 0.0) atomicAdd(&ctl->e, e_blk);
+  // one fused block reduction of the four statistics
+  my_sel = wave_sum(my_sel);
+  my_front = wave_sum(my_front);
+  my_ops = wave_sum(my_ops);
+  my_e = wave_sum(my_e);
+  if (lane == 0) {
+    s_sel[wave] = my_sel;
+    s_front[wave] = my_front;
+    s_ops[wave] = my_ops;
+    s_e[wave] = my_e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SelStat st;
+    st.sel = 0;
+    st.nfront = 0;
+    st.ops = 0;
+    st.e = 0.0;
+    for (int q = 0; q < NW; ++q) {
+      st.sel += s_sel[q];
+      st.nfront += s_front[q];
+      st.ops += s_ops[q];
+      st.e += s_e[q];
+    }
+    blk_stat[blockIdx.x] = st;
+  }
 }
 
+// Pull: F_j += sum of sent[i] over the in-links i -> j (i != j). Work items
+// are prepared with the graph: light items (rows [r0, r1), at most
+// kPullChunk links) and segments of heavy rows. Each thread stages its
+// kPullChunk / kPullBlock links with all index loads, then all gathers, in
+// flight together. Per-block partial sums of |F| and F cover the light
+// rows; heavy rows are finished by k_finalize.
+template <typename T>
+__global__ __launch_bounds__(kPullBlock) void k_pull(
+    T* __restrict__ F, const T* __restrict__ sent, const int64_t* __restrict__ csc_ptr,
+    const int32_t* __restrict__ csc_idx, const int64_t* __restrict__ it_r0,
+    const int64_t* __restrict__ it_r1, const int64_t* __restrict__ it_l0,
+    const int64_t* __restrict__ it_l1, const int32_t* __restrict__ it_seg, int64_t n_items,
+    double* __restrict__ seg_val, double* __restrict__ blk_pabs, double* __restrict__ blk_psum,
+    const Ctl* __restrict__ ctl) {
+  constexpr int U = kPullChunk / kPullBlock;
+  __shared__ double s_val[kPullChunk];
+  __shared__ double s_red[kPullBlock / 64];
+  if (ctl->done) return;
+  const int tid = threadIdx.x;
+  double pa = 0.0, ps = 0.0;
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int64_t l0 = it_l0[it], l1 = it_l1[it];
+    const int seg = it_seg[it];
+    const int nl = (int)(l1 - l0);
+    const int64_t r0 = it_r0[it], r1 = it_r1[it];
+    // the thread's first row, fetched while the links are in flight
+    const int64_t row0 = r0 + tid;
+    double f0 = 0.0;
+    int a0 = 0, b0 = 0;
+    if (seg < 0 && row0 < r1) {
+      f0 = to_d(F[row0]);
+      a0 = (int)(csc_ptr[row0] - l0);
+      b0 = (int)(csc_ptr[row0 + 1] - l0);
+    }
+    int32_t idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kPullBlock;
+      idx[u] = p < nl ? csc_idx[l0 + p] : 0;
+    }
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kPullBlock;
+      v[u] = p < nl ? to_d(sent[idx[u]]) : 0.0;
+    }
+    if (seg >= 0) {
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += v[u];
+      acc = block_sum(acc, s_red);
+      if (tid == 0) seg_val[seg] = acc;
+      continue;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kPullBlock;
+      if (p < nl) s_val[p] = v[u];
+    }
+    __syncthreads();
+    // rows r0 + tid + k * kPullBlock; a row with more than kPullLongRow links
+    // is summed by its whole wave (strided lanes, then a butterfly)
+    const int lane = tid & 63;
+    for (int64_t row = row0; row - lane < r1; row += kPullBlock) {
+      const bool valid = row < r1;
+      double f = 0.0;
+      int a = 0, b = 0;
+      if (row == row0) {
+        f = f0;
+        a = a0;
+        b = b0;
+      } else if (valid) {
+        f = to_d(F[row]);
+        a = (int)(csc_ptr[row] - l0);
+        b = (int)(csc_ptr[row + 1] - l0);
+      }
+      const bool longrow = valid && (b - a) > kPullLongRow;
+      double acc = 0.0;
+      if (valid && !longrow)
+        for (int q = a; q < b; ++q) acc += s_val[q];
+      unsigned long long mask = __ballot(longrow);
+      while (mask) {
+        const int src = __ffsll(mask) - 1;
+        mask &= mask - 1;
+        const int la = __shfl(a, src, 64), lb = __shfl(b, src, 64);
+        double part = 0.0;
+        for (int q = la + lane; q < lb; q += 64) part += s_val[q];
+        part = wave_sum(part);
+        if (lane == src) acc = part;
+      }
+      if (valid) {
+        if (acc != 0.0) {
+          const T nv = (T)(f + acc);
+          F[row] = nv;
+          f = to_d(nv);
+        }
+        pa += fabs(f);
+        ps += f;
+      }
+    }
+    __syncthreads();
+  }
+  pa = block_sum(pa, s_red);
+  ps = block_sum(ps, s_red);
+  if (tid == 0) {
+    blk_pabs[blockIdx.x] = pa;
+    blk_psum[blockIdx.x] = ps;
+  }
+}
+
+// Push: block b moves the frontier of select block b. Entries are staged in
+// LDS; each lane finds the entry of its link by binary search on the local
+// link offsets and adds the entry's amount to F[col] atomically.
 template <typename T>
 __global__ __launch_bounds__(kPushBlock) void k_push(T* __restrict__ F,
                                                      const int32_t* __restrict__ col,
-                                                     const int64_t* __restrict__ fr_start,
+                                                     const int64_t* __restrict__ fr_lstart,
                                                      const int64_t* __restrict__ fr_base,
                                                      const T* __restrict__ fr_s,
-                                                     const int32_t* __restrict__ tile_first,
-                                                     Ctl* __restrict__ ctl) {
-  __shared__ int32_t s_start[kPushTile + 1];
-  __shared__ int64_t s_base[kPushTile + 1];
-  __shared__ T s_val[kPushTile + 1];
+                                                     const SelStat* __restrict__ blk_stat,
+                                                     const Ctl* __restrict__ ctl) {
+  __shared__ int64_t s_start[kSelectNodes];
+  __shared__ int64_t s_base[kSelectNodes];
+  __shared__ T s_val[kSelectNodes];
   if (ctl->done) return;
-  const int slot = ctl->cur % 3;
-  const unsigned long long packed = ctl->packed[slot];
-  const int64_t nfront = (int64_t)(packed & kPackNodeMask);
-  const int64_t E = (int64_t)(packed >> kPackShift);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->edges_total += (unsigned long long)E;
-    ctl->front_total += (unsigned long long)nfront;
-    ctl->sel_total += ctl->sel[slot];
+  const int nf = (int)blk_stat[blockIdx.x].nfront;
+  if (nf == 0) return;
+  const int64_t E = (int64_t)blk_stat[blockIdx.x].ops;
+  const int64_t fbase = (int64_t)blockIdx.x * kSelectNodes;
+  for (int q = threadIdx.x; q < nf; q += blockDim.x) {
+    s_start[q] = fr_lstart[fbase + q];
+    s_base[q] = fr_base[fbase + q] - fr_lstart[fbase + q];
+    s_val[q] = fr_s[fbase + q];
   }
-  const int64_t ntiles = (E + kPushTile - 1) / kPushTile;
-  for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
-    const int64_t t0 = b * kPushTile;
-    const int k0 = tile_first[b];
-    const int k1 = (b + 1 < ntiles) ? tile_first[b + 1] : (int)(nfront - 1);
-    const int cnt = k1 - k0 + 1;
-    for (int q = threadIdx.x; q < cnt; q += kPushBlock) {
-      const int64_t es = fr_start[k0 + q];
-      s_start[q] = (int32_t)(es - t0);
-      s_base[q] = fr_base[k0 + q] - es + t0;
-      s_val[q] = fr_s[k0 + q];
+  __syncthreads();
+  int lo = 0;
+  for (int64_t e = threadIdx.x; e < E; e += blockDim.x) {
+    int hi = nf - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_start[mid] <= e) lo = mid;
+      else hi = mid - 1;
     }
-    __syncthreads();
-    const int lim = (int)((E - t0) < kPushTile ? (E - t0) : kPushTile);
-    int lo = 0;
-    for (int el = threadIdx.x; el < lim; el += kPushBlock) {
-      int hi = cnt - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_start[mid] <= el) lo = mid;
-        else hi = mid - 1;
+    const int32_t j = col[s_base[lo] + e];
+    atomic_add(&F[j], s_val[lo]);
+  }
+}
+
+// Single block: finishes heavy rows (pull), sums every partial in a fixed
+// order into r = sum |F| and sum F, accumulates the cycle's statistics and
+// runs the stop test. start != 0: the test before the first cycle (no
+// selection happened; the partials come from k_start / k_reduce).
+template <typename T>
+__global__ __launch_bounds__(kFinalBlock) void k_finalize(
+    T* __restrict__ F, const int32_t* __restrict__ heavy_row, const int64_t* __restrict__ heavy_seg,
+    const int64_t* __restrict__ hb_h0, const int64_t* __restrict__ hb_h1, int64_t n_hbatch,
+    const double* __restrict__ seg_val, const double* __restrict__ blk_pabs,
+    const double* __restrict__ blk_psum, int nparts, const SelStat* __restrict__ blk_stat,
+    int nsel, int start, double d, double tol, int method, int stop, int max_cycles,
+    Ctl* __restrict__ ctl) {
+  __shared__ double s_seg[kFinalSegBatch];
+  __shared__ double s_red[kFinalBlock / 64];
+  __shared__ unsigned long long s_red64[kFinalBlock / 64];
+  if (ctl->done) return;
+  const int tid = threadIdx.x;
+  double pa = 0.0, ps = 0.0;
+  if (!start) {
+    for (int64_t b = 0; b < n_hbatch; ++b) {
+      const int64_t h0 = hb_h0[b], h1 = hb_h1[b];
+      const int64_t s0 = heavy_seg[h0], s1 = heavy_seg[h1];
+      const int64_t ns = s1 - s0;
+      if (ns > kFinalSegBatch) {
+        // one row with many segments: a block-wide sum
+        double acc = 0.0;
+        for (int64_t s = s0 + tid; s < s1; s += blockDim.x) acc += seg_val[s];
+        acc = block_sum(acc, s_red);
+        if (tid == 0) {
+          const int32_t row = heavy_row[h0];
+          double f = to_d(F[row]);
+          if (acc != 0.0) {
+            const T nv = (T)(f + acc);
+            F[row] = nv;
+            f = to_d(nv);
+          }
+          pa += fabs(f);
+          ps += f;
+        }
+        continue;
       }
-      const int32_t j = col[s_base[lo] + el];
-      atomic_add(&F[j], s_val[lo]);
+      for (int64_t q = tid; q < ns; q += blockDim.x) s_seg[q] = seg_val[s0 + q];
+      __syncthreads();
+      for (int64_t h = h0 + tid; h < h1; h += blockDim.x) {
+        const int32_t row = heavy_row[h];
+        double acc = 0.0;
+        for (int64_t s = heavy_seg[h]; s < heavy_seg[h + 1]; ++s) acc += s_seg[s - s0];
+        double f = to_d(F[row]);
+        if (acc != 0.0) {
+          const T nv = (T)(f + acc);
+          F[row] = nv;
+          f = to_d(nv);
+        }
+        pa += fabs(f);
+        ps += f;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
+  for (int p = tid; p < nparts; p += blockDim.x) {
+    pa += blk_pabs[p];
+    ps += blk_psum[p];
+  }
+  double e_c = 0.0;
+  unsigned long long sel = 0, front = 0, ops = 0;
+  if (!start) {
+    for (int b = tid; b < nsel; b += blockDim.x) {
+      const SelStat st = blk_stat[b];
+      sel += st.sel;
+      front += st.nfront;
+      ops += st.ops;
+      e_c += st.e;
+    }
+  }
+  const double r = block_sum(pa, s_red);
+  const double psum = block_sum(ps, s_red);
+  e_c = block_sum(e_c, s_red);
+  sel = block_sum(sel, s_red64);
+  front = block_sum(front, s_red64);
+  ops = block_sum(ops, s_red64);
+  if (tid != 0) return;
+  Ctl c = *ctl;
+  if (!start) {
+    const double r_used = c.r;
+    c.cycles += 1;
+    if (c.cycles == 1) c.r_first = r_used;
+    c.r_last = r_used;
+    c.edges_total += ops;
+    c.front_total += front;
+    c.sel_total += sel;
+    c.e += e_c;
+    // a DI-SOP cycle that diffused nothing (possible only through rounding
+    // at a tie) is followed by one DI-CYC cycle
+    const bool empty = sel == 0 && r > 0.0;
+    c.cyc_mode = (method == DI_CYC || empty) ? 1 : 0;
+    if (method != DI_CYC && empty) c.fallback += 1;
+  } else {
+    c.cyc_mode = method == DI_CYC ? 1 : 0;
+  }
+  c.r = r;
+  c.psum = psum;
+  if (!isfinite(r)) {
+    c.final_r = r;
+    c.done = 3;
+  } else {
+    bool stop_now;
+    if (stop == DI_STOP_RESID) {
+      stop_now = r <= tol;
+    } else {
+      stop_now = false;
+      if (!start) {
+        c.paper_err = psum / (1.0 - d - d * c.e);
+        stop_now = c.paper_err <= tol;
+      }
+    }
+    if (stop_now) {
+      c.final_r = r;
+      c.done = 1;
+    } else if (c.cycles >= max_cycles) {
+      c.final_r = r;
+      c.done = 2;
+    }
+  }
+  *ctl = c;
 }
 
 template <typename T>
@@ -325,28 +538,33 @@ __global__ void k_h_to_x(const T* __restrict__ H, double* __restrict__ X, int64_
     X[i] = to_d(H[i]);
 }
 
-inline unsigned int grid_for(int64_t n, int block, unsigned int cap) {
+inline unsigned int grid_for(int64_t n, int block, int64_t cap) {
   int64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return (unsigned int)g;
 }
 
+template <typename T>
+hipError_t launch_finalize(const CycleArgs& a, int nparts, int start) {
+  const di_graph* g = a.g;
+  Workspace* ws = a.ws;
+  const bool pull = a.direction == kPull;
+  hipLaunchKernelGGL(k_finalize<T>, dim3(1), dim3(kFinalBlock), 0, a.stream, (T*)ws->F,
+                     g->heavy_row, g->heavy_seg, g->hb_h0, g->hb_h1,
+                     pull ? g->n_hbatch : (int64_t)0, ws->seg_val, ws->blk_pabs, ws->blk_psum,
+                     nparts, ws->blk_stat, (int)grid_for(g->n, kSelectNodes, 0x7fffffff), start,
+                     a.d, a.tol, a.method, a.stop, a.max_cycles, ws->ctl);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-int reduce_parts(int64_t n) {
-  int64_t p = (n + 8 * kReduceBlock - 1) / (8 * kReduceBlock);
-  if (p < 1) p = 1;
-  if (p > kMaxParts) p = kMaxParts;
-  return (int)p;
-}
+int select_grid(int64_t n) { return (int)grid_for(n, kSelectNodes, 0x7fffffff); }
 
-int push_grid(int64_t Lp) {
-  int64_t g = (Lp + kPushTile - 1) / kPushTile;
-  if (g < 1) g = 1;
-  if (g > kMaxPushGrid) g = kMaxPushGrid;
-  return (int)g;
-}
+int pull_grid(const di_graph* g) { return (int)grid_for(g->n_items, 1, kPullMaxGrid); }
+
+int reduce_grid(int64_t n) { return (int)grid_for(n, kReduceBlock, kReduceGrid); }
 
 hipError_t launch_reset_ctl(const CycleArgs& a) {
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, a.stream, a.ws->ctl);
@@ -354,35 +572,60 @@ hipError_t launch_reset_ctl(const CycleArgs& a) {
 }
 
 template <typename T>
-hipError_t launch_init(const CycleArgs& a, const double* B, double b_uniform) {
-  hipLaunchKernelGGL(k_init<T>, dim3(grid_for(a.g->n, 256, 4096)), dim3(256), 0, a.stream,
-                     (T*)a.ws->F, (T*)a.ws->H, B, b_uniform, a.g->n);
-  return hipGetLastError();
+hipError_t launch_start(const CycleArgs& a, const double* B, double b_uniform) {
+  const int grid = reduce_grid(a.g->n);
+  hipLaunchKernelGGL(k_start<T>, dim3(grid), dim3(kReduceBlock), 0, a.stream, (T*)a.ws->F,
+                     (T*)a.ws->H, B, b_uniform, a.g->n, a.ws->blk_pabs, a.ws->blk_psum);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return launch_finalize<T>(a, grid, 1);
 }
 
 template <typename T>
-hipError_t launch_reduce(const CycleArgs& a) {
-  hipLaunchKernelGGL(k_reduce<T>, dim3(a.nparts), dim3(kReduceBlock), 0, a.stream,
-                     (const T*)a.ws->F, a.g->n, a.ws->part_abs, a.ws->part_sum, a.ws->ctl);
-  return hipGetLastError();
+hipError_t launch_start_state(const CycleArgs& a) {
+  const int grid = reduce_grid(a.g->n);
+  hipLaunchKernelGGL(k_reduce<T>, dim3(grid), dim3(kReduceBlock), 0, a.stream, (const T*)a.ws->F,
+                     a.g->n, a.ws->blk_pabs, a.ws->blk_psum, a.ws->ctl);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return launch_finalize<T>(a, grid, 1);
 }
 
 template <typename T>
-hipError_t launch_select(const CycleArgs& a) {
-  const unsigned int grid = grid_for(a.g->n, kSelectNodes, 0x7fffffffu);
-  hipLaunchKernelGGL(k_select<T>, dim3(grid), dim3(kSelectBlock), 0, a.stream, (T*)a.ws->F,
-                     (T*)a.ws->H, a.g->info, a.g->row_ptr, a.g->n, a.g->L, a.d, a.tol, a.method,
-                     a.stop, a.max_cycles, a.ws->part_abs, a.ws->part_sum, a.nparts,
-                     a.ws->fr_start, a.ws->fr_base, (T*)a.ws->fr_s, a.ws->tile_first, a.ws->ctl);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_push(const CycleArgs& a) {
-  hipLaunchKernelGGL(k_push<T>, dim3(a.push_grid), dim3(kPushBlock), 0, a.stream, (T*)a.ws->F,
-                     a.g->col, a.ws->fr_start, a.ws->fr_base, (const T*)a.ws->fr_s,
-                     a.ws->tile_first, a.ws->ctl);
-  return hipGetLastError();
+hipError_t launch_cycle(const CycleArgs& a, hipEvent_t ev0, hipEvent_t ev1) {
+  const di_graph* g = a.g;
+  Workspace* ws = a.ws;
+  const int sgrid = select_grid(g->n);
+  hipError_t err;
+  if (a.direction == kPull) {
+    hipLaunchKernelGGL((k_select<T, true>), dim3(sgrid), dim3(kSelectBlock), 0, a.stream,
+                       (T*)ws->F, (T*)ws->H, g->info, g->row_ptr, g->n, g->L, a.d, (T*)ws->sent,
+                       (int64_t*)nullptr, (int64_t*)nullptr, (T*)nullptr, ws->blk_stat, ws->ctl);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (ev0 && (err = hipEventRecord(ev0, a.stream)) != hipSuccess) return err;
+    const int pgrid = pull_grid(g);
+    hipLaunchKernelGGL(k_pull<T>, dim3(pgrid), dim3(kPullBlock), 0, a.stream, (T*)ws->F,
+                       (const T*)ws->sent, g->csc_ptr, g->csc_idx, g->it_r0, g->it_r1, g->it_l0,
+                       g->it_l1, g->it_seg, g->n_items, ws->seg_val, ws->blk_pabs, ws->blk_psum,
+                       ws->ctl);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (ev1 && (err = hipEventRecord(ev1, a.stream)) != hipSuccess) return err;
+    return launch_finalize<T>(a, pgrid, 0);
+  }
+  hipLaunchKernelGGL((k_select<T, false>), dim3(sgrid), dim3(kSelectBlock), 0, a.stream,
+                     (T*)ws->F, (T*)ws->H, g->info, g->row_ptr, g->n, g->L, a.d, (T*)nullptr,
+                     ws->fr_lstart, ws->fr_base, (T*)ws->fr_s, ws->blk_stat, ws->ctl);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if (ev0 && (err = hipEventRecord(ev0, a.stream)) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_push<T>, dim3(sgrid), dim3(kPushBlock), 0, a.stream, (T*)ws->F, g->col,
+                     ws->fr_lstart, ws->fr_base, (const T*)ws->fr_s, ws->blk_stat, ws->ctl);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if (ev1 && (err = hipEventRecord(ev1, a.stream)) != hipSuccess) return err;
+  const int rgrid = reduce_grid(g->n);
+  hipLaunchKernelGGL(k_reduce<T>, dim3(rgrid), dim3(kReduceBlock), 0, a.stream, (const T*)ws->F,
+                     g->n, ws->blk_pabs, ws->blk_psum, ws->ctl);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  return launch_finalize<T>(a, rgrid, 0);
 }
 
 template <typename T>
@@ -392,14 +635,12 @@ hipError_t launch_h_to_x(const CycleArgs& a, double* X) {
   return hipGetLastError();
 }
 
-template hipError_t launch_init<double>(const CycleArgs&, const double*, double);
-template hipError_t launch_init<float>(const CycleArgs&, const double*, double);
-template hipError_t launch_reduce<double>(const CycleArgs&);
-template hipError_t launch_reduce<float>(const CycleArgs&);
-template hipError_t launch_select<double>(const CycleArgs&);
-template hipError_t launch_select<float>(const CycleArgs&);
-template hipError_t launch_push<double>(const CycleArgs&);
-template hipError_t launch_push<float>(const CycleArgs&);
+template hipError_t launch_start<double>(const CycleArgs&, const double*, double);
+template hipError_t launch_start<float>(const CycleArgs&, const double*, double);
+template hipError_t launch_start_state<double>(const CycleArgs&);
+template hipError_t launch_start_state<float>(const CycleArgs&);
+template hipError_t launch_cycle<double>(const CycleArgs&, hipEvent_t, hipEvent_t);
+template hipError_t launch_cycle<float>(const CycleArgs&, hipEvent_t, hipEvent_t);
 template hipError_t launch_h_to_x<double>(const CycleArgs&, double*);
 template hipError_t launch_h_to_x<float>(const CycleArgs&, double*);
 

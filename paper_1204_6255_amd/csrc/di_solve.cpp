@@ -1,10 +1,10 @@
 // libdi solve driver: workspace pool, the cycle loop and the stop check.
 //
-// The host queues whole cycles (reduce, select, push) in chunks; the device
-// keeps the cycle index and the stop flag, and every kernel returns at once
-// after the stop, so a chunk may run past convergence at the cost of empty
-// launches. After each chunk the host reads the control block (a pinned
-// copy) and sizes the next chunk from the observed contraction of r.
+// The host queues whole cycles in chunks; the device keeps the stop flag and
+// every kernel returns at once after the stop, so a chunk may run past
+// convergence at the cost of empty launches. After each chunk the host reads
+// the control block (a pinned copy) and sizes the next chunk from the
+// observed contraction of r per cycle.
 
 #include <algorithm>
 #include <cmath>
@@ -18,17 +18,10 @@ namespace di {
 
 void free_workspace(Workspace* ws) {
   if (!ws) return;
-  (void)hipFree(ws->F);
-  (void)hipFree(ws->H);
-  (void)hipFree(ws->fr_start);
-  (void)hipFree(ws->fr_base);
-  (void)hipFree(ws->fr_s);
-  (void)hipFree(ws->tile_first);
-  (void)hipFree(ws->part_abs);
-  (void)hipFree(ws->part_sum);
-  (void)hipFree(ws->ctl);
-  (void)hipFree(ws->X64);
-  (void)hipFree(ws->R64);
+  void* ptrs[] = {ws->F,        ws->H,        ws->sent,    ws->fr_lstart, ws->fr_base,
+                  ws->fr_s,     ws->blk_stat, ws->blk_pabs, ws->blk_psum, ws->seg_val,
+                  ws->ctl,      ws->X64,      ws->B64};
+  for (void* p : ptrs) (void)hipFree(p);
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   for (hipEvent_t e : ws->events) (void)hipEventDestroy(e);
   delete ws;
@@ -51,21 +44,20 @@ di_status alloc_workspace(const di_graph* g, int prec, Workspace** out) {
   Workspace* ws = new (std::nothrow) Workspace;
   if (!ws) return DI_E_NOMEM;
   ws->prec = prec;
-  ws->n = g->n;
   const size_t n = (size_t)g->n;
   const size_t s = prec == kF64 ? sizeof(double) : sizeof(float);
-  const size_t tiles = (size_t)((g->Lp + kPushTile - 1) / kPushTile) + 2;
+  const size_t nsel = (size_t)select_grid(g->n);
+  const size_t nparts = (size_t)std::max(kPullMaxGrid, kReduceGrid);
   di_status st = DI_OK;
   if (st == DI_OK) st = dmalloc(&ws->F, n * s);
   if (st == DI_OK) st = dmalloc(&ws->H, n * s);
-  if (st == DI_OK) st = dmalloc((void**)&ws->fr_start, n * sizeof(int64_t));
-  if (st == DI_OK) st = dmalloc((void**)&ws->fr_base, n * sizeof(int64_t));
-  if (st == DI_OK) st = dmalloc(&ws->fr_s, n * s);
-  if (st == DI_OK) st = dmalloc((void**)&ws->tile_first, tiles * sizeof(int32_t));
-  if (st == DI_OK) st = dmalloc((void**)&ws->part_abs, kMaxParts * sizeof(double));
-  if (st == DI_OK) st = dmalloc((void**)&ws->part_sum, kMaxParts * sizeof(double));
+  if (st == DI_OK) st = dmalloc(&ws->sent, n * s);
+  if (st == DI_OK) st = dmalloc((void**)&ws->blk_stat, nsel * sizeof(SelStat));
+  if (st == DI_OK) st = dmalloc((void**)&ws->blk_pabs, nparts * sizeof(double));
+  if (st == DI_OK) st = dmalloc((void**)&ws->blk_psum, nparts * sizeof(double));
+  if (st == DI_OK)
+    st = dmalloc((void**)&ws->seg_val, (size_t)std::max<int64_t>(g->n_segs, 1) * sizeof(double));
   if (st == DI_OK) st = dmalloc((void**)&ws->ctl, sizeof(Ctl));
-  if (st == DI_OK) st = dmalloc((void**)&ws->R64, n * sizeof(double));
   if (st == DI_OK) {
     hipError_t err = hipHostMalloc((void**)&ws->host_ctl, sizeof(Ctl), hipHostMallocDefault);
     if (err != hipSuccess) {
@@ -79,6 +71,17 @@ di_status alloc_workspace(const di_graph* g, int prec, Workspace** out) {
     return st;
   }
   *out = ws;
+  return DI_OK;
+}
+
+// Push buffers are allocated on first use (pull solves never need them).
+di_status ensure_push_buffers(const di_graph* g, Workspace* ws) {
+  if (ws->fr_lstart) return DI_OK;
+  const size_t slots = (size_t)select_grid(g->n) * kSelectNodes;
+  const size_t s = ws->prec == kF64 ? sizeof(double) : sizeof(float);
+  DI_TRY(dmalloc((void**)&ws->fr_base, slots * sizeof(int64_t)));
+  DI_TRY(dmalloc(&ws->fr_s, slots * s));
+  DI_TRY(dmalloc((void**)&ws->fr_lstart, slots * sizeof(int64_t)));
   return DI_OK;
 }
 
@@ -121,28 +124,43 @@ di_status ensure_events(Workspace* ws, size_t count) {
   return DI_OK;
 }
 
-// Runs cycles until the device reports a stop. Fills the timing fields of
-// *st and leaves the final control block in ws->host_ctl.
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+struct RunTimes {
+  double seconds = 0.0;       // first queued kernel to the end of the last
+  double move_seconds = 0.0;  // summed pull/push kernel time (timing flag)
+  int move_launches = 0;
+};
+
+// Queues cycles until the device reports a stop; the final control block
+// is left in ws->host_ctl. ev_begin was recorded before the start kernels.
 template <typename T>
-di_status run_cycles(const CycleArgs& a, bool timing, double* seconds, double* push_seconds,
-                     int* push_launches) {
+di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTimes* rt) {
   Workspace* ws = a.ws;
-  hipEvent_t ev_begin, ev_end;
   DI_TRY(ensure_events(ws, 2));
-  ev_begin = ws->events[0];
-  ev_end = ws->events[1];
-  DI_HIP(hipEventRecord(ev_begin, a.stream));
+  hipEvent_t ev_end = ws->events[1];
   int launched = 0;
   int chunk = 8;
-  for (;;) {
-    const int todo = std::min(chunk, a.max_cycles + 1 - launched);
+  // the start kernels already ran the stop test before the first cycle
+  DI_HIP(hipEventRecord(ev_end, a.stream));
+  DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, a.stream));
+  DI_HIP(hipStreamSynchronize(a.stream));
+  while (!ws->host_ctl->done) {
+    const int todo = std::max(1, std::min(chunk, a.max_cycles - launched));
     if (timing) DI_TRY(ensure_events(ws, 2 + 2 * (size_t)(launched + todo)));
     for (int q = 0; q < todo; ++q) {
-      DI_HIP(launch_reduce<T>(a));
-      DI_HIP(launch_select<T>(a));
-      if (timing) DI_HIP(hipEventRecord(ws->events[2 + 2 * (size_t)launched], a.stream));
-      DI_HIP(launch_push<T>(a));
-      if (timing) DI_HIP(hipEventRecord(ws->events[3 + 2 * (size_t)launched], a.stream));
+      hipEvent_t e0 = timing ? ws->events[2 + 2 * (size_t)launched] : nullptr;
+      hipEvent_t e1 = timing ? ws->events[3 + 2 * (size_t)launched] : nullptr;
+      DI_HIP(launch_cycle<T>(a, e0, e1));
       ++launched;
     }
     DI_HIP(hipEventRecord(ev_end, a.stream));
@@ -150,40 +168,44 @@ di_status run_cycles(const CycleArgs& a, bool timing, double* seconds, double* p
     DI_HIP(hipStreamSynchronize(a.stream));
     const Ctl& h = *ws->host_ctl;
     if (h.done) break;
-    if (launched > a.max_cycles) {
+    if (launched >= a.max_cycles) {
       set_error("internal: the device did not stop after max_cycles");
       return DI_E_DEVICE;
     }
-    // size the next chunk from the contraction of r per cycle so far
+    // cycles still needed, from the contraction of r per cycle so far
     int next = 16;
-    if (a.stop == DI_STOP_RESID && h.cycles >= 2 && h.r_first > 0.0 && h.r_last > 0.0 &&
-        h.r_last < h.r_first) {
-      const double rate = std::log(h.r_last / h.r_first) / (double)(h.cycles - 1);
-      const double need = std::log(a.tol / h.r_last) / rate;  // cycles still needed
+    if (a.stop == DI_STOP_RESID && h.cycles >= 1 && h.r_first > 0.0 && h.r > 0.0 &&
+        h.r < h.r_first && a.tol > 0.0) {
+      const double rate = std::log(h.r / h.r_first) / (double)h.cycles;
+      const double need = std::log(a.tol / h.r) / rate;
       if (std::isfinite(need)) next = (int)std::ceil(need) + 1;
     }
     chunk = std::max(2, std::min(next, 64));
   }
   float ms = 0.f;
   DI_HIP(hipEventElapsedTime(&ms, ev_begin, ev_end));
-  *seconds = ms * 1e-3;
-  *push_seconds = 0.0;
-  *push_launches = 0;
+  rt->seconds = ms * 1e-3;
   if (timing) {
     const int real = std::min(ws->host_ctl->cycles, launched);
     for (int c = 0; c < real; ++c) {
       float pm = 0.f;
       DI_HIP(hipEventElapsedTime(&pm, ws->events[2 + 2 * (size_t)c], ws->events[3 + 2 * (size_t)c]));
-      *push_seconds += pm * 1e-3;
+      rt->move_seconds += pm * 1e-3;
     }
-    *push_launches = real;
+    rt->move_launches = real;
   }
   return DI_OK;
 }
 
-template <typename T>
-void fill_stats(const di_graph* g, const Workspace* ws, double d, int precision_bytes, di_stats* st) {
-  const Ctl& h = *ws->host_ctl;
+// Algorithmic bytes (s = bytes per fluid value).
+//   select, per cycle: N (2s + 4) (F and the node word read, sent or frontier
+//     written) + 3s per diffused node (H read and written, F written);
+//   pull, per cycle: Lp (4 + s) (in-link id, sender's amount) + N (8 + 2s)
+//     (in-link offsets, F read and written);
+//   push, per cycle: links pushed (4 + 2s) (out-link id, atomic read-modify-
+//     write) + frontier entries (16 + s), and the reduction N s.
+void fill_stats(const di_graph* g, const Ctl& h, double d, int s_bytes, int direction,
+                const RunTimes& rt, di_stats* st) {
   st->cycles = h.cycles;
   st->fallback_cycles = h.fallback;
   st->edges_pushed = (int64_t)h.edges_total;
@@ -192,18 +214,19 @@ void fill_stats(const di_graph* g, const Workspace* ws, double d, int precision_
   st->err_bound = h.final_r / (1.0 - d);
   st->paper_err = h.paper_err;
   st->e = h.e;
-  // algorithmic bytes (s = bytes per fluid value):
-  //   push:   per link 4 (index) + 2s (atomic read-modify-write);
-  //           per frontier entry 8 + 8 + s (entry read into LDS);
-  //   reduce: N s per cycle; select: N (s + 4) per cycle, 3s per diffused
-  //           node (F write, H read and write), 8 + 8 + 8 + s per frontier
-  //           entry (offset read, entry write).
-  const double s = precision_bytes;
-  const double push = (double)h.edges_total * (4.0 + 2.0 * s) + (double)h.front_total * (16.0 + s);
-  const double per_cycle = (double)g->n * (2.0 * s + 4.0);
-  st->push_bytes = push;
-  st->bytes_moved = push + (double)h.cycles * per_cycle + (double)h.sel_total * 3.0 * s +
-                    (double)h.front_total * (24.0 + s);
+  const double s = s_bytes, N = (double)g->n, C = (double)h.cycles;
+  double move;
+  if (direction == kPull) {
+    move = C * ((double)g->Lp * (4.0 + s) + N * (8.0 + 2.0 * s));
+  } else {
+    move = (double)h.edges_total * (4.0 + 2.0 * s) + (double)h.front_total * (16.0 + s) + C * N * s;
+  }
+  const double select = C * N * (2.0 * s + 4.0) + (double)h.sel_total * 3.0 * s;
+  st->move_bytes = rt.move_launches > 0 ? move : 0.0;
+  st->bytes_moved = move + select;
+  st->seconds = rt.seconds;
+  st->move_seconds = rt.move_seconds;
+  st->move_launches = rt.move_launches;
 }
 
 di_status status_from_done(int done) {
@@ -241,19 +264,14 @@ di_status check_common(const di_graph* g, double d, double tol, const di_opts& o
     set_error("precision not supported by this entry point");
     return DI_E_INVAL;
   }
+  if (o.kernel < DI_KERNEL_AUTO || o.kernel > DI_KERNEL_PUSH) {
+    set_error("unknown kernel direction");
+    return DI_E_INVAL;
+  }
   return DI_OK;
 }
 
-struct DeviceScope {
-  int prev = -1;
-  explicit DeviceScope(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-    else prev = -1;
-  }
-  ~DeviceScope() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
+int direction_of(const di_opts& o) { return o.kernel == DI_KERNEL_PUSH ? kPush : kPull; }
 
 template <typename T>
 di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const di_opts& o,
@@ -266,24 +284,20 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   a.method = o.method;
   a.stop = o.stop;
   a.max_cycles = o.max_cycles > 0 ? o.max_cycles : 100000;
-  a.nparts = reduce_parts(g->n);
-  a.push_grid = push_grid(g->Lp);
+  a.direction = direction_of(o);
   a.stream = stream;
+  if (a.direction == kPush) DI_TRY(ensure_push_buffers(g, ws));
+  DI_TRY(ensure_events(ws, 2));
   DI_HIP(launch_reset_ctl(a));
-  DI_HIP(launch_init<T>(a, B_dev, (1.0 - d) / (double)g->n));
-  double secs = 0.0, push_secs = 0.0;
-  int push_launches = 0;
-  di_status rs = run_cycles<T>(a, (o.flags & DI_FLAG_KERNEL_TIMING) != 0, &secs, &push_secs,
-                               &push_launches);
-  if (rs != DI_OK) return rs;
+  DI_HIP(hipEventRecord(ws->events[0], stream));
+  DI_HIP(launch_start<T>(a, B_dev, (1.0 - d) / (double)g->n));
+  RunTimes rt;
+  DI_TRY(run_cycles<T>(a, (o.flags & DI_FLAG_KERNEL_TIMING) != 0, ws->events[0], &rt));
   DI_HIP(launch_h_to_x<T>(a, X_dev));
   DI_HIP(hipStreamSynchronize(stream));
   di_stats tmp;
   std::memset(&tmp, 0, sizeof(tmp));
-  fill_stats<T>(g, ws, d, (int)sizeof(T), &tmp);
-  tmp.seconds = secs;
-  tmp.push_seconds = push_secs;
-  tmp.push_launches = push_launches;
+  fill_stats(g, *ws->host_ctl, d, (int)sizeof(T), a.direction, rt, &tmp);
   if (st) *st = tmp;
   return status_from_done(ws->host_ctl->done);
 }
@@ -293,8 +307,7 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
   di_opts o;
   di_opts_default(&o);
   if (opts) o = *opts;
-  di_status cs = check_common(gc, d, tol, o);
-  if (cs != DI_OK) return cs;
+  DI_TRY(check_common(gc, d, tol, o));
   if (!X) {
     set_error("X is NULL");
     return DI_E_INVAL;
@@ -317,15 +330,13 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
   const size_t nbytes = (size_t)g->n * sizeof(double);
   const double* B_dev = B;
   if (B && B_on_host) {
-    DI_HIP(hipMemcpyAsync(ws->R64, B, nbytes, hipMemcpyHostToDevice, stream));
-    B_dev = ws->R64;
+    if (!ws->B64) DI_TRY(dmalloc((void**)&ws->B64, nbytes));
+    DI_HIP(hipMemcpyAsync(ws->B64, B, nbytes, hipMemcpyHostToDevice, stream));
+    B_dev = ws->B64;
   }
   double* X_dev = X;
   if (X_on_host) {
-    if (!ws->X64) {
-      di_status s2 = dmalloc((void**)&ws->X64, nbytes);
-      if (s2 != DI_OK) return s2;
-    }
+    if (!ws->X64) DI_TRY(dmalloc((void**)&ws->X64, nbytes));
     X_dev = ws->X64;
   }
   di_status rs = prec == kF64 ? solve_t<double>(g, B_dev, d, tol, o, X_dev, st, ws, stream)
@@ -335,6 +346,75 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
   return rs;
 }
 
+template <typename Fn>
+di_status guarded(Fn&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DI_E_NOMEM;
+  } catch (...) {
+    set_error("unexpected exception");
+    return DI_E_INVAL;
+  }
+}
+
+di_status cycles_dev(const di_graph* gc, double d, int32_t method, double* F_dev, double* H_dev,
+                     int32_t cycles, double* e_inout, void* stream_v, di_stats* stats) {
+  if (!gc || !F_dev || !H_dev || cycles < 0 || !(d > 0.0 && d < 1.0) ||
+      (method != DI_SOP && method != DI_CYC)) {
+    set_error("di_cycles_dev: invalid argument");
+    return DI_E_INVAL;
+  }
+  di_graph* g = const_cast<di_graph*>(gc);
+  DeviceScope scope(g->device);
+  di_status ast = DI_OK;
+  Workspace* ws = acquire(g, kF64, &ast);
+  if (ast != DI_OK) return ast;
+  PoolGuard guard{g, ws};
+  // run on the caller's state: the workspace with F and H swapped in
+  struct Swap {
+    Workspace* ws;
+    void* F;
+    void* H;
+    ~Swap() {
+      ws->F = F;
+      ws->H = H;
+    }
+  } swap{ws, ws->F, ws->H};
+  ws->F = F_dev;
+  ws->H = H_dev;
+  hipStream_t stream = (hipStream_t)stream_v;
+  CycleArgs a{};
+  a.g = g;
+  a.ws = ws;
+  a.d = d;
+  a.tol = -1.0;  // no stop test: exactly `cycles` cycles
+  a.method = method;
+  a.stop = DI_STOP_RESID;
+  a.max_cycles = cycles;
+  a.direction = kPull;
+  a.stream = stream;
+  DI_TRY(ensure_events(ws, 2));
+  DI_HIP(launch_reset_ctl(a));
+  if (e_inout)
+    DI_HIP(hipMemcpyAsync(&ws->ctl->e, e_inout, sizeof(double), hipMemcpyHostToDevice, stream));
+  DI_HIP(hipEventRecord(ws->events[0], stream));
+  DI_HIP(launch_start_state<double>(a));
+  RunTimes rt;
+  DI_TRY(run_cycles<double>(a, false, ws->events[0], &rt));
+  const Ctl& h = *ws->host_ctl;
+  if (h.done == 3) return status_from_done(3);
+  if (e_inout) *e_inout = h.e;
+  if (stats) {
+    di_stats tmp;
+    std::memset(&tmp, 0, sizeof(tmp));
+    fill_stats(g, h, d, 8, a.direction, rt, &tmp);
+    *stats = tmp;
+  }
+  return DI_OK;
+}
+
 }  // namespace
 }  // namespace di
 
@@ -342,87 +422,19 @@ extern "C" {
 
 di_status di_solve(const di_graph* g, const double* B, double d, double tol, const di_opts* opts,
                    double* X, di_stats* stats) {
-  try {
-    return di::solve_any(g, B, true, d, tol, opts, X, true, stats);
-  } catch (const std::bad_alloc&) {
-    di::set_error("host allocation failed");
-    return DI_E_NOMEM;
-  } catch (...) {
-    di::set_error("unexpected exception");
-    return DI_E_INVAL;
-  }
+  return di::guarded([&] { return di::solve_any(g, B, true, d, tol, opts, X, true, stats); });
 }
 
 di_status di_solve_dev(const di_graph* g, const double* B_dev, double d, double tol,
                        const di_opts* opts, double* X_dev, di_stats* stats) {
-  try {
-    return di::solve_any(g, B_dev, false, d, tol, opts, X_dev, false, stats);
-  } catch (const std::bad_alloc&) {
-    di::set_error("host allocation failed");
-    return DI_E_NOMEM;
-  } catch (...) {
-    di::set_error("unexpected exception");
-    return DI_E_INVAL;
-  }
+  return di::guarded(
+      [&] { return di::solve_any(g, B_dev, false, d, tol, opts, X_dev, false, stats); });
 }
 
-di_status di_cycles_dev(const di_graph* gc, double d, int32_t method, double* F_dev,
-                        double* H_dev, int32_t cycles, double* e_inout, void* stream_v,
-                        di_stats* stats) {
-  try {
-    if (!gc || !F_dev || !H_dev || cycles < 0 || !(d > 0.0 && d < 1.0) ||
-        (method != DI_SOP && method != DI_CYC)) {
-      di::set_error("di_cycles_dev: invalid argument");
-      return DI_E_INVAL;
-    }
-    di_graph* g = const_cast<di_graph*>(gc);
-    di::DeviceScope scope(g->device);
-    di_status ast = DI_OK;
-    di::Workspace* ws = di::acquire(g, di::kF64, &ast);
-    if (ast != DI_OK) return ast;
-    di::PoolGuard guard{g, ws};
-    // run on the caller's state: borrow the workspace with F and H swapped
-    di::Workspace view = *ws;
-    view.F = F_dev;
-    view.H = H_dev;
-    hipStream_t stream = (hipStream_t)stream_v;
-    di::CycleArgs a{};
-    a.g = g;
-    a.ws = &view;
-    a.d = d;
-    a.tol = -1.0;  // never stops early
-    a.method = method;
-    a.stop = DI_STOP_RESID;
-    a.max_cycles = cycles;
-    a.nparts = di::reduce_parts(g->n);
-    a.push_grid = di::push_grid(g->Lp);
-    a.stream = stream;
-    DI_HIP(di::launch_reset_ctl(a));
-    if (e_inout)
-      DI_HIP(hipMemcpyAsync(&ws->ctl->e, e_inout, sizeof(double), hipMemcpyHostToDevice, stream));
-    double secs = 0.0, ps = 0.0;
-    int pl = 0;
-    di_status rs = di::run_cycles<double>(a, false, &secs, &ps, &pl);
-    ws->events = view.events;  // keep events created while borrowing
-    if (rs != DI_OK) return rs;
-    const di::Ctl& h = *ws->host_ctl;
-    if (h.done == 3) return di::status_from_done(3);
-    if (e_inout) *e_inout = h.e;
-    if (stats) {
-      di_stats tmp;
-      std::memset(&tmp, 0, sizeof(tmp));
-      di::fill_stats<double>(g, ws, d, 8, &tmp);
-      tmp.seconds = secs;
-      *stats = tmp;
-    }
-    return DI_OK;
-  } catch (const std::bad_alloc&) {
-    di::set_error("host allocation failed");
-    return DI_E_NOMEM;
-  } catch (...) {
-    di::set_error("unexpected exception");
-    return DI_E_INVAL;
-  }
+di_status di_cycles_dev(const di_graph* g, double d, int32_t method, double* F_dev, double* H_dev,
+                        int32_t cycles, double* e_inout, void* stream, di_stats* stats) {
+  return di::guarded(
+      [&] { return di::cycles_dev(g, d, method, F_dev, H_dev, cycles, e_inout, stream, stats); });
 }
 
 }  // extern "C"

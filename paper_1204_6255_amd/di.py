@@ -25,7 +25,7 @@ DI_SOP, DI_CYC = 0, 1
 DI_FP64, DI_FP32_REFINE, DI_FP32 = 0, 1, 2
 DI_STOP_RESID, DI_STOP_PAPER = 0, 1
 DI_FLAG_KERNEL_TIMING = 1
-DI_BUILD_CSC = 1
+DI_KERNEL_AUTO, DI_KERNEL_PULL, DI_KERNEL_PUSH = 0, 1, 2
 
 STATUS_NAMES = {
     0: "DI_OK", 1: "DI_PENDING", -1: "DI_E_INVAL", -2: "DI_E_UNSORTED", -3: "DI_E_DUP",
@@ -41,7 +41,7 @@ class di_opts(ctypes.Structure):
         ("stop", ctypes.c_int32),
         ("max_cycles", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved0", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
         ("inner_tol", ctypes.c_double),
         ("stream", ctypes.c_void_p),
     ]
@@ -52,7 +52,7 @@ class di_stats(ctypes.Structure):
         ("cycles", ctypes.c_int32),
         ("fallback_cycles", ctypes.c_int32),
         ("refinements", ctypes.c_int32),
-        ("push_launches", ctypes.c_int32),
+        ("move_launches", ctypes.c_int32),
         ("edges_pushed", ctypes.c_int64),
         ("nb_iter", ctypes.c_double),
         ("resid_l1", ctypes.c_double),
@@ -60,9 +60,9 @@ class di_stats(ctypes.Structure):
         ("paper_err", ctypes.c_double),
         ("e", ctypes.c_double),
         ("seconds", ctypes.c_double),
-        ("push_seconds", ctypes.c_double),
+        ("move_seconds", ctypes.c_double),
         ("bytes_moved", ctypes.c_double),
-        ("push_bytes", ctypes.c_double),
+        ("move_bytes", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -211,8 +211,8 @@ def di_cycles_dev(h, d: float, method: int, F_dev, H_dev, cycles: int, e: float 
 class Graph:
     """Owning wrapper of a di_graph handle."""
 
-    def __init__(self, n: int, src, dst, csc: bool = False):
-        status, h = di_graph_create(n, src, dst, DI_BUILD_CSC if csc else 0)
+    def __init__(self, n: int, src, dst):
+        status, h = di_graph_create(n, src, dst)
         _check(status)
         self.handle = h
         self.n, self.L, self.n_dangling, self.n_loops = di_graph_info(h)

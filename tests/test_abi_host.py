@@ -56,6 +56,11 @@ def test_graph_create_rejects_bad_link_lists(n, src, dst, expect):
     assert di.di_last_error()
 
 
+def test_graph_create_rejects_flags():
+    st, h = di.di_graph_create(3, np.array([0], np.int32), np.array([1], np.int32), flags=4)
+    assert st == di.DI_E_INVAL
+
+
 def test_graph_create_null_arrays():
     h = ctypes.c_void_p()
     assert di.lib().di_graph_create(4, 2, None, None, 0, ctypes.byref(h)) == di.DI_E_INVAL

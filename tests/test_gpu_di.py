@@ -133,8 +133,12 @@ def test_cycles_match_oracle_sync_schedule(torch_cuda, case):
 
 # ------------------------------------------------------------- full solves
 
+KERNELS = [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("seed", range(6))
-def test_small_random_graphs_vs_dense(torch_cuda, seed):
+def test_small_random_graphs_vs_dense(torch_cuda, seed, kernel):
     from tests.test_oracle_pins import _random_graph
     rng = np.random.default_rng(500 + seed)
     n = int(rng.integers(2, 51))
@@ -144,45 +148,50 @@ def test_small_random_graphs_vs_dense(torch_cuda, seed):
     B = rng.random(n)
     X_ref, _ = dense_solve(n, src, dst, D, B)
     g = di.Graph(n, src, dst)
-    X, st, _ = gpu_solve(torch_cuda, g, B, tol=1e-13)
+    X, st, _ = gpu_solve(torch_cuda, g, B, tol=1e-13, kernel=kernel)
     assert np.abs(X - X_ref).sum() <= 1e-13 / (1 - D) + 1e-13 * X_ref.sum()
     assert st.resid_l1 <= 1e-13
 
 
-def test_closed_forms(torch_cuda):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_closed_forms(torch_cuda, kernel):
+    import functools
     torch = torch_cuda
+    gpu_solve_k = functools.partial(gpu_solve, kernel=kernel)
     # directed cycle: X = 1/N
     n = 1000
     src = np.arange(n, dtype=np.int32)
     dst = ((np.arange(n) + 1) % n).astype(np.int32)
     order = np.lexsort((dst, src))
-    X, _, _ = gpu_solve(torch, di.Graph(n, src[order], dst[order]), None, tol=1e-14)
+    X, _, _ = gpu_solve_k(torch, di.Graph(n, src[order], dst[order]), None, tol=1e-14)
     assert np.allclose(X, 1.0 / n, rtol=0, atol=1e-15)
     # complete digraph with self-loops: X = 1/N (transit formula)
     n = 40
     src, dst = np.divmod(np.arange(n * n), n)
-    X, _, _ = gpu_solve(torch, di.Graph(n, src.astype(np.int32), dst.astype(np.int32)), None, tol=1e-15)
+    X, _, _ = gpu_solve_k(torch, di.Graph(n, src.astype(np.int32), dst.astype(np.int32)), None, tol=1e-15)
     assert np.allclose(X, 1.0 / n, rtol=0, atol=1e-15)
     # chain 0 -> 1: the tie case of the selection rule
-    X, st, _ = gpu_solve(torch, di.Graph(2, np.array([0], np.int32), np.array([1], np.int32)), None, tol=1e-16)
+    X, st, _ = gpu_solve_k(torch, di.Graph(2, np.array([0], np.int32), np.array([1], np.int32)), None, tol=1e-16)
     assert np.allclose(X, [(1 - D) / 2, (1 - D) * (1 + D) / 2], rtol=0, atol=1e-16)
     assert st.fallback_cycles == 0
     # lone self-loop plus an isolated node
-    X, _, _ = gpu_solve(torch, di.Graph(2, np.array([0], np.int32), np.array([0], np.int32)),
+    X, _, _ = gpu_solve_k(torch, di.Graph(2, np.array([0], np.int32), np.array([0], np.int32)),
                         np.array([0.2, 0.3]), tol=1e-16)
     assert abs(X[0] - 0.2 / (1 - D)) < 1e-15 and X[1] == 0.3
     # no links at all: X = B after one cycle
     B = np.linspace(0.1, 1.0, 5)
-    X, st, _ = gpu_solve(torch, di.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32)), B, tol=1e-16)
+    X, st, _ = gpu_solve_k(torch, di.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32)), B, tol=1e-16)
     assert np.array_equal(X, B) and st.cycles == 1 and st.edges_pushed == 0
     # single node, no links
-    X, _, _ = gpu_solve(torch, di.Graph(1, np.zeros(0, np.int32), np.zeros(0, np.int32)), None)
+    X, _, _ = gpu_solve_k(torch, di.Graph(1, np.zeros(0, np.int32), np.zeros(0, np.int32)), None)
     assert X[0] == 1 - D
 
 
-def test_star_spans_many_push_tiles(torch_cuda):
-    """One node with 30000 out-links (about 30 push tiles) and a hub with
-    30000 in-links (all atomics on one address)."""
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_star_spans_many_push_tiles(torch_cuda, kernel):
+    """One node with 30000 out-links (a frontier entry far longer than a push
+    block) and a hub with 30000 in-links (split into 15 pull segments; on
+    the push side, all atomics on one address)."""
     n = 30001
     src = np.concatenate([np.zeros(n - 1, np.int64), np.arange(1, n)]).astype(np.int32)
     dst = np.concatenate([np.arange(1, n), np.zeros(n - 1, np.int64)]).astype(np.int32)
@@ -191,17 +200,18 @@ def test_star_spans_many_push_tiles(torch_cuda):
     rng = np.random.default_rng(1)
     B = rng.random(n) / n
     og, X_ref = oracle_ref(n, src, dst, B)
-    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), B)
+    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), B, kernel=kernel)
     assert np.abs(X - X_ref).sum() <= 1e-9
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("alpha", [graphgen.ALPHA_L_MATCHED, graphgen.ALPHA_LITERAL])
-def test_parity_10k_pagerank(torch_cuda, alpha):
+def test_parity_10k_pagerank(torch_cuda, alpha, kernel):
     n = 10000
     src, dst = web(n, alpha=alpha)
     B = graphgen.uniform_rhs(n, D)
     og, X_ref = oracle_ref(n, src, dst, B)
-    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), None)
+    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), None, kernel=kernel)
     assert np.abs(X - X_ref).sum() <= 1e-9
     # sum |F| is the residual of H: recompute it from X with the oracle
     _, r_true = oracle.residual(og, B, D, X)
@@ -228,17 +238,24 @@ def test_parity_1m_bench_configuration(torch_cuda):
     X9, st9, _ = gpu_solve(torch_cuda, g, None, tol=1e-9)
     assert st9.resid_l1 <= 1e-9
     assert np.abs(X9 - X_ref).sum() <= st9.err_bound + 1e-12
-    # repeated runs differ only by the order of atomic additions
+    # the pull direction is bit-reproducible
     X2, _, _ = gpu_solve(torch_cuda, g, None)
-    assert np.abs(X2 - X).sum() <= 1e-12
+    assert np.array_equal(X2, X)
+    # the push direction differs only by the order of atomic additions
+    Xp, stp, _ = gpu_solve(torch_cuda, g, None, kernel=di.DI_KERNEL_PUSH)
+    assert np.abs(Xp - X_ref).sum() <= 1e-9
+    assert np.abs(Xp - X).sum() <= 1e-12
+    assert stp.cycles == st.cycles
 
 
-def test_fp32_fluid(torch_cuda):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fp32_fluid(torch_cuda, kernel):
     n = 10000
     src, dst = web(n)
     B = graphgen.uniform_rhs(n, D)
     og, X_ref = oracle_ref(n, src, dst, B)
-    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), None, tol=1e-7, precision=di.DI_FP32)
+    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), None, tol=1e-7, precision=di.DI_FP32,
+                         kernel=kernel)
     assert np.abs(X - X_ref).sum() <= 2e-6 * X_ref.sum()
 
 
