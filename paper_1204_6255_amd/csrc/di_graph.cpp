@@ -49,9 +49,8 @@ void free_workspace(Workspace* ws);
 namespace {
 
 void free_graph_device(di_graph* g) {
-  void* ptrs[] = {g->row_ptr, g->col,   g->info,   g->csc_ptr,   g->csc_idx,
-                  g->it_r0,   g->it_r1, g->it_l0,  g->it_l1,     g->it_seg,
-                  g->heavy_row, g->heavy_seg, g->hb_h0, g->hb_h1};
+  void* ptrs[] = {g->row_ptr, g->col,    g->info,   g->csc_ptr,  g->csc_idx, g->it_r0,
+                  g->it_r1,   g->it_l0,  g->it_l1,  g->it_seg,   g->heavy_row, g->heavy_seg};
   for (void* p : ptrs) (void)hipFree(p);
   g->row_ptr = nullptr;
   g->col = nullptr;
@@ -62,7 +61,6 @@ void free_graph_device(di_graph* g) {
   g->it_seg = nullptr;
   g->heavy_row = nullptr;
   g->heavy_seg = nullptr;
-  g->hb_h0 = g->hb_h1 = nullptr;
 }
 
 template <typename V>
@@ -152,18 +150,30 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
 
     // host build: out-link lists without self-loops, per-node words, CSC
     std::vector<int64_t> row_ptr((size_t)n + 1, 0);
-    std::vector<uint32_t> info((size_t)n, 0);
+    std::vector<int64_t> outc((size_t)n, 0);
+    std::vector<uint8_t> loopf((size_t)n, 0);
     int64_t n_loops = 0;
     for (int64_t e = 0; e < m; ++e) {
       const int32_t a = src[e];
-      info[a] += 1;
+      outc[a] += 1;
       if (a == dst[e]) {
-        info[a] |= di::kLoopBit;
+        loopf[a] = 1;
         ++n_loops;
       } else {
         row_ptr[a + 1] += 1;
       }
     }
+    std::vector<uint32_t> info((size_t)n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      if (outc[i] > (int64_t)di::kOutMask) {
+        di::set_error("di_graph_create: node " + std::to_string(i) +
+                      " has 2^30 or more out-links (not supported)");
+        return DI_E_INVAL;
+      }
+      info[i] = (uint32_t)outc[i] | (loopf[i] ? di::kLoopBit : 0u);
+    }
+    std::vector<int64_t>().swap(outc);
+    std::vector<uint8_t>().swap(loopf);
     int64_t n_dangling = 0, max_out = 0;
     for (int64_t i = 0; i < n; ++i) {
       row_ptr[i + 1] += row_ptr[i];
@@ -230,6 +240,7 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
           flush(j);
           hrow.push_back((int32_t)j);
           hseg.push_back(nseg);
+          info[j] |= di::kHeavyBit;
           for (int64_t lo = cptr[j]; lo < cptr[j + 1]; lo += di::kPullChunk) {
             r0v.push_back(j);
             r1v.push_back(j + 1);
@@ -247,21 +258,10 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       }
       flush(n);
       hseg.push_back(nseg);
-      // group heavy rows into finalize batches of at most kFinalSegBatch
-      // segments (a row with more segments is a batch of its own)
-      std::vector<int64_t> hb0, hb1;
-      for (int64_t h = 0; h < (int64_t)hrow.size();) {
-        int64_t e = h + 1;
-        if (hseg[h + 1] - hseg[h] <= di::kFinalSegBatch)
-          while (e < (int64_t)hrow.size() && hseg[e + 1] - hseg[h] <= di::kFinalSegBatch) ++e;
-        hb0.push_back(h);
-        hb1.push_back(e);
-        h = e;
-      }
-      g->n_hbatch = (int64_t)hb0.size();
       g->n_items = (int64_t)r0v.size();
       g->n_heavy = (int64_t)hrow.size();
       g->n_segs = nseg;
+      g->heavy_atomic = g->n_heavy > di::kHeavyLds;
       st = upload(&g->csc_ptr, cptr);
       if (st == DI_OK) st = upload(&g->csc_idx, cidx);
       if (st == DI_OK) st = upload(&g->it_r0, r0v);
@@ -271,8 +271,10 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       if (st == DI_OK) st = upload(&g->it_seg, segv);
       if (st == DI_OK) st = upload(&g->heavy_row, hrow);
       if (st == DI_OK) st = upload(&g->heavy_seg, hseg);
-      if (st == DI_OK) st = upload(&g->hb_h0, hb0);
-      if (st == DI_OK) st = upload(&g->hb_h1, hb1);
+      // the node words carry the heavy flags
+      if (st == DI_OK)
+        DI_HIP(hipMemcpy(g->info, info.data(), info.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+
     }
     if (st != DI_OK) {
       free_graph_device(g);

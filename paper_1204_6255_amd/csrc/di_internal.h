@@ -14,27 +14,41 @@
 namespace di {
 
 // ---- launch geometry ------------------------------------------------------
-constexpr int kSelectBlock = 256;     // threads per select block
-constexpr int kSelectPerThread = 2;   // nodes per select thread (block-strided)
-constexpr int kSelectNodes = kSelectBlock * kSelectPerThread;
+// select tiles: pull direction 1024 threads x 4 nodes (a grid of at most
+// kSelectGridPull blocks loops over tiles); push direction 256 x 2 (one tile
+// per block; the push block of the same index moves its frontier)
+constexpr int kSelectBlockPull = 1024;
+constexpr int kSelectPerThreadPull = 4;
+constexpr int kSelectTilePull = kSelectBlockPull * kSelectPerThreadPull;
+constexpr int kSelectGridPull = 256;
+constexpr int kSelectBlockPush = 256;
+constexpr int kSelectPerThreadPush = 2;
+constexpr int kSelectTilePush = kSelectBlockPush * kSelectPerThreadPush;
 constexpr int kPullBlock = 256;       // threads per pull block
 constexpr int kPullChunk = 2048;      // in-links per pull work item (LDS staged)
 constexpr int kPullMaxRows = 2048;    // rows per pull work item
 constexpr int kPullLongRow = 32;      // rows with more in-links: summed by a wave
 constexpr int kPullMaxGrid = 2048;    // pull blocks (grid-stride over items)
+constexpr int kXcds = 8;              // XCDs; workgroups are dealt round-robin
 constexpr int kPushBlock = 256;       // threads per push block
 constexpr int kReduceBlock = 256;     // threads per reduction block
-constexpr int kReduceGrid = 1024;     // reduction blocks (push direction)
-constexpr int kFinalBlock = 1024;     // threads of the single finalize block
-constexpr int kFinalSegBatch = 4096;  // heavy-row segment sums staged per pass
+constexpr int kReduceGrid = 256;      // reduction blocks (push direction)
 
-// Per-node word: out-degree (self-loop included) in bits 0..30, self-loop
-// flag in bit 31.
+// Per-node word: out-degree (self-loop included) in bits 0..29, heavy-row
+// flag (more than kPullChunk in-links) in bit 30, self-loop flag in bit 31.
 constexpr uint32_t kLoopBit = 0x80000000u;
-constexpr uint32_t kOutMask = 0x7fffffffu;
+constexpr uint32_t kHeavyBit = 0x40000000u;
+constexpr uint32_t kOutMask = 0x3fffffffu;
+// Heavy rows completed deterministically by the select kernel (their values
+// are kept in its LDS); graphs with more heavy rows add the segment sums of
+// every heavy row to F with atomics instead.
+constexpr int kHeavyLds = 4096;
 
-// Device control block of one solve. During the cycles only the
-// single-block finalize kernel writes it; the other kernels read it.
+// Control block: two copies. The select kernel of cycle c reads copy c & 1
+// (the state after cycle c - 1) and its block 0 writes copy (c + 1) & 1; the
+// pull (or push) of cycle c reads copy (c + 1) & 1.
+
+// Device control block of one solve.
 struct Ctl {
   double r;          // sum |F| after the last cycle: r of the next selection
   double psum;       // sum F after the last cycle
@@ -52,10 +66,21 @@ struct Ctl {
   unsigned long long sel_total;    // diffused nodes
 };
 
-// Per select block: what its nodes did in the cycle.
+// Per select tile: what its nodes did in the cycle.
 struct SelStat {
   unsigned long long ops;  // link operations
   double e;                // fluid absorbed by dangling nodes
+  unsigned int sel;        // diffused nodes
+  unsigned int nfront;     // diffused nodes with links to push
+};
+
+// Per pull / reduce / start block: its rows' sums, and the select
+// statistics of the select blocks it folded in.
+struct Part {
+  double pabs;             // sum |F| over the block's rows
+  double psum;             // sum F over the block's rows
+  double e;                // absorbed fluid
+  unsigned long long ops;  // link operations
   unsigned int sel;        // diffused nodes
   unsigned int nfront;     // diffused nodes with links to push
 };
@@ -67,16 +92,16 @@ struct Workspace {
   int prec = kF64;
   void* F = nullptr;            // fluid, n values of the fluid type
   void* H = nullptr;            // history, n values
-  void* sent = nullptr;         // pull: amount each node sends per link
+  void* sent = nullptr;         // pull: amount each diffused node sends per link
+  unsigned long long* front_bits = nullptr;  // pull: bit i set = node i sends
   int64_t* fr_lstart = nullptr; // push: per-block frontier, local link offset
   int64_t* fr_base = nullptr;   // push: CSR offset of the entry's links
   void* fr_s = nullptr;         // push: amount sent along each link
-  SelStat* blk_stat = nullptr;  // per select block
-  double* blk_pabs = nullptr;   // per pull/reduce block: sum |F|
-  double* blk_psum = nullptr;   // per pull/reduce block: sum F
-  double* seg_val = nullptr;    // pull: partial sums of split in-link lists
-  Ctl* ctl = nullptr;
-  Ctl* host_ctl = nullptr;      // pinned copy for the stop check
+  SelStat* tile_stat = nullptr; // per select tile
+  Part* blk_part = nullptr;     // per pull/reduce/start block
+  double* seg_val = nullptr;    // pull: sums of the heavy-row segments
+  Ctl* ctl = nullptr;           // two copies (see Ctl)
+  Ctl* host_ctl = nullptr;      // pinned copy of both, for the stop check
   double* X64 = nullptr;        // host entry points: device copy of X
   double* B64 = nullptr;        // host entry points: device copy of B
   std::vector<hipEvent_t> events;
@@ -101,24 +126,21 @@ struct di_graph {
   int64_t* csc_ptr = nullptr;  // n + 1
   int32_t* csc_idx = nullptr;  // Lp
   // pull work items: light items cover rows [r0, r1) and their in-links
-  // [l0, l1); a segment item (seg >= 0) covers links [l0, l1) of one heavy
-  // row and writes seg_val[seg]
+  // [l0, l1); a segment item (seg >= 0) covers links [l0, l1) of the heavy
+  // row r0 and writes its sum to seg_val[seg] (or adds it to F[r0]
+  // atomically when heavy_atomic)
   int64_t n_items = 0;
   int64_t* it_r0 = nullptr;
   int64_t* it_r1 = nullptr;
   int64_t* it_l0 = nullptr;
   int64_t* it_l1 = nullptr;
   int32_t* it_seg = nullptr;
-  // heavy rows (more than kPullChunk in-links): row id and segment range
+  // heavy rows (more than kPullChunk in-links)
   int64_t n_heavy = 0;
   int64_t n_segs = 0;
-  int32_t* heavy_row = nullptr;   // n_heavy
-  int64_t* heavy_seg = nullptr;   // n_heavy + 1
-  // batches of heavy rows for the finalize kernel: rows [hb_h0, hb_h1) with
-  // at most kFinalSegBatch segments, or a single row with more
-  int64_t n_hbatch = 0;
-  int64_t* hb_h0 = nullptr;
-  int64_t* hb_h1 = nullptr;
+  bool heavy_atomic = false;      // n_heavy > kHeavyLds
+  int32_t* heavy_row = nullptr;   // n_heavy, ascending
+  int64_t* heavy_seg = nullptr;   // n_heavy + 1: segment range of each
   std::mutex mu;
   std::vector<di::Workspace*> pool;
 };
@@ -163,22 +185,27 @@ struct CycleArgs {
   hipStream_t stream;
 };
 
-int select_grid(int64_t n);
+int select_tiles(int64_t n, int direction);
+int select_grid(int64_t n, int direction);
 int pull_grid(const di_graph* g);
 int reduce_grid(int64_t n);
+int part_count(const CycleArgs& a);
 
 hipError_t launch_reset_ctl(const CycleArgs& a);
-// F = B (or the uniform value), H = 0, per-block sum |F| / sum F partials,
-// then the finalize kernel's stop test before the first cycle.
+// F = B (or the uniform value), H = 0, and the per-block records of sum |F|
+// and sum F that the first selection reads.
 template <typename T>
 hipError_t launch_start(const CycleArgs& a, const double* B, double b_uniform);
-// As launch_start for a state (F, H) already in the workspace buffers.
+// The same records for a state (F, H) already in the workspace buffers.
 template <typename T>
 hipError_t launch_start_state(const CycleArgs& a);
-// One cycle: select (+claim), pull or push (+reduce), finalize. With
-// non-null events, the pull (or push) launch is bracketed by them.
+// The selection of cycle c (its stop test first; first != 0 for c = 0).
 template <typename T>
-hipError_t launch_cycle(const CycleArgs& a, hipEvent_t ev_before_main, hipEvent_t ev_after_main);
+hipError_t launch_select(const CycleArgs& a, int cycle, int first);
+// The move of cycle c: pull, or push + reduction. With non-null events the
+// pull (or push) launch is bracketed by them.
+template <typename T>
+hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_h_to_x(const CycleArgs& a, double* X);
 

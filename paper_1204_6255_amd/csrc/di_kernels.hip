@@ -7,19 +7,25 @@
 // arrives during the cycle waits for the next one, so the selected set and
 // the moved amounts depend only on the state at the start of the cycle.
 //
-// The move has two implementations with identical results:
-//   pull  each node sums sent[i] over its in-links (CSC without self-loops),
-//         staged through LDS in work items of at most kPullChunk links;
-//         in-link lists longer than that are split into segments whose sums
-//         the finalize kernel adds. No atomics; the result is deterministic.
-//   push  each selected node's out-links (CSR) receive transit*d/out_i by
-//         device-scope float atomics; a select block's frontier is pushed
-//         by the push block of the same index, link-balanced through LDS.
-// A single-block finalize kernel then sums the per-block partials in a fixed
-// order into r (the residual |B + P.H - H|_1 = sum |F|), accumulates the
-// statistics and runs the stop test. Only it writes the control block while
-// cycles run; every kernel returns at once after the stop, so the host may
-// queue cycles ahead of the test.
+// A cycle is two launches:
+//   select  every block first sums the per-block records left by the
+//           previous move (sum |F|, sum F, and the statistics of the
+//           previous selection) in one fixed order, plus |F| of the heavy
+//           rows, so all blocks hold the same r bit for bit; thread 0 of
+//           each block takes the same stop decision and block 0 writes the
+//           next copy of the control block. Then the block selects and
+//           claims the nodes of its tiles.
+//   move    pull (default): each node sums sent[i] over its in-links (CSC
+//           without self-loops) whose sender bit is set in the frontier
+//           bitmap, staged through LDS in work items of at most kPullChunk
+//           links; each block writes one record (sums over its rows and the
+//           folded tile statistics). A row with more in-links is split into
+//           segments whose sums are added to F[row] with a few FP64 atomics.
+//           push: each selected node's out-links (CSR) receive
+//           transit*d/out_i by device-scope float atomics (one push block
+//           per select tile), then a reduction writes the records.
+// Kernels return at once after the stop, so the host may queue cycles ahead
+// of the stop test.
 
 #include "di_internal.h"
 
@@ -56,232 +62,440 @@ __device__ V block_sum(V v, V* lds) {
   return total;
 }
 
-__global__ void k_reset_ctl(Ctl* ctl) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->r = 0.0;
-    ctl->psum = 0.0;
-    ctl->e = 0.0;
-    ctl->final_r = 0.0;
-    ctl->paper_err = 0.0;
-    ctl->r_first = 0.0;
-    ctl->r_last = 0.0;
-    ctl->cycles = 0;
-    ctl->fallback = 0;
-    ctl->done = 0;
-    ctl->cyc_mode = 0;
-    ctl->edges_total = 0;
-    ctl->front_total = 0;
-    ctl->sel_total = 0;
+__device__ inline void part_add(Part& a, const Part& b) {
+  a.pabs += b.pabs;
+  a.psum += b.psum;
+  a.e += b.e;
+  a.ops += b.ops;
+  a.sel += b.sel;
+  a.nfront += b.nfront;
+}
+
+// Block sum of a Part (fixed order); valid in thread 0. lds: blockDim.x/64.
+__device__ Part block_sum_part(Part v, Part* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v.pabs = wave_sum(v.pabs);
+  v.psum = wave_sum(v.psum);
+  v.e = wave_sum(v.e);
+  v.ops = wave_sum(v.ops);
+  v.sel = wave_sum(v.sel);
+  v.nfront = wave_sum(v.nfront);
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  Part t{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  if (threadIdx.x == 0)
+    for (int w = 0; w < nw; ++w) part_add(t, lds[w]);
+  __syncthreads();
+  return t;
+}
+
+// Adds the tile statistics of tiles [b*k, (b+1)*k) to v, where
+// k = ceil(ntiles / gridDim.x): every tile is folded by exactly one block.
+__device__ inline void fold_tile_stats(const SelStat* __restrict__ tile_stat, int64_t ntiles,
+                                       Part& v) {
+  const int64_t k = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int64_t q0 = (int64_t)blockIdx.x * k;
+  for (int64_t t = threadIdx.x; t < k; t += blockDim.x) {
+    const int64_t q = q0 + t;
+    if (q < ntiles) {
+      const SelStat st = tile_stat[q];
+      v.e += st.e;
+      v.ops += st.ops;
+      v.sel += st.sel;
+      v.nfront += st.nfront;
+    }
   }
 }
 
-// F = B, H = 0, and per-block partial sums of |F| and F over all nodes.
+__global__ void k_reset_ctl(Ctl* ctl) {
+  if (blockIdx.x == 0 && threadIdx.x < 2) {
+    Ctl c;
+    c.r = 0.0;
+    c.psum = 0.0;
+    c.e = 0.0;
+    c.final_r = 0.0;
+    c.paper_err = 0.0;
+    c.r_first = 0.0;
+    c.r_last = 0.0;
+    c.cycles = 0;
+    c.fallback = 0;
+    c.done = 0;
+    c.cyc_mode = 0;
+    c.edges_total = 0;
+    c.front_total = 0;
+    c.sel_total = 0;
+    ctl[threadIdx.x] = c;
+  }
+}
+
+// F = B, H = 0, and per-block sums of |F| and F over all nodes.
 template <typename T>
 __global__ __launch_bounds__(kReduceBlock) void k_start(T* __restrict__ F, T* __restrict__ H,
                                                         const double* __restrict__ B,
                                                         double b_uniform, int64_t n,
-                                                        double* __restrict__ blk_pabs,
-                                                        double* __restrict__ blk_psum) {
-  __shared__ double lds[kReduceBlock / 64];
-  double pa = 0.0, ps = 0.0;
+                                                        Part* __restrict__ blk_part) {
+  __shared__ Part lds[kReduceBlock / 64];
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const T f = B ? (T)B[i] : (T)b_uniform;
     F[i] = f;
     H[i] = (T)0;
-    pa += fabs(to_d(f));
-    ps += to_d(f);
+    v.pabs += fabs(to_d(f));
+    v.psum += to_d(f);
   }
-  pa = block_sum(pa, lds);
-  ps = block_sum(ps, lds);
-  if (threadIdx.x == 0) {
-    blk_pabs[blockIdx.x] = pa;
-    blk_psum[blockIdx.x] = ps;
-  }
+  v = block_sum_part(v, lds);
+  if (threadIdx.x == 0) blk_part[blockIdx.x] = v;
 }
 
-// Per-block partial sums of |F| and F (push direction, after the push).
+// Sums of |F| and F per block over all nodes: the start of a caller-held
+// state (ctl == nullptr), or the push direction after its push (folding the
+// tile statistics).
 template <typename T>
 __global__ __launch_bounds__(kReduceBlock) void k_reduce(const T* __restrict__ F, int64_t n,
-                                                         double* __restrict__ blk_pabs,
-                                                         double* __restrict__ blk_psum,
+                                                         const SelStat* __restrict__ tile_stat,
+                                                         int64_t ntiles,
+                                                         Part* __restrict__ blk_part,
                                                          const Ctl* __restrict__ ctl) {
-  __shared__ double lds[kReduceBlock / 64];
-  if (ctl->done) return;
-  double pa = 0.0, ps = 0.0;
+  __shared__ Part lds[kReduceBlock / 64];
+  if (ctl && ctl->done) return;
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  if (ctl) fold_tile_stats(tile_stat, ntiles, v);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double f = to_d(F[i]);
-    pa += fabs(f);
-    ps += f;
+    v.pabs += fabs(f);
+    v.psum += f;
   }
-  pa = block_sum(pa, lds);
-  ps = block_sum(ps, lds);
-  if (threadIdx.x == 0) {
-    blk_pabs[blockIdx.x] = pa;
-    blk_psum[blockIdx.x] = ps;
-  }
+  v = block_sum_part(v, lds);
+  if (threadIdx.x == 0) blk_part[blockIdx.x] = v;
 }
 
-// Selection and claim. Thread t of block b owns the nodes
-// b*kSelectNodes + t + m*kSelectBlock, m < kSelectPerThread (coalesced).
-// PULL: writes sent[i] (0 for nodes not diffused) for every node.
-// PUSH: writes the block's frontier (nodes with links to push) at
-//       [b*kSelectNodes, ...) with block-local link offsets that grow with
-//       the entry index.
-template <typename T, bool PULL>
-__global__ __launch_bounds__(kSelectBlock) void k_select(
+// The stop test and the next control-block copy, from the sums of the
+// records (v) and the current copy (c). first: no cycle has run yet.
+__device__ inline Ctl next_ctl(Ctl c, const Part& v, int first, double d, double tol, int method,
+                               int stop, int max_cycles) {
+  if (c.done) return c;
+  if (!first) {
+    const double r_used = c.r;
+    c.cycles += 1;
+    if (c.cycles == 1) c.r_first = r_used;
+    c.r_last = r_used;
+    c.edges_total += v.ops;
+    c.front_total += v.nfront;
+    c.sel_total += v.sel;
+    c.e += v.e;
+    // a DI-SOP cycle that diffused nothing (possible only through rounding
+    // at a tie) is followed by one DI-CYC cycle
+    const bool empty = v.sel == 0 && v.pabs > 0.0;
+    c.cyc_mode = (method == DI_CYC || empty) ? 1 : 0;
+    if (method != DI_CYC && empty) c.fallback += 1;
+  } else {
+    c.cyc_mode = method == DI_CYC ? 1 : 0;
+  }
+  const double r = v.pabs;
+  c.r = r;
+  c.psum = v.psum;
+  if (!isfinite(r)) {
+    c.final_r = r;
+    c.done = 3;
+    return c;
+  }
+  bool stop_now;
+  if (stop == DI_STOP_RESID) {
+    stop_now = r <= tol;
+  } else {
+    stop_now = false;
+    if (!first) {
+      c.paper_err = v.psum / (1.0 - d - d * c.e);
+      stop_now = c.paper_err <= tol;
+    }
+  }
+  if (stop_now) {
+    c.final_r = r;
+    c.done = 1;
+  } else if (c.cycles >= max_cycles) {
+    c.final_r = r;
+    c.done = 2;
+  }
+  return c;
+}
+
+// Selection and claim. Tile t covers nodes [t*TILE, (t+1)*TILE); thread j of
+// the block owns nodes t*TILE + j + m*BLOCK, m < M (coalesced; a wave's 64
+// lanes hold 64 consecutive nodes). Blocks loop over tiles.
+// PULL: writes sent[i] for the diffused nodes with links, and the frontier
+//       bitmap word of each wave (bit set = the node sends this cycle).
+// PUSH: writes the tile's frontier (nodes with links to push) at
+//       [t*TILE, ...) with tile-local link offsets growing with the entry.
+template <typename T, bool PULL, int BLOCK, int M>
+__global__ __launch_bounds__(BLOCK) void k_select(
     T* __restrict__ F, T* __restrict__ H, const uint32_t* __restrict__ info,
-    const int64_t* __restrict__ row_ptr, int64_t n, int64_t L, double d,
-    T* __restrict__ sent, int64_t* __restrict__ fr_lstart, int64_t* __restrict__ fr_base,
-    T* __restrict__ fr_s, SelStat* __restrict__ blk_stat, const Ctl* __restrict__ ctl) {
-  constexpr int M = kSelectPerThread;
-  constexpr int NW = kSelectBlock / 64;
+    const int64_t* __restrict__ row_ptr, int64_t n, int64_t L, T* __restrict__ sent,
+    unsigned long long* __restrict__ front_bits, int64_t* __restrict__ fr_lstart,
+    int64_t* __restrict__ fr_base, T* __restrict__ fr_s, SelStat* __restrict__ tile_stat,
+    const Part* __restrict__ blk_part, int nparts, const int32_t* __restrict__ heavy_row,
+    const int64_t* __restrict__ heavy_seg, const double* __restrict__ seg_val, int64_t n_heavy,
+    int heavy_atomic, Ctl* __restrict__ ctl, int parity, int first, double d, double tol,
+    int method, int stop, int max_cycles) {
+  constexpr int TILE = BLOCK * M;
+  constexpr int NW = BLOCK / 64;
+  // heavy rows completed here (not first, not heavy_atomic): row and value
+  __shared__ int32_t s_hrow[PULL ? kHeavyLds : 1];
+  __shared__ double s_hval[PULL ? kHeavyLds : 1];
+  __shared__ Part s_part[NW];
   __shared__ unsigned long long s_ops[NW];
   __shared__ double s_e[NW];
   __shared__ unsigned int s_sel[NW], s_front[NW];
-  if (ctl->done) return;
-  const double r = ctl->r;
-  const bool cyc = ctl->cyc_mode != 0;
-  const double rl = r / (double)L;
+  __shared__ double s_r;
+  __shared__ int s_done, s_was_done, s_cyc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ntiles = (n + TILE - 1) / TILE;
 
-  const int64_t base = (int64_t)blockIdx.x * kSelectNodes + threadIdx.x;
+  // first round of loads: the first tile's nodes, the records, the heavy
+  // rows and the control block are independent of one another
+  int64_t tile = blockIdx.x;
   double f[M];
   uint32_t w[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
-    const int64_t i = base + (int64_t)m * kSelectBlock;
-    f[m] = i < n ? to_d(F[i]) : 0.0;
-    w[m] = i < n ? info[i] : 0u;
+    const int64_t i = tile * TILE + tid + (int64_t)m * BLOCK;
+    f[m] = (tile < ntiles && i < n) ? to_d(F[i]) : 0.0;
+    w[m] = (tile < ntiles && i < n) ? info[i] : 0u;
   }
-  int npush[M];
-  double snd[M];
-  unsigned int my_sel = 0, my_front = 0;
-  unsigned long long my_ops = 0;
-  double my_e = 0.0;
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    npush[m] = 0;
-    snd[m] = 0.0;
-    const int64_t i = base + (int64_t)m * kSelectBlock;
-    if (i < n) {
-      const int out = (int)(w[m] & kOutMask);
-      const bool loop = (w[m] & kLoopBit) != 0;
-      const double a = fabs(f[m]);
-      const double thr = (cyc || out == 0) ? 0.0 : rl * (double)out;
-      if (a > 0.0 && a >= thr) {
-        const double t = loop ? f[m] * (double)out / ((double)out - d) : f[m];
-        H[i] = (T)(to_d(H[i]) + t);
-        F[i] = (T)0;
-        ++my_sel;
-        if (out == 0) {
-          my_e += t;
-        } else {
-          const int np = out - (loop ? 1 : 0);
-          if (np > 0) {
-            npush[m] = np;
-            snd[m] = t * d / (double)out;
-            my_ops += (unsigned long long)np;
-            ++my_front;
-          }
-        }
-      }
-      if (PULL) sent[i] = (T)snd[m];
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  for (int p = tid; p < nparts; p += BLOCK) part_add(v, blk_part[p]);
+  // After a pull the records leave out the heavy rows (the start records
+  // cover every row): add their values, completing them with their segment
+  // sums in a fixed order unless the pull added those atomically.
+  const bool heavy_here = PULL && !first && !heavy_atomic;
+  for (int64_t h = first ? n_heavy : tid; h < n_heavy; h += BLOCK) {
+    const int32_t row = heavy_row[h];
+    double fh = to_d(F[row]);
+    if (heavy_here) {
+      double acc = 0.0;
+      for (int64_t q = heavy_seg[h]; q < heavy_seg[h + 1]; ++q) acc += seg_val[q];
+      fh = to_d((T)(fh + acc));
+      s_hrow[h] = row;
+      s_hval[h] = fh;
     }
+    v.pabs += fabs(fh);
+    v.psum += fh;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (!PULL) {
-    // block-local exclusive scan of (entries, links) over (thread, m) order
-    unsigned int cnt_incl = my_front;
-    unsigned long long lnk_incl = my_ops;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const unsigned int u = __shfl_up(cnt_incl, off, 64);
-      const unsigned long long v = __shfl_up(lnk_incl, off, 64);
-      if (lane >= off) {
-        cnt_incl += u;
-        lnk_incl += v;
-      }
-    }
-    if (lane == 63) {
-      s_front[wave] = cnt_incl;
-      s_ops[wave] = lnk_incl;
-    }
-    __syncthreads();
-    unsigned int cnt_before = 0;
-    unsigned long long lnk_before = 0;
-    for (int q = 0; q < wave; ++q) {
-      cnt_before += s_front[q];
-      lnk_before += s_ops[q];
-    }
-    __syncthreads();
-    unsigned int k = cnt_before + cnt_incl - my_front;
-    unsigned long long lo = lnk_before + lnk_incl - my_ops;
-    const int64_t fbase = (int64_t)blockIdx.x * kSelectNodes;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      if (npush[m] > 0) {
-        fr_lstart[fbase + k] = (int64_t)lo;
-        fr_base[fbase + k] = row_ptr[base + (int64_t)m * kSelectBlock];
-        fr_s[fbase + k] = (T)snd[m];
-        ++k;
-        lo += (unsigned long long)npush[m];
-      }
-    }
-  }
-  // one fused block reduction of the four statistics
-  my_sel = wave_sum(my_sel);
-  my_front = wave_sum(my_front);
-  my_ops = wave_sum(my_ops);
-  my_e = wave_sum(my_e);
-  if (lane == 0) {
-    s_sel[wave] = my_sel;
-    s_front[wave] = my_front;
-    s_ops[wave] = my_ops;
-    s_e[wave] = my_e;
+  v = block_sum_part(v, s_part);
+  if (tid == 0) {
+    const Ctl c0 = ctl[parity];
+    const Ctl c = next_ctl(c0, v, first, d, tol, method, stop, max_cycles);
+    if (blockIdx.x == 0) ctl[parity ^ 1] = c;
+    s_done = c.done;
+    s_was_done = c0.done;
+    s_cyc = c.cyc_mode;
+    s_r = c.r;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    SelStat st;
-    st.sel = 0;
-    st.nfront = 0;
-    st.ops = 0;
-    st.e = 0.0;
-    for (int q = 0; q < NW; ++q) {
-      st.sel += s_sel[q];
-      st.nfront += s_front[q];
-      st.ops += s_ops[q];
-      st.e += s_e[q];
+  if (s_done) {
+    // stopping now: the completed heavy rows still go to F (by the block
+    // that owns their tile)
+    if (heavy_here && !s_was_done)
+      for (int64_t h = tid; h < n_heavy; h += BLOCK) {
+        const int32_t row = s_hrow[h];
+        if ((row / TILE) % gridDim.x == blockIdx.x) F[row] = (T)s_hval[h];
+      }
+    return;
+  }
+  const bool cyc = s_cyc != 0;
+  const double rl = s_r / (double)L;
+
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int64_t base = tile * TILE + tid;
+    if (tile != (int64_t)blockIdx.x) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int64_t i = base + (int64_t)m * BLOCK;
+        f[m] = i < n ? to_d(F[i]) : 0.0;
+        w[m] = i < n ? info[i] : 0u;
+      }
     }
-    blk_stat[blockIdx.x] = st;
+    int npush[M];
+    double snd[M];
+    unsigned int my_sel = 0, my_front = 0;
+    unsigned long long my_ops = 0;
+    double my_e = 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      npush[m] = 0;
+      snd[m] = 0.0;
+      const int64_t i = base + (int64_t)m * BLOCK;
+      if (i < n) {
+        const int out = (int)(w[m] & kOutMask);
+        const bool loop = (w[m] & kLoopBit) != 0;
+        const bool heavy = heavy_here && (w[m] & kHeavyBit) != 0;
+        if (heavy) {  // the completed value, found by binary search in LDS
+          int lo = 0, hi = (int)n_heavy - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_hrow[mid] < i) lo = mid + 1;
+            else hi = mid;
+          }
+          f[m] = s_hval[lo];
+        }
+        const double a = fabs(f[m]);
+        const double thr = (cyc || out == 0) ? 0.0 : rl * (double)out;
+        if (a > 0.0 && a >= thr) {
+          const double t = loop ? f[m] * (double)out / ((double)out - d) : f[m];
+          H[i] = (T)(to_d(H[i]) + t);
+          F[i] = (T)0;
+          ++my_sel;
+          if (out == 0) {
+            my_e += t;
+          } else {
+            const int np = out - (loop ? 1 : 0);
+            if (np > 0) {
+              npush[m] = np;
+              snd[m] = t * d / (double)out;
+              my_ops += (unsigned long long)np;
+              ++my_front;
+            }
+          }
+        } else if (heavy) {
+          F[i] = (T)f[m];  // the completed value stays
+        }
+        if (PULL && npush[m] > 0) sent[i] = (T)snd[m];
+      }
+    }
+    if (PULL) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const unsigned long long word = __ballot(npush[m] > 0);
+        const int64_t first_node = base - lane + (int64_t)m * BLOCK;  // multiple of 64
+        if (lane == 0 && first_node < n) front_bits[first_node >> 6] = word;
+      }
+    } else {
+      // tile-local exclusive scan of (entries, links) over (thread, m) order
+      unsigned int cnt_incl = my_front;
+      unsigned long long lnk_incl = my_ops;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const unsigned int u = __shfl_up(cnt_incl, off, 64);
+        const unsigned long long x = __shfl_up(lnk_incl, off, 64);
+        if (lane >= off) {
+          cnt_incl += u;
+          lnk_incl += x;
+        }
+      }
+      if (lane == 63) {
+        s_front[wave] = cnt_incl;
+        s_ops[wave] = lnk_incl;
+      }
+      __syncthreads();
+      unsigned int cnt_before = 0;
+      unsigned long long lnk_before = 0;
+      for (int q = 0; q < wave; ++q) {
+        cnt_before += s_front[q];
+        lnk_before += s_ops[q];
+      }
+      __syncthreads();
+      unsigned int k = cnt_before + cnt_incl - my_front;
+      unsigned long long lo = lnk_before + lnk_incl - my_ops;
+      const int64_t fbase = tile * TILE;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if (npush[m] > 0) {
+          fr_lstart[fbase + k] = (int64_t)lo;
+          fr_base[fbase + k] = row_ptr[base + (int64_t)m * BLOCK];
+          fr_s[fbase + k] = (T)snd[m];
+          ++k;
+          lo += (unsigned long long)npush[m];
+        }
+      }
+    }
+    // the tile's statistics: one fused block reduction
+    my_sel = wave_sum(my_sel);
+    my_front = wave_sum(my_front);
+    my_ops = wave_sum(my_ops);
+    my_e = wave_sum(my_e);
+    if (lane == 0) {
+      s_sel[wave] = my_sel;
+      s_front[wave] = my_front;
+      s_ops[wave] = my_ops;
+      s_e[wave] = my_e;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      SelStat st;
+      st.sel = 0;
+      st.nfront = 0;
+      st.ops = 0;
+      st.e = 0.0;
+      for (int q = 0; q < NW; ++q) {
+        st.sel += s_sel[q];
+        st.nfront += s_front[q];
+        st.ops += s_ops[q];
+        st.e += s_e[q];
+      }
+      tile_stat[tile] = st;
+    }
+    __syncthreads();
   }
 }
 
-// Pull: F_j += sum of sent[i] over the in-links i -> j (i != j). Work items
-// are prepared with the graph: light items (rows [r0, r1), at most
-// kPullChunk links) and segments of heavy rows. Each thread stages its
-// kPullChunk / kPullBlock links with all index loads, then all gathers, in
-// flight together. Per-block partial sums of |F| and F cover the light
-// rows; heavy rows are finished by k_finalize.
+// Pull: F_j += sum of sent[i] over the in-links i -> j (i != j) whose sender
+// bit is set. Work items are prepared with the graph: light items (rows
+// [r0, r1), at most kPullChunk links) and segments of heavy rows. Each
+// thread stages its kPullChunk / kPullBlock links with all index loads,
+// then all bitmap loads, then the gathers of the set bits, in flight
+// together. Every block writes one Part record: the sums over its light
+// rows and the folded tile statistics.
 template <typename T>
 __global__ __launch_bounds__(kPullBlock) void k_pull(
-    T* __restrict__ F, const T* __restrict__ sent, const int64_t* __restrict__ csc_ptr,
+    T* __restrict__ F, const T* __restrict__ sent,
+    const unsigned long long* __restrict__ front_bits, const int64_t* __restrict__ csc_ptr,
     const int32_t* __restrict__ csc_idx, const int64_t* __restrict__ it_r0,
     const int64_t* __restrict__ it_r1, const int64_t* __restrict__ it_l0,
     const int64_t* __restrict__ it_l1, const int32_t* __restrict__ it_seg, int64_t n_items,
-    double* __restrict__ seg_val, double* __restrict__ blk_pabs, double* __restrict__ blk_psum,
-    const Ctl* __restrict__ ctl) {
+    double* __restrict__ seg_val, int heavy_atomic, const SelStat* __restrict__ tile_stat,
+    int64_t ntiles, Part* __restrict__ blk_part, const Ctl* __restrict__ ctl) {
   constexpr int U = kPullChunk / kPullBlock;
   __shared__ double s_val[kPullChunk];
   __shared__ double s_red[kPullBlock / 64];
-  if (ctl->done) return;
+  __shared__ Part s_part[kPullBlock / 64];
   const int tid = threadIdx.x;
-  double pa = 0.0, ps = 0.0;
-  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const int64_t l0 = it_l0[it], l1 = it_l1[it];
-    const int seg = it_seg[it];
+  // XCD-aware order: workgroups are dealt round-robin to the XCDs, so when
+  // the grid is a multiple of kXcds, XCD x works through the x-th contiguous
+  // eighth of the items and its L2 sees one range of rows and senders
+  int64_t it_begin = blockIdx.x, it_end = n_items, it_step = gridDim.x;
+  if (gridDim.x % kXcds == 0) {
+    const int64_t x = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+    const int64_t lo = n_items * x / kXcds, hi = n_items * (x + 1) / kXcds;
+    it_begin = lo + blockIdx.x / kXcds;
+    it_end = hi;
+    it_step = per;
+  }
+  // the first item's descriptor, read with the control block
+  int64_t nl0 = 0, nl1 = 0, nr0 = 0, nr1 = 0;
+  int nseg = -1;
+  if (it_begin < it_end) {
+    nl0 = it_l0[it_begin];
+    nl1 = it_l1[it_begin];
+    nr0 = it_r0[it_begin];
+    nr1 = it_r1[it_begin];
+    nseg = it_seg[it_begin];
+  }
+  Part acc_part{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  fold_tile_stats(tile_stat, ntiles, acc_part);
+  if (ctl->done) return;
+  for (int64_t it = it_begin; it < it_end; it += it_step) {
+    const int64_t l0 = nl0, l1 = nl1, r0 = nr0, r1 = nr1;
+    const int seg = nseg;
+    const int64_t nx = it + it_step;
+    if (nx < it_end) {  // prefetch the next descriptor
+      nl0 = it_l0[nx];
+      nl1 = it_l1[nx];
+      nr0 = it_r0[nx];
+      nr1 = it_r1[nx];
+      nseg = it_seg[nx];
+    }
     const int nl = (int)(l1 - l0);
-    const int64_t r0 = it_r0[it], r1 = it_r1[it];
     // the thread's first row, fetched while the links are in flight
     const int64_t row0 = r0 + tid;
     double f0 = 0.0;
@@ -297,18 +511,27 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
       const int p = tid + u * kPullBlock;
       idx[u] = p < nl ? csc_idx[l0 + p] : 0;
     }
-    double v[U];
+    unsigned long long word[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = tid + u * kPullBlock;
-      v[u] = p < nl ? to_d(sent[idx[u]]) : 0.0;
+      word[u] = p < nl ? front_bits[idx[u] >> 6] : 0ull;
     }
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = (word[u] >> (idx[u] & 63)) & 1ull ? to_d(sent[idx[u]]) : 0.0;
     if (seg >= 0) {
+      // a segment of a heavy row: its sum is completed by the next
+      // selection (or, with too many heavy rows, added to F[r0] atomically)
       double acc = 0.0;
 #pragma unroll
       for (int u = 0; u < U; ++u) acc += v[u];
       acc = block_sum(acc, s_red);
-      if (tid == 0) seg_val[seg] = acc;
+      if (tid == 0) {
+        if (!heavy_atomic) seg_val[seg] = acc;
+        else if (acc != 0.0) atomic_add(&F[r0], (T)acc);
+      }
       continue;
     }
 #pragma unroll
@@ -353,21 +576,17 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
           F[row] = nv;
           f = to_d(nv);
         }
-        pa += fabs(f);
-        ps += f;
+        acc_part.pabs += fabs(f);
+        acc_part.psum += f;
       }
     }
     __syncthreads();
   }
-  pa = block_sum(pa, s_red);
-  ps = block_sum(ps, s_red);
-  if (tid == 0) {
-    blk_pabs[blockIdx.x] = pa;
-    blk_psum[blockIdx.x] = ps;
-  }
+  acc_part = block_sum_part(acc_part, s_part);
+  if (tid == 0) blk_part[blockIdx.x] = acc_part;
 }
 
-// Push: block b moves the frontier of select block b. Entries are staged in
+// Push: block b moves the frontier of select tile b. Entries are staged in
 // LDS; each lane finds the entry of its link by binary search on the local
 // link offsets and adds the entry's amount to F[col] atomically.
 template <typename T>
@@ -376,16 +595,16 @@ __global__ __launch_bounds__(kPushBlock) void k_push(T* __restrict__ F,
                                                      const int64_t* __restrict__ fr_lstart,
                                                      const int64_t* __restrict__ fr_base,
                                                      const T* __restrict__ fr_s,
-                                                     const SelStat* __restrict__ blk_stat,
+                                                     const SelStat* __restrict__ tile_stat,
                                                      const Ctl* __restrict__ ctl) {
-  __shared__ int64_t s_start[kSelectNodes];
-  __shared__ int64_t s_base[kSelectNodes];
-  __shared__ T s_val[kSelectNodes];
+  __shared__ int64_t s_start[kSelectTilePush];
+  __shared__ int64_t s_base[kSelectTilePush];
+  __shared__ T s_val[kSelectTilePush];
   if (ctl->done) return;
-  const int nf = (int)blk_stat[blockIdx.x].nfront;
+  const int nf = (int)tile_stat[blockIdx.x].nfront;
   if (nf == 0) return;
-  const int64_t E = (int64_t)blk_stat[blockIdx.x].ops;
-  const int64_t fbase = (int64_t)blockIdx.x * kSelectNodes;
+  const int64_t E = (int64_t)tile_stat[blockIdx.x].ops;
+  const int64_t fbase = (int64_t)blockIdx.x * kSelectTilePush;
   for (int q = threadIdx.x; q < nf; q += blockDim.x) {
     s_start[q] = fr_lstart[fbase + q];
     s_base[q] = fr_base[fbase + q] - fr_lstart[fbase + q];
@@ -405,132 +624,6 @@ __global__ __launch_bounds__(kPushBlock) void k_push(T* __restrict__ F,
   }
 }
 
-// Single block: finishes heavy rows (pull), sums every partial in a fixed
-// order into r = sum |F| and sum F, accumulates the cycle's statistics and
-// runs the stop test. start != 0: the test before the first cycle (no
-// selection happened; the partials come from k_start / k_reduce).
-template <typename T>
-__global__ __launch_bounds__(kFinalBlock) void k_finalize(
-    T* __restrict__ F, const int32_t* __restrict__ heavy_row, const int64_t* __restrict__ heavy_seg,
-    const int64_t* __restrict__ hb_h0, const int64_t* __restrict__ hb_h1, int64_t n_hbatch,
-    const double* __restrict__ seg_val, const double* __restrict__ blk_pabs,
-    const double* __restrict__ blk_psum, int nparts, const SelStat* __restrict__ blk_stat,
-    int nsel, int start, double d, double tol, int method, int stop, int max_cycles,
-    Ctl* __restrict__ ctl) {
-  __shared__ double s_seg[kFinalSegBatch];
-  __shared__ double s_red[kFinalBlock / 64];
-  __shared__ unsigned long long s_red64[kFinalBlock / 64];
-  if (ctl->done) return;
-  const int tid = threadIdx.x;
-  double pa = 0.0, ps = 0.0;
-  if (!start) {
-    for (int64_t b = 0; b < n_hbatch; ++b) {
-      const int64_t h0 = hb_h0[b], h1 = hb_h1[b];
-      const int64_t s0 = heavy_seg[h0], s1 = heavy_seg[h1];
-      const int64_t ns = s1 - s0;
-      if (ns > kFinalSegBatch) {
-        // one row with many segments: a block-wide sum
-        double acc = 0.0;
-        for (int64_t s = s0 + tid; s < s1; s += blockDim.x) acc += seg_val[s];
-        acc = block_sum(acc, s_red);
-        if (tid == 0) {
-          const int32_t row = heavy_row[h0];
-          double f = to_d(F[row]);
-          if (acc != 0.0) {
-            const T nv = (T)(f + acc);
-            F[row] = nv;
-            f = to_d(nv);
-          }
-          pa += fabs(f);
-          ps += f;
-        }
-        continue;
-      }
-      for (int64_t q = tid; q < ns; q += blockDim.x) s_seg[q] = seg_val[s0 + q];
-      __syncthreads();
-      for (int64_t h = h0 + tid; h < h1; h += blockDim.x) {
-        const int32_t row = heavy_row[h];
-        double acc = 0.0;
-        for (int64_t s = heavy_seg[h]; s < heavy_seg[h + 1]; ++s) acc += s_seg[s - s0];
-        double f = to_d(F[row]);
-        if (acc != 0.0) {
-          const T nv = (T)(f + acc);
-          F[row] = nv;
-          f = to_d(nv);
-        }
-        pa += fabs(f);
-        ps += f;
-      }
-      __syncthreads();
-    }
-  }
-  for (int p = tid; p < nparts; p += blockDim.x) {
-    pa += blk_pabs[p];
-    ps += blk_psum[p];
-  }
-  double e_c = 0.0;
-  unsigned long long sel = 0, front = 0, ops = 0;
-  if (!start) {
-    for (int b = tid; b < nsel; b += blockDim.x) {
-      const SelStat st = blk_stat[b];
-      sel += st.sel;
-      front += st.nfront;
-      ops += st.ops;
-      e_c += st.e;
-    }
-  }
-  const double r = block_sum(pa, s_red);
-  const double psum = block_sum(ps, s_red);
-  e_c = block_sum(e_c, s_red);
-  sel = block_sum(sel, s_red64);
-  front = block_sum(front, s_red64);
-  ops = block_sum(ops, s_red64);
-  if (tid != 0) return;
-  Ctl c = *ctl;
-  if (!start) {
-    const double r_used = c.r;
-    c.cycles += 1;
-    if (c.cycles == 1) c.r_first = r_used;
-    c.r_last = r_used;
-    c.edges_total += ops;
-    c.front_total += front;
-    c.sel_total += sel;
-    c.e += e_c;
-    // a DI-SOP cycle that diffused nothing (possible only through rounding
-    // at a tie) is followed by one DI-CYC cycle
-    const bool empty = sel == 0 && r > 0.0;
-    c.cyc_mode = (method == DI_CYC || empty) ? 1 : 0;
-    if (method != DI_CYC && empty) c.fallback += 1;
-  } else {
-    c.cyc_mode = method == DI_CYC ? 1 : 0;
-  }
-  c.r = r;
-  c.psum = psum;
-  if (!isfinite(r)) {
-    c.final_r = r;
-    c.done = 3;
-  } else {
-    bool stop_now;
-    if (stop == DI_STOP_RESID) {
-      stop_now = r <= tol;
-    } else {
-      stop_now = false;
-      if (!start) {
-        c.paper_err = psum / (1.0 - d - d * c.e);
-        stop_now = c.paper_err <= tol;
-      }
-    }
-    if (stop_now) {
-      c.final_r = r;
-      c.done = 1;
-    } else if (c.cycles >= max_cycles) {
-      c.final_r = r;
-      c.done = 2;
-    }
-  }
-  *ctl = c;
-}
-
 template <typename T>
 __global__ void k_h_to_x(const T* __restrict__ H, double* __restrict__ X, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -538,33 +631,39 @@ __global__ void k_h_to_x(const T* __restrict__ H, double* __restrict__ X, int64_
     X[i] = to_d(H[i]);
 }
 
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 inline unsigned int grid_for(int64_t n, int block, int64_t cap) {
-  int64_t g = (n + block - 1) / block;
+  int64_t g = ceil_div(n, block);
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return (unsigned int)g;
 }
 
-template <typename T>
-hipError_t launch_finalize(const CycleArgs& a, int nparts, int start) {
-  const di_graph* g = a.g;
-  Workspace* ws = a.ws;
-  const bool pull = a.direction == kPull;
-  hipLaunchKernelGGL(k_finalize<T>, dim3(1), dim3(kFinalBlock), 0, a.stream, (T*)ws->F,
-                     g->heavy_row, g->heavy_seg, g->hb_h0, g->hb_h1,
-                     pull ? g->n_hbatch : (int64_t)0, ws->seg_val, ws->blk_pabs, ws->blk_psum,
-                     nparts, ws->blk_stat, (int)grid_for(g->n, kSelectNodes, 0x7fffffff), start,
-                     a.d, a.tol, a.method, a.stop, a.max_cycles, ws->ctl);
-  return hipGetLastError();
-}
-
 }  // namespace
 
-int select_grid(int64_t n) { return (int)grid_for(n, kSelectNodes, 0x7fffffff); }
+int select_tiles(int64_t n, int direction) {
+  const int64_t tile = direction == kPull ? kSelectTilePull : kSelectTilePush;
+  const int64_t t = ceil_div(n, tile);
+  return (int)(t < 1 ? 1 : t);
+}
 
-int pull_grid(const di_graph* g) { return (int)grid_for(g->n_items, 1, kPullMaxGrid); }
+int select_grid(int64_t n, int direction) {
+  const int t = select_tiles(n, direction);
+  return direction == kPull ? (t < kSelectGridPull ? t : kSelectGridPull) : t;
+}
+
+int pull_grid(const di_graph* g) {
+  int grid = (int)grid_for(g->n_items, 1, kPullMaxGrid);
+  if (grid >= 8 * kXcds) grid -= grid % kXcds;  // XCD-aware order (k_pull)
+  return grid;
+}
 
 int reduce_grid(int64_t n) { return (int)grid_for(n, kReduceBlock, kReduceGrid); }
+
+int part_count(const CycleArgs& a) {
+  return a.direction == kPull ? pull_grid(a.g) : reduce_grid(a.g->n);
+}
 
 hipError_t launch_reset_ctl(const CycleArgs& a) {
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, a.stream, a.ws->ctl);
@@ -573,59 +672,73 @@ hipError_t launch_reset_ctl(const CycleArgs& a) {
 
 template <typename T>
 hipError_t launch_start(const CycleArgs& a, const double* B, double b_uniform) {
-  const int grid = reduce_grid(a.g->n);
-  hipLaunchKernelGGL(k_start<T>, dim3(grid), dim3(kReduceBlock), 0, a.stream, (T*)a.ws->F,
-                     (T*)a.ws->H, B, b_uniform, a.g->n, a.ws->blk_pabs, a.ws->blk_psum);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  return launch_finalize<T>(a, grid, 1);
+  hipLaunchKernelGGL(k_start<T>, dim3(part_count(a)), dim3(kReduceBlock), 0, a.stream,
+                     (T*)a.ws->F, (T*)a.ws->H, B, b_uniform, a.g->n, a.ws->blk_part);
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_start_state(const CycleArgs& a) {
-  const int grid = reduce_grid(a.g->n);
-  hipLaunchKernelGGL(k_reduce<T>, dim3(grid), dim3(kReduceBlock), 0, a.stream, (const T*)a.ws->F,
-                     a.g->n, a.ws->blk_pabs, a.ws->blk_psum, a.ws->ctl);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  return launch_finalize<T>(a, grid, 1);
+  hipLaunchKernelGGL(k_reduce<T>, dim3(part_count(a)), dim3(kReduceBlock), 0, a.stream,
+                     (const T*)a.ws->F, a.g->n, (const SelStat*)a.ws->tile_stat, (int64_t)0,
+                     a.ws->blk_part, (const Ctl*)nullptr);
+  return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cycle(const CycleArgs& a, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
   const di_graph* g = a.g;
   Workspace* ws = a.ws;
-  const int sgrid = select_grid(g->n);
-  hipError_t err;
+  const int grid = select_grid(g->n, a.direction);
+  const int parity = cycle & 1;
+  const int nparts = part_count(a);
   if (a.direction == kPull) {
-    hipLaunchKernelGGL((k_select<T, true>), dim3(sgrid), dim3(kSelectBlock), 0, a.stream,
-                       (T*)ws->F, (T*)ws->H, g->info, g->row_ptr, g->n, g->L, a.d, (T*)ws->sent,
-                       (int64_t*)nullptr, (int64_t*)nullptr, (T*)nullptr, ws->blk_stat, ws->ctl);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    if (ev0 && (err = hipEventRecord(ev0, a.stream)) != hipSuccess) return err;
-    const int pgrid = pull_grid(g);
-    hipLaunchKernelGGL(k_pull<T>, dim3(pgrid), dim3(kPullBlock), 0, a.stream, (T*)ws->F,
-                       (const T*)ws->sent, g->csc_ptr, g->csc_idx, g->it_r0, g->it_r1, g->it_l0,
-                       g->it_l1, g->it_seg, g->n_items, ws->seg_val, ws->blk_pabs, ws->blk_psum,
-                       ws->ctl);
+    hipLaunchKernelGGL((k_select<T, true, kSelectBlockPull, kSelectPerThreadPull>), dim3(grid),
+                       dim3(kSelectBlockPull), 0, a.stream, (T*)ws->F, (T*)ws->H, g->info,
+                       g->row_ptr, g->n, g->L, (T*)ws->sent, ws->front_bits, (int64_t*)nullptr,
+                       (int64_t*)nullptr, (T*)nullptr, ws->tile_stat, (const Part*)ws->blk_part,
+                       nparts, g->heavy_row, g->heavy_seg, (const double*)ws->seg_val,
+                       g->n_heavy, (int)g->heavy_atomic, ws->ctl, parity, first, a.d, a.tol,
+                       a.method, a.stop, a.max_cycles);
+  } else {
+    hipLaunchKernelGGL((k_select<T, false, kSelectBlockPush, kSelectPerThreadPush>), dim3(grid),
+                       dim3(kSelectBlockPush), 0, a.stream, (T*)ws->F, (T*)ws->H, g->info,
+                       g->row_ptr, g->n, g->L, (T*)nullptr, (unsigned long long*)nullptr,
+                       ws->fr_lstart, ws->fr_base, (T*)ws->fr_s, ws->tile_stat,
+                       (const Part*)ws->blk_part, nparts, (const int32_t*)nullptr,
+                       (const int64_t*)nullptr, (const double*)nullptr, (int64_t)0, 0, ws->ctl,
+                       parity, first, a.d, a.tol, a.method, a.stop, a.max_cycles);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1) {
+  const di_graph* g = a.g;
+  Workspace* ws = a.ws;
+  const Ctl* ctl = ws->ctl + ((cycle + 1) & 1);
+  const int64_t ntiles = select_tiles(g->n, a.direction);
+  hipError_t err;
+  if (ev0 && (err = hipEventRecord(ev0, a.stream)) != hipSuccess) return err;
+  if (a.direction == kPull) {
+    hipLaunchKernelGGL(k_pull<T>, dim3(pull_grid(g)), dim3(kPullBlock), 0, a.stream, (T*)ws->F,
+                       (const T*)ws->sent, ws->front_bits, g->csc_ptr, g->csc_idx, g->it_r0,
+                       g->it_r1, g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->seg_val,
+                       (int)g->heavy_atomic, (const SelStat*)ws->tile_stat, ntiles, ws->blk_part,
+                       ctl);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (ev1 && (err = hipEventRecord(ev1, a.stream)) != hipSuccess) return err;
-    return launch_finalize<T>(a, pgrid, 0);
+    return hipSuccess;
   }
-  hipLaunchKernelGGL((k_select<T, false>), dim3(sgrid), dim3(kSelectBlock), 0, a.stream,
-                     (T*)ws->F, (T*)ws->H, g->info, g->row_ptr, g->n, g->L, a.d, (T*)nullptr,
-                     ws->fr_lstart, ws->fr_base, (T*)ws->fr_s, ws->blk_stat, ws->ctl);
-  if ((err = hipGetLastError()) != hipSuccess) return err;
-  if (ev0 && (err = hipEventRecord(ev0, a.stream)) != hipSuccess) return err;
-  hipLaunchKernelGGL(k_push<T>, dim3(sgrid), dim3(kPushBlock), 0, a.stream, (T*)ws->F, g->col,
-                     ws->fr_lstart, ws->fr_base, (const T*)ws->fr_s, ws->blk_stat, ws->ctl);
+  hipLaunchKernelGGL(k_push<T>, dim3(ntiles), dim3(kPushBlock), 0, a.stream, (T*)ws->F, g->col,
+                     ws->fr_lstart, ws->fr_base, (const T*)ws->fr_s,
+                     (const SelStat*)ws->tile_stat, ctl);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   if (ev1 && (err = hipEventRecord(ev1, a.stream)) != hipSuccess) return err;
-  const int rgrid = reduce_grid(g->n);
-  hipLaunchKernelGGL(k_reduce<T>, dim3(rgrid), dim3(kReduceBlock), 0, a.stream, (const T*)ws->F,
-                     g->n, ws->blk_pabs, ws->blk_psum, ws->ctl);
-  if ((err = hipGetLastError()) != hipSuccess) return err;
-  return launch_finalize<T>(a, rgrid, 0);
+  hipLaunchKernelGGL(k_reduce<T>, dim3(reduce_grid(g->n)), dim3(kReduceBlock), 0, a.stream,
+                     (const T*)ws->F, g->n, (const SelStat*)ws->tile_stat, ntiles, ws->blk_part,
+                     ctl);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -639,8 +752,10 @@ template hipError_t launch_start<double>(const CycleArgs&, const double*, double
 template hipError_t launch_start<float>(const CycleArgs&, const double*, double);
 template hipError_t launch_start_state<double>(const CycleArgs&);
 template hipError_t launch_start_state<float>(const CycleArgs&);
-template hipError_t launch_cycle<double>(const CycleArgs&, hipEvent_t, hipEvent_t);
-template hipError_t launch_cycle<float>(const CycleArgs&, hipEvent_t, hipEvent_t);
+template hipError_t launch_select<double>(const CycleArgs&, int, int);
+template hipError_t launch_select<float>(const CycleArgs&, int, int);
+template hipError_t launch_move<double>(const CycleArgs&, int, hipEvent_t, hipEvent_t);
+template hipError_t launch_move<float>(const CycleArgs&, int, hipEvent_t, hipEvent_t);
 template hipError_t launch_h_to_x<double>(const CycleArgs&, double*);
 template hipError_t launch_h_to_x<float>(const CycleArgs&, double*);
 

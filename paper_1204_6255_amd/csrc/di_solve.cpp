@@ -18,9 +18,9 @@ namespace di {
 
 void free_workspace(Workspace* ws) {
   if (!ws) return;
-  void* ptrs[] = {ws->F,        ws->H,        ws->sent,    ws->fr_lstart, ws->fr_base,
-                  ws->fr_s,     ws->blk_stat, ws->blk_pabs, ws->blk_psum, ws->seg_val,
-                  ws->ctl,      ws->X64,      ws->B64};
+  void* ptrs[] = {ws->F,         ws->H,         ws->sent,     ws->front_bits,
+                  ws->fr_lstart, ws->fr_base,   ws->fr_s,     ws->tile_stat,
+                  ws->blk_part,  ws->seg_val,   ws->ctl,      ws->X64,      ws->B64};
   for (void* p : ptrs) (void)hipFree(p);
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   for (hipEvent_t e : ws->events) (void)hipEventDestroy(e);
@@ -46,20 +46,21 @@ di_status alloc_workspace(const di_graph* g, int prec, Workspace** out) {
   ws->prec = prec;
   const size_t n = (size_t)g->n;
   const size_t s = prec == kF64 ? sizeof(double) : sizeof(float);
-  const size_t nsel = (size_t)select_grid(g->n);
+  const size_t ntiles =
+      (size_t)std::max(select_tiles(g->n, kPull), select_tiles(g->n, kPush));
   const size_t nparts = (size_t)std::max(kPullMaxGrid, kReduceGrid);
   di_status st = DI_OK;
   if (st == DI_OK) st = dmalloc(&ws->F, n * s);
   if (st == DI_OK) st = dmalloc(&ws->H, n * s);
   if (st == DI_OK) st = dmalloc(&ws->sent, n * s);
-  if (st == DI_OK) st = dmalloc((void**)&ws->blk_stat, nsel * sizeof(SelStat));
-  if (st == DI_OK) st = dmalloc((void**)&ws->blk_pabs, nparts * sizeof(double));
-  if (st == DI_OK) st = dmalloc((void**)&ws->blk_psum, nparts * sizeof(double));
+  if (st == DI_OK) st = dmalloc((void**)&ws->front_bits, ((n + 63) / 64) * sizeof(unsigned long long));
+  if (st == DI_OK) st = dmalloc((void**)&ws->tile_stat, ntiles * sizeof(SelStat));
+  if (st == DI_OK) st = dmalloc((void**)&ws->blk_part, nparts * sizeof(Part));
   if (st == DI_OK)
     st = dmalloc((void**)&ws->seg_val, (size_t)std::max<int64_t>(g->n_segs, 1) * sizeof(double));
-  if (st == DI_OK) st = dmalloc((void**)&ws->ctl, sizeof(Ctl));
+  if (st == DI_OK) st = dmalloc((void**)&ws->ctl, 2 * sizeof(Ctl));
   if (st == DI_OK) {
-    hipError_t err = hipHostMalloc((void**)&ws->host_ctl, sizeof(Ctl), hipHostMallocDefault);
+    hipError_t err = hipHostMalloc((void**)&ws->host_ctl, 2 * sizeof(Ctl), hipHostMallocDefault);
     if (err != hipSuccess) {
       ws->host_ctl = nullptr;
       set_error(std::string("hipHostMalloc: ") + hipGetErrorString(err));
@@ -77,7 +78,7 @@ di_status alloc_workspace(const di_graph* g, int prec, Workspace** out) {
 // Push buffers are allocated on first use (pull solves never need them).
 di_status ensure_push_buffers(const di_graph* g, Workspace* ws) {
   if (ws->fr_lstart) return DI_OK;
-  const size_t slots = (size_t)select_grid(g->n) * kSelectNodes;
+  const size_t slots = (size_t)select_tiles(g->n, kPush) * kSelectTilePush;
   const size_t s = ws->prec == kF64 ? sizeof(double) : sizeof(float);
   DI_TRY(dmalloc((void**)&ws->fr_base, slots * sizeof(int64_t)));
   DI_TRY(dmalloc(&ws->fr_s, slots * s));
@@ -139,54 +140,59 @@ struct RunTimes {
   double seconds = 0.0;       // first queued kernel to the end of the last
   double move_seconds = 0.0;  // summed pull/push kernel time (timing flag)
   int move_launches = 0;
+  Ctl state{};                // the final control block
 };
 
-// Queues cycles until the device reports a stop; the final control block
-// is left in ws->host_ctl. ev_begin was recorded before the start kernels.
+// Queues cycles until the device reports a stop: the selection of cycle 0,
+// then (move c, selection c + 1) pairs in chunks. The newest control copy
+// after selection c is copy (c + 1) & 1; it is left in rt->state.
+// ev_begin was recorded before the start kernels.
 template <typename T>
 di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTimes* rt) {
   Workspace* ws = a.ws;
   DI_TRY(ensure_events(ws, 2));
   hipEvent_t ev_end = ws->events[1];
-  int launched = 0;
+  int last_sel = 0;
+  DI_HIP(launch_select<T>(a, 0, 1));
   int chunk = 8;
-  // the start kernels already ran the stop test before the first cycle
-  DI_HIP(hipEventRecord(ev_end, a.stream));
-  DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, a.stream));
-  DI_HIP(hipStreamSynchronize(a.stream));
-  while (!ws->host_ctl->done) {
-    const int todo = std::max(1, std::min(chunk, a.max_cycles - launched));
-    if (timing) DI_TRY(ensure_events(ws, 2 + 2 * (size_t)(launched + todo)));
-    for (int q = 0; q < todo; ++q) {
-      hipEvent_t e0 = timing ? ws->events[2 + 2 * (size_t)launched] : nullptr;
-      hipEvent_t e1 = timing ? ws->events[3 + 2 * (size_t)launched] : nullptr;
-      DI_HIP(launch_cycle<T>(a, e0, e1));
-      ++launched;
-    }
+  for (;;) {
     DI_HIP(hipEventRecord(ev_end, a.stream));
-    DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, a.stream));
+    DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost, a.stream));
     DI_HIP(hipStreamSynchronize(a.stream));
-    const Ctl& h = *ws->host_ctl;
+    const Ctl& h = ws->host_ctl[(last_sel + 1) & 1];
     if (h.done) break;
-    if (launched >= a.max_cycles) {
+    if (last_sel >= a.max_cycles) {
       set_error("internal: the device did not stop after max_cycles");
       return DI_E_DEVICE;
     }
-    // cycles still needed, from the contraction of r per cycle so far
-    int next = 16;
-    if (a.stop == DI_STOP_RESID && h.cycles >= 1 && h.r_first > 0.0 && h.r > 0.0 &&
-        h.r < h.r_first && a.tol > 0.0) {
-      const double rate = std::log(h.r / h.r_first) / (double)h.cycles;
-      const double need = std::log(a.tol / h.r) / rate;
-      if (std::isfinite(need)) next = (int)std::ceil(need) + 1;
+    if (last_sel > 0) {
+      // cycles still needed, from the contraction of r per cycle so far
+      int next = 16;
+      if (a.stop == DI_STOP_RESID && h.cycles >= 1 && h.r_first > 0.0 && h.r > 0.0 &&
+          h.r < h.r_first && a.tol > 0.0) {
+        const double rate = std::log(h.r / h.r_first) / (double)h.cycles;
+        const double need = std::log(a.tol / h.r) / rate;
+        if (std::isfinite(need)) next = (int)std::ceil(need) + 1;
+      }
+      chunk = std::max(2, std::min(next, 64));
     }
-    chunk = std::max(2, std::min(next, 64));
+    const int todo = std::max(1, std::min(chunk, a.max_cycles - last_sel));
+    if (timing) DI_TRY(ensure_events(ws, 2 + 2 * (size_t)(last_sel + todo)));
+    for (int q = 0; q < todo; ++q) {
+      const int c = last_sel;
+      hipEvent_t e0 = timing ? ws->events[2 + 2 * (size_t)c] : nullptr;
+      hipEvent_t e1 = timing ? ws->events[3 + 2 * (size_t)c] : nullptr;
+      DI_HIP(launch_move<T>(a, c, e0, e1));
+      DI_HIP(launch_select<T>(a, c + 1, 0));
+      last_sel = c + 1;
+    }
   }
+  rt->state = ws->host_ctl[(last_sel + 1) & 1];
   float ms = 0.f;
   DI_HIP(hipEventElapsedTime(&ms, ev_begin, ev_end));
   rt->seconds = ms * 1e-3;
   if (timing) {
-    const int real = std::min(ws->host_ctl->cycles, launched);
+    const int real = std::min(rt->state.cycles, last_sel);
     for (int c = 0; c < real; ++c) {
       float pm = 0.f;
       DI_HIP(hipEventElapsedTime(&pm, ws->events[2 + 2 * (size_t)c], ws->events[3 + 2 * (size_t)c]));
@@ -297,9 +303,9 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   DI_HIP(hipStreamSynchronize(stream));
   di_stats tmp;
   std::memset(&tmp, 0, sizeof(tmp));
-  fill_stats(g, *ws->host_ctl, d, (int)sizeof(T), a.direction, rt, &tmp);
+  fill_stats(g, rt.state, d, (int)sizeof(T), a.direction, rt, &tmp);
   if (st) *st = tmp;
-  return status_from_done(ws->host_ctl->done);
+  return status_from_done(rt.state.done);
 }
 
 di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double d, double tol,
@@ -403,7 +409,7 @@ di_status cycles_dev(const di_graph* gc, double d, int32_t method, double* F_dev
   DI_HIP(launch_start_state<double>(a));
   RunTimes rt;
   DI_TRY(run_cycles<double>(a, false, ws->events[0], &rt));
-  const Ctl& h = *ws->host_ctl;
+  const Ctl& h = rt.state;
   if (h.done == 3) return status_from_done(3);
   if (e_inout) *e_inout = h.e;
   if (stats) {
