@@ -50,7 +50,8 @@ namespace {
 
 void free_graph_device(di_graph* g) {
   void* ptrs[] = {g->row_ptr, g->col,    g->info,   g->csc_ptr,  g->csc_idx, g->it_r0,
-                  g->it_r1,   g->it_l0,  g->it_l1,  g->it_seg,   g->heavy_row, g->heavy_seg};
+                  g->it_r1,   g->it_l0,  g->it_l1,  g->it_seg,   g->heavy_row, g->heavy_seg,
+                  g->hc_seg0, g->hc_seg1, g->hc_off};
   for (void* p : ptrs) (void)hipFree(p);
   g->row_ptr = nullptr;
   g->col = nullptr;
@@ -61,6 +62,7 @@ void free_graph_device(di_graph* g) {
   g->it_seg = nullptr;
   g->heavy_row = nullptr;
   g->heavy_seg = nullptr;
+  g->hc_seg0 = g->hc_seg1 = g->hc_off = nullptr;
 }
 
 template <typename V>
@@ -261,7 +263,18 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       g->n_items = (int64_t)r0v.size();
       g->n_heavy = (int64_t)hrow.size();
       g->n_segs = nseg;
-      g->heavy_atomic = g->n_heavy > di::kHeavyLds;
+      // completion chunks of at most kHeavyChunkSegs segment sums
+      std::vector<int64_t> hc0, hc1, hoff;
+      for (size_t h = 0; h < hrow.size(); ++h) {
+        hoff.push_back((int64_t)hc0.size());
+        for (int64_t q = hseg[h]; q < hseg[h + 1]; q += di::kHeavyChunkSegs) {
+          hc0.push_back(q);
+          hc1.push_back(std::min<int64_t>(q + di::kHeavyChunkSegs, hseg[h + 1]));
+        }
+      }
+      hoff.push_back((int64_t)hc0.size());
+      g->n_hchunks = (int64_t)hc0.size();
+      g->heavy_atomic = g->n_heavy > di::kHeavyLds || g->n_hchunks > di::kHeavyLds;
       st = upload(&g->csc_ptr, cptr);
       if (st == DI_OK) st = upload(&g->csc_idx, cidx);
       if (st == DI_OK) st = upload(&g->it_r0, r0v);
@@ -271,6 +284,9 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       if (st == DI_OK) st = upload(&g->it_seg, segv);
       if (st == DI_OK) st = upload(&g->heavy_row, hrow);
       if (st == DI_OK) st = upload(&g->heavy_seg, hseg);
+      if (st == DI_OK) st = upload(&g->hc_seg0, hc0);
+      if (st == DI_OK) st = upload(&g->hc_seg1, hc1);
+      if (st == DI_OK) st = upload(&g->hc_off, hoff);
       // the node words carry the heavy flags
       if (st == DI_OK)
         DI_HIP(hipMemcpy(g->info, info.data(), info.size() * sizeof(uint32_t), hipMemcpyHostToDevice));

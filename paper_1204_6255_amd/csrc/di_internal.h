@@ -43,6 +43,7 @@ constexpr uint32_t kOutMask = 0x3fffffffu;
 // are kept in its LDS); graphs with more heavy rows add the segment sums of
 // every heavy row to F with atomics instead.
 constexpr int kHeavyLds = 4096;
+constexpr int kHeavyChunkSegs = 16;   // segment sums per completion chunk
 
 // Control block: two copies. The select kernel of cycle c reads copy c & 1
 // (the state after cycle c - 1) and its block 0 writes copy (c + 1) & 1; the
@@ -138,9 +139,15 @@ struct di_graph {
   // heavy rows (more than kPullChunk in-links)
   int64_t n_heavy = 0;
   int64_t n_segs = 0;
-  bool heavy_atomic = false;      // n_heavy > kHeavyLds
+  bool heavy_atomic = false;      // n_heavy or n_hchunks > kHeavyLds
   int32_t* heavy_row = nullptr;   // n_heavy, ascending
   int64_t* heavy_seg = nullptr;   // n_heavy + 1: segment range of each
+  // completion chunks: chunk k sums segments [hc_seg0[k], hc_seg1[k]) of one
+  // heavy row; row h owns chunks [hc_off[h], hc_off[h + 1])
+  int64_t n_hchunks = 0;
+  int64_t* hc_seg0 = nullptr;
+  int64_t* hc_seg1 = nullptr;
+  int64_t* hc_off = nullptr;
   std::mutex mu;
   std::vector<di::Workspace*> pool;
 };

@@ -235,12 +235,15 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     unsigned long long* __restrict__ front_bits, int64_t* __restrict__ fr_lstart,
     int64_t* __restrict__ fr_base, T* __restrict__ fr_s, SelStat* __restrict__ tile_stat,
     const Part* __restrict__ blk_part, int nparts, const int32_t* __restrict__ heavy_row,
-    const int64_t* __restrict__ heavy_seg, const double* __restrict__ seg_val, int64_t n_heavy,
-    int heavy_atomic, Ctl* __restrict__ ctl, int parity, int first, double d, double tol,
-    int method, int stop, int max_cycles) {
+    const int64_t* __restrict__ hc_seg0, const int64_t* __restrict__ hc_seg1,
+    const int64_t* __restrict__ hc_off, const double* __restrict__ seg_val, int64_t n_heavy,
+    int64_t n_hchunks, int heavy_atomic, Ctl* __restrict__ ctl, int parity, int first, double d,
+    double tol, int method, int stop, int max_cycles) {
   constexpr int TILE = BLOCK * M;
   constexpr int NW = BLOCK / 64;
-  // heavy rows completed here (not first, not heavy_atomic): row and value
+  constexpr int HPT = PULL ? kHeavyLds / BLOCK : 1;  // heavy rows per thread
+  // heavy rows completed here (not first, not heavy_atomic): the chunk sums,
+  // then (same space) the completed values; and the row ids
   __shared__ int32_t s_hrow[PULL ? kHeavyLds : 1];
   __shared__ double s_hval[PULL ? kHeavyLds : 1];
   __shared__ Part s_part[NW];
@@ -255,36 +258,77 @@ __global__ __launch_bounds__(BLOCK) void k_select(
   // first round of loads: the first tile's nodes, the records, the heavy
   // rows and the control block are independent of one another
   int64_t tile = blockIdx.x;
-  double f[M];
+  double f[M], hv[M];
   uint32_t w[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int64_t i = tile * TILE + tid + (int64_t)m * BLOCK;
-    f[m] = (tile < ntiles && i < n) ? to_d(F[i]) : 0.0;
-    w[m] = (tile < ntiles && i < n) ? info[i] : 0u;
+    const bool in = tile < ntiles && i < n;
+    f[m] = in ? to_d(F[i]) : 0.0;
+    hv[m] = in ? to_d(H[i]) : 0.0;
+    w[m] = in ? info[i] : 0u;
   }
+  Ctl c0;
+  if (tid == 0) c0 = ctl[parity];
   Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
   for (int p = tid; p < nparts; p += BLOCK) part_add(v, blk_part[p]);
   // After a pull the records leave out the heavy rows (the start records
   // cover every row): add their values, completing them with their segment
   // sums in a fixed order unless the pull added those atomically.
   const bool heavy_here = PULL && !first && !heavy_atomic;
-  for (int64_t h = first ? n_heavy : tid; h < n_heavy; h += BLOCK) {
-    const int32_t row = heavy_row[h];
-    double fh = to_d(F[row]);
-    if (heavy_here) {
-      double acc = 0.0;
-      for (int64_t q = heavy_seg[h]; q < heavy_seg[h + 1]; ++q) acc += seg_val[q];
-      fh = to_d((T)(fh + acc));
-      s_hrow[h] = row;
-      s_hval[h] = fh;
+  if (heavy_here) {
+    // chunk sums (one round of loads), then each row's chunks in order
+    int32_t hr[HPT];
+    double hf[HPT];
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int64_t h = tid + (int64_t)k * BLOCK;
+      hr[k] = h < n_heavy ? heavy_row[h] : 0;
     }
-    v.pabs += fabs(fh);
-    v.psum += fh;
+    for (int64_t k = tid; k < n_hchunks; k += BLOCK) {
+      const int64_t q0 = hc_seg0[k], q1 = hc_seg1[k];
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < kHeavyChunkSegs; ++u)
+        if (q0 + u < q1) acc += seg_val[q0 + u];
+      s_hval[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int64_t h = tid + (int64_t)k * BLOCK;
+      hf[k] = h < n_heavy ? to_d(F[hr[k]]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int64_t h = tid + (int64_t)k * BLOCK;
+      if (h < n_heavy) {
+        double acc = 0.0;
+        for (int64_t q = hc_off[h]; q < hc_off[h + 1]; ++q) acc += s_hval[q];
+        hf[k] = to_d((T)(hf[k] + acc));
+        v.pabs += fabs(hf[k]);
+        v.psum += hf[k];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int64_t h = tid + (int64_t)k * BLOCK;
+      if (h < n_heavy) {
+        s_hrow[h] = hr[k];
+        s_hval[h] = hf[k];
+      }
+    }
+  } else if (PULL && !first) {
+    // heavy_atomic: the pull added the segment sums to F
+    for (int64_t h = tid; h < n_heavy; h += BLOCK) {
+      const double fh = to_d(F[heavy_row[h]]);
+      v.pabs += fabs(fh);
+      v.psum += fh;
+    }
   }
   v = block_sum_part(v, s_part);
   if (tid == 0) {
-    const Ctl c0 = ctl[parity];
     const Ctl c = next_ctl(c0, v, first, d, tol, method, stop, max_cycles);
     if (blockIdx.x == 0) ctl[parity ^ 1] = c;
     s_done = c.done;
@@ -313,6 +357,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
       for (int m = 0; m < M; ++m) {
         const int64_t i = base + (int64_t)m * BLOCK;
         f[m] = i < n ? to_d(F[i]) : 0.0;
+        hv[m] = i < n ? to_d(H[i]) : 0.0;
         w[m] = i < n ? info[i] : 0u;
       }
     }
@@ -343,7 +388,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
         const double thr = (cyc || out == 0) ? 0.0 : rl * (double)out;
         if (a > 0.0 && a >= thr) {
           const double t = loop ? f[m] * (double)out / ((double)out - d) : f[m];
-          H[i] = (T)(to_d(H[i]) + t);
+          H[i] = (T)(hv[m] + t);
           F[i] = (T)0;
           ++my_sel;
           if (out == 0) {
@@ -697,17 +742,18 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        dim3(kSelectBlockPull), 0, a.stream, (T*)ws->F, (T*)ws->H, g->info,
                        g->row_ptr, g->n, g->L, (T*)ws->sent, ws->front_bits, (int64_t*)nullptr,
                        (int64_t*)nullptr, (T*)nullptr, ws->tile_stat, (const Part*)ws->blk_part,
-                       nparts, g->heavy_row, g->heavy_seg, (const double*)ws->seg_val,
-                       g->n_heavy, (int)g->heavy_atomic, ws->ctl, parity, first, a.d, a.tol,
-                       a.method, a.stop, a.max_cycles);
+                       nparts, g->heavy_row, g->hc_seg0, g->hc_seg1, g->hc_off,
+                       (const double*)ws->seg_val, g->n_heavy, g->n_hchunks, (int)g->heavy_atomic,
+                       ws->ctl, parity, first, a.d, a.tol, a.method, a.stop, a.max_cycles);
   } else {
     hipLaunchKernelGGL((k_select<T, false, kSelectBlockPush, kSelectPerThreadPush>), dim3(grid),
                        dim3(kSelectBlockPush), 0, a.stream, (T*)ws->F, (T*)ws->H, g->info,
                        g->row_ptr, g->n, g->L, (T*)nullptr, (unsigned long long*)nullptr,
                        ws->fr_lstart, ws->fr_base, (T*)ws->fr_s, ws->tile_stat,
                        (const Part*)ws->blk_part, nparts, (const int32_t*)nullptr,
-                       (const int64_t*)nullptr, (const double*)nullptr, (int64_t)0, 0, ws->ctl,
-                       parity, first, a.d, a.tol, a.method, a.stop, a.max_cycles);
+                       (const int64_t*)nullptr, (const int64_t*)nullptr, (const int64_t*)nullptr,
+                       (const double*)nullptr, (int64_t)0, (int64_t)0, 0, ws->ctl, parity, first,
+                       a.d, a.tol, a.method, a.stop, a.max_cycles);
   }
   return hipGetLastError();
 }
