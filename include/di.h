@@ -92,7 +92,12 @@ typedef struct di_opts {
   uint32_t flags;     /* DI_FLAG_* */
   int32_t kernel;     /* DI_KERNEL_* (default DI_KERNEL_AUTO) */
   double inner_tol;   /* DI_FP32_REFINE: relative residual reduction asked
-                         of each FP32 pass (<= 0: 1e-5) */
+                         of each FP32 pass (<= 0: 1e-5). A refined solve
+                         runs FP32 DI-SOP cycles until sum|F| <=
+                         max(tol/2, inner_tol * r_start), then folds H
+                         into an FP64 X and recomputes the fluid as the
+                         FP64 residual B + P.X - X; it stops when that
+                         residual is <= tol. DI_STOP_RESID only. */
   void* stream;       /* hipStream_t for the *_dev calls; NULL = the
                          default (null) stream */
 } di_opts;
@@ -171,6 +176,17 @@ di_status di_solve_dev(const di_graph* g, const double* B_dev, double d, double 
 di_status di_cycles_dev(const di_graph* g, double d, int32_t method, double* F_dev,
                         double* H_dev, int32_t cycles, double* e_inout, void* stream,
                         di_stats* stats);
+
+/* The FP64 residual R = B + P.X - X of an approximate solution X, and
+ * |R|_1 (the refinement step of DI_FP32_REFINE, which recomputes the fluid
+ * of Section 2.2 as F = B - (I - P).X). B_dev: n doubles on the device, or
+ * NULL for the PageRank right-hand side (1-d)/n. X_dev: n doubles on the
+ * device (read only). R_dev: n doubles on the device, or NULL when only the
+ * norm is wanted. *l1 (host, may be NULL) receives |R|_1, summed in FP64.
+ * Work is queued on `stream` (NULL = the null stream); the call returns
+ * once it has finished. */
+di_status di_residual_dev(const di_graph* g, const double* B_dev, double d, const double* X_dev,
+                          double* R_dev, double* l1, void* stream);
 
 /* Message describing the calling thread's last failure ("" if none). */
 const char* di_last_error(void);

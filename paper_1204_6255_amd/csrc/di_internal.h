@@ -58,9 +58,11 @@ struct Ctl {
   double paper_err;  // last sum F / (1 - d - d e)
   double r_first;    // r used by the first cycle
   double r_last;     // r used by the last cycle
+  double r_start;    // sum |F| at the first selection of the run
   int cycles;        // cycles run
   int fallback;      // DI-CYC cycles run after an empty DI-SOP cycle
-  int done;          // 0 running, 1 converged, 2 max_cycles, 3 non-finite
+  int done;          // 0 running, 1 converged, 2 max_cycles, 3 non-finite,
+                     // 4 inner stop (the FP32 pass of a refined solve ended)
   int cyc_mode;      // next cycle selects every |F_i| > 0
   unsigned long long edges_total;  // link operations (pushes along j != i)
   unsigned long long front_total;  // diffused nodes with links to push
@@ -103,6 +105,8 @@ struct Workspace {
   double* seg_val = nullptr;    // pull: sums of the heavy-row segments
   Ctl* ctl = nullptr;           // two copies (see Ctl)
   Ctl* host_ctl = nullptr;      // pinned copy of both, for the stop check
+  double* Y64 = nullptr;        // refinement: d X_j / out_j
+  Part* host_part = nullptr;    // pinned copy of the records (residual norm)
   double* X64 = nullptr;        // host entry points: device copy of X
   double* B64 = nullptr;        // host entry points: device copy of B
   std::vector<hipEvent_t> events;
@@ -184,7 +188,11 @@ struct CycleArgs {
   const di_graph* g;
   Workspace* ws;
   double d;
-  double tol;
+  double tol;      // converged when sum |F| <= tol (first selection of a
+                   // refined run: the FP64 residual of X)
+  double tol_in;   // refined runs (tol_rel >= 0): after a cycle, stop the
+  double tol_rel;  // FP32 pass when sum |F| <= max(tol_in, tol_rel * r_start)
+  int first_parts; // records the first selection sums
   int method;      // DI_SOP or DI_CYC
   int stop;        // DI_STOP_RESID or DI_STOP_PAPER
   int max_cycles;  // the solve stops after this many cycles
@@ -215,5 +223,12 @@ template <typename T>
 hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_h_to_x(const CycleArgs& a, double* X);
+// FP64 residual pass: with H, first X += H and H = 0; then y = d X / out and
+// R = B + P.X - X (B == nullptr: b_uniform everywhere), written to R_out as
+// T, with the records of sum |R| and sum R in blk_part[0, pull_grid] (the
+// last one covers the heavy rows). Every record is FP64.
+template <typename T>
+hipError_t launch_refine(const CycleArgs& a, double* X, T* H, const double* B, double b_uniform,
+                         T* R_out);
 
 }  // namespace di

@@ -117,6 +117,7 @@ __global__ void k_reset_ctl(Ctl* ctl) {
     c.paper_err = 0.0;
     c.r_first = 0.0;
     c.r_last = 0.0;
+    c.r_start = 0.0;
     c.cycles = 0;
     c.fallback = 0;
     c.done = 0;
@@ -145,7 +146,12 @@ __global__ __launch_bounds__(kReduceBlock) void k_start(T* __restrict__ F, T* __
     v.psum += to_d(f);
   }
   v = block_sum_part(v, lds);
-  if (threadIdx.x == 0) blk_part[blockIdx.x] = v;
+  if (threadIdx.x == 0) {
+    blk_part[blockIdx.x] = v;
+    // the record after the last one (the heavy-row record of a residual
+    // pass) is empty: a first selection sums gridDim.x + 1 records
+    if (blockIdx.x == 0) blk_part[gridDim.x] = Part{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  }
 }
 
 // Sums of |F| and F per block over all nodes: the start of a caller-held
@@ -168,13 +174,21 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce(const T* __restrict__ F
     v.psum += f;
   }
   v = block_sum_part(v, lds);
-  if (threadIdx.x == 0) blk_part[blockIdx.x] = v;
+  if (threadIdx.x == 0) {
+    blk_part[blockIdx.x] = v;
+    if (!ctl && blockIdx.x == 0) blk_part[gridDim.x] = Part{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  }
 }
 
 // The stop test and the next control-block copy, from the sums of the
 // records (v) and the current copy (c). first: no cycle has run yet.
-__device__ inline Ctl next_ctl(Ctl c, const Part& v, int first, double d, double tol, int method,
-                               int stop, int max_cycles) {
+// tol_rel >= 0 marks the FP32 pass of a refined solve: only the first
+// selection may declare convergence (its r is the FP64 residual of X);
+// after a cycle the pass ends (done = 4) once r <= max(tol_in,
+// tol_rel * r_start).
+__device__ inline Ctl next_ctl(Ctl c, const Part& v, int first, double d, double tol,
+                               double tol_in, double tol_rel, int method, int stop,
+                               int max_cycles) {
   if (c.done) return c;
   if (!first) {
     const double r_used = c.r;
@@ -201,9 +215,19 @@ __device__ inline Ctl next_ctl(Ctl c, const Part& v, int first, double d, double
     c.done = 3;
     return c;
   }
+  if (first) c.r_start = r;
   bool stop_now;
   if (stop == DI_STOP_RESID) {
-    stop_now = r <= tol;
+    if (tol_rel >= 0.0 && !first) {
+      if (r <= fmax(tol_in, tol_rel * c.r_start)) {
+        c.final_r = r;
+        c.done = 4;
+        return c;
+      }
+      stop_now = false;
+    } else {
+      stop_now = r <= tol;
+    }
   } else {
     stop_now = false;
     if (!first) {
@@ -238,7 +262,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     const int64_t* __restrict__ hc_seg0, const int64_t* __restrict__ hc_seg1,
     const int64_t* __restrict__ hc_off, const double* __restrict__ seg_val, int64_t n_heavy,
     int64_t n_hchunks, int heavy_atomic, Ctl* __restrict__ ctl, int parity, int first, double d,
-    double tol, int method, int stop, int max_cycles) {
+    double tol, double tol_in, double tol_rel, int method, int stop, int max_cycles) {
   constexpr int TILE = BLOCK * M;
   constexpr int NW = BLOCK / 64;
   constexpr int HPT = PULL ? kHeavyLds / BLOCK : 1;  // heavy rows per thread
@@ -329,7 +353,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
   }
   v = block_sum_part(v, s_part);
   if (tid == 0) {
-    const Ctl c = next_ctl(c0, v, first, d, tol, method, stop, max_cycles);
+    const Ctl c = next_ctl(c0, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
     if (blockIdx.x == 0) ctl[parity ^ 1] = c;
     s_done = c.done;
     s_was_done = c0.done;
@@ -676,6 +700,135 @@ __global__ void k_h_to_x(const T* __restrict__ H, double* __restrict__ X, int64_
     X[i] = to_d(H[i]);
 }
 
+// ---- FP64 residual pass (refinement of an FP32 solve) -----------------
+// With the history folded into X, the exact residual R = B + P.X - X is
+// recomputed in FP64 and becomes the new fluid: (F, H) = (R, 0) satisfies
+// F = R - (I - P).H again, so the next FP32 pass solves for the correction.
+
+// X += H, H = 0 (when H is given); y_j = d X_j / out_j, 0 for dangling j.
+template <typename T>
+__global__ void k_refine_y(double* __restrict__ X, T* __restrict__ H,
+                           const uint32_t* __restrict__ info, double d, int64_t n,
+                           double* __restrict__ y) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double x = X[i];
+    if (H) {
+      x += to_d(H[i]);
+      X[i] = x;
+      H[i] = (T)0;
+    }
+    const int out = (int)(info[i] & kOutMask);
+    y[i] = out > 0 ? d * x / (double)out : 0.0;
+  }
+}
+
+// R_i = B_i - X_i + (self-loop ? y_i : 0) + sum of y_j over the in-links
+// j -> i (j != i), over the pull work items (in-link ids staged through
+// LDS, ascending within a row). Heavy-row segments leave their sums in
+// seg_val for k_refine_heavy. Each block writes one record of its rows'
+// sum |R| and sum R.
+template <typename T>
+__global__ __launch_bounds__(kPullBlock) void k_refine_r(
+    T* __restrict__ R, const double* __restrict__ X, const double* __restrict__ y,
+    const double* __restrict__ B, double b_uniform, const uint32_t* __restrict__ info,
+    const int64_t* __restrict__ csc_ptr, const int32_t* __restrict__ csc_idx,
+    const int64_t* __restrict__ it_r0, const int64_t* __restrict__ it_r1,
+    const int64_t* __restrict__ it_l0, const int64_t* __restrict__ it_l1,
+    const int32_t* __restrict__ it_seg, int64_t n_items, double* __restrict__ seg_val,
+    Part* __restrict__ blk_part) {
+  constexpr int U = kPullChunk / kPullBlock;
+  __shared__ double s_val[kPullChunk];
+  __shared__ double s_red[kPullBlock / 64];
+  __shared__ Part s_part[kPullBlock / 64];
+  const int tid = threadIdx.x, lane = tid & 63;
+  Part acc_part{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int64_t l0 = it_l0[it], l1 = it_l1[it], r0 = it_r0[it], r1 = it_r1[it];
+    const int seg = it_seg[it];
+    const int nl = (int)(l1 - l0);
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kPullBlock;
+      v[u] = p < nl ? y[csc_idx[l0 + p]] : 0.0;
+    }
+    if (seg >= 0) {
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += v[u];
+      acc = block_sum(acc, s_red);
+      if (tid == 0) seg_val[seg] = acc;
+      continue;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kPullBlock;
+      if (p < nl) s_val[p] = v[u];
+    }
+    __syncthreads();
+    for (int64_t row = r0 + tid; row - lane < r1; row += kPullBlock) {
+      const bool valid = row < r1;
+      int a = 0, b = 0;
+      if (valid) {
+        a = (int)(csc_ptr[row] - l0);
+        b = (int)(csc_ptr[row + 1] - l0);
+      }
+      const bool longrow = valid && (b - a) > kPullLongRow;
+      double acc = 0.0;
+      if (valid && !longrow)
+        for (int q = a; q < b; ++q) acc += s_val[q];
+      unsigned long long mask = __ballot(longrow);
+      while (mask) {
+        const int src = __ffsll(mask) - 1;
+        mask &= mask - 1;
+        const int la = __shfl(a, src, 64), lb = __shfl(b, src, 64);
+        double part = 0.0;
+        for (int q = la + lane; q < lb; q += 64) part += s_val[q];
+        part = wave_sum(part);
+        if (lane == src) acc = part;
+      }
+      if (valid) {
+        const double bi = B ? B[row] : b_uniform;
+        const double self = (info[row] & kLoopBit) ? y[row] : 0.0;
+        const double r = bi - X[row] + self + acc;
+        R[row] = (T)r;
+        acc_part.pabs += fabs(r);
+        acc_part.psum += r;
+      }
+    }
+    __syncthreads();
+  }
+  acc_part = block_sum_part(acc_part, s_part);
+  if (tid == 0) blk_part[blockIdx.x] = acc_part;
+}
+
+// The heavy rows of a residual pass: their segment sums in order. One
+// block; writes the record blk_part[slot].
+template <typename T>
+__global__ __launch_bounds__(kReduceBlock) void k_refine_heavy(
+    T* __restrict__ R, const double* __restrict__ X, const double* __restrict__ y,
+    const double* __restrict__ B, double b_uniform, const uint32_t* __restrict__ info,
+    const int32_t* __restrict__ heavy_row, const int64_t* __restrict__ heavy_seg,
+    int64_t n_heavy, const double* __restrict__ seg_val, Part* __restrict__ blk_part,
+    int slot) {
+  __shared__ Part lds[kReduceBlock / 64];
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  for (int64_t h = threadIdx.x; h < n_heavy; h += blockDim.x) {
+    const int64_t row = heavy_row[h];
+    double acc = 0.0;
+    for (int64_t q = heavy_seg[h]; q < heavy_seg[h + 1]; ++q) acc += seg_val[q];
+    const double bi = B ? B[row] : b_uniform;
+    const double self = (info[row] & kLoopBit) ? y[row] : 0.0;
+    const double r = bi - X[row] + self + acc;
+    R[row] = (T)r;
+    v.pabs += fabs(r);
+    v.psum += r;
+  }
+  v = block_sum_part(v, lds);
+  if (threadIdx.x == 0) blk_part[slot] = v;
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline unsigned int grid_for(int64_t n, int block, int64_t cap) {
@@ -736,7 +889,7 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
   Workspace* ws = a.ws;
   const int grid = select_grid(g->n, a.direction);
   const int parity = cycle & 1;
-  const int nparts = part_count(a);
+  const int nparts = first ? a.first_parts : part_count(a);
   if (a.direction == kPull) {
     hipLaunchKernelGGL((k_select<T, true, kSelectBlockPull, kSelectPerThreadPull>), dim3(grid),
                        dim3(kSelectBlockPull), 0, a.stream, (T*)ws->F, (T*)ws->H, g->info,
@@ -744,7 +897,8 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        (int64_t*)nullptr, (T*)nullptr, ws->tile_stat, (const Part*)ws->blk_part,
                        nparts, g->heavy_row, g->hc_seg0, g->hc_seg1, g->hc_off,
                        (const double*)ws->seg_val, g->n_heavy, g->n_hchunks, (int)g->heavy_atomic,
-                       ws->ctl, parity, first, a.d, a.tol, a.method, a.stop, a.max_cycles);
+                       ws->ctl, parity, first, a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop,
+                       a.max_cycles);
   } else {
     hipLaunchKernelGGL((k_select<T, false, kSelectBlockPush, kSelectPerThreadPush>), dim3(grid),
                        dim3(kSelectBlockPush), 0, a.stream, (T*)ws->F, (T*)ws->H, g->info,
@@ -753,7 +907,7 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        (const Part*)ws->blk_part, nparts, (const int32_t*)nullptr,
                        (const int64_t*)nullptr, (const int64_t*)nullptr, (const int64_t*)nullptr,
                        (const double*)nullptr, (int64_t)0, (int64_t)0, 0, ws->ctl, parity, first,
-                       a.d, a.tol, a.method, a.stop, a.max_cycles);
+                       a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop, a.max_cycles);
   }
   return hipGetLastError();
 }
@@ -794,6 +948,28 @@ hipError_t launch_h_to_x(const CycleArgs& a, double* X) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_refine(const CycleArgs& a, double* X, T* H, const double* B, double b_uniform,
+                         T* R_out) {
+  const di_graph* g = a.g;
+  Workspace* ws = a.ws;
+  hipLaunchKernelGGL(k_refine_y<T>, dim3(grid_for(g->n, 256, 4096)), dim3(256), 0, a.stream, X, H,
+                     g->info, a.d, g->n, ws->Y64);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int grid = pull_grid(g);
+  hipLaunchKernelGGL(k_refine_r<T>, dim3(grid), dim3(kPullBlock), 0, a.stream, R_out,
+                     (const double*)X, (const double*)ws->Y64, B, b_uniform, g->info, g->csc_ptr,
+                     g->csc_idx, g->it_r0, g->it_r1, g->it_l0, g->it_l1, g->it_seg, g->n_items,
+                     ws->seg_val, ws->blk_part);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_refine_heavy<T>, dim3(1), dim3(kReduceBlock), 0, a.stream, R_out,
+                     (const double*)X, (const double*)ws->Y64, B, b_uniform, g->info,
+                     g->heavy_row, g->heavy_seg, g->n_heavy, (const double*)ws->seg_val,
+                     ws->blk_part, grid);
+  return hipGetLastError();
+}
+
 template hipError_t launch_start<double>(const CycleArgs&, const double*, double);
 template hipError_t launch_start<float>(const CycleArgs&, const double*, double);
 template hipError_t launch_start_state<double>(const CycleArgs&);
@@ -804,5 +980,9 @@ template hipError_t launch_move<double>(const CycleArgs&, int, hipEvent_t, hipEv
 template hipError_t launch_move<float>(const CycleArgs&, int, hipEvent_t, hipEvent_t);
 template hipError_t launch_h_to_x<double>(const CycleArgs&, double*);
 template hipError_t launch_h_to_x<float>(const CycleArgs&, double*);
+template hipError_t launch_refine<double>(const CycleArgs&, double*, double*, const double*, double,
+                                          double*);
+template hipError_t launch_refine<float>(const CycleArgs&, double*, float*, const double*, double,
+                                         float*);
 
 }  // namespace di

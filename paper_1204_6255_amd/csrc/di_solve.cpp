@@ -20,9 +20,11 @@ void free_workspace(Workspace* ws) {
   if (!ws) return;
   void* ptrs[] = {ws->F,         ws->H,         ws->sent,     ws->front_bits,
                   ws->fr_lstart, ws->fr_base,   ws->fr_s,     ws->tile_stat,
-                  ws->blk_part,  ws->seg_val,   ws->ctl,      ws->X64,      ws->B64};
+                  ws->blk_part,  ws->seg_val,   ws->ctl,      ws->X64,      ws->B64,
+                  ws->Y64};
   for (void* p : ptrs) (void)hipFree(p);
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
+  if (ws->host_part) (void)hipHostFree(ws->host_part);
   for (hipEvent_t e : ws->events) (void)hipEventDestroy(e);
   delete ws;
 }
@@ -48,7 +50,9 @@ di_status alloc_workspace(const di_graph* g, int prec, Workspace** out) {
   const size_t s = prec == kF64 ? sizeof(double) : sizeof(float);
   const size_t ntiles =
       (size_t)std::max(select_tiles(g->n, kPull), select_tiles(g->n, kPush));
-  const size_t nparts = (size_t)std::max(kPullMaxGrid, kReduceGrid);
+  // one record per pull/reduce block, plus the heavy-row record of a
+  // residual pass
+  const size_t nparts = (size_t)std::max(kPullMaxGrid, kReduceGrid) + 1;
   di_status st = DI_OK;
   if (st == DI_OK) st = dmalloc(&ws->F, n * s);
   if (st == DI_OK) st = dmalloc(&ws->H, n * s);
@@ -83,6 +87,38 @@ di_status ensure_push_buffers(const di_graph* g, Workspace* ws) {
   DI_TRY(dmalloc((void**)&ws->fr_base, slots * sizeof(int64_t)));
   DI_TRY(dmalloc(&ws->fr_s, slots * s));
   DI_TRY(dmalloc((void**)&ws->fr_lstart, slots * sizeof(int64_t)));
+  return DI_OK;
+}
+
+// Residual-pass buffers, allocated on first use.
+di_status ensure_refine_buffers(const di_graph* g, Workspace* ws) {
+  if (!ws->Y64) DI_TRY(dmalloc((void**)&ws->Y64, (size_t)g->n * sizeof(double)));
+  if (!ws->host_part) {
+    const size_t bytes = ((size_t)std::max(kPullMaxGrid, kReduceGrid) + 1) * sizeof(Part);
+    hipError_t err = hipHostMalloc((void**)&ws->host_part, bytes, hipHostMallocDefault);
+    if (err != hipSuccess) {
+      ws->host_part = nullptr;
+      set_error(std::string("hipHostMalloc: ") + hipGetErrorString(err));
+      return DI_E_NOMEM;
+    }
+  }
+  return DI_OK;
+}
+
+// sum |R| of the records [0, count) of a residual pass, in record order
+// (waits for the stream)
+di_status residual_norm(const CycleArgs& a, int count, double* l1, double* sum) {
+  Workspace* ws = a.ws;
+  DI_HIP(hipMemcpyAsync(ws->host_part, ws->blk_part, (size_t)count * sizeof(Part),
+                        hipMemcpyDeviceToHost, a.stream));
+  DI_HIP(hipStreamSynchronize(a.stream));
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = 0; k < count; ++k) {
+    s1 += ws->host_part[k].pabs;
+    s2 += ws->host_part[k].psum;
+  }
+  *l1 = s1;
+  if (sum) *sum = s2;
   return DI_OK;
 }
 
@@ -168,10 +204,12 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
     if (last_sel > 0) {
       // cycles still needed, from the contraction of r per cycle so far
       int next = 16;
+      const double target =
+          a.tol_rel >= 0.0 ? std::max(a.tol_in, a.tol_rel * h.r_start) : a.tol;
       if (a.stop == DI_STOP_RESID && h.cycles >= 1 && h.r_first > 0.0 && h.r > 0.0 &&
-          h.r < h.r_first && a.tol > 0.0) {
+          h.r < h.r_first && target > 0.0) {
         const double rate = std::log(h.r / h.r_first) / (double)h.cycles;
-        const double need = std::log(a.tol / h.r) / rate;
+        const double need = std::log(target / h.r) / rate;
         if (std::isfinite(need)) next = (int)std::ceil(need) + 1;
       }
       chunk = std::max(2, std::min(next, 64));
@@ -198,7 +236,7 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
       DI_HIP(hipEventElapsedTime(&pm, ws->events[2 + 2 * (size_t)c], ws->events[3 + 2 * (size_t)c]));
       rt->move_seconds += pm * 1e-3;
     }
-    rt->move_launches = real;
+    rt->move_launches += real;
   }
   return DI_OK;
 }
@@ -210,8 +248,10 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
 //     (in-link offsets, F read and written);
 //   push, per cycle: links pushed (4 + 2s) (out-link id, atomic read-modify-
 //     write) + frontier entries (16 + s), and the reduction N s.
+//   residual pass (refinement): Lp 12 (in-link id, y of the sender) +
+//     N (56 + 3s) (X, H, node word, y, B, in-link offsets, R).
 void fill_stats(const di_graph* g, const Ctl& h, double d, int s_bytes, int direction,
-                const RunTimes& rt, di_stats* st) {
+                const RunTimes& rt, int refinements, di_stats* st) {
   st->cycles = h.cycles;
   st->fallback_cycles = h.fallback;
   st->edges_pushed = (int64_t)h.edges_total;
@@ -228,8 +268,10 @@ void fill_stats(const di_graph* g, const Ctl& h, double d, int s_bytes, int dire
     move = (double)h.edges_total * (4.0 + 2.0 * s) + (double)h.front_total * (16.0 + s) + C * N * s;
   }
   const double select = C * N * (2.0 * s + 4.0) + (double)h.sel_total * 3.0 * s;
+  const double refine = (double)refinements * ((double)g->Lp * 12.0 + N * (56.0 + 3.0 * s));
+  st->refinements = refinements;
   st->move_bytes = rt.move_launches > 0 ? move : 0.0;
-  st->bytes_moved = move + select;
+  st->bytes_moved = move + select + refine;
   st->seconds = rt.seconds;
   st->move_seconds = rt.move_seconds;
   st->move_launches = rt.move_launches;
@@ -266,8 +308,12 @@ di_status check_common(const di_graph* g, double d, double tol, const di_opts& o
     set_error("unknown stop rule");
     return DI_E_INVAL;
   }
-  if (o.precision != DI_FP64 && o.precision != DI_FP32) {
-    set_error("precision not supported by this entry point");
+  if (o.precision != DI_FP64 && o.precision != DI_FP32 && o.precision != DI_FP32_REFINE) {
+    set_error("unknown precision");
+    return DI_E_INVAL;
+  }
+  if (o.precision == DI_FP32_REFINE && o.stop != DI_STOP_RESID) {
+    set_error("DI_FP32_REFINE stops on the residual only (DI_STOP_RESID)");
     return DI_E_INVAL;
   }
   if (o.kernel < DI_KERNEL_AUTO || o.kernel > DI_KERNEL_PUSH) {
@@ -279,6 +325,18 @@ di_status check_common(const di_graph* g, double d, double tol, const di_opts& o
 
 int direction_of(const di_opts& o) { return o.kernel == DI_KERNEL_PUSH ? kPush : kPull; }
 
+constexpr int kMaxRefinements = 100;
+
+// Adds the counters of one run (control block h) to the totals.
+void add_run(Ctl* tot, const Ctl& h) {
+  tot->cycles += h.cycles;
+  tot->fallback += h.fallback;
+  tot->edges_total += h.edges_total;
+  tot->front_total += h.front_total;
+  tot->sel_total += h.sel_total;
+  tot->e += h.e;
+}
+
 template <typename T>
 di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const di_opts& o,
                   double* X_dev, di_stats* st, Workspace* ws, hipStream_t stream) {
@@ -287,25 +345,74 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   a.ws = ws;
   a.d = d;
   a.tol = tol;
+  a.tol_in = tol;
+  a.tol_rel = -1.0;
   a.method = o.method;
   a.stop = o.stop;
   a.max_cycles = o.max_cycles > 0 ? o.max_cycles : 100000;
   a.direction = direction_of(o);
   a.stream = stream;
+  a.first_parts = part_count(a) + 1;
+  const bool timing = (o.flags & DI_FLAG_KERNEL_TIMING) != 0;
+  const double b_uniform = (1.0 - d) / (double)g->n;
   if (a.direction == kPush) DI_TRY(ensure_push_buffers(g, ws));
   DI_TRY(ensure_events(ws, 2));
   DI_HIP(launch_reset_ctl(a));
   DI_HIP(hipEventRecord(ws->events[0], stream));
-  DI_HIP(launch_start<T>(a, B_dev, (1.0 - d) / (double)g->n));
+  DI_HIP(launch_start<T>(a, B_dev, b_uniform));
   RunTimes rt;
-  DI_TRY(run_cycles<T>(a, (o.flags & DI_FLAG_KERNEL_TIMING) != 0, ws->events[0], &rt));
-  DI_HIP(launch_h_to_x<T>(a, X_dev));
-  DI_HIP(hipStreamSynchronize(stream));
   di_stats tmp;
   std::memset(&tmp, 0, sizeof(tmp));
-  fill_stats(g, rt.state, d, (int)sizeof(T), a.direction, rt, &tmp);
+  if (o.precision != DI_FP32_REFINE) {
+    DI_TRY(run_cycles<T>(a, timing, ws->events[0], &rt));
+    DI_HIP(launch_h_to_x<T>(a, X_dev));
+    DI_HIP(hipStreamSynchronize(stream));
+    fill_stats(g, rt.state, d, (int)sizeof(T), a.direction, rt, 0, &tmp);
+    if (st) *st = tmp;
+    return status_from_done(rt.state.done);
+  }
+  // FP32 passes with FP64 residual passes between them: X accumulates the
+  // passes' histories; each pass solves for the correction of X.
+  DI_TRY(ensure_refine_buffers(g, ws));
+  DI_HIP(hipMemsetAsync(X_dev, 0, (size_t)g->n * sizeof(double), stream));
+  a.tol_in = 0.5 * tol;
+  a.tol_rel = o.inner_tol > 0.0 ? o.inner_tol : 1e-5;
+  const int max_cycles = a.max_cycles;
+  Ctl tot{};
+  int refinements = 0;
+  di_status result = DI_OK;
+  for (;;) {
+    a.max_cycles = max_cycles - tot.cycles;
+    DI_TRY(run_cycles<T>(a, timing, ws->events[0], &rt));
+    const Ctl h = rt.state;
+    add_run(&tot, h);
+    if (h.done == 1) {  // the FP64 residual of X is within tol
+      tot.final_r = h.final_r;
+      break;
+    }
+    if (h.done == 3) return status_from_done(3);
+    // inner stop or max_cycles: fold H into X and recompute the residual
+    DI_HIP(launch_refine<T>(a, X_dev, (T*)ws->H, B_dev, b_uniform, (T*)ws->F));
+    ++refinements;
+    a.first_parts = pull_grid(g) + 1;
+    if (h.done == 2 || refinements >= kMaxRefinements) {
+      DI_TRY(residual_norm(a, a.first_parts, &tot.final_r, nullptr));
+      result = tot.final_r <= tol ? DI_OK : DI_E_NOCONV;
+      if (result != DI_OK)
+        set_error(h.done == 2 ? "max_cycles reached before the tolerance"
+                              : "refinement stalled above the tolerance");
+      break;
+    }
+    DI_HIP(launch_reset_ctl(a));
+  }
+  DI_HIP(hipEventRecord(ws->events[1], stream));
+  DI_HIP(hipEventSynchronize(ws->events[1]));
+  float ms = 0.f;
+  DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
+  rt.seconds = ms * 1e-3;
+  fill_stats(g, tot, d, (int)sizeof(T), a.direction, rt, refinements, &tmp);
   if (st) *st = tmp;
-  return status_from_done(rt.state.done);
+  return result;
 }
 
 di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double d, double tol,
@@ -327,7 +434,7 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
       }
   }
   DeviceScope scope(g->device);
-  const int prec = o.precision == DI_FP64 ? kF64 : kF32;
+  const int prec = o.precision == DI_FP64 ? kF64 : kF32;  // FP32 and FP32 + FP64 refinement
   di_status ast = DI_OK;
   Workspace* ws = acquire(g, prec, &ast);
   if (ast != DI_OK) return ast;
@@ -396,11 +503,14 @@ di_status cycles_dev(const di_graph* gc, double d, int32_t method, double* F_dev
   a.ws = ws;
   a.d = d;
   a.tol = -1.0;  // no stop test: exactly `cycles` cycles
+  a.tol_in = -1.0;
+  a.tol_rel = -1.0;
   a.method = method;
   a.stop = DI_STOP_RESID;
   a.max_cycles = cycles;
   a.direction = kPull;
   a.stream = stream;
+  a.first_parts = part_count(a) + 1;
   DI_TRY(ensure_events(ws, 2));
   DI_HIP(launch_reset_ctl(a));
   if (e_inout)
@@ -415,9 +525,37 @@ di_status cycles_dev(const di_graph* gc, double d, int32_t method, double* F_dev
   if (stats) {
     di_stats tmp;
     std::memset(&tmp, 0, sizeof(tmp));
-    fill_stats(g, h, d, 8, a.direction, rt, &tmp);
+    fill_stats(g, h, d, 8, a.direction, rt, 0, &tmp);
     *stats = tmp;
   }
+  return DI_OK;
+}
+
+di_status residual_dev(const di_graph* gc, const double* B_dev, double d, const double* X_dev,
+                       double* R_dev, double* l1_out, void* stream_v) {
+  if (!gc || !X_dev || !(d > 0.0 && d < 1.0)) {
+    set_error("di_residual_dev: invalid argument");
+    return DI_E_INVAL;
+  }
+  di_graph* g = const_cast<di_graph*>(gc);
+  DeviceScope scope(g->device);
+  di_status ast = DI_OK;
+  Workspace* ws = acquire(g, kF64, &ast);
+  if (ast != DI_OK) return ast;
+  PoolGuard guard{g, ws};
+  DI_TRY(ensure_refine_buffers(g, ws));
+  CycleArgs a{};
+  a.g = g;
+  a.ws = ws;
+  a.d = d;
+  a.direction = kPull;
+  a.stream = (hipStream_t)stream_v;
+  double* R = R_dev ? R_dev : (double*)ws->F;
+  DI_HIP(launch_refine<double>(a, const_cast<double*>(X_dev), (double*)nullptr, B_dev,
+                               (1.0 - d) / (double)g->n, R));
+  double l1 = 0.0;
+  DI_TRY(residual_norm(a, pull_grid(g) + 1, &l1, nullptr));
+  if (l1_out) *l1_out = l1;
   return DI_OK;
 }
 
@@ -441,6 +579,11 @@ di_status di_cycles_dev(const di_graph* g, double d, int32_t method, double* F_d
                         int32_t cycles, double* e_inout, void* stream, di_stats* stats) {
   return di::guarded(
       [&] { return di::cycles_dev(g, d, method, F_dev, H_dev, cycles, e_inout, stream, stats); });
+}
+
+di_status di_residual_dev(const di_graph* g, const double* B_dev, double d, const double* X_dev,
+                          double* R_dev, double* l1, void* stream) {
+  return di::guarded([&] { return di::residual_dev(g, B_dev, d, X_dev, R_dev, l1, stream); });
 }
 
 }  // extern "C"

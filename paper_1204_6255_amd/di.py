@@ -104,6 +104,8 @@ def lib():
     L.di_solve_dev.restype = i32
     L.di_cycles_dev.argtypes = [vp, dbl, i32, vp, vp, i32, P(dbl), vp, P(di_stats)]
     L.di_cycles_dev.restype = i32
+    L.di_residual_dev.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
+    L.di_residual_dev.restype = i32
     L.di_last_error.argtypes = []
     L.di_last_error.restype = ctypes.c_char_p
     L.di_version.argtypes = []
@@ -206,6 +208,16 @@ def di_cycles_dev(h, d: float, method: int, F_dev, H_dev, cycles: int, e: float 
                                  ctypes.byref(e_c), stream if stream is not None else _current_stream(),
                                  ctypes.byref(st))
     return status, e_c.value, st
+
+
+def di_residual_dev(h, B_dev, d: float, X_dev, R_dev=None, stream=None):
+    """FP64 residual R = B + P.X - X on the device (R_dev may be None).
+    Returns (status, |R|_1)."""
+    l1 = ctypes.c_double(0.0)
+    status = lib().di_residual_dev(h, _ptr(B_dev), float(d), _ptr(X_dev), _ptr(R_dev),
+                                   ctypes.byref(l1),
+                                   stream if stream is not None else _current_stream())
+    return status, l1.value
 
 
 class Graph:
