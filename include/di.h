@@ -177,6 +177,38 @@ di_status di_cycles_dev(const di_graph* g, double d, int32_t method, double* F_d
                         double* H_dev, int32_t cycles, double* e_inout, void* stream,
                         di_stats* stats);
 
+/* Solves k systems X_c = P.X_c + B_c (c < k) on one graph together, e.g.
+ * a batch of personalized PageRank vectors: every cycle applies the DI-SOP
+ * rule of Section 2.5.5 to each column with that column's own
+ * r = sum_i |F_ic| (and claims, diffuses and counts per column), and one
+ * set of launches moves all columns; a column stops when its residual is
+ * within its tolerance while the others go on.
+ *   B: k x n doubles (host), right-hand side c at B + c*n, all finite;
+ *      NULL means (1-d)/n in every column.
+ *   tol: k doubles (host), each > 0: column c stops when
+ *      |B_c + P.X_c - X_c|_1 <= tol[c].
+ *   X: k x n doubles (host), caller-allocated; column c at X + c*n.
+ *   opts: method DI_SOP or DI_CYC; precision DI_FP64, DI_FP32, or
+ *      DI_FP32_REFINE (FP32 fluid with FP64 residual passes, as di_opts
+ *      describes, per column); stop DI_STOP_RESID only; kernel AUTO or
+ *      PULL; max_cycles counts each column's cycles.
+ *   stats: NULL or k entries; entry c describes column c, except seconds,
+ *      move_seconds, bytes_moved and move_bytes, which cover the batch.
+ * Columns run in launch groups of at most 256. A group of k columns holds
+ * 3 arrays of n*KP fluid values (KP = k rounded up to a power of two,
+ * at least 8), plus 3 arrays of n*KP doubles with DI_FP32_REFINE.
+ * Returns DI_E_NOCONV (X and stats still filled) when a column reached
+ * max_cycles, DI_E_INVAL when a column's fluid became non-finite. */
+di_status di_solve_batch(const di_graph* g, int32_t k, const double* B, double d,
+                         const double* tol, const di_opts* opts, double* X, di_stats* stats);
+
+/* As di_solve_batch with B and X in device memory (k x n doubles each; B may
+ * be NULL); tol and stats stay on the host. Work is queued on opts->stream
+ * and the call returns once it has finished. */
+di_status di_solve_batch_dev(const di_graph* g, int32_t k, const double* B_dev, double d,
+                             const double* tol, const di_opts* opts, double* X_dev,
+                             di_stats* stats);
+
 /* The FP64 residual R = B + P.X - X of an approximate solution X, and
  * |R|_1 (the refinement step of DI_FP32_REFINE, which recomputes the fluid
  * of Section 2.2 as F = B - (I - P).X). B_dev: n doubles on the device, or

@@ -15,14 +15,14 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 
-HIP_SOURCES = ["di_kernels.hip", "di_graph.cpp", "di_solve.cpp"]
+HIP_SOURCES = ["di_kernels.hip", "di_graph.cpp", "di_solve.cpp", "di_batch.hip", "di_batch.cpp"]
 ARCH = "gfx950"
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 arithmetic.
 # -munsafe-fp-atomics: float/double atomicAdd become hardware atomics (the
 # graph buffers come from hipMalloc, which is coarse-grained memory).
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-shared",
     "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

@@ -316,6 +316,8 @@ void di_graph_destroy(di_graph* g) {
     std::lock_guard<std::mutex> lock(g->mu);
     for (di::Workspace* ws : g->pool) di::free_workspace(ws);
     g->pool.clear();
+    for (di::BatchWs* ws : g->bpool) di::free_batch_ws(ws);
+    g->bpool.clear();
   }
   free_graph_device(g);
   if (cur != g->device) (void)hipSetDevice(cur);

@@ -90,6 +90,9 @@ struct Part {
 
 enum Prec { kF64 = 0, kF32 = 1 };
 
+struct BatchWs;
+void free_batch_ws(BatchWs* ws);
+
 // Buffers of one solve; pooled per graph so repeated solves do not allocate.
 struct Workspace {
   int prec = kF64;
@@ -154,6 +157,7 @@ struct di_graph {
   int64_t* hc_off = nullptr;
   std::mutex mu;
   std::vector<di::Workspace*> pool;
+  std::vector<di::BatchWs*> bpool;  // batched solves (di_batch.h)
 };
 
 namespace di {

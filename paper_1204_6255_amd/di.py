@@ -106,6 +106,10 @@ def lib():
     L.di_cycles_dev.restype = i32
     L.di_residual_dev.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
     L.di_residual_dev.restype = i32
+    L.di_solve_batch.argtypes = [vp, i32, vp, dbl, vp, P(di_opts), vp, P(di_stats)]
+    L.di_solve_batch.restype = i32
+    L.di_solve_batch_dev.argtypes = [vp, i32, vp, dbl, vp, P(di_opts), vp, P(di_stats)]
+    L.di_solve_batch_dev.restype = i32
     L.di_last_error.argtypes = []
     L.di_last_error.restype = ctypes.c_char_p
     L.di_version.argtypes = []
@@ -218,6 +222,50 @@ def di_residual_dev(h, B_dev, d: float, X_dev, R_dev=None, stream=None):
                                    ctypes.byref(l1),
                                    stream if stream is not None else _current_stream())
     return status, l1.value
+
+
+def di_solve_batch(h, k: int, B, d: float, tol, opts=None, X=None):
+    """k right-hand sides at once (host arrays). B: (k, n) float64 or None;
+    tol: k values. Returns (status, X (k, n), [di_stats] * k)."""
+    tol = _tol_array(tol, k)
+    n = _graph_n(h)
+    if B is not None and k > 0:
+        B = np.ascontiguousarray(B, dtype=np.float64).reshape(k, n)
+    if X is None:
+        X = np.empty((max(k, 1), n), np.float64)
+    stats = (di_stats * max(k, 1))()
+    status = lib().di_solve_batch(h, int(k), _ptr(B), float(d), tol.ctypes.data,
+                                  ctypes.byref(opts) if opts is not None else None,
+                                  X.ctypes.data, stats)
+    return status, X, list(stats)
+
+
+def di_solve_batch_dev(h, k: int, B_dev, d: float, tol, opts=None, X_dev=None):
+    """Device variant (torch tensors of shape (k, n), float64; B_dev may be
+    None). opts.stream defaults to the current stream. Returns (status,
+    [di_stats] * k)."""
+    tol = _tol_array(tol, k)
+    if opts is None:
+        opts = di_opts_default()
+    if not opts.stream:
+        opts.stream = _current_stream().value
+    stats = (di_stats * max(k, 1))()
+    status = lib().di_solve_batch_dev(h, int(k), _ptr(B_dev), float(d), tol.ctypes.data,
+                                      ctypes.byref(opts), _ptr(X_dev), stats)
+    return status, list(stats)
+
+
+def _tol_array(tol, k: int):
+    t = np.ascontiguousarray(np.asarray(tol, np.float64).ravel())
+    if t.size == 1 and k > 1:
+        t = np.full(k, t[0])
+    return t
+
+
+def _graph_n(h) -> int:
+    n = ctypes.c_int64()
+    _check(lib().di_graph_info(h, ctypes.byref(n), None, None, None))
+    return n.value
 
 
 class Graph:
