@@ -49,7 +49,7 @@ extern "C" {
 
 typedef enum di_status {
   DI_OK = 0,
-  DI_PENDING = 1,      /* (reserved for asynchronous calls) */
+  DI_PENDING = 1,      /* the request is still running (di_serve_poll) */
   DI_E_INVAL = -1,     /* bad argument (null pointer, d outside (0,1), ...) */
   DI_E_UNSORTED = -2,  /* links not sorted by (origin, destination) */
   DI_E_DUP = -3,       /* the same link listed twice */
@@ -58,7 +58,7 @@ typedef enum di_status {
   DI_E_NOCONV = -6,    /* max_cycles reached before the tolerance */
   DI_E_DEVICE = -7,    /* no usable GPU, or a HIP call failed */
   DI_E_BUSY = -8,      /* (reserved) */
-  DI_E_NOTFOUND = -9   /* (reserved) */
+  DI_E_NOTFOUND = -9   /* unknown graph id or ticket (serving) */
 } di_status;
 
 /* di_opts.method */
@@ -208,6 +208,63 @@ di_status di_solve_batch(const di_graph* g, int32_t k, const double* B, double d
 di_status di_solve_batch_dev(const di_graph* g, int32_t k, const double* B_dev, double d,
                              const double* tol, const di_opts* opts, double* X_dev,
                              di_stats* stats);
+
+/* ---- serving ------------------------------------------------------------
+ * A server answers personalized PageRank requests (one right-hand side
+ * B = (1-d)/|S| on a seed set S, or the uniform (1-d)/n) on resident graphs
+ * with continuous batching: a worker thread keeps one batch of KP columns
+ * (k_max rounded up to a power of two, at least 8) per graph with work,
+ * starts waiting requests in columns as they free up, and finishes each
+ * request when its own residual is within its tolerance, as in
+ * di_solve_batch. A graph's batch is allocated when the graph first has
+ * work and the HBM budget allows it; idle batches of other graphs are
+ * released to make room; a request that cannot be placed waits (an
+ * admission stall). Requests with another d wait until their graph's batch
+ * has drained. Every di_serve_* call is thread-safe. */
+typedef struct di_server di_server;
+
+typedef struct di_serve_stats {
+  int64_t submitted;        /* requests accepted */
+  int64_t completed;        /* requests finished (collected or not) */
+  int64_t admission_stalls; /* times a graph's requests found no HBM room */
+  int64_t active;           /* columns in use now */
+  int64_t pending;          /* requests waiting for a column */
+  int64_t bytes_in_use;     /* device bytes held by batches */
+  double busy_seconds;      /* worker time spent on work */
+} di_serve_stats;
+
+/* Creates a server that may hold up to hbm_budget_bytes of batch buffers,
+ * with k_max in [1, 256] columns per graph. opts (may be NULL: DI-SOP,
+ * DI_FP32_REFINE) gives method, precision, max_cycles and inner_tol;
+ * stop must be DI_STOP_RESID and kernel AUTO or PULL. The device current
+ * at the call is used. */
+di_status di_serve_create(size_t hbm_budget_bytes, int32_t k_max, const di_opts* opts,
+                          di_server** out);
+
+/* Registers graph g under graph_id (unique). g must outlive the server.
+ * DI_E_NOMEM if the graph's batch alone exceeds the budget. */
+di_status di_serve_add_graph(di_server* s, const di_graph* g, int32_t graph_id);
+
+/* Queues a request: seeds (host, nseeds ids in [0, n), duplicates ignored;
+ * nseeds = 0 means the uniform right-hand side), d in (0, 1), tol > 0.
+ * *ticket receives its ticket. DI_E_NOTFOUND for an unknown graph_id,
+ * DI_E_RANGE for a seed outside [0, n). */
+di_status di_serve_submit(di_server* s, int32_t graph_id, int32_t nseeds, const int32_t* seeds,
+                          double d, double tol, uint64_t* ticket);
+
+/* DI_PENDING while the request runs. Once it has finished: copies X (host,
+ * n doubles; may be NULL) and stats (may be NULL; seconds = time from
+ * submission to completion), forgets the ticket and returns the request's
+ * status (DI_OK, DI_E_NOCONV with X filled, ...). DI_E_NOTFOUND for a
+ * ticket never issued or already collected. */
+di_status di_serve_poll(di_server* s, uint64_t ticket, double* X, di_stats* stats);
+
+/* Counters of the server. */
+di_status di_serve_info(di_server* s, di_serve_stats* out);
+
+/* Stops the worker (running requests are dropped) and frees the server.
+ * NULL is ignored. */
+void di_serve_destroy(di_server* s);
 
 /* The FP64 residual R = B + P.X - X of an approximate solution X, and
  * |R|_1 (the refinement step of DI_FP32_REFINE, which recomputes the fluid

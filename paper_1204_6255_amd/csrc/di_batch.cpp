@@ -87,6 +87,25 @@ di_status alloc_batch(const di_graph* g, int kp, int prec, bool refine, BatchWs*
   return DI_OK;
 }
 
+}  // namespace
+
+di_status batch_ws_create(const di_graph* g, int kp, int prec, bool refine, BatchWs** out) {
+  return alloc_batch(g, kp, prec, refine, out);
+}
+
+size_t batch_ws_bytes(const di_graph* g, int kp, int prec, bool refine) {
+  const size_t n = (size_t)g->n, K = (size_t)kp;
+  const size_t s = prec == kF64 ? 8 : 4;
+  const size_t sgrid = (size_t)bselect_grid(g->n);
+  size_t b = 3 * n * K * s + ((n + 63) / 64) * 8 + (size_t)nrec_needed(g) * K * 8 +
+             sgrid * (K + 1) * 12 + sgrid * K * 8 + (size_t)std::max<int64_t>(g->n_segs, 1) * K * 8 +
+             (K + 1) * sizeof(BCtl);
+  if (refine) b += 3 * n * K * 8;
+  return b;
+}
+
+namespace {
+
 BatchWs* acquire_batch(di_graph* g, int kp, int prec, bool refine, di_status* st) {
   {
     std::lock_guard<std::mutex> lock(g->mu);

@@ -104,4 +104,25 @@ hipError_t launch_brefine(const BatchArgs& a, BatchWs* ws, int* nrec);
 // X_out (k x n) = H (+ X64 when refined)
 hipError_t launch_bstore(const BatchArgs& a, BatchWs* ws, double* X_out, int k, bool refined);
 
+// Starting columns of a running batch (device arrays): flag[KP] marks the
+// columns to clear (b_uni[c]: their uniform right-hand side value, 0 for
+// seed lists); entry j < ncols starts column col[j] with value val[j] at
+// seeds[off[j] .. off[j+1]) and tolerance tol[j].
+struct ColInit {
+  int ncols;
+  const int* flag;
+  const double* b_uni;
+  const int* col;
+  const int64_t* off;
+  const int32_t* seeds;
+  const double* val;
+  const double* tol;
+};
+hipError_t launch_bcol_init(const BatchArgs& a, BatchWs* ws, const ColInit& ci);
+// X_out (n doubles, device) = column c of H (+ X64 when refined)
+hipError_t launch_bcol_out(const BatchArgs& a, BatchWs* ws, int c, bool refined, double* X_out);
+// allocation and pooling of batch workspaces (di_batch.cpp)
+di_status batch_ws_create(const di_graph* g, int kp, int prec, bool refine, BatchWs** out);
+size_t batch_ws_bytes(const di_graph* g, int kp, int prec, bool refine);
+
 }  // namespace di

@@ -744,6 +744,101 @@ __global__ __launch_bounds__(kBBlock) void k_bcount(BCtl* __restrict__ bctl,
   }
 }
 
+// ---- serving: columns started and read out one by one -------------------
+
+// Clears the columns with flag[c] != 0 in every row: F = B, Bd = B (B = 0,
+// or b_uni[c] for a column whose right-hand side is uniform), H = 0,
+// X64 = 0.
+template <typename T, int KP>
+__global__ __launch_bounds__(kBBlock) void k_bcol_clear(T* __restrict__ F, T* __restrict__ H,
+                                                        double* __restrict__ Bd,
+                                                        double* __restrict__ X64, int64_t n,
+                                                        const int* __restrict__ flag,
+                                                        const double* __restrict__ b_uni) {
+  using Ly = Lay<KP>;
+  constexpr int V = Ly::V;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / Ly::G, gl = lane % Ly::G;
+  bool m[V];
+  double bu[V];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    m[v] = flag[gl * V + v] != 0;
+    bu[v] = m[v] ? b_uni[gl * V + v] : 0.0;
+    any |= m[v];
+  }
+  if (!any) return;
+  const int64_t stride = (int64_t)gridDim.x * Ly::NG;
+  for (int64_t i = (int64_t)blockIdx.x * Ly::NG + wave * Ly::P + grp; i < n; i += stride) {
+    const int64_t q = i * KP + gl * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      if (m[v]) {
+        F[q + v] = (T)bu[v];
+        H[q + v] = (T)0;
+        if (Bd) Bd[q + v] = bu[v];
+        if (X64) X64[q + v] = 0.0;
+      }
+    }
+  }
+}
+
+// Block j starts column col[j]: B = val[j] at its seeds
+// seeds[off[j] .. off[j+1]) (or the uniform value written by k_bcol_clear
+// when the list is empty), r = sum |F| in FP64, and a fresh control block
+// (running, or converged when r <= tol[j]).
+template <typename T, int KP>
+__global__ __launch_bounds__(kBBlock) void k_bcol_seed(
+    T* __restrict__ F, double* __restrict__ Bd, BCtl* __restrict__ bctl, int64_t n,
+    const int* __restrict__ col, const int64_t* __restrict__ off, const int32_t* __restrict__ seeds,
+    const double* __restrict__ val, const double* __restrict__ tol, int method) {
+  __shared__ double lds[kBBlock / 64];
+  const int j = blockIdx.x, c = col[j];
+  const int64_t s0 = off[j], s1 = off[j + 1];
+  double r = 0.0;
+  if (s1 > s0) {
+    const T v = (T)val[j];
+    for (int64_t q = s0 + threadIdx.x; q < s1; q += kBBlock) {
+      const int64_t i = seeds[q];
+      F[i * KP + c] = v;
+      if (Bd) Bd[i * KP + c] = val[j];
+      r += fabs(to_d(v));
+    }
+  }
+  r = block_sum_all(r, lds);
+  if (threadIdx.x == 0) {
+    if (s1 == s0) r = (double)n * fabs(to_d((T)val[j]));
+    BCtl b;
+    b.r = r;
+    b.r_start = r;
+    b.final_r = r;
+    b.tol = tol[j];
+    b.e = 0.0;
+    b.edges = 0;
+    b.sel_total = 0;
+    b.cycles = 0;
+    b.pass_cycles = 0;
+    b.refinements = 0;
+    b.fallback = 0;
+    b.cyc_mode = method == DI_CYC ? 1 : 0;
+    b.state = !isfinite(r) ? kBNonFinite : (r <= b.tol ? kBConv : kBRun);
+    bctl[c] = b;
+  }
+}
+
+// X_out[i] = H[i][c] (+ X64[i][c]): one column read out.
+template <typename T, int KP>
+__global__ void k_bcol_out(const T* __restrict__ H, const double* __restrict__ X64, int c,
+                           int64_t n, double* __restrict__ X_out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double x = to_d(H[i * KP + c]);
+    if (X64) x += X64[i * KP + c];
+    X_out[i] = x;
+  }
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <typename T, int KP>
@@ -864,6 +959,27 @@ hipError_t bstore_t(const BatchArgs& a, BatchWs* ws, double* X_out, int k, bool 
   return hipGetLastError();
 }
 
+template <typename T, int KP>
+hipError_t bcol_init_t(const BatchArgs& a, BatchWs* ws, const ColInit& ci) {
+  using Ly = Lay<KP>;
+  const int grid = (int)std::min<int64_t>(ceil_div(a.g->n, Ly::NG), 4096);
+  hipLaunchKernelGGL((k_bcol_clear<T, KP>), dim3(grid), dim3(kBBlock), 0, a.stream, (T*)ws->F,
+                     (T*)ws->H, ws->Bd, ws->X64, a.g->n, ci.flag, ci.b_uni);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_bcol_seed<T, KP>), dim3(ci.ncols), dim3(kBBlock), 0, a.stream, (T*)ws->F,
+                     ws->Bd, ws->bctl, a.g->n, ci.col, ci.off, ci.seeds, ci.val, ci.tol, a.method);
+  return hipGetLastError();
+}
+
+template <typename T, int KP>
+hipError_t bcol_out_t(const BatchArgs& a, BatchWs* ws, int c, bool refined, double* X_out) {
+  hipLaunchKernelGGL((k_bcol_out<T, KP>), dim3((unsigned)std::min<int64_t>(ceil_div(a.g->n, 256), 4096)),
+                     dim3(256), 0, a.stream, (const T*)ws->H,
+                     refined ? (const double*)ws->X64 : (const double*)nullptr, c, a.g->n, X_out);
+  return hipGetLastError();
+}
+
 // Calls f.template operator()<T, KP>() for the batch's shape.
 template <typename Fn>
 hipError_t dispatch(const BatchArgs& a, Fn&& f) {
@@ -924,6 +1040,14 @@ hipError_t launch_bfirst(const BatchArgs& a, BatchWs* ws, int nrec, int want) {
 
 hipError_t launch_brefine(const BatchArgs& a, BatchWs* ws, int* nrec) {
   return dispatch(a, [&]<typename T, int KP>() { return brefine_t<T, KP>(a, ws, nrec); });
+}
+
+hipError_t launch_bcol_init(const BatchArgs& a, BatchWs* ws, const ColInit& ci) {
+  return dispatch(a, [&]<typename T, int KP>() { return bcol_init_t<T, KP>(a, ws, ci); });
+}
+
+hipError_t launch_bcol_out(const BatchArgs& a, BatchWs* ws, int c, bool refined, double* X_out) {
+  return dispatch(a, [&]<typename T, int KP>() { return bcol_out_t<T, KP>(a, ws, c, refined, X_out); });
 }
 
 hipError_t launch_bstore(const BatchArgs& a, BatchWs* ws, double* X_out, int k, bool refined) {

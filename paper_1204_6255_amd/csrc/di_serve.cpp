@@ -1,0 +1,605 @@
+// libdi serving loop: personalized PageRank requests on resident graphs,
+// continuously batched.
+//
+// Each graph with work holds one batch workspace (a "slot set" of KP
+// columns, di_batch.h). A worker thread cycles over the graphs: it starts
+// waiting requests in free columns of the running batch (the other columns
+// keep their state: the columns of a batch are independent solves), runs a
+// chunk of cycles, gives the columns whose FP32 pass ended their FP64
+// residual pass, and reads out the columns that finished, which frees them
+// for the next requests. A slot set is allocated when its graph first gets
+// work and the HBM budget allows it; idle slot sets of other graphs are
+// released to make room, and a request that cannot be placed waits (an
+// admission stall).
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "di_batch.h"
+
+namespace di {
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  uint64_t ticket;
+  std::vector<int32_t> seeds;  // sorted, unique; empty = uniform B
+  double d;
+  double tol;
+  double t_submit;
+};
+
+struct Result {
+  di_status status = DI_PENDING;
+  std::vector<double> X;
+  di_stats stats{};
+};
+
+struct Lane {
+  uint64_t ticket = 0;  // 0: free
+  double t_submit = 0.0;
+};
+
+struct GraphSlot {
+  const di_graph* g = nullptr;
+  int32_t id = 0;
+  std::deque<Request> pending;
+  BatchWs* ws = nullptr;
+  size_t ws_bytes = 0;
+  double d = 0.85;
+  std::vector<Lane> lanes;
+  int active = 0;
+  double* out_dev = nullptr;  // one column read out (n doubles)
+  bool stalled = false;       // counted once per stall episode
+};
+
+}  // namespace
+}  // namespace di
+
+struct di_server {
+  std::mutex mu;
+  std::condition_variable cv;
+  bool stop = false;
+  size_t budget = 0;
+  size_t in_use = 0;
+  int kp = 8;
+  di_opts opts{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::map<int32_t, di::GraphSlot*> graphs;
+  std::unordered_map<uint64_t, di::Result> results;
+  uint64_t next_ticket = 1;
+  int64_t submitted = 0, completed = 0, stalls = 0;
+  double busy_seconds = 0.0;
+  std::string worker_error;
+  std::thread worker;
+  // device staging for starting columns
+  int* d_flag = nullptr;
+  double* d_buni = nullptr;
+  int* d_col = nullptr;
+  int64_t* d_off = nullptr;
+  double* d_val = nullptr;
+  double* d_tol = nullptr;
+  int32_t* d_seeds = nullptr;
+  size_t seeds_cap = 0;
+};
+
+namespace di {
+namespace {
+
+bool refine_of(const di_server* s) { return s->opts.precision == DI_FP32_REFINE; }
+int prec_of(const di_server* s) { return s->opts.precision == DI_FP64 ? kF64 : kF32; }
+
+BatchArgs args_of(const di_server* s, const GraphSlot* gs) {
+  BatchArgs a{};
+  a.g = gs->g;
+  a.kp = s->kp;
+  a.prec = prec_of(s);
+  a.d = gs->d;
+  a.method = s->opts.method;
+  a.max_cycles = s->opts.max_cycles > 0 ? s->opts.max_cycles : 100000;
+  a.tol_rel = refine_of(s) ? (s->opts.inner_tol > 0.0 ? s->opts.inner_tol : 1e-5) : -1.0;
+  a.stream = s->stream;
+  return a;
+}
+
+size_t slot_bytes(const di_server* s, const di_graph* g) {
+  return batch_ws_bytes(g, s->kp, prec_of(s), refine_of(s)) + (size_t)g->n * sizeof(double);
+}
+
+// Under s->mu: makes room for gs's slot set (releasing idle slot sets of
+// other graphs); true when the bytes are reserved.
+bool reserve_slot(di_server* s, GraphSlot* gs, std::vector<GraphSlot*>* to_free) {
+  const size_t need = slot_bytes(s, gs->g);
+  if (s->in_use + need > s->budget) {
+    for (auto& kv : s->graphs) {
+      GraphSlot* o = kv.second;
+      if (o == gs || !o->ws || o->active > 0 || !o->pending.empty()) continue;
+      to_free->push_back(o);
+      s->in_use -= o->ws_bytes;  // released below, outside the lock
+      if (s->in_use + need <= s->budget) break;
+    }
+  }
+  if (s->in_use + need > s->budget) return false;
+  s->in_use += need;
+  gs->ws_bytes = need;
+  return true;
+}
+
+di_status create_slot_ws(di_server* s, GraphSlot* gs) {
+  const BatchArgs a = args_of(s, gs);
+  BatchWs* ws = nullptr;
+  DI_TRY(batch_ws_create(gs->g, s->kp, a.prec, refine_of(s), &ws));
+  gs->ws = ws;
+  hipError_t err = hipMalloc((void**)&gs->out_dev, (size_t)gs->g->n * sizeof(double));
+  if (err != hipSuccess) {
+    gs->out_dev = nullptr;
+    set_error(std::string("hipMalloc: ") + hipGetErrorString(err));
+    return DI_E_NOMEM;
+  }
+  for (int c = 0; c <= s->kp; ++c) {
+    BCtl b;
+    std::memset(&b, 0, sizeof(b));
+    b.state = kBIdle;
+    ws->host_bctl[c] = b;
+  }
+  DI_HIP(hipMemcpyAsync(ws->bctl, ws->host_bctl, (size_t)(s->kp + 1) * sizeof(BCtl),
+                        hipMemcpyHostToDevice, s->stream));
+  gs->lanes.assign((size_t)s->kp, Lane{});
+  return DI_OK;
+}
+
+di_status ensure_seed_staging(di_server* s, size_t count) {
+  if (count <= s->seeds_cap) return DI_OK;
+  if (s->d_seeds) (void)hipFree(s->d_seeds);
+  s->d_seeds = nullptr;
+  const size_t cap = std::max<size_t>(count, 4096);
+  hipError_t err = hipMalloc((void**)&s->d_seeds, cap * sizeof(int32_t));
+  if (err != hipSuccess) {
+    s->seeds_cap = 0;
+    set_error(std::string("hipMalloc: ") + hipGetErrorString(err));
+    return DI_E_NOMEM;
+  }
+  s->seeds_cap = cap;
+  return DI_OK;
+}
+
+// Starts the requests in free columns of gs's slot set.
+di_status start_requests(di_server* s, GraphSlot* gs, std::vector<Request>& reqs) {
+  const BatchArgs a = args_of(s, gs);
+  const int kp = s->kp;
+  std::vector<int> flag((size_t)kp, 0), col;
+  std::vector<double> buni((size_t)kp, 0.0), val, tol;
+  std::vector<int64_t> off{0};
+  std::vector<int32_t> seeds;
+  int c = 0;
+  for (Request& r : reqs) {
+    while (gs->lanes[(size_t)c].ticket != 0) ++c;
+    gs->lanes[(size_t)c] = Lane{r.ticket, r.t_submit};
+    flag[(size_t)c] = 1;
+    col.push_back(c);
+    const double v = r.seeds.empty() ? (1.0 - r.d) / (double)gs->g->n
+                                     : (1.0 - r.d) / (double)r.seeds.size();
+    if (r.seeds.empty()) buni[(size_t)c] = v;
+    val.push_back(v);
+    tol.push_back(r.tol);
+    seeds.insert(seeds.end(), r.seeds.begin(), r.seeds.end());
+    off.push_back((int64_t)seeds.size());
+  }
+  DI_TRY(ensure_seed_staging(s, seeds.size()));
+  const int nc = (int)col.size();
+  DI_HIP(hipMemcpyAsync(s->d_flag, flag.data(), (size_t)kp * sizeof(int), hipMemcpyHostToDevice, s->stream));
+  DI_HIP(hipMemcpyAsync(s->d_buni, buni.data(), (size_t)kp * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  DI_HIP(hipMemcpyAsync(s->d_col, col.data(), (size_t)nc * sizeof(int), hipMemcpyHostToDevice, s->stream));
+  DI_HIP(hipMemcpyAsync(s->d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s->stream));
+  DI_HIP(hipMemcpyAsync(s->d_val, val.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  DI_HIP(hipMemcpyAsync(s->d_tol, tol.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  if (!seeds.empty())
+    DI_HIP(hipMemcpyAsync(s->d_seeds, seeds.data(), seeds.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s->stream));
+  ColInit ci{nc, s->d_flag, s->d_buni, s->d_col, s->d_off, s->d_seeds, s->d_val, s->d_tol};
+  DI_HIP(launch_bcol_init(a, gs->ws, ci));
+  // the host copies are pageable: wait before they go out of scope
+  DI_HIP(hipStreamSynchronize(s->stream));
+  return DI_OK;
+}
+
+// Reads out the finished columns and completes their tickets.
+di_status finish_columns(di_server* s, GraphSlot* gs) {
+  const BatchArgs a = args_of(s, gs);
+  BatchWs* ws = gs->ws;
+  const di_graph* g = gs->g;
+  for (int c = 0; c < s->kp; ++c) {
+    Lane& ln = gs->lanes[(size_t)c];
+    const BCtl& b = ws->host_bctl[c];
+    if (ln.ticket == 0 || !(b.state == kBConv || b.state == kBMaxCyc || b.state == kBNonFinite))
+      continue;
+    Result res;
+    res.status = b.state == kBConv ? DI_OK : (b.state == kBMaxCyc ? DI_E_NOCONV : DI_E_INVAL);
+    res.X.resize((size_t)g->n);
+    DI_HIP(launch_bcol_out(a, ws, c, refine_of(s), gs->out_dev));
+    DI_HIP(hipMemcpyAsync(res.X.data(), gs->out_dev, (size_t)g->n * sizeof(double),
+                          hipMemcpyDeviceToHost, s->stream));
+    // the column is free again
+    BCtl idle = b;
+    idle.state = kBIdle;
+    ws->host_bctl[c] = idle;
+    DI_HIP(hipMemcpyAsync(ws->bctl + c, &ws->host_bctl[c], sizeof(BCtl), hipMemcpyHostToDevice,
+                          s->stream));
+    DI_HIP(hipStreamSynchronize(s->stream));
+    di_stats& t = res.stats;
+    std::memset(&t, 0, sizeof(t));
+    t.cycles = b.cycles;
+    t.fallback_cycles = b.fallback;
+    t.refinements = b.refinements;
+    t.edges_pushed = (int64_t)b.edges;
+    t.nb_iter = g->L > 0 ? (double)b.edges / (double)g->L : 0.0;
+    t.resid_l1 = b.final_r;
+    t.err_bound = b.final_r / (1.0 - gs->d);
+    t.e = b.e;
+    t.seconds = now_s() - ln.t_submit;  // latency: submission to completion
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->results[ln.ticket] = std::move(res);
+      s->completed += 1;
+      gs->active -= 1;
+    }
+    ln = Lane{};
+  }
+  return DI_OK;
+}
+
+// Cycles cycles on gs's running columns, with their residual passes.
+di_status run_slot(di_server* s, GraphSlot* gs) {
+  const BatchArgs a = args_of(s, gs);
+  BatchWs* ws = gs->ws;
+  const int kp = s->kp;
+  auto read_ctl = [&]() -> di_status {
+    DI_HIP(hipMemcpyAsync(ws->host_bctl, ws->bctl, (size_t)(kp + 1) * sizeof(BCtl),
+                          hipMemcpyDeviceToHost, s->stream));
+    DI_HIP(hipStreamSynchronize(s->stream));
+    return DI_OK;
+  };
+  DI_TRY(read_ctl());
+  int need = 2;
+  bool running = false;
+  for (int c = 0; c < kp; ++c) {
+    const BCtl& b = ws->host_bctl[c];
+    if (b.state != kBRun) continue;
+    running = true;
+    int nc = 16;
+    const double target = a.tol_rel >= 0.0 ? std::max(0.5 * b.tol, a.tol_rel * b.r_start) : b.tol;
+    if (b.pass_cycles >= 1 && b.r > 0.0 && b.r < b.r_start && target > 0.0) {
+      const double rate = std::log(b.r / b.r_start) / (double)b.pass_cycles;
+      const double est = std::log(target / b.r) / rate;
+      if (std::isfinite(est)) nc = (int)std::ceil(est) + 1;
+    }
+    need = std::max(need, nc);
+  }
+  if (running) {
+    // short chunks keep new requests waiting little
+    const int chunk = std::max(2, std::min(need, 16));
+    for (int q = 0; q < chunk; ++q) DI_HIP(launch_bcycle(a, ws, nullptr, nullptr));
+    DI_TRY(read_ctl());
+  }
+  for (;;) {
+    bool inner = false;
+    for (int c = 0; c < kp; ++c) inner |= ws->host_bctl[c].state == kBInner;
+    if (!inner) break;
+    int nrec = 0;
+    DI_HIP(launch_brefine(a, ws, &nrec));
+    DI_HIP(launch_bfirst(a, ws, nrec, kBInner));
+    DI_TRY(read_ctl());
+  }
+  return finish_columns(s, gs);
+}
+
+void fail_all(di_server* s, di_status st, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->worker_error = msg;
+  for (auto& kv : s->graphs) {
+    GraphSlot* gs = kv.second;
+    for (Lane& ln : gs->lanes)
+      if (ln.ticket) {
+        s->results[ln.ticket].status = st;
+        ln = Lane{};
+      }
+    for (Request& r : gs->pending) s->results[r.ticket].status = st;
+    gs->pending.clear();
+    gs->active = 0;
+  }
+}
+
+void worker_loop(di_server* s) {
+  (void)hipSetDevice(s->device);
+  for (;;) {
+    std::vector<GraphSlot*> work;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] {
+        if (s->stop) return true;
+        for (auto& kv : s->graphs)
+          if (kv.second->active > 0 || !kv.second->pending.empty()) return true;
+        return false;
+      });
+      if (s->stop) return;
+      for (auto& kv : s->graphs)
+        if (kv.second->active > 0 || !kv.second->pending.empty()) work.push_back(kv.second);
+    }
+    const double t0 = now_s();
+    for (GraphSlot* gs : work) {
+      std::vector<Request> admit;
+      std::vector<GraphSlot*> to_free;
+      bool need_ws = false;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!gs->pending.empty()) {
+          if (!gs->ws) {
+            if (reserve_slot(s, gs, &to_free)) {
+              need_ws = true;
+              gs->stalled = false;
+            } else if (!gs->stalled) {
+              s->stalls += 1;
+              gs->stalled = true;
+            }
+          }
+          if (gs->ws || need_ws) {
+            if (gs->active == 0) gs->d = gs->pending.front().d;
+            int free_lanes = s->kp - gs->active;
+            while (free_lanes > 0 && !gs->pending.empty() && gs->pending.front().d == gs->d) {
+              admit.push_back(std::move(gs->pending.front()));
+              gs->pending.pop_front();
+              --free_lanes;
+            }
+            gs->active += (int)admit.size();  // columns taken (started below)
+          }
+        }
+      }
+      di_status st = DI_OK;
+      for (GraphSlot* o : to_free) {
+        if (o->ws) free_batch_ws(o->ws);
+        if (o->out_dev) (void)hipFree(o->out_dev);
+        o->ws = nullptr;
+        o->out_dev = nullptr;
+        o->ws_bytes = 0;
+      }
+      if (need_ws) st = create_slot_ws(s, gs);
+      if (st == DI_OK && !admit.empty()) st = start_requests(s, gs, admit);
+      if (st == DI_OK && gs->ws && gs->active > 0) st = run_slot(s, gs);
+      if (st != DI_OK) {
+        fail_all(s, st, "serving worker: " + std::string(di_last_error()));
+        break;
+      }
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->busy_seconds += now_s() - t0;
+  }
+}
+
+template <typename Fn>
+di_status guarded_s(Fn&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DI_E_NOMEM;
+  } catch (...) {
+    set_error("unexpected exception");
+    return DI_E_INVAL;
+  }
+}
+
+di_status serve_create(size_t budget, int32_t k_max, const di_opts* opts, di_server** out) {
+  if (!out) {
+    set_error("di_serve_create: out is NULL");
+    return DI_E_INVAL;
+  }
+  *out = nullptr;
+  if (k_max < 1 || k_max > kBatchMaxKP) {
+    set_error("k_max must lie in [1, 256]");
+    return DI_E_INVAL;
+  }
+  di_opts o;
+  di_opts_default(&o);
+  if (opts) o = *opts;
+  if (!opts) o.precision = DI_FP32_REFINE;
+  if (o.method != DI_SOP && o.method != DI_CYC) {
+    set_error("unknown method");
+    return DI_E_INVAL;
+  }
+  if (o.precision != DI_FP64 && o.precision != DI_FP32 && o.precision != DI_FP32_REFINE) {
+    set_error("unknown precision");
+    return DI_E_INVAL;
+  }
+  if (o.stop != DI_STOP_RESID || o.kernel == DI_KERNEL_PUSH) {
+    set_error("serving stops on the residual and moves fluid by the pull kernel only");
+    return DI_E_INVAL;
+  }
+  int dev = 0;
+  DI_TRY(check_device(&dev));
+  di_server* s = new (std::nothrow) di_server;
+  if (!s) return DI_E_NOMEM;
+  s->budget = budget;
+  int kp = 8;
+  while (kp < k_max) kp <<= 1;
+  s->kp = kp;
+  s->opts = o;
+  s->device = dev;
+  hipError_t err = hipStreamCreate(&s->stream);
+  if (err == hipSuccess) err = hipMalloc((void**)&s->d_flag, (size_t)kp * sizeof(int));
+  if (err == hipSuccess) err = hipMalloc((void**)&s->d_buni, (size_t)kp * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc((void**)&s->d_col, (size_t)kp * sizeof(int));
+  if (err == hipSuccess) err = hipMalloc((void**)&s->d_off, (size_t)(kp + 1) * sizeof(int64_t));
+  if (err == hipSuccess) err = hipMalloc((void**)&s->d_val, (size_t)kp * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc((void**)&s->d_tol, (size_t)kp * sizeof(double));
+  if (err != hipSuccess) {
+    set_error(std::string("di_serve_create: ") + hipGetErrorString(err));
+    di_serve_destroy(s);
+    return DI_E_DEVICE;
+  }
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return DI_OK;
+}
+
+}  // namespace
+}  // namespace di
+
+extern "C" {
+
+di_status di_serve_create(size_t hbm_budget_bytes, int32_t k_max, const di_opts* opts,
+                          di_server** out) {
+  return di::guarded_s([&] { return di::serve_create(hbm_budget_bytes, k_max, opts, out); });
+}
+
+di_status di_serve_add_graph(di_server* s, const di_graph* g, int32_t graph_id) {
+  return di::guarded_s([&]() -> di_status {
+    if (!s || !g) {
+      di::set_error("di_serve_add_graph: NULL argument");
+      return DI_E_INVAL;
+    }
+    if (di::slot_bytes(s, g) > s->budget) {
+      di::set_error("the graph's slot set alone exceeds the HBM budget");
+      return DI_E_NOMEM;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->graphs.count(graph_id)) {
+      di::set_error("graph_id already registered");
+      return DI_E_INVAL;
+    }
+    di::GraphSlot* gs = new di::GraphSlot;
+    gs->g = g;
+    gs->id = graph_id;
+    s->graphs[graph_id] = gs;
+    return DI_OK;
+  });
+}
+
+di_status di_serve_submit(di_server* s, int32_t graph_id, int32_t nseeds, const int32_t* seeds,
+                          double d, double tol, uint64_t* ticket) {
+  return di::guarded_s([&]() -> di_status {
+    if (!s || !ticket || nseeds < 0 || (nseeds > 0 && !seeds)) {
+      di::set_error("di_serve_submit: invalid argument");
+      return DI_E_INVAL;
+    }
+    if (!(d > 0.0 && d < 1.0) || !(tol > 0.0)) {
+      di::set_error("d must lie in (0, 1) and tol must be > 0");
+      return DI_E_INVAL;
+    }
+    di::Request r;
+    r.seeds.assign(seeds, seeds + nseeds);
+    std::sort(r.seeds.begin(), r.seeds.end());
+    r.seeds.erase(std::unique(r.seeds.begin(), r.seeds.end()), r.seeds.end());
+    r.d = d;
+    r.tol = tol;
+    r.t_submit = di::now_s();
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->graphs.find(graph_id);
+    if (it == s->graphs.end()) {
+      di::set_error("unknown graph_id");
+      return DI_E_NOTFOUND;
+    }
+    if (!s->worker_error.empty()) {
+      di::set_error(s->worker_error);
+      return DI_E_DEVICE;
+    }
+    const int64_t n = it->second->g->n;
+    if (!r.seeds.empty() && (r.seeds.front() < 0 || r.seeds.back() >= n)) {
+      di::set_error("seed id outside [0, n)");
+      return DI_E_RANGE;
+    }
+    r.ticket = s->next_ticket++;
+    *ticket = r.ticket;
+    s->results[r.ticket].status = DI_PENDING;
+    it->second->pending.push_back(std::move(r));
+    s->submitted += 1;
+    s->cv.notify_all();
+    return DI_OK;
+  });
+}
+
+di_status di_serve_poll(di_server* s, uint64_t ticket, double* X, di_stats* stats) {
+  return di::guarded_s([&]() -> di_status {
+    if (!s) {
+      di::set_error("di_serve_poll: server is NULL");
+      return DI_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) {
+      di::set_error("unknown ticket (never issued, or already collected)");
+      return DI_E_NOTFOUND;
+    }
+    di::Result& r = it->second;
+    if (r.status == DI_PENDING) return DI_PENDING;
+    const di_status st = r.status;
+    if (X && !r.X.empty()) std::memcpy(X, r.X.data(), r.X.size() * sizeof(double));
+    if (stats) *stats = r.stats;
+    if (st != DI_OK) di::set_error(st == DI_E_NOCONV ? "max_cycles reached before the tolerance"
+                                                    : "the request failed: " + s->worker_error);
+    s->results.erase(it);
+    return st;
+  });
+}
+
+di_status di_serve_info(di_server* s, di_serve_stats* out) {
+  if (!s || !out) {
+    di::set_error("di_serve_info: NULL argument");
+    return DI_E_INVAL;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->admission_stalls = s->stalls;
+  int64_t active = 0, pending = 0;
+  for (auto& kv : s->graphs) {
+    active += kv.second->active;
+    pending += (int64_t)kv.second->pending.size();
+  }
+  out->active = active;
+  out->pending = pending;
+  out->bytes_in_use = (int64_t)s->in_use;
+  out->busy_seconds = s->busy_seconds;
+  return DI_OK;
+}
+
+void di_serve_destroy(di_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != s->device) (void)hipSetDevice(s->device);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  for (auto& kv : s->graphs) {
+    di::GraphSlot* gs = kv.second;
+    if (gs->ws) di::free_batch_ws(gs->ws);
+    if (gs->out_dev) (void)hipFree(gs->out_dev);
+    delete gs;
+  }
+  void* ptrs[] = {s->d_flag, s->d_buni, s->d_col, s->d_off, s->d_val, s->d_tol, s->d_seeds};
+  for (void* p : ptrs) (void)hipFree(p);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (cur != s->device) (void)hipSetDevice(cur);
+  delete s;
+}
+
+}  // extern "C"

@@ -69,6 +69,21 @@ class di_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class di_serve_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("admission_stalls", ctypes.c_int64),
+        ("active", ctypes.c_int64),
+        ("pending", ctypes.c_int64),
+        ("bytes_in_use", ctypes.c_int64),
+        ("busy_seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class DIError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -106,6 +121,18 @@ def lib():
     L.di_cycles_dev.restype = i32
     L.di_residual_dev.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
     L.di_residual_dev.restype = i32
+    L.di_serve_create.argtypes = [ctypes.c_size_t, i32, P(di_opts), P(vp)]
+    L.di_serve_create.restype = i32
+    L.di_serve_add_graph.argtypes = [vp, vp, i32]
+    L.di_serve_add_graph.restype = i32
+    L.di_serve_submit.argtypes = [vp, i32, i32, vp, dbl, dbl, P(ctypes.c_uint64)]
+    L.di_serve_submit.restype = i32
+    L.di_serve_poll.argtypes = [vp, ctypes.c_uint64, vp, P(di_stats)]
+    L.di_serve_poll.restype = i32
+    L.di_serve_info.argtypes = [vp, P(di_serve_stats)]
+    L.di_serve_info.restype = i32
+    L.di_serve_destroy.argtypes = [vp]
+    L.di_serve_destroy.restype = None
     L.di_solve_batch.argtypes = [vp, i32, vp, dbl, vp, P(di_opts), vp, P(di_stats)]
     L.di_solve_batch.restype = i32
     L.di_solve_batch_dev.argtypes = [vp, i32, vp, dbl, vp, P(di_opts), vp, P(di_stats)]
@@ -253,6 +280,45 @@ def di_solve_batch_dev(h, k: int, B_dev, d: float, tol, opts=None, X_dev=None):
     status = lib().di_solve_batch_dev(h, int(k), _ptr(B_dev), float(d), tol.ctypes.data,
                                       ctypes.byref(opts), _ptr(X_dev), stats)
     return status, list(stats)
+
+
+def di_serve_create(hbm_budget_bytes: int, k_max: int, opts=None):
+    """Returns (status, server handle)."""
+    h = ctypes.c_void_p()
+    status = lib().di_serve_create(int(hbm_budget_bytes), int(k_max),
+                                   ctypes.byref(opts) if opts is not None else None, ctypes.byref(h))
+    return status, h
+
+
+def di_serve_add_graph(s, g, graph_id: int) -> int:
+    return lib().di_serve_add_graph(s, g, int(graph_id))
+
+
+def di_serve_submit(s, graph_id: int, seeds, d: float, tol: float):
+    """seeds: int32 ids (empty or None = uniform B). Returns (status, ticket)."""
+    seeds = np.ascontiguousarray(np.asarray([] if seeds is None else seeds, dtype=np.int32))
+    t = ctypes.c_uint64(0)
+    status = lib().di_serve_submit(s, int(graph_id), int(seeds.size),
+                                   seeds.ctypes.data if seeds.size else None, float(d), float(tol),
+                                   ctypes.byref(t))
+    return status, t.value
+
+
+def di_serve_poll(s, ticket: int, X=None):
+    """X: float64 host array of n values (or None). Returns (status, stats)."""
+    st = di_stats()
+    status = lib().di_serve_poll(s, ctypes.c_uint64(ticket), _ptr(X), ctypes.byref(st))
+    return status, st
+
+
+def di_serve_info(s):
+    out = di_serve_stats()
+    status = lib().di_serve_info(s, ctypes.byref(out))
+    return status, out
+
+
+def di_serve_destroy(s) -> None:
+    lib().di_serve_destroy(s)
 
 
 def _tol_array(tol, k: int):

@@ -78,3 +78,20 @@ def test_valid_graph_without_gpu_reports_device_error():
     st, h = di.di_graph_create(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32))
     assert st == di.DI_E_DEVICE
     assert "no CPU fallback" in di.di_last_error()
+
+
+def test_serving_struct_layout():
+    assert ctypes.sizeof(di.di_serve_stats) == 6 * 8 + 8
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-GPU path")
+def test_serving_without_gpu_reports_device_error():
+    st, h = di.di_serve_create(1 << 30, 8)
+    assert st == di.DI_E_DEVICE and not h.value
+    st, _ = di.di_serve_create(1 << 30, 0)
+    assert st == di.DI_E_INVAL
+
+
+def test_batch_rejects_bad_arguments_before_device_work():
+    st, _, _ = di.di_solve_batch(None, 2, None, 0.85, [1e-9, 1e-9])
+    assert st == di.DI_E_INVAL
