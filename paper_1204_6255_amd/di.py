@@ -255,7 +255,7 @@ def di_solve_batch(h, k: int, B, d: float, tol, opts=None, X=None):
     """k right-hand sides at once (host arrays). B: (k, n) float64 or None;
     tol: k values. Returns (status, X (k, n), [di_stats] * k)."""
     tol = _tol_array(tol, k)
-    n = _graph_n(h)
+    n = _graph_n(h) if h else 0
     if B is not None and k > 0:
         B = np.ascontiguousarray(B, dtype=np.float64).reshape(k, n)
     if X is None:
