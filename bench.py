@@ -14,7 +14,21 @@ same steps (events add stream packets, so they stay out of `value`). The
 cpu_baseline object times the CPU oracle (sequential DI-SOP, one thread)
 on the same graph.
 
+The same line also reports, on the same graph unless stated:
+  fp32_refine   the same solve with FP32 fluid and FP64 residual passes;
+  batched_ppr   personalized PageRank batches (k = 8, 64, 256 seed sets of
+                1..100 nodes, tol 1e-9 each, FP32 + FP64 refinement, one
+                batch per call): solves/s, against single FP64 solves of the
+                same right-hand sides;
+  serving       32 graphs with N log-uniform in [1e4, 5e6] (seeds 1..32);
+                requests pick a graph uniformly, a seed set of 1..100 nodes
+                and tol 1e-6 or 1e-9 (50/50); closed loop with 1024
+                requests in flight gives the saturated rate mu, then Poisson
+                arrivals at 0.5 mu and 0.8 mu: solves/s, p50 / p99 latency
+                (submission to completion), admission stalls.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
+                       [--no-extras] [--serve-seconds S]
 """
 
 from __future__ import annotations
@@ -46,6 +60,11 @@ def parse_args():
     p.add_argument("--kernel", choices=["auto", "pull", "push"], default="auto")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the CPU-oracle sample (0 disables it)")
+    p.add_argument("--no-extras", action="store_true",
+                   help="headline solve only (no FP32, batched or serving sections)")
+    p.add_argument("--serve-seconds", type=float, default=6.0,
+                   help="length of each serving phase")
+    p.add_argument("--serve-kmax", type=int, default=16)
     p.add_argument("--calibration-copy", action="store_true",
                    help="after the timed region, copy 256 MiB once (a plain copy of known size "
                         "for scaling memory counters)")
@@ -93,6 +112,162 @@ def cpu_baseline(n, src, dst, d, tol, budget_s):
         "sample": f"{len(times)} full solves of the same N={n} graph to sum|F| <= {tol:g} "
                   f"(sequential DI-SOP, one thread, FP64)",
     }
+
+
+def time_solves(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [fn() for _ in range(reps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out[-1]
+
+
+def fp32_refine_section(di, g, X, d, tol):
+    o = di.di_opts_default()
+    o.precision = di.DI_FP32_REFINE
+
+    def solve():
+        status, st = di.di_solve_dev(g.handle, None, d, tol, o, X)
+        if status != di.DI_OK:
+            raise RuntimeError(di.di_last_error())
+        return st
+
+    sec, st = time_solves(solve, 10)
+    return {"s_per_solve": sec, "cycles": int(st.cycles), "refinements": int(st.refinements),
+            "resid_l1": float(st.resid_l1)}
+
+
+def batched_section(di, graphgen, g, n, d, tol):
+    import numpy as np
+    import torch
+    out = {"precision": "fp32+fp64 refinement", "tol": tol, "seed_sets": "1..100 nodes, seed 1000+j"}
+    # single FP64 solves of the first right-hand side, for comparison
+    B0 = torch.from_numpy(graphgen.ppr_rhs(n, graphgen.ppr_seed_sets(n, 1)[0], d)).cuda()
+    X = torch.empty(n, dtype=torch.float64, device="cuda")
+    o64 = di.di_opts_default()
+
+    def single():
+        status, st = di.di_solve_dev(g.handle, B0, d, tol, o64, X)
+        if status != di.DI_OK:
+            raise RuntimeError(di.di_last_error())
+        return st
+
+    sec1, _ = time_solves(single, 5)
+    out["single_fp64_solves_per_s"] = 1.0 / sec1
+    runs = []
+    for k in (8, 64, 256):
+        B = np.stack([graphgen.ppr_rhs(n, s, d) for s in graphgen.ppr_seed_sets(n, k)])
+        Bd = torch.from_numpy(B).cuda()
+        Xd = torch.empty((k, n), dtype=torch.float64, device="cuda")
+        o = di.di_opts_default()
+        o.precision = di.DI_FP32_REFINE
+
+        def batch():
+            status, st = di.di_solve_batch_dev(g.handle, k, Bd, d, tol, o, Xd)
+            if status != di.DI_OK:
+                raise RuntimeError(di.di_last_error())
+            return st
+
+        sec, st = time_solves(batch, 2)
+        runs.append({"k": k, "s_per_batch": sec, "solves_per_s": k / sec,
+                     "vs_single_fp64": (k / sec) * sec1,
+                     "max_cycles": max(x.cycles for x in st),
+                     "max_resid_l1": max(x.resid_l1 for x in st)})
+        del Bd, Xd
+        torch.cuda.empty_cache()
+    out["runs"] = runs
+    return out
+
+
+def serving_section(di, graphgen, d, seconds, kmax):
+    import numpy as np
+    ng = 32
+    Ns = [int(round(np.exp(np.random.default_rng(gid).uniform(np.log(1e4), np.log(5e6)))))
+          for gid in range(1, ng + 1)]
+    graphs = []
+    for gid, n in enumerate(Ns, 1):
+        s, t = graphgen.web_graph(n, seed=gid)
+        graphs.append(di.Graph(n, s, t))
+    status, srv = di.di_serve_create(200 << 30, kmax)
+    if status != di.DI_OK:
+        raise RuntimeError(di.di_last_error())
+    for gid, G in enumerate(graphs):
+        di.di_serve_add_graph(srv, G.handle, gid)
+    bufs = [np.empty(n) for n in Ns]
+
+    def request(i):
+        r = np.random.default_rng(1_000_000 + i)
+        gid = int(r.integers(0, ng))
+        size = int(r.integers(1, 101))
+        seeds = r.choice(Ns[gid], size=size, replace=False).astype(np.int32)
+        return gid, seeds, (1e-6 if r.random() < 0.5 else 1e-9)
+
+    counter = [0]
+
+    def submit(inflight):
+        gid, seeds, tol = request(counter[0])
+        counter[0] += 1
+        st, tk = di.di_serve_submit(srv, gid, seeds, d, tol)
+        if st != di.DI_OK:
+            raise RuntimeError(di.di_last_error())
+        inflight[tk] = gid
+
+    def reap(inflight, lat):
+        for tk in list(inflight):
+            st, sts = di.di_serve_poll(srv, tk, bufs[inflight[tk]])
+            if st != di.DI_PENDING:
+                if st != di.DI_OK:
+                    raise RuntimeError(di.di_last_error())
+                del inflight[tk]
+                lat.append(sts.seconds)
+
+    def drain(inflight):
+        while inflight:
+            reap(inflight, [])
+            time.sleep(0.001)
+
+    # closed loop: 1024 requests in flight
+    inflight, lat = {}, []
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        while len(inflight) < 1024:
+            submit(inflight)
+        reap(inflight, lat)
+        time.sleep(0.0005)
+    el = time.perf_counter() - t0
+    mu = len(lat) / el
+    closed = {"in_flight": 1024, "solves_per_s": mu, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+              "p99_ms": 1e3 * float(np.percentile(lat, 99)), "requests": len(lat)}
+    drain(inflight)
+    poisson = []
+    for frac in (0.5, 0.8):
+        lam = frac * mu
+        nreq = int(min(10000, lam * seconds))
+        arr = np.cumsum(np.random.default_rng(int(frac * 10)).exponential(1.0 / lam, nreq))
+        inflight, lat = {}, []
+        t0 = time.perf_counter()
+        q = 0
+        while q < nreq or inflight:
+            now = time.perf_counter() - t0
+            while q < nreq and arr[q] <= now:
+                submit(inflight)
+                q += 1
+            reap(inflight, lat)
+            time.sleep(0.0002)
+        el = time.perf_counter() - t0
+        poisson.append({"lambda_per_s": lam, "requests": nreq, "solves_per_s": nreq / el,
+                        "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                        "p99_ms": 1e3 * float(np.percentile(lat, 99))})
+    _, info = di.di_serve_info(srv)
+    di.di_serve_destroy(srv)
+    for G in graphs:
+        G.close()
+    return {"graphs": ng, "total_nodes": int(sum(Ns)), "k_max": kmax,
+            "precision": "fp32+fp64 refinement", "closed_loop": closed, "poisson": poisson,
+            "admission_stalls": int(info.admission_stalls),
+            "hbm_bytes_in_use": int(info.bytes_in_use)}
 
 
 def main():
@@ -197,6 +372,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
     line["hbm_frac"] = line["roofline"]["frac"]
+    if not args.no_extras:
+        line["fp32_refine"] = fp32_refine_section(di, g, X, d, tol)
+        line["batched_ppr"] = batched_section(di, graphgen, g, n, d, tol)
+        line["serving"] = serving_section(di, graphgen, d, args.serve_seconds, args.serve_kmax)
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(n, src, dst, d, tol, args.cpu_seconds)
     else:
