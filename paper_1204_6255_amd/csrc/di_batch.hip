@@ -3,7 +3,7 @@
 //
 // Each column is an independent DI-SOP solve (Sections 2.3 and 2.5.5) with
 // its own r = sum_i |F_ic|, tolerance and pass state; the columns share the
-// graph and the launches. A cycle is four launches:
+// graph and the launches. A cycle is three launches:
 //   select  per (node, column): the DI-SOP rule against the column's r;
 //           claim (H += transit, F = 0); the node's amounts per link go to
 //           sent[node][*] (0 in the columns that did not select it), and the
@@ -14,8 +14,12 @@
 //           of the block take equal shares of the links and add the senders'
 //           rows of KP values; rows cut by a share boundary are finished in
 //           a fixed order. Per-block sums of |F| per column are written.
-//   heavy   rows split into segments: the segment sums in order.
-//   reduce  one block per column: the stop test and the next state.
+//   reduce  one block per column: completes the rows split into segments
+//           (the segment sums in order), then the stop test and the next
+//           state.
+// Lanes whose columns are all idle load and store nothing, and the serving
+// loop fills the lowest free columns first, so a batch with few running
+// columns touches few cache lines per node.
 // The residual pass of a refined solve (FP64: R = B + P.X - X) runs through
 // the same pull and heavy kernels with y = d X / out as the senders' rows,
 // for the columns waiting for it.
@@ -250,67 +254,84 @@ __global__ __launch_bounds__(kBBlock) void k_bselect(
   }
   unsigned long long fops = 0;
   unsigned int fnodes = 0;
-  const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+  bool lane_run = false;  // a lane whose columns are all idle loads nothing
+#pragma unroll
+  for (int v = 0; v < V; ++v) lane_run |= run[v];
+  const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull);
+  constexpr int NT = 64 / P;          // passes per 64-node word
+  constexpr int NB = NT < 4 ? NT : 4;  // passes whose loads are issued together
   const int64_t words = (n + 63) / 64;
   for (int64_t w = (int64_t)blockIdx.x * Ly::NW + wave; w < words;
        w += (int64_t)gridDim.x * Ly::NW) {
     unsigned long long word = 0;
-    for (int t = 0; t < 64 / P; ++t) {
-      const int64_t i = w * 64 + t * P + grp;
-      bool lane_front = false;
-      int np = 0;
-      Pack<T, V> s = zero_pack<T, V>();
-      if (i < n) {
-        const uint32_t wi = info[i];
-        const int out = (int)(wi & kOutMask);
-        const bool loop = (wi & kLoopBit) != 0;
-        np = out - (loop ? 1 : 0);
-        T* Fi = F + i * KP + gl * V;
-        Pack<T, V> f = ld<T, V>(Fi);
-        double tr[V];
-        bool any_sel = false;
+    for (int t0 = 0; t0 < NT; t0 += NB) {
+      uint32_t wis[NB];
+      Pack<T, V> fs[NB];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          tr[v] = 0.0;
-          const double fv = to_d(f.v[v]);
-          const double a = fabs(fv);
-          const double thr = (cyc[v] || out == 0) ? 0.0 : rl[v] * (double)out;
-          if (run[v] && a > 0.0 && a >= thr) {
-            tr[v] = loop ? fv * (double)out / ((double)out - d) : fv;
-            f.v[v] = (T)0;
-            any_sel = true;
-            ++sel[v];
-            if (out == 0) {
-              eab[v] += tr[v];
-            } else if (np > 0) {
-              s.v[v] = (T)(tr[v] * d / (double)out);
-              ops[v] += (unsigned long long)np;
-              lane_front = true;
+      for (int u = 0; u < NB; ++u) {
+        const int64_t i = w * 64 + (t0 + u) * P + grp;
+        wis[u] = i < n ? info[i] : 0u;
+        fs[u] = (i < n && lane_run) ? ld<T, V>(F + i * KP + gl * V) : zero_pack<T, V>();
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int t = t0 + u;
+        const int64_t i = w * 64 + t * P + grp;
+        bool lane_front = false;
+        int np = 0;
+        Pack<T, V> sv = zero_pack<T, V>();
+        if (i < n) {
+          const uint32_t wi = wis[u];
+          const int out = (int)(wi & kOutMask);
+          const bool loop = (wi & kLoopBit) != 0;
+          np = out - (loop ? 1 : 0);
+          Pack<T, V> f = fs[u];
+          double tr[V];
+          bool any_sel = false;
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            tr[v] = 0.0;
+            const double fv = to_d(f.v[v]);
+            const double a = fabs(fv);
+            const double thr = (cyc[v] || out == 0) ? 0.0 : rl[v] * (double)out;
+            if (run[v] && a > 0.0 && a >= thr) {
+              tr[v] = loop ? fv * (double)out / ((double)out - d) : fv;
+              f.v[v] = (T)0;
+              any_sel = true;
+              ++sel[v];
+              if (out == 0) {
+                eab[v] += tr[v];
+              } else if (np > 0) {
+                sv.v[v] = (T)(tr[v] * d / (double)out);
+                ops[v] += (unsigned long long)np;
+                lane_front = true;
+              }
             }
           }
-        }
-        if (any_sel) {
-          st<T, V>(Fi, f);
-          T* Hi = H + i * KP + gl * V;
-          Pack<T, V> h = ld<T, V>(Hi);
+          if (any_sel) {
+            st<T, V>(F + i * KP + gl * V, f);
+            T* Hi = H + i * KP + gl * V;
+            Pack<T, V> h = ld<T, V>(Hi);
 #pragma unroll
-          for (int v = 0; v < V; ++v)
-            if (tr[v] != 0.0) h.v[v] = (T)(to_d(h.v[v]) + tr[v]);
-          st<T, V>(Hi, h);
+            for (int v = 0; v < V; ++v)
+              if (tr[v] != 0.0) h.v[v] = (T)(to_d(h.v[v]) + tr[v]);
+            st<T, V>(Hi, h);
+          }
         }
-      }
-      const unsigned long long b = __ballot(lane_front);
-      const bool front = ((b >> (grp * G)) & gmask) != 0;
-      if (front) {
-        st<T, V>(sent + i * KP + gl * V, s);
-        if (gl == 0) {
-          fops += (unsigned long long)np;
-          ++fnodes;
+        const unsigned long long b = __ballot(lane_front);
+        const bool front = ((b >> (grp * G)) & gmask) != 0;
+        if (front) {
+          // the pull reads the sender rows of running columns only
+          if (lane_run) st<T, V>(sent + i * KP + gl * V, sv);
+          if (gl == 0) {
+            fops += (unsigned long long)np;
+            ++fnodes;
+          }
         }
-      }
 #pragma unroll
-      for (int g2 = 0; g2 < P; ++g2)
-        if ((b >> (g2 * G)) & gmask) word |= 1ull << (t * P + g2);
+        for (int g2 = 0; g2 < P; ++g2)
+          if ((b >> (g2 * G)) & gmask) word |= 1ull << (t * P + g2);
+      }
     }
     if (lane == 0) front_bits[w] = word;
   }
@@ -361,6 +382,10 @@ __device__ inline void row_epilogue(const PullIo<T, KP, MODE>& io, int64_t row, 
   constexpr int V = Lay<KP>::V;
   T* Fr = io.F + row * KP + gl * V;
   if (MODE == 0) {
+    bool anym = false;
+#pragma unroll
+    for (int v = 0; v < V; ++v) anym |= mask[v];
+    if (!anym) return;  // idle columns: no arrivals, no record needed
     Pack<T, V> f = ld<T, V>(Fr);
     bool ch = false;
 #pragma unroll
@@ -396,13 +421,18 @@ __device__ inline void row_epilogue(const PullIo<T, KP, MODE>& io, int64_t row, 
   }
 }
 
+// MODE 0 also adds the selection's node-level counters (column KP of
+// rec_ops / rec_sel, nsel rows) to entry KP of the control blocks (block 0),
+// once the selection is known to have run.
 template <typename T, int KP, int MODE>
 __global__ __launch_bounds__(kBBlock) void k_bpull(
     PullIo<T, KP, MODE> io, const int64_t* __restrict__ csc_ptr,
     const int32_t* __restrict__ csc_idx, const int64_t* __restrict__ it_r0,
     const int64_t* __restrict__ it_r1, const int64_t* __restrict__ it_l0,
     const int64_t* __restrict__ it_l1, const int32_t* __restrict__ it_seg, int64_t n_items,
-    double* __restrict__ segv, double* __restrict__ rec, const BCtl* __restrict__ bctl) {
+    double* __restrict__ segv, double* __restrict__ rec, BCtl* __restrict__ bctl,
+    const unsigned long long* __restrict__ rec_ops, const unsigned int* __restrict__ rec_sel,
+    int nsel) {
   using Ly = Lay<KP>;
   constexpr int G = Ly::G, P = Ly::P, V = Ly::V, NG = Ly::NG;
   constexpr int U = 4;  // gathers in flight per group
@@ -411,6 +441,7 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
   __shared__ int32_t s_ptr[kPullMaxRows + 1];
   __shared__ double s_part[NG * 2 * KP];
   __shared__ double s_rec[Ly::NW * KP];
+  __shared__ unsigned long long s_cnt[Ly::NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane / G, gl = lane % G;
   const int gid = wave * P + grp;
@@ -424,8 +455,26 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
   for (int c = tid; c < KP; c += kBBlock)
     any |= bctl[c].state == (MODE == 0 ? kBRun : kBInner) ? 1 : 0;
   if (!__syncthreads_or(any)) return;
+  if (MODE == 0 && blockIdx.x == 0) {
+    unsigned long long na = 0, nb = 0;
+    for (int q = tid; q < nsel; q += kBBlock) {
+      na += rec_ops[(int64_t)q * (KP + 1) + KP];
+      nb += rec_sel[(int64_t)q * (KP + 1) + KP];
+    }
+    na = block_sum_all(na, s_cnt);
+    nb = block_sum_all(nb, s_cnt);
+    if (tid == 0) {
+      bctl[KP].cycles += 1;
+      bctl[KP].edges += na;
+      bctl[KP].sel_total += nb;
+    }
+  }
+  bool lane_on = false;  // the lane has a column this pass works on
 #pragma unroll
-  for (int v = 0; v < V; ++v) mask[v] = bctl[gl * V + v].state == (MODE == 0 ? kBRun : kBInner);
+  for (int v = 0; v < V; ++v) {
+    mask[v] = bctl[gl * V + v].state == (MODE == 0 ? kBRun : kBInner);
+    lane_on |= mask[v];
+  }
   double rsum[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) rsum[v] = 0.0;
@@ -473,8 +522,8 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int src = q + u < q1 ? s_idx[q + u] : -1;
-          val[u] = src >= 0 ? ld<SrcT, V>(src_rows + (int64_t)src * KP + gl * V)
-                            : zero_pack<SrcT, V>();
+          val[u] = (src >= 0 && lane_on) ? ld<SrcT, V>(src_rows + (int64_t)src * KP + gl * V)
+                                         : zero_pack<SrcT, V>();
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -637,12 +686,15 @@ __global__ __launch_bounds__(kBBlock) void k_brefine_y(double* __restrict__ X64,
 // state `want` (kBFresh or kBInner) take r = the records' sum as the start
 // of a pass (converged if r <= tol). CYCLE: running columns fold the
 // cycle's records and selection counters.
-template <int KP, bool FIRST>
+// CYCLE also completes the column's heavy rows (F += the segment sums, in
+// segment order) and adds their |F| to the sum.
+template <typename T, int KP, bool FIRST>
 __global__ __launch_bounds__(kBBlock) void k_breduce(
     BCtl* __restrict__ bctl, const double* __restrict__ rec, int nrec,
     const unsigned long long* __restrict__ rec_ops, const unsigned int* __restrict__ rec_sel,
     const double* __restrict__ rec_e, int nsel, int method, int max_cycles, double tol_rel,
-    int want) {
+    int want, T* __restrict__ F, const int32_t* __restrict__ heavy_row,
+    const int64_t* __restrict__ heavy_seg, int64_t n_heavy, const double* __restrict__ segv) {
   __shared__ double s_d[kBBlock / 64];
   __shared__ unsigned long long s_u[kBBlock / 64];
   const int c = blockIdx.x, tid = threadIdx.x;
@@ -651,6 +703,20 @@ __global__ __launch_bounds__(kBBlock) void k_breduce(
   if (!mine) return;
   double r = 0.0;
   for (int q = tid; q < nrec; q += kBBlock) r += rec[(int64_t)q * KP + c];
+  if (!FIRST) {
+    for (int64_t h = tid; h < n_heavy; h += kBBlock) {
+      const int64_t qi = (int64_t)heavy_row[h] * KP + c;
+      double acc = 0.0;
+      for (int64_t q = heavy_seg[h]; q < heavy_seg[h + 1]; ++q) acc += segv[q * KP + c];
+      double f = to_d(F[qi]);
+      if (acc != 0.0) {
+        const T nv = (T)(f + acc);
+        F[qi] = nv;
+        f = to_d(nv);
+      }
+      r += fabs(f);
+    }
+  }
   r = block_sum_all(r, s_d);
   unsigned long long ops = 0, sel = 0;
   double e = 0.0;
@@ -716,32 +782,6 @@ __global__ __launch_bounds__(kBBlock) void k_breduce(
     }
   }
   bctl[c] = b;
-}
-
-// Node-level totals of a cycle (entry KP): runs after the selection, while
-// the column states are still the ones it saw; counts nothing when no
-// column was running (the selection then wrote no counters).
-template <int KP>
-__global__ __launch_bounds__(kBBlock) void k_bcount(BCtl* __restrict__ bctl,
-                                                    const unsigned long long* __restrict__ rec_ops,
-                                                    const unsigned int* __restrict__ rec_sel,
-                                                    int nsel) {
-  __shared__ unsigned long long s_u[kBBlock / 64];
-  int any = 0;
-  for (int q = threadIdx.x; q < KP; q += kBBlock) any |= bctl[q].state == kBRun ? 1 : 0;
-  if (!__syncthreads_or(any)) return;
-  unsigned long long a = 0, b = 0;
-  for (int q = threadIdx.x; q < nsel; q += kBBlock) {
-    a += rec_ops[(int64_t)q * (KP + 1) + KP];
-    b += rec_sel[(int64_t)q * (KP + 1) + KP];
-  }
-  a = block_sum_all(a, s_u);
-  b = block_sum_all(b, s_u);
-  if (threadIdx.x == 0) {
-    bctl[KP].cycles += 1;
-    bctl[KP].edges += a;
-    bctl[KP].sel_total += b;
-  }
 }
 
 // ---- serving: columns started and read out one by one -------------------
@@ -891,37 +931,30 @@ hipError_t bcycle_t(const BatchArgs& a, BatchWs* ws, hipEvent_t ev0, hipEvent_t 
                      (const BCtl*)ws->bctl, ws->rec_ops, ws->rec_sel, ws->rec_e);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_bcount<KP>), dim3(1), dim3(kBBlock), 0, a.stream, ws->bctl,
-                     (const unsigned long long*)ws->rec_ops, (const unsigned int*)ws->rec_sel,
-                     sgrid);
-  if ((err = hipGetLastError()) != hipSuccess) return err;
   if (ev0 && (err = hipEventRecord(ev0, a.stream)) != hipSuccess) return err;
   const int pgrid = pull_grid(g);
   hipLaunchKernelGGL((k_bpull<T, KP, 0>), dim3(pgrid), dim3(kBBlock), 0, a.stream,
                      fluid_io<T, KP>(a, ws), g->csc_ptr, g->csc_idx, g->it_r0, g->it_r1, g->it_l0,
-                     g->it_l1, g->it_seg, g->n_items, ws->segv, ws->rec, (const BCtl*)ws->bctl);
+                     g->it_l1, g->it_seg, g->n_items, ws->segv, ws->rec, ws->bctl,
+                     (const unsigned long long*)ws->rec_ops, (const unsigned int*)ws->rec_sel,
+                     sgrid);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   if (ev1 && (err = hipEventRecord(ev1, a.stream)) != hipSuccess) return err;
-  const int hgrid = bheavy_grid(g);
-  if (hgrid > 0) {
-    hipLaunchKernelGGL((k_bheavy<T, KP, 0>), dim3(hgrid), dim3(kBBlock), 0, a.stream,
-                       fluid_io<T, KP>(a, ws), g->heavy_row, g->heavy_seg, g->n_heavy,
-                       (const double*)ws->segv, ws->rec, pgrid, (const BCtl*)ws->bctl);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-  }
-  hipLaunchKernelGGL((k_breduce<KP, false>), dim3(KP), dim3(kBBlock), 0, a.stream, ws->bctl,
-                     (const double*)ws->rec, pgrid + hgrid, (const unsigned long long*)ws->rec_ops,
+  hipLaunchKernelGGL((k_breduce<T, KP, false>), dim3(KP), dim3(kBBlock), 0, a.stream, ws->bctl,
+                     (const double*)ws->rec, pgrid, (const unsigned long long*)ws->rec_ops,
                      (const unsigned int*)ws->rec_sel, (const double*)ws->rec_e, sgrid, a.method,
-                     a.max_cycles, a.tol_rel, (int)kBRun);
+                     a.max_cycles, a.tol_rel, (int)kBRun, (T*)ws->F, g->heavy_row, g->heavy_seg,
+                     g->n_heavy, (const double*)ws->segv);
   return hipGetLastError();
 }
 
-template <int KP>
+template <typename T, int KP>
 hipError_t bfirst_t(const BatchArgs& a, BatchWs* ws, int nrec, int want) {
-  hipLaunchKernelGGL((k_breduce<KP, true>), dim3(KP), dim3(kBBlock), 0, a.stream, ws->bctl,
+  hipLaunchKernelGGL((k_breduce<T, KP, true>), dim3(KP), dim3(kBBlock), 0, a.stream, ws->bctl,
                      (const double*)ws->rec, nrec, (const unsigned long long*)nullptr,
                      (const unsigned int*)nullptr, (const double*)nullptr, 0, a.method,
-                     a.max_cycles, a.tol_rel, want);
+                     a.max_cycles, a.tol_rel, want, (T*)nullptr, (const int32_t*)nullptr,
+                     (const int64_t*)nullptr, (int64_t)0, (const double*)nullptr);
   return hipGetLastError();
 }
 
@@ -937,8 +970,8 @@ hipError_t brefine_t(const BatchArgs& a, BatchWs* ws, int* nrec) {
   const int pgrid = pull_grid(g);
   hipLaunchKernelGGL((k_bpull<T, KP, 1>), dim3(pgrid), dim3(kBBlock), 0, a.stream,
                      residual_io<T, KP>(a, ws), g->csc_ptr, g->csc_idx, g->it_r0, g->it_r1,
-                     g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->segv, ws->rec,
-                     (const BCtl*)ws->bctl);
+                     g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->segv, ws->rec, ws->bctl,
+                     (const unsigned long long*)nullptr, (const unsigned int*)nullptr, 0);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   const int hgrid = bheavy_grid(g);
   if (hgrid > 0) {
@@ -1035,7 +1068,7 @@ hipError_t launch_bcycle(const BatchArgs& a, BatchWs* ws, hipEvent_t ev0, hipEve
 }
 
 hipError_t launch_bfirst(const BatchArgs& a, BatchWs* ws, int nrec, int want) {
-  return dispatch(a, [&]<typename T, int KP>() { return bfirst_t<KP>(a, ws, nrec, want); });
+  return dispatch(a, [&]<typename T, int KP>() { return bfirst_t<T, KP>(a, ws, nrec, want); });
 }
 
 hipError_t launch_brefine(const BatchArgs& a, BatchWs* ws, int* nrec) {

@@ -2,12 +2,14 @@
 // continuously batched.
 //
 // Each graph with work holds one batch workspace (a "slot set" of KP
-// columns, di_batch.h). A worker thread cycles over the graphs: it starts
-// waiting requests in free columns of the running batch (the other columns
-// keep their state: the columns of a batch are independent solves), runs a
-// chunk of cycles, gives the columns whose FP32 pass ended their FP64
-// residual pass, and reads out the columns that finished, which frees them
-// for the next requests. A slot set is allocated when its graph first gets
+// columns, di_batch.h) and its own HIP stream, so the graphs' kernels
+// overlap on the device. A worker thread moves every graph on its own:
+// when the work queued for a graph has finished, it reads out the columns
+// that finished (which frees them), starts waiting requests in free
+// columns (the other columns keep their state: the columns of a batch are
+// independent solves), and queues the residual passes its columns are
+// waiting for, the next chunk of cycles and the read-back of the column
+// states. A slot set is allocated when its graph first gets
 // work and the HBM budget allows it; idle slot sets of other graphs are
 // released to make room, and a request that cannot be placed waits (an
 // admission stall).
@@ -65,6 +67,9 @@ struct GraphSlot {
   int active = 0;
   double* out_dev = nullptr;  // one column read out (n doubles)
   bool stalled = false;       // counted once per stall episode
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;    // end of the graph's queued work
+  bool launched = false;
 };
 
 }  // namespace
@@ -79,7 +84,6 @@ struct di_server {
   int kp = 8;
   di_opts opts{};
   int device = 0;
-  hipStream_t stream = nullptr;
   std::map<int32_t, di::GraphSlot*> graphs;
   std::unordered_map<uint64_t, di::Result> results;
   uint64_t next_ticket = 1;
@@ -113,7 +117,7 @@ BatchArgs args_of(const di_server* s, const GraphSlot* gs) {
   a.method = s->opts.method;
   a.max_cycles = s->opts.max_cycles > 0 ? s->opts.max_cycles : 100000;
   a.tol_rel = refine_of(s) ? (s->opts.inner_tol > 0.0 ? s->opts.inner_tol : 1e-5) : -1.0;
-  a.stream = s->stream;
+  a.stream = gs->stream;
   return a;
 }
 
@@ -128,7 +132,7 @@ bool reserve_slot(di_server* s, GraphSlot* gs, std::vector<GraphSlot*>* to_free)
   if (s->in_use + need > s->budget) {
     for (auto& kv : s->graphs) {
       GraphSlot* o = kv.second;
-      if (o == gs || !o->ws || o->active > 0 || !o->pending.empty()) continue;
+      if (o == gs || !o->ws || o->launched || o->active > 0 || !o->pending.empty()) continue;
       to_free->push_back(o);
       s->in_use -= o->ws_bytes;  // released below, outside the lock
       if (s->in_use + need <= s->budget) break;
@@ -158,7 +162,7 @@ di_status create_slot_ws(di_server* s, GraphSlot* gs) {
     ws->host_bctl[c] = b;
   }
   DI_HIP(hipMemcpyAsync(ws->bctl, ws->host_bctl, (size_t)(s->kp + 1) * sizeof(BCtl),
-                        hipMemcpyHostToDevice, s->stream));
+                        hipMemcpyHostToDevice, gs->stream));
   gs->lanes.assign((size_t)s->kp, Lane{});
   return DI_OK;
 }
@@ -202,19 +206,19 @@ di_status start_requests(di_server* s, GraphSlot* gs, std::vector<Request>& reqs
   }
   DI_TRY(ensure_seed_staging(s, seeds.size()));
   const int nc = (int)col.size();
-  DI_HIP(hipMemcpyAsync(s->d_flag, flag.data(), (size_t)kp * sizeof(int), hipMemcpyHostToDevice, s->stream));
-  DI_HIP(hipMemcpyAsync(s->d_buni, buni.data(), (size_t)kp * sizeof(double), hipMemcpyHostToDevice, s->stream));
-  DI_HIP(hipMemcpyAsync(s->d_col, col.data(), (size_t)nc * sizeof(int), hipMemcpyHostToDevice, s->stream));
-  DI_HIP(hipMemcpyAsync(s->d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s->stream));
-  DI_HIP(hipMemcpyAsync(s->d_val, val.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
-  DI_HIP(hipMemcpyAsync(s->d_tol, tol.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
+  DI_HIP(hipMemcpyAsync(s->d_flag, flag.data(), (size_t)kp * sizeof(int), hipMemcpyHostToDevice, gs->stream));
+  DI_HIP(hipMemcpyAsync(s->d_buni, buni.data(), (size_t)kp * sizeof(double), hipMemcpyHostToDevice, gs->stream));
+  DI_HIP(hipMemcpyAsync(s->d_col, col.data(), (size_t)nc * sizeof(int), hipMemcpyHostToDevice, gs->stream));
+  DI_HIP(hipMemcpyAsync(s->d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, gs->stream));
+  DI_HIP(hipMemcpyAsync(s->d_val, val.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, gs->stream));
+  DI_HIP(hipMemcpyAsync(s->d_tol, tol.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, gs->stream));
   if (!seeds.empty())
     DI_HIP(hipMemcpyAsync(s->d_seeds, seeds.data(), seeds.size() * sizeof(int32_t),
-                          hipMemcpyHostToDevice, s->stream));
+                          hipMemcpyHostToDevice, gs->stream));
   ColInit ci{nc, s->d_flag, s->d_buni, s->d_col, s->d_off, s->d_seeds, s->d_val, s->d_tol};
   DI_HIP(launch_bcol_init(a, gs->ws, ci));
   // the host copies are pageable: wait before they go out of scope
-  DI_HIP(hipStreamSynchronize(s->stream));
+  DI_HIP(hipStreamSynchronize(gs->stream));
   return DI_OK;
 }
 
@@ -233,14 +237,14 @@ di_status finish_columns(di_server* s, GraphSlot* gs) {
     res.X.resize((size_t)g->n);
     DI_HIP(launch_bcol_out(a, ws, c, refine_of(s), gs->out_dev));
     DI_HIP(hipMemcpyAsync(res.X.data(), gs->out_dev, (size_t)g->n * sizeof(double),
-                          hipMemcpyDeviceToHost, s->stream));
+                          hipMemcpyDeviceToHost, gs->stream));
     // the column is free again
     BCtl idle = b;
     idle.state = kBIdle;
     ws->host_bctl[c] = idle;
     DI_HIP(hipMemcpyAsync(ws->bctl + c, &ws->host_bctl[c], sizeof(BCtl), hipMemcpyHostToDevice,
-                          s->stream));
-    DI_HIP(hipStreamSynchronize(s->stream));
+                          gs->stream));
+    DI_HIP(hipStreamSynchronize(gs->stream));
     di_stats& t = res.stats;
     std::memset(&t, 0, sizeof(t));
     t.cycles = b.cycles;
@@ -263,24 +267,21 @@ di_status finish_columns(di_server* s, GraphSlot* gs) {
   return DI_OK;
 }
 
-// Cycles cycles on gs's running columns, with their residual passes.
-di_status run_slot(di_server* s, GraphSlot* gs) {
+// Queues gs's next work on its stream: the residual passes of the
+// columns whose FP32 pass ended (states from the last read-back), a chunk
+// of cycles, and the read-back of the column states.
+di_status launch_slot(di_server* s, GraphSlot* gs) {
   const BatchArgs a = args_of(s, gs);
   BatchWs* ws = gs->ws;
   const int kp = s->kp;
-  auto read_ctl = [&]() -> di_status {
-    DI_HIP(hipMemcpyAsync(ws->host_bctl, ws->bctl, (size_t)(kp + 1) * sizeof(BCtl),
-                          hipMemcpyDeviceToHost, s->stream));
-    DI_HIP(hipStreamSynchronize(s->stream));
-    return DI_OK;
-  };
-  DI_TRY(read_ctl());
+  bool inner = false;
   int need = 2;
-  bool running = false;
   for (int c = 0; c < kp; ++c) {
     const BCtl& b = ws->host_bctl[c];
+    inner |= b.state == kBInner;
+    // a column just started has no read-back state yet
+    if (gs->lanes[(size_t)c].ticket != 0 && b.state == kBIdle) need = std::max(need, 16);
     if (b.state != kBRun) continue;
-    running = true;
     int nc = 16;
     const double target = a.tol_rel >= 0.0 ? std::max(0.5 * b.tol, a.tol_rel * b.r_start) : b.tol;
     if (b.pass_cycles >= 1 && b.r > 0.0 && b.r < b.r_start && target > 0.0) {
@@ -290,22 +291,20 @@ di_status run_slot(di_server* s, GraphSlot* gs) {
     }
     need = std::max(need, nc);
   }
-  if (running) {
-    // short chunks keep new requests waiting little
-    const int chunk = std::max(2, std::min(need, 16));
-    for (int q = 0; q < chunk; ++q) DI_HIP(launch_bcycle(a, ws, nullptr, nullptr));
-    DI_TRY(read_ctl());
-  }
-  for (;;) {
-    bool inner = false;
-    for (int c = 0; c < kp; ++c) inner |= ws->host_bctl[c].state == kBInner;
-    if (!inner) break;
+  if (inner) {
     int nrec = 0;
     DI_HIP(launch_brefine(a, ws, &nrec));
     DI_HIP(launch_bfirst(a, ws, nrec, kBInner));
-    DI_TRY(read_ctl());
   }
-  return finish_columns(s, gs);
+  // short chunks keep new requests waiting little; the kernels of columns
+  // that are not running return at once
+  const int chunk = std::max(2, std::min(need, 16));
+  for (int q = 0; q < chunk; ++q) DI_HIP(launch_bcycle(a, ws, nullptr, nullptr));
+  DI_HIP(hipMemcpyAsync(ws->host_bctl, ws->bctl, (size_t)(kp + 1) * sizeof(BCtl),
+                        hipMemcpyDeviceToHost, gs->stream));
+  DI_HIP(hipEventRecord(gs->ev, gs->stream));
+  gs->launched = true;
+  return DI_OK;
 }
 
 void fail_all(di_server* s, di_status st, const std::string& msg) {
@@ -324,24 +323,49 @@ void fail_all(di_server* s, di_status st, const std::string& msg) {
   }
 }
 
+// The worker: graphs progress independently. A graph whose queued work has
+// finished (its event) is collected and relaunched at once, with the
+// requests that arrived meanwhile started in its free columns; the loop
+// naps briefly only when no graph could move.
 void worker_loop(di_server* s) {
   (void)hipSetDevice(s->device);
   for (;;) {
     std::vector<GraphSlot*> work;
     {
       std::unique_lock<std::mutex> lk(s->mu);
+      auto busy = [](const GraphSlot* gs) {
+        return gs->launched || gs->active > 0 || !gs->pending.empty();
+      };
       s->cv.wait(lk, [&] {
         if (s->stop) return true;
         for (auto& kv : s->graphs)
-          if (kv.second->active > 0 || !kv.second->pending.empty()) return true;
+          if (busy(kv.second)) return true;
         return false;
       });
       if (s->stop) return;
       for (auto& kv : s->graphs)
-        if (kv.second->active > 0 || !kv.second->pending.empty()) work.push_back(kv.second);
+        if (busy(kv.second)) work.push_back(kv.second);
     }
     const double t0 = now_s();
+    di_status st = DI_OK;
+    bool progressed = false;
     for (GraphSlot* gs : work) {
+      if (gs->launched) {
+        const hipError_t q = hipEventQuery(gs->ev);
+        if (q == hipErrorNotReady) {
+          (void)hipGetLastError();  // not an error: keep it out of later checks
+          continue;
+        }
+        gs->launched = false;
+        if (q != hipSuccess) {
+          set_error(std::string("serving worker: ") + hipGetErrorString(q));
+          st = DI_E_DEVICE;
+          break;
+        }
+        st = finish_columns(s, gs);
+        if (st != DI_OK) break;
+        progressed = true;
+      }
       std::vector<Request> admit;
       std::vector<GraphSlot*> to_free;
       bool need_ws = false;
@@ -369,7 +393,6 @@ void worker_loop(di_server* s) {
           }
         }
       }
-      di_status st = DI_OK;
       for (GraphSlot* o : to_free) {
         if (o->ws) free_batch_ws(o->ws);
         if (o->out_dev) (void)hipFree(o->out_dev);
@@ -379,12 +402,22 @@ void worker_loop(di_server* s) {
       }
       if (need_ws) st = create_slot_ws(s, gs);
       if (st == DI_OK && !admit.empty()) st = start_requests(s, gs, admit);
-      if (st == DI_OK && gs->ws && gs->active > 0) st = run_slot(s, gs);
-      if (st != DI_OK) {
-        fail_all(s, st, "serving worker: " + std::string(di_last_error()));
-        break;
+      if (st == DI_OK && gs->ws && gs->active > 0) {
+        st = launch_slot(s, gs);
+        progressed = true;
       }
+      if (st != DI_OK) break;
     }
+    if (st != DI_OK) {
+      // drain what was queued before failing the requests
+      for (GraphSlot* gs : work)
+        if (gs->launched) {
+          (void)hipEventSynchronize(gs->ev);
+          gs->launched = false;
+        }
+      fail_all(s, st, "serving worker: " + std::string(di_last_error()));
+    }
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
     std::lock_guard<std::mutex> lk(s->mu);
     s->busy_seconds += now_s() - t0;
   }
@@ -439,8 +472,7 @@ di_status serve_create(size_t budget, int32_t k_max, const di_opts* opts, di_ser
   s->kp = kp;
   s->opts = o;
   s->device = dev;
-  hipError_t err = hipStreamCreate(&s->stream);
-  if (err == hipSuccess) err = hipMalloc((void**)&s->d_flag, (size_t)kp * sizeof(int));
+  hipError_t err = hipMalloc((void**)&s->d_flag, (size_t)kp * sizeof(int));
   if (err == hipSuccess) err = hipMalloc((void**)&s->d_buni, (size_t)kp * sizeof(double));
   if (err == hipSuccess) err = hipMalloc((void**)&s->d_col, (size_t)kp * sizeof(int));
   if (err == hipSuccess) err = hipMalloc((void**)&s->d_off, (size_t)(kp + 1) * sizeof(int64_t));
@@ -484,6 +516,18 @@ di_status di_serve_add_graph(di_server* s, const di_graph* g, int32_t graph_id) 
     di::GraphSlot* gs = new di::GraphSlot;
     gs->g = g;
     gs->id = graph_id;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != s->device) (void)hipSetDevice(s->device);
+    hipError_t err = hipStreamCreate(&gs->stream);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&gs->ev, hipEventDisableTiming);
+    if (cur != s->device) (void)hipSetDevice(cur);
+    if (err != hipSuccess) {
+      if (gs->stream) (void)hipStreamDestroy(gs->stream);
+      delete gs;
+      di::set_error(std::string("di_serve_add_graph: ") + hipGetErrorString(err));
+      return DI_E_DEVICE;
+    }
     s->graphs[graph_id] = gs;
     return DI_OK;
   });
@@ -588,16 +632,17 @@ void di_serve_destroy(di_server* s) {
   if (s->worker.joinable()) s->worker.join();
   int cur = 0;
   if (hipGetDevice(&cur) == hipSuccess && cur != s->device) (void)hipSetDevice(s->device);
-  if (s->stream) (void)hipStreamSynchronize(s->stream);
   for (auto& kv : s->graphs) {
     di::GraphSlot* gs = kv.second;
+    if (gs->stream) (void)hipStreamSynchronize(gs->stream);
     if (gs->ws) di::free_batch_ws(gs->ws);
     if (gs->out_dev) (void)hipFree(gs->out_dev);
+    if (gs->ev) (void)hipEventDestroy(gs->ev);
+    if (gs->stream) (void)hipStreamDestroy(gs->stream);
     delete gs;
   }
   void* ptrs[] = {s->d_flag, s->d_buni, s->d_col, s->d_off, s->d_val, s->d_tol, s->d_seeds};
   for (void* p : ptrs) (void)hipFree(p);
-  if (s->stream) (void)hipStreamDestroy(s->stream);
   if (cur != s->device) (void)hipSetDevice(cur);
   delete s;
 }
