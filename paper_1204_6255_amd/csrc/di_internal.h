@@ -17,10 +17,20 @@ namespace di {
 // select tiles: pull direction 1024 threads x 4 nodes (a grid of at most
 // kSelectGridPull blocks loops over tiles); push direction 256 x 2 (one tile
 // per block; the push block of the same index moves its frontier)
-constexpr int kSelectBlockPull = 1024;
-constexpr int kSelectPerThreadPull = 4;
+// (the three pull-direction select shapes may be set at build time)
+#ifndef DI_SELECT_BLOCK
+#define DI_SELECT_BLOCK 1024
+#endif
+#ifndef DI_SELECT_PER_THREAD
+#define DI_SELECT_PER_THREAD 4
+#endif
+#ifndef DI_SELECT_GRID
+#define DI_SELECT_GRID 256
+#endif
+constexpr int kSelectBlockPull = DI_SELECT_BLOCK;
+constexpr int kSelectPerThreadPull = DI_SELECT_PER_THREAD;
 constexpr int kSelectTilePull = kSelectBlockPull * kSelectPerThreadPull;
-constexpr int kSelectGridPull = 256;
+constexpr int kSelectGridPull = DI_SELECT_GRID;
 constexpr int kSelectBlockPush = 256;
 constexpr int kSelectPerThreadPush = 2;
 constexpr int kSelectTilePush = kSelectBlockPush * kSelectPerThreadPush;

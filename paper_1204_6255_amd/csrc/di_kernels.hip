@@ -515,8 +515,15 @@ __global__ __launch_bounds__(BLOCK) void k_select(
 // then all bitmap loads, then the gathers of the set bits, in flight
 // together. Every block writes one Part record: the sums over its light
 // rows and the folded tile statistics.
+// Eight waves per SIMD (at most 64 VGPRs): the whole pull grid (2048 blocks
+// of 4 waves) is resident at once, which measured faster than six waves
+// without the register cap, a few spilled registers included.
+#ifndef DI_PULL_WAVES_PER_EU
+#define DI_PULL_WAVES_PER_EU 8
+#endif
 template <typename T>
-__global__ __launch_bounds__(kPullBlock) void k_pull(
+__global__ __launch_bounds__(kPullBlock)
+__attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
     T* __restrict__ F, const T* __restrict__ sent,
     const unsigned long long* __restrict__ front_bits, const int64_t* __restrict__ csc_ptr,
     const int32_t* __restrict__ csc_idx, const int64_t* __restrict__ it_r0,
@@ -550,8 +557,7 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
     nr1 = it_r1[it_begin];
     nseg = it_seg[it_begin];
   }
-  Part acc_part{0.0, 0.0, 0.0, 0ull, 0u, 0u};
-  fold_tile_stats(tile_stat, ntiles, acc_part);
+  double acc_abs = 0.0, acc_sum = 0.0;  // the block's rows: sum |F|, sum F
   if (ctl->done) return;
   for (int64_t it = it_begin; it < it_end; it += it_step) {
     const int64_t l0 = nl0, l1 = nl1, r0 = nr0, r1 = nr1;
@@ -645,12 +651,14 @@ __global__ __launch_bounds__(kPullBlock) void k_pull(
           F[row] = nv;
           f = to_d(nv);
         }
-        acc_part.pabs += fabs(f);
-        acc_part.psum += f;
+        acc_abs += fabs(f);
+        acc_sum += f;
       }
     }
     __syncthreads();
   }
+  Part acc_part{acc_abs, acc_sum, 0.0, 0ull, 0u, 0u};
+  fold_tile_stats(tile_stat, ntiles, acc_part);
   acc_part = block_sum_part(acc_part, s_part);
   if (tid == 0) blk_part[blockIdx.x] = acc_part;
 }
