@@ -89,6 +89,42 @@ __device__ Part block_sum_part(Part v, Part* lds) {
   return t;
 }
 
+// Block sum of a Part for a block of NW waves: butterflies within each
+// wave, then wave 0 folds the NW wave sums (lanes < NW, butterfly). Fixed
+// order; valid in thread 0. The link and frontier counts are summed only
+// when `counts` (they feed the control block, which block 0 writes).
+template <int NW>
+__device__ Part block_sum_part_w0(Part v, Part* lds, bool counts) {
+  static_assert((NW & (NW - 1)) == 0 && NW <= 64, "NW: a power of two <= 64");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v.pabs = wave_sum(v.pabs);
+  v.psum = wave_sum(v.psum);
+  v.e = wave_sum(v.e);
+  v.sel = wave_sum(v.sel);
+  if (counts) {
+    v.ops = wave_sum(v.ops);
+    v.nfront = wave_sum(v.nfront);
+  }
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  Part t{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  if (wave == 0) {
+    if (lane < NW) t = lds[lane];
+#pragma unroll
+    for (int off = NW / 2; off >= 1; off >>= 1) {
+      t.pabs += __shfl_xor(t.pabs, off, 64);
+      t.psum += __shfl_xor(t.psum, off, 64);
+      t.e += __shfl_xor(t.e, off, 64);
+      t.sel += __shfl_xor(t.sel, off, 64);
+      if (counts) {
+        t.ops += __shfl_xor(t.ops, off, 64);
+        t.nfront += __shfl_xor(t.nfront, off, 64);
+      }
+    }
+  }
+  return t;
+}
+
 // Adds the tile statistics of tiles [b*k, (b+1)*k) to v, where
 // k = ceil(ntiles / gridDim.x): every tile is folded by exactly one block.
 __device__ inline void fold_tile_stats(const SelStat* __restrict__ tile_stat, int64_t ntiles,
@@ -351,7 +387,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
       v.psum += fh;
     }
   }
-  v = block_sum_part(v, s_part);
+  v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
   if (tid == 0) {
     const Ctl c = next_ctl(c0, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
     if (blockIdx.x == 0) ctl[parity ^ 1] = c;
@@ -478,7 +514,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
         }
       }
     }
-    // the tile's statistics: one fused block reduction
+    // the tile's statistics: wave butterflies, then wave 0 folds the waves
     my_sel = wave_sum(my_sel);
     my_front = wave_sum(my_front);
     my_ops = wave_sum(my_ops);
@@ -490,21 +526,22 @@ __global__ __launch_bounds__(BLOCK) void k_select(
       s_e[wave] = my_e;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (wave == 0) {
       SelStat st;
-      st.sel = 0;
-      st.nfront = 0;
-      st.ops = 0;
-      st.e = 0.0;
-      for (int q = 0; q < NW; ++q) {
-        st.sel += s_sel[q];
-        st.nfront += s_front[q];
-        st.ops += s_ops[q];
-        st.e += s_e[q];
+      st.sel = lane < NW ? s_sel[lane] : 0u;
+      st.nfront = lane < NW ? s_front[lane] : 0u;
+      st.ops = lane < NW ? s_ops[lane] : 0ull;
+      st.e = lane < NW ? s_e[lane] : 0.0;
+#pragma unroll
+      for (int off = NW / 2; off >= 1; off >>= 1) {
+        st.sel += __shfl_xor(st.sel, off, 64);
+        st.nfront += __shfl_xor(st.nfront, off, 64);
+        st.ops += __shfl_xor(st.ops, off, 64);
+        st.e += __shfl_xor(st.e, off, 64);
       }
-      tile_stat[tile] = st;
+      if (lane == 0) tile_stat[tile] = st;
     }
-    __syncthreads();
+    if (tile + gridDim.x < ntiles) __syncthreads();  // LDS reused by the next tile
   }
 }
 
