@@ -56,6 +56,9 @@ def parse_args():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=1_000_000)
     p.add_argument("--alpha", type=float, default=1.68)
+    p.add_argument("--kmax", type=int, default=500, help="largest out-degree of the generator")
+    p.add_argument("--precision", choices=["fp64", "fp32", "fp32r"], default="fp64",
+                   help="fluid precision (fp32r: FP32 with FP64 residual passes)")
     p.add_argument("--tol", type=float, default=1e-9)
     p.add_argument("--kernel", choices=["auto", "pull", "push"], default="auto")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -286,12 +289,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     n, d, tol = args.n, 0.85, args.tol
-    src, dst = graphgen.web_graph(n, seed=0, alpha=args.alpha)
+    src, dst = graphgen.web_graph(n, seed=0, alpha=args.alpha, kmax=args.kmax)
     stats = graphgen.graph_stats(n, src, dst)
     g = di.Graph(n, src, dst)
+    del src, dst
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     opts = di.di_opts_default()
     opts.kernel = {"auto": di.DI_KERNEL_AUTO, "pull": di.DI_KERNEL_PULL, "push": di.DI_KERNEL_PUSH}[args.kernel]
+    opts.precision = {"fp64": di.DI_FP64, "fp32": di.DI_FP32, "fp32r": di.DI_FP32_REFINE}[args.precision]
+    headline = (n == 1_000_000 and args.kmax == 500 and args.precision == "fp64"
+                and args.alpha == 1.68 and args.kernel != "push")
 
     def solve():
         status, st = di.di_solve_dev(g.handle, None, d, tol, opts, X)
@@ -324,7 +331,7 @@ def main():
     per_launch_bytes = move_bytes / max(launches, 1)
     per_launch_s = move_secs / max(launches, 1)
     achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
-    traffic = read_traffic()
+    traffic = read_traffic() if headline else None
     edges = float(np.mean([r.edges_pushed for r in runs]))
 
     line = {
@@ -338,12 +345,12 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32r": "f32 fluid, f64 residual"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": f"web graph N={n} seed 0, out-degree power law alpha={args.alpha} on [1,500], "
-                        f"15% dangling, 70% links within +-500, rest Zipf(1); d={d}, B=(1-d)/N, "
-                        f"stop at sum|F|<={tol:g}, FP64",
+            "workload": f"web graph N={n} seed 0, out-degree power law alpha={args.alpha} on "
+                        f"[1,{args.kmax}], 15% dangling, 70% links within +-500, rest Zipf(1); "
+                        f"d={d}, B=(1-d)/N, stop at sum|F|<={tol:g}, {args.precision}",
             "n": n, "links": int(stats.L), "dangling": int(stats.D),
             "kernel": "push" if opts.kernel == di.DI_KERNEL_PUSH else "pull",
         },
@@ -354,7 +361,8 @@ def main():
         "err_bound": float(last.err_bound),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_pull<double>" if opts.kernel != di.DI_KERNEL_PUSH else "k_push<double>",
+            "kernel": ("k_pull" if opts.kernel != di.DI_KERNEL_PUSH else "k_push")
+                      + ("<double>" if args.precision == "fp64" else "<float>"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -372,11 +380,12 @@ def main():
         torch.cuda.synchronize()
         del a, b
     line["hbm_frac"] = line["roofline"]["frac"]
-    if not args.no_extras:
+    if not args.no_extras and headline:
         line["fp32_refine"] = fp32_refine_section(di, g, X, d, tol)
         line["batched_ppr"] = batched_section(di, graphgen, g, n, d, tol)
         line["serving"] = serving_section(di, graphgen, d, args.serve_seconds, args.serve_kmax)
     if args.cpu_seconds > 0:
+        src, dst = graphgen.web_graph(n, seed=0, alpha=args.alpha, kmax=args.kmax)
         line["cpu_baseline"] = cpu_baseline(n, src, dst, d, tol, args.cpu_seconds)
     else:
         line["cpu_baseline"] = None

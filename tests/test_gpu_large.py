@@ -1,0 +1,72 @@
+"""Large graphs: the 50M-node configuration (out-degrees up to 2000, about
+600M links, FP32 fluid with FP64 residual passes) and a 5M-node version of
+it that runs by default. Set DI_LARGE=1 to run the 50M case.
+
+At these sizes the oracle's full solve is slow, so the bar is the
+property that holds at any size: the residual |B + P.X - X|_1 of the GPU's
+X, recomputed by the oracle in FP64, is within tol, which bounds
+|X - X_exact|_1 by tol / (1 - d) (Section 2.2). At 5M nodes the oracle's
+solve is also compared entry by entry.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1204_6255_amd import di, graphgen
+
+pytestmark = pytest.mark.gpu
+
+D = 0.85
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def solve(torch, g, precision, tol):
+    o = di.di_opts_default()
+    o.precision = precision
+    X = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    status, st = di.di_solve_dev(g.handle, None, D, tol, o, X)
+    assert status == di.DI_OK, (di.STATUS_NAMES.get(status), di.di_last_error())
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), st
+
+
+def run_case(torch, n, full_oracle):
+    src, dst = graphgen.web_graph(n, seed=0, kmax=2000)
+    g = di.Graph(n, src, dst)
+    og = oracle.Graph(n, src, dst)
+    del src, dst
+    B = graphgen.uniform_rhs(n, D)
+    tol = 1e-9
+    Xr, str_ = solve(torch, g, di.DI_FP32_REFINE, tol)
+    _, r_true = oracle.residual(og, B, D, Xr)
+    assert r_true <= tol * (1 + 1e-6)
+    assert abs(r_true - str_.resid_l1) <= 1e-15 + 1e-6 * r_true
+    X64, st64 = solve(torch, g, di.DI_FP64, tol)
+    _, r64 = oracle.residual(og, B, D, X64)
+    assert abs(r64 - st64.resid_l1) <= 1e-14 + 1e-6 * r64 and r64 <= tol * (1 + 1e-6)
+    # both are within tol / (1 - d) of the exact solution
+    assert np.abs(Xr - X64).sum() <= 2 * tol / (1 - D)
+    if full_oracle:
+        ref, _, ost = oracle.diter(og, B, D, oracle.SOP, oracle.SEQUENTIAL, tol=1e-12)
+        assert ost.status == oracle.OK
+        assert np.abs(Xr - ref).sum() <= tol / (1 - D) + 1e-11
+        assert np.abs(X64 - ref).sum() <= tol / (1 - D) + 1e-11
+    g.close()
+
+
+def test_5m_out_degrees_to_2000(torch_cuda):
+    run_case(torch_cuda, 5_000_000, full_oracle=True)
+
+
+@pytest.mark.skipif(os.environ.get("DI_LARGE") != "1", reason="50M-node case: set DI_LARGE=1")
+def test_50m_configuration(torch_cuda):
+    run_case(torch_cuda, 50_000_000, full_oracle=False)
