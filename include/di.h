@@ -268,9 +268,9 @@ void di_serve_destroy(di_server* s);
 
 /* The FP64 residual R = B + P.X - X of an approximate solution X, and
  * |R|_1 (the refinement step of DI_FP32_REFINE, which recomputes the fluid
- * of Section 2.2 as F = B - (I - P).X). B_dev: n doubles on the device, or
- * NULL for the PageRank right-hand side (1-d)/n. X_dev: n doubles on the
- * device (read only). R_dev: n doubles on the device, or NULL when only the
+ * of Sections 2.5.4-2.5.5 as F = B - (I - P).X). B_dev: n doubles on the
+ * device, or NULL for the PageRank right-hand side (1-d)/n. X_dev: n
+ * doubles on the device (read only). R_dev: n doubles on the device, or NULL when only the
  * norm is wanted. *l1 (host, may be NULL) receives |R|_1, summed in FP64.
  * Work is queued on `stream` (NULL = the null stream); the call returns
  * once it has finished. */

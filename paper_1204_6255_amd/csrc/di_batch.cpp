@@ -178,6 +178,7 @@ di_status batch_group(di_graph* g, int k, const double* B_dev, double d, const d
   BatchArgs a{};
   a.g = g;
   a.kp = kp;
+  a.ke = kp;
   a.prec = prec;
   a.d = d;
   a.method = o.method;

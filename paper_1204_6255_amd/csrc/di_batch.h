@@ -50,6 +50,9 @@ struct BCtl {
 struct BatchArgs {
   const di_graph* g;
   int kp;              // columns (8 .. 256, power of two)
+  int ke;              // working width: columns >= ke are idle (8 .. kp,
+                       // power of two); the cycle and residual kernels
+                       // look at columns [0, ke) only
   int prec;            // kF64 or kF32
   double d;
   int method;          // DI_SOP or DI_CYC

@@ -98,22 +98,22 @@ __device__ A block_sum_all(A v, A* lds) {
 }
 
 // Per-column block totals of acc (each thread holds columns gl*V + v),
-// written to out[0, KP). lds: (kBBlock / 64) * KP values. Fixed order.
-template <int KP, typename A>
-__device__ inline void col_sum_store(A (&acc)[Lay<KP>::V], A* lds, A* out) {
-  using Ly = Lay<KP>;
+// written to out[0, KW). lds: (kBBlock / 64) * KW values. Fixed order.
+template <int KW, typename A>
+__device__ inline void col_sum_store(A (&acc)[Lay<KW>::V], A* lds, A* out) {
+  using Ly = Lay<KW>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int v = 0; v < Ly::V; ++v) acc[v] = group_fold<Ly::G>(acc[v]);
   if (lane < Ly::G) {
 #pragma unroll
-    for (int v = 0; v < Ly::V; ++v) lds[wave * KP + lane * Ly::V + v] = acc[v];
+    for (int v = 0; v < Ly::V; ++v) lds[wave * KW + lane * Ly::V + v] = acc[v];
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < KP; c += kBBlock) {
+  for (int c = threadIdx.x; c < KW; c += kBBlock) {
     A s = 0;
 #pragma unroll
-    for (int w = 0; w < Ly::NW; ++w) s += lds[w * KP + c];
+    for (int w = 0; w < Ly::NW; ++w) s += lds[w * KW + c];
     out[c] = s;
   }
   __syncthreads();
@@ -211,25 +211,27 @@ __global__ __launch_bounds__(kBBlock) void k_brecords(const T* __restrict__ F, i
 // in 64 / P passes of P nodes. Per-column counters go to the block's
 // records (rec_ops / rec_sel / rec_e row blockIdx.x); column KP of rec_ops
 // and rec_sel holds the node-level frontier (links gathered, nodes).
-template <typename T, int KP>
+// Only columns [0, KE) are looked at (the others are idle); rows are KP
+// values apart.
+template <typename T, int KP, int KE>
 __global__ __launch_bounds__(kBBlock) void k_bselect(
     T* __restrict__ F, T* __restrict__ H, T* __restrict__ sent,
     unsigned long long* __restrict__ front_bits, const uint32_t* __restrict__ info, int64_t n,
     int64_t L, double d, const BCtl* __restrict__ bctl, unsigned long long* __restrict__ rec_ops,
     unsigned int* __restrict__ rec_sel, double* __restrict__ rec_e) {
-  using Ly = Lay<KP>;
+  using Ly = Lay<KE>;
   constexpr int G = Ly::G, P = Ly::P, V = Ly::V;
-  __shared__ double s_rl[KP];
-  __shared__ int s_flag[KP];
-  __shared__ unsigned long long s_u64[Ly::NW * KP];
-  __shared__ unsigned int s_u32[Ly::NW * KP];
-  __shared__ double s_f64[Ly::NW * KP];
+  __shared__ double s_rl[KE];
+  __shared__ int s_flag[KE];
+  __shared__ unsigned long long s_u64[Ly::NW * KE];
+  __shared__ unsigned int s_u32[Ly::NW * KE];
+  __shared__ double s_f64[Ly::NW * KE];
   __shared__ unsigned long long s_n64[Ly::NW];
   __shared__ unsigned int s_n32[Ly::NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane / G, gl = lane % G;
   int any = 0;
-  for (int c = tid; c < KP; c += kBBlock) {
+  for (int c = tid; c < KE; c += kBBlock) {
     const int state = bctl[c].state;
     const int run = state == kBRun ? 1 : 0;
     s_flag[c] = run | (bctl[c].cyc_mode ? 2 : 0);
@@ -337,9 +339,9 @@ __global__ __launch_bounds__(kBBlock) void k_bselect(
   }
   unsigned long long* ro = rec_ops + (int64_t)blockIdx.x * (KP + 1);
   unsigned int* rs = rec_sel + (int64_t)blockIdx.x * (KP + 1);
-  col_sum_store<KP>(ops, s_u64, ro);
-  col_sum_store<KP>(sel, s_u32, rs);
-  col_sum_store<KP>(eab, s_f64, rec_e + (int64_t)blockIdx.x * KP);
+  col_sum_store<KE>(ops, s_u64, ro);
+  col_sum_store<KE>(sel, s_u32, rs);
+  col_sum_store<KE>(eab, s_f64, rec_e + (int64_t)blockIdx.x * KP);
   fops = wave_sum(fops);
   fnodes = wave_sum(fnodes);
   if (lane == 0) {
@@ -375,11 +377,11 @@ struct PullIo {
 // Finishes row `row` with its in-link sum acc (this lane's V columns).
 // MODE 0: F += acc; MODE 1: F = R = B - X + (self-loop ? y : 0) + acc for
 // the masked columns. rsum += |F| (or |R|) per column.
-template <typename T, int KP, int MODE>
+template <typename T, int KP, int KE, int MODE>
 __device__ inline void row_epilogue(const PullIo<T, KP, MODE>& io, int64_t row, int gl,
-                                    const double (&acc)[Lay<KP>::V], const bool (&mask)[Lay<KP>::V],
-                                    double (&rsum)[Lay<KP>::V]) {
-  constexpr int V = Lay<KP>::V;
+                                    const double (&acc)[Lay<KE>::V], const bool (&mask)[Lay<KE>::V],
+                                    double (&rsum)[Lay<KE>::V]) {
+  constexpr int V = Lay<KE>::V;
   T* Fr = io.F + row * KP + gl * V;
   if (MODE == 0) {
     bool anym = false;
@@ -423,8 +425,8 @@ __device__ inline void row_epilogue(const PullIo<T, KP, MODE>& io, int64_t row, 
 
 // MODE 0 also adds the selection's node-level counters (column KP of
 // rec_ops / rec_sel, nsel rows) to entry KP of the control blocks (block 0),
-// once the selection is known to have run.
-template <typename T, int KP, int MODE>
+// once the selection is known to have run. Columns [0, KE) only.
+template <typename T, int KP, int KE, int MODE>
 __global__ __launch_bounds__(kBBlock) void k_bpull(
     PullIo<T, KP, MODE> io, const int64_t* __restrict__ csc_ptr,
     const int32_t* __restrict__ csc_idx, const int64_t* __restrict__ it_r0,
@@ -433,14 +435,14 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
     double* __restrict__ segv, double* __restrict__ rec, BCtl* __restrict__ bctl,
     const unsigned long long* __restrict__ rec_ops, const unsigned int* __restrict__ rec_sel,
     int nsel) {
-  using Ly = Lay<KP>;
+  using Ly = Lay<KE>;
   constexpr int G = Ly::G, P = Ly::P, V = Ly::V, NG = Ly::NG;
-  constexpr int U = 4;  // gathers in flight per group
+  constexpr int U = 4;
   using SrcT = typename std::conditional<MODE == 0, T, double>::type;
   __shared__ int32_t s_idx[kPullChunk];
   __shared__ int32_t s_ptr[kPullMaxRows + 1];
-  __shared__ double s_part[NG * 2 * KP];
-  __shared__ double s_rec[Ly::NW * KP];
+  __shared__ double s_part[NG * 2 * KE];
+  __shared__ double s_rec[Ly::NW * KE];
   __shared__ unsigned long long s_cnt[Ly::NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane / G, gl = lane % G;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
   // ones waiting for a residual pass
   bool mask[V];
   int any = 0;
-  for (int c = tid; c < KP; c += kBBlock)
+  for (int c = tid; c < KE; c += kBBlock)
     any |= bctl[c].state == (MODE == 0 ? kBRun : kBInner) ? 1 : 0;
   if (!__syncthreads_or(any)) return;
   if (MODE == 0 && blockIdx.x == 0) {
@@ -530,10 +532,10 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
           const int qq = q + u;
           if (qq < q1) {
             if (qq >= end) {  // seg < 0 only: row `cur` ends inside the share
-              if (s_ptr[cur] >= q0) row_epilogue<T, KP, MODE>(io, r0 + cur, gl, acc, mask, rsum);
+              if (s_ptr[cur] >= q0) row_epilogue<T, KP, KE, MODE>(io, r0 + cur, gl, acc, mask, rsum);
               else {
 #pragma unroll
-                for (int v = 0; v < V; ++v) s_part[(gid * 2) * KP + gl * V + v] = acc[v];
+                for (int v = 0; v < V; ++v) s_part[(gid * 2) * KE + gl * V + v] = acc[v];
               }
 #pragma unroll
               for (int v = 0; v < V; ++v) acc[v] = 0.0;
@@ -549,21 +551,21 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
       }
       // the share's last row: finished here when it lies inside the share
       if (seg < 0 && s_ptr[cur] >= q0 && s_ptr[cur + 1] <= q1) {
-        row_epilogue<T, KP, MODE>(io, r0 + cur, gl, acc, mask, rsum);
+        row_epilogue<T, KP, KE, MODE>(io, r0 + cur, gl, acc, mask, rsum);
       } else {
         const int slot = (seg >= 0 || cur == first_row) ? 0 : 1;
 #pragma unroll
-        for (int v = 0; v < V; ++v) s_part[(gid * 2 + slot) * KP + gl * V + v] = acc[v];
+        for (int v = 0; v < V; ++v) s_part[(gid * 2 + slot) * KE + gl * V + v] = acc[v];
       }
     }
     __syncthreads();
     if (seg >= 0) {
       // a segment of a heavy row: the shares' sums in order
-      for (int c = tid; c < KP; c += kBBlock) {
+      for (int c = tid; c < KE; c += kBBlock) {
         double s = 0.0;
         for (int g2 = 0; g2 < NG; ++g2) {
           const int qa = (int)((int64_t)nl * g2 / NG), qb = (int)((int64_t)nl * (g2 + 1) / NG);
-          if (qa < qb) s += s_part[(g2 * 2) * KP + c];
+          if (qa < qb) s += s_part[(g2 * 2) * KE + c];
         }
         segv[(int64_t)seg * KP + c] = s;
       }
@@ -573,40 +575,40 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
         double tot[V];
         const int slot = cur == first_row ? 0 : 1;
 #pragma unroll
-        for (int v = 0; v < V; ++v) tot[v] = s_part[(gid * 2 + slot) * KP + gl * V + v];
+        for (int v = 0; v < V; ++v) tot[v] = s_part[(gid * 2 + slot) * KE + gl * V + v];
         for (int g2 = gid + 1; g2 < NG; ++g2) {
           const int qa = (int)((int64_t)nl * g2 / NG), qb = (int)((int64_t)nl * (g2 + 1) / NG);
           if (qa >= s_ptr[cur + 1]) break;
           if (qa < qb) {
 #pragma unroll
-            for (int v = 0; v < V; ++v) tot[v] += s_part[(g2 * 2) * KP + gl * V + v];
+            for (int v = 0; v < V; ++v) tot[v] += s_part[(g2 * 2) * KE + gl * V + v];
           }
         }
-        row_epilogue<T, KP, MODE>(io, r0 + cur, gl, tot, mask, rsum);
+        row_epilogue<T, KP, KE, MODE>(io, r0 + cur, gl, tot, mask, rsum);
       }
       // rows without in-links
       double zero[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) zero[v] = 0.0;
       for (int r = gid; r < nrows; r += NG)
-        if (s_ptr[r] == s_ptr[r + 1]) row_epilogue<T, KP, MODE>(io, r0 + r, gl, zero, mask, rsum);
+        if (s_ptr[r] == s_ptr[r + 1]) row_epilogue<T, KP, KE, MODE>(io, r0 + r, gl, zero, mask, rsum);
     }
     __syncthreads();
   }
-  col_sum_store<KP>(rsum, s_rec, rec + (int64_t)blockIdx.x * KP);
+  col_sum_store<KE>(rsum, s_rec, rec + (int64_t)blockIdx.x * KP);
 }
 
 // Heavy rows: F += (MODE 1: F = R with) the sum of the row's segment sums,
 // in segment order. Block b handles heavy rows b*HPB + hs (strided); its
 // per-column sums of |F| go to rec[rec_base + b].
-template <typename T, int KP, int MODE>
+template <typename T, int KP, int KE, int MODE>
 __global__ __launch_bounds__(kBBlock) void k_bheavy(
     PullIo<T, KP, MODE> io, const int32_t* __restrict__ heavy_row,
     const int64_t* __restrict__ heavy_seg, int64_t n_heavy, const double* __restrict__ segv,
     double* __restrict__ rec, int rec_base, const BCtl* __restrict__ bctl) {
-  constexpr int HPB = kBBlock / KP;
+  constexpr int HPB = kBBlock / KE;
   __shared__ double s_sum[kBBlock];
-  const int c = threadIdx.x % KP, hs = threadIdx.x / KP;
+  const int c = threadIdx.x % KE, hs = threadIdx.x / KE;
   const int want = MODE == 0 ? kBRun : kBInner;
   const bool m = bctl[c].state == want;
   double rsum = 0.0;
@@ -632,22 +634,22 @@ __global__ __launch_bounds__(kBBlock) void k_bheavy(
   }
   s_sum[threadIdx.x] = rsum;
   __syncthreads();
-  if (threadIdx.x < KP) {
+  if (threadIdx.x < KE) {
     double t = 0.0;
-    for (int q = 0; q < HPB; ++q) t += s_sum[q * KP + threadIdx.x];
+    for (int q = 0; q < HPB; ++q) t += s_sum[q * KE + threadIdx.x];
     rec[(int64_t)(rec_base + blockIdx.x) * KP + threadIdx.x] = t;
   }
 }
 
 // ---- residual pass: fold H into X and the senders' rows ------------------
 
-template <typename T, int KP>
+template <typename T, int KP, int KE>
 __global__ __launch_bounds__(kBBlock) void k_brefine_y(double* __restrict__ X64,
                                                        T* __restrict__ H, double* __restrict__ Y,
                                                        const uint32_t* __restrict__ info,
                                                        int64_t n, double d,
                                                        const BCtl* __restrict__ bctl) {
-  using Ly = Lay<KP>;
+  using Ly = Lay<KE>;
   constexpr int V = Ly::V;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / Ly::G, gl = lane % Ly::G;
@@ -922,25 +924,25 @@ hipError_t brecords_t(const BatchArgs& a, BatchWs* ws) {
   return hipGetLastError();
 }
 
-template <typename T, int KP>
+template <typename T, int KP, int KE>
 hipError_t bcycle_t(const BatchArgs& a, BatchWs* ws, hipEvent_t ev0, hipEvent_t ev1) {
   const di_graph* g = a.g;
   const int sgrid = bselect_grid(g->n);
-  hipLaunchKernelGGL((k_bselect<T, KP>), dim3(sgrid), dim3(kBBlock), 0, a.stream, (T*)ws->F,
+  hipLaunchKernelGGL((k_bselect<T, KP, KE>), dim3(sgrid), dim3(kBBlock), 0, a.stream, (T*)ws->F,
                      (T*)ws->H, (T*)ws->sent, ws->front_bits, g->info, g->n, g->L, a.d,
                      (const BCtl*)ws->bctl, ws->rec_ops, ws->rec_sel, ws->rec_e);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (ev0 && (err = hipEventRecord(ev0, a.stream)) != hipSuccess) return err;
   const int pgrid = pull_grid(g);
-  hipLaunchKernelGGL((k_bpull<T, KP, 0>), dim3(pgrid), dim3(kBBlock), 0, a.stream,
+  hipLaunchKernelGGL((k_bpull<T, KP, KE, 0>), dim3(pgrid), dim3(kBBlock), 0, a.stream,
                      fluid_io<T, KP>(a, ws), g->csc_ptr, g->csc_idx, g->it_r0, g->it_r1, g->it_l0,
                      g->it_l1, g->it_seg, g->n_items, ws->segv, ws->rec, ws->bctl,
                      (const unsigned long long*)ws->rec_ops, (const unsigned int*)ws->rec_sel,
                      sgrid);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   if (ev1 && (err = hipEventRecord(ev1, a.stream)) != hipSuccess) return err;
-  hipLaunchKernelGGL((k_breduce<T, KP, false>), dim3(KP), dim3(kBBlock), 0, a.stream, ws->bctl,
+  hipLaunchKernelGGL((k_breduce<T, KP, false>), dim3(KE), dim3(kBBlock), 0, a.stream, ws->bctl,
                      (const double*)ws->rec, pgrid, (const unsigned long long*)ws->rec_ops,
                      (const unsigned int*)ws->rec_sel, (const double*)ws->rec_e, sgrid, a.method,
                      a.max_cycles, a.tol_rel, (int)kBRun, (T*)ws->F, g->heavy_row, g->heavy_seg,
@@ -950,7 +952,7 @@ hipError_t bcycle_t(const BatchArgs& a, BatchWs* ws, hipEvent_t ev0, hipEvent_t 
 
 template <typename T, int KP>
 hipError_t bfirst_t(const BatchArgs& a, BatchWs* ws, int nrec, int want) {
-  hipLaunchKernelGGL((k_breduce<T, KP, true>), dim3(KP), dim3(kBBlock), 0, a.stream, ws->bctl,
+  hipLaunchKernelGGL((k_breduce<T, KP, true>), dim3(a.ke), dim3(kBBlock), 0, a.stream, ws->bctl,
                      (const double*)ws->rec, nrec, (const unsigned long long*)nullptr,
                      (const unsigned int*)nullptr, (const double*)nullptr, 0, a.method,
                      a.max_cycles, a.tol_rel, want, (T*)nullptr, (const int32_t*)nullptr,
@@ -958,24 +960,24 @@ hipError_t bfirst_t(const BatchArgs& a, BatchWs* ws, int nrec, int want) {
   return hipGetLastError();
 }
 
-template <typename T, int KP>
+template <typename T, int KP, int KE>
 hipError_t brefine_t(const BatchArgs& a, BatchWs* ws, int* nrec) {
   const di_graph* g = a.g;
-  using Ly = Lay<KP>;
+  using Ly = Lay<KE>;
   const int ygrid = (int)std::min<int64_t>(ceil_div(g->n, Ly::NG), 8192);
-  hipLaunchKernelGGL((k_brefine_y<T, KP>), dim3(ygrid), dim3(kBBlock), 0, a.stream, ws->X64,
+  hipLaunchKernelGGL((k_brefine_y<T, KP, KE>), dim3(ygrid), dim3(kBBlock), 0, a.stream, ws->X64,
                      (T*)ws->H, ws->Y64, g->info, g->n, a.d, (const BCtl*)ws->bctl);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int pgrid = pull_grid(g);
-  hipLaunchKernelGGL((k_bpull<T, KP, 1>), dim3(pgrid), dim3(kBBlock), 0, a.stream,
+  hipLaunchKernelGGL((k_bpull<T, KP, KE, 1>), dim3(pgrid), dim3(kBBlock), 0, a.stream,
                      residual_io<T, KP>(a, ws), g->csc_ptr, g->csc_idx, g->it_r0, g->it_r1,
                      g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->segv, ws->rec, ws->bctl,
                      (const unsigned long long*)nullptr, (const unsigned int*)nullptr, 0);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   const int hgrid = bheavy_grid(g);
   if (hgrid > 0) {
-    hipLaunchKernelGGL((k_bheavy<T, KP, 1>), dim3(hgrid), dim3(kBBlock), 0, a.stream,
+    hipLaunchKernelGGL((k_bheavy<T, KP, KE, 1>), dim3(hgrid), dim3(kBBlock), 0, a.stream,
                        residual_io<T, KP>(a, ws), g->heavy_row, g->heavy_seg, g->n_heavy,
                        (const double*)ws->segv, ws->rec, pgrid, (const BCtl*)ws->bctl);
     if ((err = hipGetLastError()) != hipSuccess) return err;
@@ -1011,6 +1013,32 @@ hipError_t bcol_out_t(const BatchArgs& a, BatchWs* ws, int c, bool refined, doub
                      dim3(256), 0, a.stream, (const T*)ws->H,
                      refined ? (const double*)ws->X64 : (const double*)nullptr, c, a.g->n, X_out);
   return hipGetLastError();
+}
+
+// Calls f.template operator()<T, KP, KE>() for a working width KE <= KP.
+template <typename T, int KP, typename Fn>
+hipError_t dispatch_ke(int ke, Fn&& f) {
+  switch (ke) {
+    case 8:
+      if constexpr (KP >= 8) return f.template operator()<T, KP, 8>();
+      break;
+    case 16:
+      if constexpr (KP >= 16) return f.template operator()<T, KP, 16>();
+      break;
+    case 32:
+      if constexpr (KP >= 32) return f.template operator()<T, KP, 32>();
+      break;
+    case 64:
+      if constexpr (KP >= 64) return f.template operator()<T, KP, 64>();
+      break;
+    case 128:
+      if constexpr (KP >= 128) return f.template operator()<T, KP, 128>();
+      break;
+    case 256:
+      if constexpr (KP >= 256) return f.template operator()<T, KP, 256>();
+      break;
+  }
+  return hipErrorInvalidValue;
 }
 
 // Calls f.template operator()<T, KP>() for the batch's shape.
@@ -1064,7 +1092,11 @@ hipError_t launch_brecords(const BatchArgs& a, BatchWs* ws) {
 }
 
 hipError_t launch_bcycle(const BatchArgs& a, BatchWs* ws, hipEvent_t ev0, hipEvent_t ev1) {
-  return dispatch(a, [&]<typename T, int KP>() { return bcycle_t<T, KP>(a, ws, ev0, ev1); });
+  return dispatch(a, [&]<typename T, int KP>() {
+    return dispatch_ke<T, KP>(a.ke, [&]<typename T2, int KP2, int KE>() {
+      return bcycle_t<T2, KP2, KE>(a, ws, ev0, ev1);
+    });
+  });
 }
 
 hipError_t launch_bfirst(const BatchArgs& a, BatchWs* ws, int nrec, int want) {
@@ -1072,7 +1104,11 @@ hipError_t launch_bfirst(const BatchArgs& a, BatchWs* ws, int nrec, int want) {
 }
 
 hipError_t launch_brefine(const BatchArgs& a, BatchWs* ws, int* nrec) {
-  return dispatch(a, [&]<typename T, int KP>() { return brefine_t<T, KP>(a, ws, nrec); });
+  return dispatch(a, [&]<typename T, int KP>() {
+    return dispatch_ke<T, KP>(a.ke, [&]<typename T2, int KP2, int KE>() {
+      return brefine_t<T2, KP2, KE>(a, ws, nrec);
+    });
+  });
 }
 
 hipError_t launch_bcol_init(const BatchArgs& a, BatchWs* ws, const ColInit& ci) {

@@ -1,17 +1,21 @@
 // libdi serving loop: personalized PageRank requests on resident graphs,
 // continuously batched.
 //
-// Each graph with work holds one batch workspace (a "slot set" of KP
-// columns, di_batch.h) and its own HIP stream, so the graphs' kernels
-// overlap on the device. A worker thread moves every graph on its own:
-// when the work queued for a graph has finished, it reads out the columns
-// that finished (which frees them), starts waiting requests in free
-// columns (the other columns keep their state: the columns of a batch are
-// independent solves), and queues the residual passes its columns are
-// waiting for, the next chunk of cycles and the read-back of the column
-// states. A slot set is allocated when its graph first gets
-// work and the HBM budget allows it; idle slot sets of other graphs are
-// released to make room, and a request that cannot be placed waits (an
+// A graph with work holds one or more column sets: batch workspaces of KP
+// columns (di_batch.h), each with its own HIP stream, so the kernels of
+// different sets and graphs overlap on the device. A graph has one open set
+// whose width follows its demand (a power of two from 8 to k_max); when the
+// demand outgrows it or shrinks well below it, a new open set of the right
+// width takes the new requests and the old one drains. Requests take the
+// lowest free column, and a set's kernels look only at the power-of-two
+// prefix of columns that covers the occupied ones. A worker thread moves every set on its own: when the work queued for a
+// set has finished, it reads out the columns that finished (which frees
+// them), starts waiting requests in free columns (the other columns keep
+// their state: the columns of a batch are independent solves), and queues
+// the residual passes its columns are waiting for, the next chunk of cycles
+// and the read-back of the column states. A new set is allocated when a
+// graph's requests find no free column and the HBM budget allows it; idle
+// sets are released to make room; a request that cannot be placed waits (an
 // admission stall).
 
 #include <algorithm>
@@ -32,6 +36,8 @@
 
 namespace di {
 namespace {
+
+constexpr int kMaxSetsPerGraph = 64;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -56,20 +62,32 @@ struct Lane {
   double t_submit = 0.0;
 };
 
-struct GraphSlot {
-  const di_graph* g = nullptr;
-  int32_t id = 0;
-  std::deque<Request> pending;
+struct GraphSlot;
+
+// One batch workspace of a graph. `active` and `d` change under the server
+// mutex; the rest is the worker's.
+struct ColumnSet {
+  GraphSlot* owner = nullptr;
+  int kp = 8;                 // columns of this set
   BatchWs* ws = nullptr;
-  size_t ws_bytes = 0;
+  size_t bytes = 0;
   double d = 0.85;
   std::vector<Lane> lanes;
   int active = 0;
   double* out_dev = nullptr;  // one column read out (n doubles)
-  bool stalled = false;       // counted once per stall episode
   hipStream_t stream = nullptr;
-  hipEvent_t ev = nullptr;    // end of the graph's queued work
+  hipEvent_t ev = nullptr;    // end of the set's queued work
   bool launched = false;
+  bool ready = false;         // workspace, stream and event exist
+  bool draining = false;      // takes no new requests; freed once idle
+};
+
+struct GraphSlot {
+  const di_graph* g = nullptr;
+  int32_t id = 0;
+  std::deque<Request> pending;
+  std::vector<ColumnSet*> sets;
+  bool stalled = false;  // counted once per stall episode
 };
 
 }  // namespace
@@ -91,7 +109,7 @@ struct di_server {
   double busy_seconds = 0.0;
   std::string worker_error;
   std::thread worker;
-  // device staging for starting columns
+  // device staging for starting columns (used by one set at a time)
   int* d_flag = nullptr;
   double* d_buni = nullptr;
   int* d_col = nullptr;
@@ -108,62 +126,99 @@ namespace {
 bool refine_of(const di_server* s) { return s->opts.precision == DI_FP32_REFINE; }
 int prec_of(const di_server* s) { return s->opts.precision == DI_FP64 ? kF64 : kF32; }
 
-BatchArgs args_of(const di_server* s, const GraphSlot* gs) {
+// The working width of a set: its occupied columns are the lowest ones
+// (requests take the lowest free column), so the cycle kernels only look
+// at the power of two that covers the highest occupied column.
+int pow2_at_least(int k) {
+  int p = 8;
+  while (p < k) p <<= 1;
+  return p;
+}
+
+int working_width(const ColumnSet* cs) {
+  int hi = 0;
+  for (int c = 0; c < (int)cs->lanes.size(); ++c)
+    if (cs->lanes[(size_t)c].ticket != 0) hi = c + 1;
+  return std::min(pow2_at_least(hi), cs->kp);
+}
+
+BatchArgs args_of(const di_server* s, const ColumnSet* cs) {
   BatchArgs a{};
-  a.g = gs->g;
-  a.kp = s->kp;
+  a.g = cs->owner->g;
+  a.kp = cs->kp;
+  a.ke = working_width(cs);
   a.prec = prec_of(s);
-  a.d = gs->d;
+  a.d = cs->d;
   a.method = s->opts.method;
   a.max_cycles = s->opts.max_cycles > 0 ? s->opts.max_cycles : 100000;
   a.tol_rel = refine_of(s) ? (s->opts.inner_tol > 0.0 ? s->opts.inner_tol : 1e-5) : -1.0;
-  a.stream = gs->stream;
+  a.stream = cs->stream;
   return a;
 }
 
-size_t slot_bytes(const di_server* s, const di_graph* g) {
-  return batch_ws_bytes(g, s->kp, prec_of(s), refine_of(s)) + (size_t)g->n * sizeof(double);
+size_t set_bytes(const di_server* s, const di_graph* g, int kp) {
+  return batch_ws_bytes(g, kp, prec_of(s), refine_of(s)) + (size_t)g->n * sizeof(double);
 }
 
-// Under s->mu: makes room for gs's slot set (releasing idle slot sets of
-// other graphs); true when the bytes are reserved.
-bool reserve_slot(di_server* s, GraphSlot* gs, std::vector<GraphSlot*>* to_free) {
-  const size_t need = slot_bytes(s, gs->g);
+bool set_idle(const ColumnSet* cs) { return cs->active == 0 && !cs->launched; }
+
+// Under s->mu: reserves the bytes of a new set for gs, taking idle sets of
+// graphs without waiting requests out of the books (the caller frees them
+// outside the lock). True when the bytes are reserved.
+bool reserve_set(di_server* s, GraphSlot* gs, int kp, std::vector<ColumnSet*>* to_free) {
+  const size_t need = set_bytes(s, gs->g, kp);
   if (s->in_use + need > s->budget) {
     for (auto& kv : s->graphs) {
       GraphSlot* o = kv.second;
-      if (o == gs || !o->ws || o->launched || o->active > 0 || !o->pending.empty()) continue;
-      to_free->push_back(o);
-      s->in_use -= o->ws_bytes;  // released below, outside the lock
+      if (o == gs || !o->pending.empty()) continue;
+      for (size_t q = 0; q < o->sets.size() && s->in_use + need > s->budget;) {
+        ColumnSet* cs = o->sets[q];
+        if (cs->ready && set_idle(cs)) {
+          s->in_use -= cs->bytes;
+          to_free->push_back(cs);
+          o->sets.erase(o->sets.begin() + (long)q);
+        } else {
+          ++q;
+        }
+      }
       if (s->in_use + need <= s->budget) break;
     }
   }
   if (s->in_use + need > s->budget) return false;
   s->in_use += need;
-  gs->ws_bytes = need;
   return true;
 }
 
-di_status create_slot_ws(di_server* s, GraphSlot* gs) {
-  const BatchArgs a = args_of(s, gs);
-  BatchWs* ws = nullptr;
-  DI_TRY(batch_ws_create(gs->g, s->kp, a.prec, refine_of(s), &ws));
-  gs->ws = ws;
-  hipError_t err = hipMalloc((void**)&gs->out_dev, (size_t)gs->g->n * sizeof(double));
+void destroy_set(ColumnSet* cs) {
+  if (cs->stream) (void)hipStreamSynchronize(cs->stream);
+  if (cs->ws) free_batch_ws(cs->ws);
+  if (cs->out_dev) (void)hipFree(cs->out_dev);
+  if (cs->ev) (void)hipEventDestroy(cs->ev);
+  if (cs->stream) (void)hipStreamDestroy(cs->stream);
+  delete cs;
+}
+
+di_status create_set_ws(di_server* s, ColumnSet* cs) {
+  const di_graph* g = cs->owner->g;
+  DI_HIP(hipStreamCreate(&cs->stream));
+  DI_HIP(hipEventCreateWithFlags(&cs->ev, hipEventDisableTiming));
+  DI_TRY(batch_ws_create(g, cs->kp, prec_of(s), refine_of(s), &cs->ws));
+  hipError_t err = hipMalloc((void**)&cs->out_dev, (size_t)g->n * sizeof(double));
   if (err != hipSuccess) {
-    gs->out_dev = nullptr;
+    cs->out_dev = nullptr;
     set_error(std::string("hipMalloc: ") + hipGetErrorString(err));
     return DI_E_NOMEM;
   }
-  for (int c = 0; c <= s->kp; ++c) {
+  for (int c = 0; c <= cs->kp; ++c) {
     BCtl b;
     std::memset(&b, 0, sizeof(b));
     b.state = kBIdle;
-    ws->host_bctl[c] = b;
+    cs->ws->host_bctl[c] = b;
   }
-  DI_HIP(hipMemcpyAsync(ws->bctl, ws->host_bctl, (size_t)(s->kp + 1) * sizeof(BCtl),
-                        hipMemcpyHostToDevice, gs->stream));
-  gs->lanes.assign((size_t)s->kp, Lane{});
+  DI_HIP(hipMemcpyAsync(cs->ws->bctl, cs->ws->host_bctl, (size_t)(cs->kp + 1) * sizeof(BCtl),
+                        hipMemcpyHostToDevice, cs->stream));
+  cs->lanes.assign((size_t)cs->kp, Lane{});
+  cs->ready = true;
   return DI_OK;
 }
 
@@ -182,21 +237,21 @@ di_status ensure_seed_staging(di_server* s, size_t count) {
   return DI_OK;
 }
 
-// Starts the requests in free columns of gs's slot set.
-di_status start_requests(di_server* s, GraphSlot* gs, std::vector<Request>& reqs) {
-  const BatchArgs a = args_of(s, gs);
-  const int kp = s->kp;
+// Starts the requests in the lowest free columns of cs.
+di_status start_requests(di_server* s, ColumnSet* cs, std::vector<Request>& reqs) {
+  const BatchArgs a = args_of(s, cs);
+  const int kp = cs->kp;
   std::vector<int> flag((size_t)kp, 0), col;
   std::vector<double> buni((size_t)kp, 0.0), val, tol;
   std::vector<int64_t> off{0};
   std::vector<int32_t> seeds;
   int c = 0;
   for (Request& r : reqs) {
-    while (gs->lanes[(size_t)c].ticket != 0) ++c;
-    gs->lanes[(size_t)c] = Lane{r.ticket, r.t_submit};
+    while (cs->lanes[(size_t)c].ticket != 0) ++c;
+    cs->lanes[(size_t)c] = Lane{r.ticket, r.t_submit};
     flag[(size_t)c] = 1;
     col.push_back(c);
-    const double v = r.seeds.empty() ? (1.0 - r.d) / (double)gs->g->n
+    const double v = r.seeds.empty() ? (1.0 - r.d) / (double)a.g->n
                                      : (1.0 - r.d) / (double)r.seeds.size();
     if (r.seeds.empty()) buni[(size_t)c] = v;
     val.push_back(v);
@@ -206,45 +261,46 @@ di_status start_requests(di_server* s, GraphSlot* gs, std::vector<Request>& reqs
   }
   DI_TRY(ensure_seed_staging(s, seeds.size()));
   const int nc = (int)col.size();
-  DI_HIP(hipMemcpyAsync(s->d_flag, flag.data(), (size_t)kp * sizeof(int), hipMemcpyHostToDevice, gs->stream));
-  DI_HIP(hipMemcpyAsync(s->d_buni, buni.data(), (size_t)kp * sizeof(double), hipMemcpyHostToDevice, gs->stream));
-  DI_HIP(hipMemcpyAsync(s->d_col, col.data(), (size_t)nc * sizeof(int), hipMemcpyHostToDevice, gs->stream));
-  DI_HIP(hipMemcpyAsync(s->d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, gs->stream));
-  DI_HIP(hipMemcpyAsync(s->d_val, val.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, gs->stream));
-  DI_HIP(hipMemcpyAsync(s->d_tol, tol.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, gs->stream));
+  hipStream_t st = cs->stream;
+  DI_HIP(hipMemcpyAsync(s->d_flag, flag.data(), (size_t)kp * sizeof(int), hipMemcpyHostToDevice, st));
+  DI_HIP(hipMemcpyAsync(s->d_buni, buni.data(), (size_t)kp * sizeof(double), hipMemcpyHostToDevice, st));
+  DI_HIP(hipMemcpyAsync(s->d_col, col.data(), (size_t)nc * sizeof(int), hipMemcpyHostToDevice, st));
+  DI_HIP(hipMemcpyAsync(s->d_off, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  DI_HIP(hipMemcpyAsync(s->d_val, val.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, st));
+  DI_HIP(hipMemcpyAsync(s->d_tol, tol.data(), (size_t)nc * sizeof(double), hipMemcpyHostToDevice, st));
   if (!seeds.empty())
     DI_HIP(hipMemcpyAsync(s->d_seeds, seeds.data(), seeds.size() * sizeof(int32_t),
-                          hipMemcpyHostToDevice, gs->stream));
+                          hipMemcpyHostToDevice, st));
   ColInit ci{nc, s->d_flag, s->d_buni, s->d_col, s->d_off, s->d_seeds, s->d_val, s->d_tol};
-  DI_HIP(launch_bcol_init(a, gs->ws, ci));
-  // the host copies are pageable: wait before they go out of scope
-  DI_HIP(hipStreamSynchronize(gs->stream));
+  DI_HIP(launch_bcol_init(a, cs->ws, ci));
+  // the host copies are pageable and the staging is shared: wait
+  DI_HIP(hipStreamSynchronize(st));
   return DI_OK;
 }
 
-// Reads out the finished columns and completes their tickets.
-di_status finish_columns(di_server* s, GraphSlot* gs) {
-  const BatchArgs a = args_of(s, gs);
-  BatchWs* ws = gs->ws;
-  const di_graph* g = gs->g;
-  for (int c = 0; c < s->kp; ++c) {
-    Lane& ln = gs->lanes[(size_t)c];
+// Reads out cs's finished columns and completes their tickets.
+di_status finish_columns(di_server* s, ColumnSet* cs) {
+  const BatchArgs a = args_of(s, cs);
+  BatchWs* ws = cs->ws;
+  const di_graph* g = a.g;
+  for (int c = 0; c < cs->kp; ++c) {
+    Lane& ln = cs->lanes[(size_t)c];
     const BCtl& b = ws->host_bctl[c];
     if (ln.ticket == 0 || !(b.state == kBConv || b.state == kBMaxCyc || b.state == kBNonFinite))
       continue;
     Result res;
     res.status = b.state == kBConv ? DI_OK : (b.state == kBMaxCyc ? DI_E_NOCONV : DI_E_INVAL);
     res.X.resize((size_t)g->n);
-    DI_HIP(launch_bcol_out(a, ws, c, refine_of(s), gs->out_dev));
-    DI_HIP(hipMemcpyAsync(res.X.data(), gs->out_dev, (size_t)g->n * sizeof(double),
-                          hipMemcpyDeviceToHost, gs->stream));
+    DI_HIP(launch_bcol_out(a, ws, c, refine_of(s), cs->out_dev));
+    DI_HIP(hipMemcpyAsync(res.X.data(), cs->out_dev, (size_t)g->n * sizeof(double),
+                          hipMemcpyDeviceToHost, cs->stream));
     // the column is free again
     BCtl idle = b;
     idle.state = kBIdle;
     ws->host_bctl[c] = idle;
     DI_HIP(hipMemcpyAsync(ws->bctl + c, &ws->host_bctl[c], sizeof(BCtl), hipMemcpyHostToDevice,
-                          gs->stream));
-    DI_HIP(hipStreamSynchronize(gs->stream));
+                          cs->stream));
+    DI_HIP(hipStreamSynchronize(cs->stream));
     di_stats& t = res.stats;
     std::memset(&t, 0, sizeof(t));
     t.cycles = b.cycles;
@@ -253,34 +309,34 @@ di_status finish_columns(di_server* s, GraphSlot* gs) {
     t.edges_pushed = (int64_t)b.edges;
     t.nb_iter = g->L > 0 ? (double)b.edges / (double)g->L : 0.0;
     t.resid_l1 = b.final_r;
-    t.err_bound = b.final_r / (1.0 - gs->d);
+    t.err_bound = b.final_r / (1.0 - cs->d);
     t.e = b.e;
     t.seconds = now_s() - ln.t_submit;  // latency: submission to completion
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->results[ln.ticket] = std::move(res);
       s->completed += 1;
-      gs->active -= 1;
+      cs->active -= 1;
     }
     ln = Lane{};
   }
   return DI_OK;
 }
 
-// Queues gs's next work on its stream: the residual passes of the
-// columns whose FP32 pass ended (states from the last read-back), a chunk
-// of cycles, and the read-back of the column states.
-di_status launch_slot(di_server* s, GraphSlot* gs) {
-  const BatchArgs a = args_of(s, gs);
-  BatchWs* ws = gs->ws;
-  const int kp = s->kp;
+// Queues cs's next work on its stream: the residual passes of the columns
+// whose FP32 pass ended (states from the last read-back), a chunk of
+// cycles, and the read-back of the column states.
+di_status launch_set(di_server* s, ColumnSet* cs) {
+  const BatchArgs a = args_of(s, cs);
+  BatchWs* ws = cs->ws;
+  const int kp = cs->kp;
   bool inner = false;
   int need = 2;
   for (int c = 0; c < kp; ++c) {
     const BCtl& b = ws->host_bctl[c];
     inner |= b.state == kBInner;
     // a column just started has no read-back state yet
-    if (gs->lanes[(size_t)c].ticket != 0 && b.state == kBIdle) need = std::max(need, 16);
+    if (cs->lanes[(size_t)c].ticket != 0 && b.state == kBIdle) need = std::max(need, 16);
     if (b.state != kBRun) continue;
     int nc = 16;
     const double target = a.tol_rel >= 0.0 ? std::max(0.5 * b.tol, a.tol_rel * b.r_start) : b.tol;
@@ -301,9 +357,9 @@ di_status launch_slot(di_server* s, GraphSlot* gs) {
   const int chunk = std::max(2, std::min(need, 16));
   for (int q = 0; q < chunk; ++q) DI_HIP(launch_bcycle(a, ws, nullptr, nullptr));
   DI_HIP(hipMemcpyAsync(ws->host_bctl, ws->bctl, (size_t)(kp + 1) * sizeof(BCtl),
-                        hipMemcpyDeviceToHost, gs->stream));
-  DI_HIP(hipEventRecord(gs->ev, gs->stream));
-  gs->launched = true;
+                        hipMemcpyDeviceToHost, cs->stream));
+  DI_HIP(hipEventRecord(cs->ev, cs->stream));
+  cs->launched = true;
   return DI_OK;
 }
 
@@ -312,111 +368,192 @@ void fail_all(di_server* s, di_status st, const std::string& msg) {
   s->worker_error = msg;
   for (auto& kv : s->graphs) {
     GraphSlot* gs = kv.second;
-    for (Lane& ln : gs->lanes)
-      if (ln.ticket) {
-        s->results[ln.ticket].status = st;
-        ln = Lane{};
-      }
+    for (ColumnSet* cs : gs->sets) {
+      for (Lane& ln : cs->lanes)
+        if (ln.ticket) {
+          s->results[ln.ticket].status = st;
+          ln = Lane{};
+        }
+      cs->active = 0;
+    }
     for (Request& r : gs->pending) s->results[r.ticket].status = st;
     gs->pending.clear();
-    gs->active = 0;
   }
 }
 
-// The worker: graphs progress independently. A graph whose queued work has
+bool graph_busy(const GraphSlot* gs) {
+  if (!gs->pending.empty()) return true;
+  for (const ColumnSet* cs : gs->sets)
+    if (cs->launched || cs->active > 0) return true;
+  return false;
+}
+
+struct Placement {
+  ColumnSet* cs;
+  std::vector<Request> reqs;
+};
+
+// Under s->mu: places waiting requests of gs. A graph has at most one open
+// set (the others drain: they take no new requests and are freed once
+// idle). The open set's width follows the demand (columns in use plus
+// requests waiting, as a power of two from 8 to k_max): when the demand
+// outgrows it, or falls to a quarter of it, a new open set of the demanded
+// width is reserved (*fresh, not yet created) and the old one drains. A set
+// takes requests of its own d; an idle open set takes the d of the next
+// request. Idle sets of other graphs released to make room go to *to_free.
+void place_requests(di_server* s, GraphSlot* gs, std::vector<Placement>* out,
+                    ColumnSet** fresh, std::vector<ColumnSet*>* to_free) {
+  *fresh = nullptr;
+  if (gs->pending.empty()) return;
+  ColumnSet* open = nullptr;
+  int demand = (int)gs->pending.size();
+  for (ColumnSet* cs : gs->sets) {
+    demand += cs->active;
+    if (!cs->draining) open = cs;
+  }
+  const int want = std::min(pow2_at_least(demand), s->kp);
+  if (open && open->ready && open->active == 0) open->d = gs->pending.front().d;
+  const bool resize = !open || want > open->kp || want * 4 <= open->kp;
+  if (open && open->ready) {
+    Placement p{open, {}};
+    while (open->active + (int)p.reqs.size() < open->kp && !gs->pending.empty() &&
+           gs->pending.front().d == open->d && !resize) {
+      p.reqs.push_back(std::move(gs->pending.front()));
+      gs->pending.pop_front();
+    }
+    if (!p.reqs.empty()) {
+      open->active += (int)p.reqs.size();  // columns taken (started by the worker)
+      out->push_back(std::move(p));
+    }
+  }
+  if (gs->pending.empty()) {
+    gs->stalled = false;
+    return;
+  }
+  if (!resize && open) return;  // the open set is full: wait for its columns
+  if ((int)gs->sets.size() >= kMaxSetsPerGraph) return;
+  if (!reserve_set(s, gs, want, to_free)) {
+    if (!gs->stalled) {
+      s->stalls += 1;
+      gs->stalled = true;
+    }
+    return;
+  }
+  gs->stalled = false;
+  if (open) open->draining = true;
+  ColumnSet* cs = new ColumnSet;
+  cs->owner = gs;
+  cs->kp = want;
+  cs->bytes = set_bytes(s, gs->g, want);
+  cs->d = gs->pending.front().d;
+  Placement p{cs, {}};
+  while ((int)p.reqs.size() < want && !gs->pending.empty() && gs->pending.front().d == cs->d) {
+    p.reqs.push_back(std::move(gs->pending.front()));
+    gs->pending.pop_front();
+  }
+  cs->active = (int)p.reqs.size();
+  gs->sets.push_back(cs);
+  *fresh = cs;
+  out->push_back(std::move(p));
+}
+
+// Under s->mu: takes gs's idle draining sets out of the books; the caller
+// frees them.
+void retire_drained(di_server* s, GraphSlot* gs, std::vector<ColumnSet*>* to_free) {
+  for (size_t q = 0; q < gs->sets.size();) {
+    ColumnSet* cs = gs->sets[q];
+    if (cs->draining && cs->ready && set_idle(cs)) {
+      s->in_use -= cs->bytes;
+      to_free->push_back(cs);
+      gs->sets.erase(gs->sets.begin() + (long)q);
+    } else {
+      ++q;
+    }
+  }
+}
+
+// The worker: sets progress independently. A set whose queued work has
 // finished (its event) is collected and relaunched at once, with the
 // requests that arrived meanwhile started in its free columns; the loop
-// naps briefly only when no graph could move.
+// naps briefly only when no set could move.
 void worker_loop(di_server* s) {
   (void)hipSetDevice(s->device);
   for (;;) {
     std::vector<GraphSlot*> work;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      auto busy = [](const GraphSlot* gs) {
-        return gs->launched || gs->active > 0 || !gs->pending.empty();
-      };
       s->cv.wait(lk, [&] {
         if (s->stop) return true;
         for (auto& kv : s->graphs)
-          if (busy(kv.second)) return true;
+          if (graph_busy(kv.second)) return true;
         return false;
       });
       if (s->stop) return;
       for (auto& kv : s->graphs)
-        if (busy(kv.second)) work.push_back(kv.second);
+        if (graph_busy(kv.second)) work.push_back(kv.second);
     }
     const double t0 = now_s();
     di_status st = DI_OK;
     bool progressed = false;
     for (GraphSlot* gs : work) {
-      if (gs->launched) {
-        const hipError_t q = hipEventQuery(gs->ev);
+      // collect the sets whose work has finished
+      std::vector<ColumnSet*> sets;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        sets = gs->sets;
+      }
+      for (ColumnSet* cs : sets) {
+        if (!cs->launched) continue;
+        const hipError_t q = hipEventQuery(cs->ev);
         if (q == hipErrorNotReady) {
           (void)hipGetLastError();  // not an error: keep it out of later checks
           continue;
         }
-        gs->launched = false;
+        cs->launched = false;
         if (q != hipSuccess) {
           set_error(std::string("serving worker: ") + hipGetErrorString(q));
           st = DI_E_DEVICE;
           break;
         }
-        st = finish_columns(s, gs);
+        st = finish_columns(s, cs);
         if (st != DI_OK) break;
         progressed = true;
       }
-      std::vector<Request> admit;
-      std::vector<GraphSlot*> to_free;
-      bool need_ws = false;
+      if (st != DI_OK) break;
+      // place waiting requests
+      std::vector<Placement> places;
+      ColumnSet* fresh = nullptr;
+      std::vector<ColumnSet*> to_free;
       {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (!gs->pending.empty()) {
-          if (!gs->ws) {
-            if (reserve_slot(s, gs, &to_free)) {
-              need_ws = true;
-              gs->stalled = false;
-            } else if (!gs->stalled) {
-              s->stalls += 1;
-              gs->stalled = true;
-            }
-          }
-          if (gs->ws || need_ws) {
-            if (gs->active == 0) gs->d = gs->pending.front().d;
-            int free_lanes = s->kp - gs->active;
-            while (free_lanes > 0 && !gs->pending.empty() && gs->pending.front().d == gs->d) {
-              admit.push_back(std::move(gs->pending.front()));
-              gs->pending.pop_front();
-              --free_lanes;
-            }
-            gs->active += (int)admit.size();  // columns taken (started below)
-          }
-        }
+        retire_drained(s, gs, &to_free);
+        place_requests(s, gs, &places, &fresh, &to_free);
+        sets = gs->sets;
       }
-      for (GraphSlot* o : to_free) {
-        if (o->ws) free_batch_ws(o->ws);
-        if (o->out_dev) (void)hipFree(o->out_dev);
-        o->ws = nullptr;
-        o->out_dev = nullptr;
-        o->ws_bytes = 0;
-      }
-      if (need_ws) st = create_slot_ws(s, gs);
-      if (st == DI_OK && !admit.empty()) st = start_requests(s, gs, admit);
-      if (st == DI_OK && gs->ws && gs->active > 0) {
-        st = launch_slot(s, gs);
+      for (ColumnSet* cs : to_free) destroy_set(cs);
+      if (fresh) st = create_set_ws(s, fresh);
+      for (size_t q = 0; st == DI_OK && q < places.size(); ++q)
+        st = start_requests(s, places[q].cs, places[q].reqs);
+      // queue the next work of every set with columns in use
+      for (ColumnSet* cs : sets) {
+        if (st != DI_OK) break;
+        if (!cs->ready || cs->launched || cs->active == 0) continue;
+        st = launch_set(s, cs);
         progressed = true;
       }
       if (st != DI_OK) break;
     }
     if (st != DI_OK) {
       // drain what was queued before failing the requests
-      for (GraphSlot* gs : work)
-        if (gs->launched) {
-          (void)hipEventSynchronize(gs->ev);
-          gs->launched = false;
-        }
-      fail_all(s, st, "serving worker: " + std::string(di_last_error()));
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (auto& kv : s->graphs)
+        for (ColumnSet* cs : kv.second->sets)
+          if (cs->launched) {
+            (void)hipEventSynchronize(cs->ev);
+            cs->launched = false;
+          }
     }
+    if (st != DI_OK) fail_all(s, st, "serving worker: " + std::string(di_last_error()));
     if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
     std::lock_guard<std::mutex> lk(s->mu);
     s->busy_seconds += now_s() - t0;
@@ -504,8 +641,8 @@ di_status di_serve_add_graph(di_server* s, const di_graph* g, int32_t graph_id) 
       di::set_error("di_serve_add_graph: NULL argument");
       return DI_E_INVAL;
     }
-    if (di::slot_bytes(s, g) > s->budget) {
-      di::set_error("the graph's slot set alone exceeds the HBM budget");
+    if (di::set_bytes(s, g, 8) > s->budget) {
+      di::set_error("one column set of the graph exceeds the HBM budget");
       return DI_E_NOMEM;
     }
     std::lock_guard<std::mutex> lk(s->mu);
@@ -516,18 +653,6 @@ di_status di_serve_add_graph(di_server* s, const di_graph* g, int32_t graph_id) 
     di::GraphSlot* gs = new di::GraphSlot;
     gs->g = g;
     gs->id = graph_id;
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    if (cur != s->device) (void)hipSetDevice(s->device);
-    hipError_t err = hipStreamCreate(&gs->stream);
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&gs->ev, hipEventDisableTiming);
-    if (cur != s->device) (void)hipSetDevice(cur);
-    if (err != hipSuccess) {
-      if (gs->stream) (void)hipStreamDestroy(gs->stream);
-      delete gs;
-      di::set_error(std::string("di_serve_add_graph: ") + hipGetErrorString(err));
-      return DI_E_DEVICE;
-    }
     s->graphs[graph_id] = gs;
     return DI_OK;
   });
@@ -612,7 +737,7 @@ di_status di_serve_info(di_server* s, di_serve_stats* out) {
   out->admission_stalls = s->stalls;
   int64_t active = 0, pending = 0;
   for (auto& kv : s->graphs) {
-    active += kv.second->active;
+    for (const di::ColumnSet* cs : kv.second->sets) active += cs->active;
     pending += (int64_t)kv.second->pending.size();
   }
   out->active = active;
@@ -633,13 +758,8 @@ void di_serve_destroy(di_server* s) {
   int cur = 0;
   if (hipGetDevice(&cur) == hipSuccess && cur != s->device) (void)hipSetDevice(s->device);
   for (auto& kv : s->graphs) {
-    di::GraphSlot* gs = kv.second;
-    if (gs->stream) (void)hipStreamSynchronize(gs->stream);
-    if (gs->ws) di::free_batch_ws(gs->ws);
-    if (gs->out_dev) (void)hipFree(gs->out_dev);
-    if (gs->ev) (void)hipEventDestroy(gs->ev);
-    if (gs->stream) (void)hipStreamDestroy(gs->stream);
-    delete gs;
+    for (di::ColumnSet* cs : kv.second->sets) di::destroy_set(cs);
+    delete kv.second;
   }
   void* ptrs[] = {s->d_flag, s->d_buni, s->d_col, s->d_off, s->d_val, s->d_tol, s->d_seeds};
   for (void* p : ptrs) (void)hipFree(p);

@@ -164,3 +164,23 @@ def random_small_graph(n: int, p_edge: float, rng, self_loops: bool = True):
         np.fill_diagonal(mask, False)
     src, dst = np.nonzero(mask)
     return src.astype(np.int32), dst.astype(np.int32)
+
+
+def transpose(src, dst):
+    """The transposed link list (every link j -> i becomes i -> j), sorted
+    by (origin, destination): the workload of P's transpose, where the
+    generator's in-degree hubs become out-degree hubs."""
+    s = np.ascontiguousarray(dst, dtype=np.int32)
+    t = np.ascontiguousarray(src, dtype=np.int32)
+    order = np.lexsort((t, s))
+    return s[order], t[order]
+
+
+def prefix_subgraph(m: int, src, dst):
+    """The subgraph induced on the node ids [0, m): the links with both ends
+    below m, in the original (sorted) order."""
+    src = np.asarray(src)
+    dst = np.asarray(dst)
+    keep = (src < m) & (dst < m)
+    return (np.ascontiguousarray(src[keep], dtype=np.int32),
+            np.ascontiguousarray(dst[keep], dtype=np.int32))

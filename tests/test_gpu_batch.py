@@ -2,7 +2,8 @@
 the CPU oracle, one oracle solve per column.
 
 Reading: each column is its own DI-SOP solve, so column c must satisfy
-|X_c - X_ref_c|_1 <= tol_c / (1 - d) (the error bound of Section 2.2) plus
+|X_c - X_ref_c|_1 <= tol_c / (1 - d) (the columns of P sum to at most d, so
+|(I - P)^-1|_1 <= 1 / (1 - d) bounds the error by the residual) plus
 the oracle's own 1e-13, and its residual recomputed by the oracle must be
 within tol_c. Columns with the same right-hand side in one batch go through
 the same arithmetic and must agree bit for bit.

@@ -5,8 +5,8 @@ it that runs by default. Set DI_LARGE=1 to run the 50M case.
 At these sizes the oracle's full solve is slow, so the bar is the
 property that holds at any size: the residual |B + P.X - X|_1 of the GPU's
 X, recomputed by the oracle in FP64, is within tol, which bounds
-|X - X_exact|_1 by tol / (1 - d) (Section 2.2). At 5M nodes the oracle's
-solve is also compared entry by entry.
+|X - X_exact|_1 by tol / (1 - d) (P's columns sum to at most d). At 5M
+nodes the oracle's solve is also compared entry by entry.
 """
 
 import os

@@ -5,7 +5,8 @@ The residual pass is compared entry by entry with the oracle's R = B + P.X
 - X, within a rounding bound derived from the magnitudes that enter each
 entry. A refined solve must return an X whose residual, recomputed by the
 oracle, is within tol, and whose distance to the oracle's X is within the
-error bound tol / (1 - d) of Section 2.2 plus the oracle's own 1e-13.
+error bound tol / (1 - d) (P's columns sum to at most d) plus the oracle's
+own 1e-13.
 """
 
 import numpy as np

@@ -3,7 +3,8 @@ PageRank requests) through the C ABI.
 
 Every finished request is checked against the CPU oracle: its residual,
 recomputed by the oracle, must be within its tolerance, and its distance to
-the oracle's solution within tol / (1 - d) (Section 2.2) plus 1e-12. A
+the oracle's solution within tol / (1 - d) (the residual bound: P's columns
+sum to at most d) plus 1e-12. A
 request served alone and the same request served in a mix of others must
 both pass; they may differ only within those bounds.
 """

@@ -115,3 +115,24 @@ def test_small_and_degenerate_sizes():
             assert np.all(src != dst) and np.all(dst < n)
     with pytest.raises(ValueError):
         graphgen.web_graph(-1)
+
+
+def test_transpose_and_prefix_subgraph():
+    n = 3000
+    src, dst = graphgen.web_graph(n, seed=4)
+    ts, td = graphgen.transpose(src, dst)
+    # sorted by (origin, destination), the same link set reversed
+    key = ts.astype(np.int64) * n + td
+    assert np.all(np.diff(key) > 0)
+    assert set(zip(ts.tolist(), td.tolist())) == set(zip(dst.tolist(), src.tolist()))
+    st = graphgen.graph_stats(n, src, dst)
+    tt = graphgen.graph_stats(n, ts, td)
+    assert tt.L == st.L and tt.max_in == st.max_out and tt.max_out == st.max_in
+    # transposing twice gives the original list back
+    bs, bd = graphgen.transpose(ts, td)
+    assert np.array_equal(bs, src) and np.array_equal(bd, dst)
+    m = 1000
+    ps, pd = graphgen.prefix_subgraph(m, src, dst)
+    assert np.all(ps < m) and np.all(pd < m)
+    expect = [(a, b) for a, b in zip(src.tolist(), dst.tolist()) if a < m and b < m]
+    assert list(zip(ps.tolist(), pd.tolist())) == expect
