@@ -24,8 +24,11 @@
 // the same pull and heavy kernels with y = d X / out as the senders' rows,
 // for the columns waiting for it.
 //
-// Lane layout: a group of G = min(KP, 64) lanes holds one node's KP values,
-// V = KP / G consecutive columns per lane; a wave holds P = 64 / G groups.
+// Lane layout: a group of G = KP / V lanes holds one node's KP values, V = 8
+// consecutive columns per lane (one 32-byte access in FP32; V = 4 at KP =
+// 256); a wave holds P = 64 / G groups. In the pull each group walks its share of an item's
+// links, so narrow batches get many short shares with their gathers in
+// flight together.
 
 #include <algorithm>
 #include <type_traits>
@@ -37,11 +40,14 @@ namespace {
 
 template <int KP>
 struct Lay {
-  static constexpr int G = KP < 64 ? KP : 64;
-  static constexpr int P = 64 / G;
-  static constexpr int V = KP / G;
+  // consecutive columns per lane: 8 (32 or 64 bytes); the widest batches
+  // keep 4 (64 lanes per node), which measured faster there
+  static constexpr int V = KP >= 256 ? 4 : 8;
+  static constexpr int G = KP / V;   // lanes per node
+  static constexpr int P = 64 / G;   // nodes (or link shares) per wave
   static constexpr int NW = kBBlock / 64;
   static constexpr int NG = NW * P;
+  static_assert(KP >= V && KP % V == 0 && G <= 64, "KP: a multiple of 8, at most 512");
 };
 
 __device__ inline double to_d(double x) { return x; }
@@ -330,9 +336,13 @@ __global__ __launch_bounds__(kBBlock) void k_bselect(
             ++fnodes;
           }
         }
+        if constexpr (G == 1) {
+          word |= b;  // one node per lane: the ballot is the word
+        } else {
 #pragma unroll
-        for (int g2 = 0; g2 < P; ++g2)
-          if ((b >> (g2 * G)) & gmask) word |= 1ull << (t * P + g2);
+          for (int g2 = 0; g2 < P; ++g2)
+            if ((b >> (g2 * G)) & gmask) word |= 1ull << (t * P + g2);
+        }
       }
     }
     if (lane == 0) front_bits[w] = word;
