@@ -103,6 +103,23 @@ __device__ A block_sum_all(A v, A* lds) {
   return t;
 }
 
+// Sum of v[q * stride] for q in [q0, q1), added in order; the loads are
+// issued eight at a time so a long run does not wait on each one.
+__device__ inline double ordered_sum(const double* __restrict__ v, int64_t q0, int64_t q1,
+                                     int64_t stride) {
+  double acc = 0.0;
+  int64_t q = q0;
+  for (; q + 8 <= q1; q += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = v[(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += t[u];
+  }
+  for (; q < q1; ++q) acc += v[q * stride];
+  return acc;
+}
+
 // Per-column block totals of acc (each thread holds columns gl*V + v),
 // written to out[0, KW). lds: (kBBlock / 64) * KW values. Fixed order.
 template <int KW, typename A>
@@ -624,8 +641,7 @@ __global__ __launch_bounds__(kBBlock) void k_bheavy(
   double rsum = 0.0;
   for (int64_t h = (int64_t)blockIdx.x * HPB + hs; h < n_heavy; h += (int64_t)gridDim.x * HPB) {
     const int64_t row = heavy_row[h];
-    double acc = 0.0;
-    for (int64_t q = heavy_seg[h]; q < heavy_seg[h + 1]; ++q) acc += segv[q * KP + c];
+    const double acc = ordered_sum(segv + c, heavy_seg[h], heavy_seg[h + 1], KP);
     const int64_t qi = row * KP + c;
     if (MODE == 0) {
       double f = to_d(io.F[qi]);
@@ -714,12 +730,20 @@ __global__ __launch_bounds__(kBBlock) void k_breduce(
   const bool mine = FIRST ? state == want : state == kBRun;
   if (!mine) return;
   double r = 0.0;
-  for (int q = tid; q < nrec; q += kBBlock) r += rec[(int64_t)q * KP + c];
+  for (int q0 = tid; q0 < nrec; q0 += 8 * kBBlock) {  // 8 loads in flight, same order
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = q0 + u * kBBlock;
+      t[u] = q < nrec ? rec[(int64_t)q * KP + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r += t[u];
+  }
   if (!FIRST) {
     for (int64_t h = tid; h < n_heavy; h += kBBlock) {
       const int64_t qi = (int64_t)heavy_row[h] * KP + c;
-      double acc = 0.0;
-      for (int64_t q = heavy_seg[h]; q < heavy_seg[h + 1]; ++q) acc += segv[q * KP + c];
+      const double acc = ordered_sum(segv + c, heavy_seg[h], heavy_seg[h + 1], KP);
       double f = to_d(F[qi]);
       if (acc != 0.0) {
         const T nv = (T)(f + acc);

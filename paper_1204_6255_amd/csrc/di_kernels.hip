@@ -62,6 +62,23 @@ __device__ V block_sum(V v, V* lds) {
   return total;
 }
 
+// Sum of v[q * stride] for q in [q0, q1), added in order; the loads are
+// issued eight at a time so a long run does not wait on each one.
+__device__ inline double ordered_sum(const double* __restrict__ v, int64_t q0, int64_t q1,
+                                     int64_t stride) {
+  double acc = 0.0;
+  int64_t q = q0;
+  for (; q + 8 <= q1; q += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = v[(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += t[u];
+  }
+  for (; q < q1; ++q) acc += v[q * stride];
+  return acc;
+}
+
 __device__ inline void part_add(Part& a, const Part& b) {
   a.pabs += b.pabs;
   a.psum += b.psum;
@@ -861,8 +878,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_refine_heavy(
   Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
   for (int64_t h = threadIdx.x; h < n_heavy; h += blockDim.x) {
     const int64_t row = heavy_row[h];
-    double acc = 0.0;
-    for (int64_t q = heavy_seg[h]; q < heavy_seg[h + 1]; ++q) acc += seg_val[q];
+    const double acc = ordered_sum(seg_val, heavy_seg[h], heavy_seg[h + 1], 1);
     const double bi = B ? B[row] : b_uniform;
     const double self = (info[row] & kLoopBit) ? y[row] : 0.0;
     const double r = bi - X[row] + self + acc;
