@@ -24,11 +24,11 @@
 // the same pull and heavy kernels with y = d X / out as the senders' rows,
 // for the columns waiting for it.
 //
-// Lane layout: a group of G = KP / V lanes holds one node's KP values, V = 8
-// consecutive columns per lane (one 32-byte access in FP32; V = 4 at KP =
-// 256); a wave holds P = 64 / G groups. In the pull each group walks its share of an item's
-// links, so narrow batches get many short shares with their gathers in
-// flight together.
+// Lane layouts (per kernel; the memory layout is shared): the pull gives a
+// lane 8 consecutive columns (one 32-byte gather in FP32; 4 at 256 columns)
+// so each lane group walks a short share of an item's links and narrow
+// batches get many shares with their gathers in flight together; the
+// selection keeps one column per lane up to 64 columns.
 
 #include <algorithm>
 #include <type_traits>
@@ -38,17 +38,27 @@
 namespace di {
 namespace {
 
-template <int KP>
-struct Lay {
-  // consecutive columns per lane: 8 (32 or 64 bytes); the widest batches
-  // keep 4 (64 lanes per node), which measured faster there
-  static constexpr int V = KP >= 256 ? 4 : 8;
-  static constexpr int G = KP / V;   // lanes per node
-  static constexpr int P = 64 / G;   // nodes (or link shares) per wave
+// Lane layouts: a group of G = KP / V lanes holds one node's KP values, V
+// consecutive columns per lane; a wave holds P = 64 / G groups. The memory
+// layout ([n][KP]) is the same for every kernel; the lane layout is each
+// kernel's own choice.
+template <int KP, int V_>
+struct LayV {
+  static constexpr int V = V_;
+  static constexpr int G = KP / V;
+  static constexpr int P = 64 / G;
   static constexpr int NW = kBBlock / 64;
   static constexpr int NG = NW * P;
-  static_assert(KP >= V && KP % V == 0 && G <= 64, "KP: a multiple of 8, at most 512");
+  static_assert(KP % V == 0 && G >= 1 && G <= 64, "lane layout");
 };
+// selection: one column per lane up to 64 columns (per-column work stays
+// spread over lanes)
+template <int KP>
+using LaySel = LayV<KP, (KP <= 64 ? 1 : KP / 64)>;
+// pull: 8 columns per lane (one 32-byte gather in FP32), so each lane group
+// walks a short share of an item's links; 4 at 256 columns
+template <int KP>
+using Lay = LayV<KP, (KP >= 256 ? 4 : 8)>;
 
 __device__ inline double to_d(double x) { return x; }
 __device__ inline double to_d(float x) { return (double)x; }
@@ -122,9 +132,8 @@ __device__ inline double ordered_sum(const double* __restrict__ v, int64_t q0, i
 
 // Per-column block totals of acc (each thread holds columns gl*V + v),
 // written to out[0, KW). lds: (kBBlock / 64) * KW values. Fixed order.
-template <int KW, typename A>
-__device__ inline void col_sum_store(A (&acc)[Lay<KW>::V], A* lds, A* out) {
-  using Ly = Lay<KW>;
+template <typename Ly, int KW, typename A>
+__device__ inline void col_sum_store(A (&acc)[Ly::V], A* lds, A* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int v = 0; v < Ly::V; ++v) acc[v] = group_fold<Ly::G>(acc[v]);
@@ -225,7 +234,7 @@ __global__ __launch_bounds__(kBBlock) void k_brecords(const T* __restrict__ F, i
 #pragma unroll
     for (int v = 0; v < Ly::V; ++v) acc[v] += fabs(to_d(f.v[v]));
   }
-  col_sum_store<KP>(acc, lds, rec + (int64_t)blockIdx.x * KP);
+  col_sum_store<Ly, KP>(acc, lds, rec + (int64_t)blockIdx.x * KP);
 }
 
 // ---- selection ----------------------------------------------------------
@@ -242,7 +251,7 @@ __global__ __launch_bounds__(kBBlock) void k_bselect(
     unsigned long long* __restrict__ front_bits, const uint32_t* __restrict__ info, int64_t n,
     int64_t L, double d, const BCtl* __restrict__ bctl, unsigned long long* __restrict__ rec_ops,
     unsigned int* __restrict__ rec_sel, double* __restrict__ rec_e) {
-  using Ly = Lay<KE>;
+  using Ly = LaySel<KE>;
   constexpr int G = Ly::G, P = Ly::P, V = Ly::V;
   __shared__ double s_rl[KE];
   __shared__ int s_flag[KE];
@@ -366,9 +375,9 @@ __global__ __launch_bounds__(kBBlock) void k_bselect(
   }
   unsigned long long* ro = rec_ops + (int64_t)blockIdx.x * (KP + 1);
   unsigned int* rs = rec_sel + (int64_t)blockIdx.x * (KP + 1);
-  col_sum_store<KE>(ops, s_u64, ro);
-  col_sum_store<KE>(sel, s_u32, rs);
-  col_sum_store<KE>(eab, s_f64, rec_e + (int64_t)blockIdx.x * KP);
+  col_sum_store<Ly, KE>(ops, s_u64, ro);
+  col_sum_store<Ly, KE>(sel, s_u32, rs);
+  col_sum_store<Ly, KE>(eab, s_f64, rec_e + (int64_t)blockIdx.x * KP);
   fops = wave_sum(fops);
   fnodes = wave_sum(fnodes);
   if (lane == 0) {
@@ -622,7 +631,7 @@ __global__ __launch_bounds__(kBBlock) void k_bpull(
     }
     __syncthreads();
   }
-  col_sum_store<KE>(rsum, s_rec, rec + (int64_t)blockIdx.x * KP);
+  col_sum_store<Ly, KE>(rsum, s_rec, rec + (int64_t)blockIdx.x * KP);
 }
 
 // Heavy rows: F += (MODE 1: F = R with) the sum of the row's segment sums,
