@@ -31,6 +31,7 @@ class _Params(ctypes.Structure):
         ("radius", ctypes.c_int32),
         ("p_dangling", ctypes.c_double),
         ("p_local", ctypes.c_double),
+        ("p_forward", ctypes.c_double),
     ]
 
 
@@ -73,14 +74,16 @@ def _load():
 
 
 def web_graph(n: int, seed: int = 0, alpha: float = ALPHA_L_MATCHED, kmax: int = 500,
-              p_dangling: float = 0.15, p_local: float = 0.7, radius: int = 500):
+              p_dangling: float = 0.15, p_local: float = 0.7, radius: int = 500,
+              p_forward: float = 0.0):
     """Return (src, dst) int32 arrays of a synthetic web-like digraph.
 
     Links are sorted by (src, dst), without self-loops or duplicates.
+    p_forward > 0 turns local links forward with that probability.
     """
     lib = _load()
     p = _Params(int(n), int(seed) & ((1 << 64) - 1), float(alpha), int(kmax), int(radius),
-                float(p_dangling), float(p_local))
+                float(p_dangling), float(p_local), float(p_forward))
     h = ctypes.c_void_p()
     rc = lib.dg_generate(ctypes.byref(p), ctypes.byref(h))
     if rc != 0:

@@ -13,6 +13,11 @@
 //     uniform in [-radius, radius] \ {0} (redrawn until the target lies in
 //     [0, n)), else to pi(r) where r ~ Zipf(1) on {1..n} and pi is a random
 //     permutation of the ids drawn once per graph;
+//   * with p_forward > 0, a local link points forward (o > 0) with
+//     probability p_forward (dropped for the last node): mostly-forward
+//     graphs where most nodes lie on no cycle, like the paper's Dataset 2
+//     (E/N 0.91). p_forward = 0 draws no extra number, so such graphs are
+//     the same as without the option;
 //   * self-loops and duplicate links are dropped; links come out sorted by
 //     (origin, destination), the input format of Section 2.1.
 //
@@ -123,6 +128,7 @@ typedef struct dg_params {
   int32_t radius;     // local-link half width
   double p_dangling;  // probability that a node has no out-links
   double p_local;     // probability that a link is local
+  double p_forward;   // probability that a local link points forward
 } dg_params;
 
 typedef struct dg_result {
@@ -149,7 +155,8 @@ int dg_generate(const dg_params* p, dg_result** out) {
   const int64_t n = p->n;
   if (n < 0 || n > 2147483647LL || p->kmax < 1 || p->radius < 1 ||
       !(p->alpha > 0.0) || !(p->p_dangling >= 0.0 && p->p_dangling <= 1.0) ||
-      !(p->p_local >= 0.0 && p->p_local <= 1.0))
+      !(p->p_local >= 0.0 && p->p_local <= 1.0) ||
+      !(p->p_forward >= 0.0 && p->p_forward <= 1.0))
     return -1;
   dg_result* res = new (std::nothrow) dg_result;
   if (!res) return -5;
@@ -200,7 +207,11 @@ int dg_generate(const dg_params* p, dg_result** out) {
           if (g.uniform() < p->p_local) {
             do {
               const int64_t o = (int64_t)g.below(2 * (uint64_t)p->radius);
-              const int64_t off = o < p->radius ? o - p->radius : o - p->radius + 1;
+              int64_t off = o < p->radius ? o - p->radius : o - p->radius + 1;
+              // a forward link from the last node has no target: it is
+              // dropped (as a self-loop would be)
+              if (p->p_forward > 0.0 && g.uniform() < p->p_forward)
+                off = i + 1 < n ? (off < 0 ? -off : off) : 0;
               j = i + off;
             } while (j < 0 || j >= n);
           } else {

@@ -6,6 +6,10 @@
 - prefix subgraphs of the N = 1M graph (the subgraph induced on the node
   ids below m), the paper's way of varying N (Section 2.6, Table 1).
 
+- a graph whose links all point forward (a DAG, every node of the
+  Notations' E class), where DI-CYC ends in finitely many cycles with no
+  fluid left (the finite convergence the paper notes for Dataset 2).
+
 Each solve is compared with the CPU oracle's solution within the error
 bound of the stopping rule (residual / (1 - d)), as in the main parity
 tests.
@@ -91,3 +95,30 @@ def test_prefix_subgraphs(torch_cuda, m):
     assert np.abs(X - ref).sum() <= 1e-9
     _, _, so = oracle.diter(og, B, D, oracle.SOP, oracle.SYNC, tol=TOL_PAR)
     assert abs(st.cycles - so.cycles) <= 1
+
+
+def test_dag_converges_in_finitely_many_cycles(torch_cuda):
+    n = 3000
+    src, dst = graphgen.web_graph(n, seed=2, alpha=graphgen.ALPHA_LITERAL, p_dangling=0.48,
+                                  p_local=1.0, p_forward=1.0)
+    assert np.all(dst > src)
+    # longest path in links: an upper bound on the cycles DI-CYC needs
+    depth = np.zeros(n, np.int64)
+    for a, b in zip(src.tolist(), dst.tolist()):  # sorted by origin: a DAG in id order
+        depth[b] = max(depth[b], depth[a] + 1)
+    og, B, ref = oracle_x(n, src, dst)
+    # one ascending sweep of the oracle's DI-CYC is exact on a forward DAG
+    exact, _, ost = oracle.diter(og, B, D, oracle.CYC, oracle.SEQUENTIAL, tol=1e-300)
+    assert ost.status == oracle.OK and ost.resid_l1 == 0.0
+    g = di.Graph(n, src, dst)
+    o = di.di_opts_default()
+    o.method = di.DI_CYC
+    X = torch_cuda.empty(n, dtype=torch_cuda.float64, device="cuda")
+    status, st = di.di_solve_dev(g.handle, None, D, 1e-300, o, X)
+    assert status == di.DI_OK, di.di_last_error()
+    torch_cuda.cuda.synchronize()
+    assert st.resid_l1 == 0.0 and st.cycles <= int(depth.max()) + 1
+    assert np.abs(X.cpu().numpy() - exact).sum() <= 1e-14
+    # DI-SOP reaches the tolerance on the same graph as well
+    Xs, sts = gpu_x(torch_cuda, n, src, dst)
+    assert np.abs(Xs - ref).sum() <= 1e-9

@@ -136,3 +136,18 @@ def test_transpose_and_prefix_subgraph():
     assert np.all(ps < m) and np.all(pd < m)
     expect = [(a, b) for a, b in zip(src.tolist(), dst.tolist()) if a < m and b < m]
     assert list(zip(ps.tolist(), pd.tolist())) == expect
+
+
+def test_forward_links_give_a_dag():
+    """p_forward = 1 with local links only: every link points forward, so
+    every node converges in finitely many steps (E = N); p_forward = 0
+    leaves the generator's output unchanged."""
+    n = 5000
+    s, d = graphgen.web_graph(n, seed=2, alpha=graphgen.ALPHA_LITERAL, p_dangling=0.48,
+                              p_local=1.0, p_forward=1.0)
+    assert np.all(d > s)
+    st = graphgen.graph_stats(n, s, d)
+    assert st.E == n and st.zero_in >= 1
+    a = graphgen.web_graph(n, seed=2)
+    b = graphgen.web_graph(n, seed=2, p_forward=0.0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
