@@ -28,6 +28,7 @@
 // of the stop test.
 
 #include "di_internal.h"
+#include <hip/hip_ext.h>
 
 namespace di {
 namespace {
@@ -979,23 +980,34 @@ hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t
   Workspace* ws = a.ws;
   const Ctl* ctl = ws->ctl + ((cycle + 1) & 1);
   const int64_t ntiles = select_tiles(g->n, a.direction);
-  hipError_t err;
-  if (ev0 && (err = hipEventRecord(ev0, a.stream)) != hipSuccess) return err;
+  // Timing events travel in the kernel's own dispatch and take its start and
+  // end times (an event recorded beside a launch also times the gap to it).
+  const bool timed = ev0 || ev1;
   if (a.direction == kPull) {
-    hipLaunchKernelGGL(k_pull<T>, dim3(pull_grid(g)), dim3(kPullBlock), 0, a.stream, (T*)ws->F,
-                       (const T*)ws->sent, ws->front_bits, g->csc_ptr, g->csc_idx, g->it_r0,
-                       g->it_r1, g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->seg_val,
-                       (int)g->heavy_atomic, (const SelStat*)ws->tile_stat, ntiles, ws->blk_part,
-                       ctl);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    if (ev1 && (err = hipEventRecord(ev1, a.stream)) != hipSuccess) return err;
-    return hipSuccess;
+    const dim3 grid(pull_grid(g)), block(kPullBlock);
+    if (timed)
+      hipExtLaunchKernelGGL(k_pull<T>, grid, block, 0, a.stream, ev0, ev1, 0u, (T*)ws->F,
+                            (const T*)ws->sent, ws->front_bits, g->csc_ptr, g->csc_idx, g->it_r0,
+                            g->it_r1, g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->seg_val,
+                            (int)g->heavy_atomic, (const SelStat*)ws->tile_stat, ntiles,
+                            ws->blk_part, ctl);
+    else
+      hipLaunchKernelGGL(k_pull<T>, grid, block, 0, a.stream, (T*)ws->F, (const T*)ws->sent,
+                         ws->front_bits, g->csc_ptr, g->csc_idx, g->it_r0, g->it_r1, g->it_l0,
+                         g->it_l1, g->it_seg, g->n_items, ws->seg_val, (int)g->heavy_atomic,
+                         (const SelStat*)ws->tile_stat, ntiles, ws->blk_part, ctl);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_push<T>, dim3(ntiles), dim3(kPushBlock), 0, a.stream, (T*)ws->F, g->col,
-                     ws->fr_lstart, ws->fr_base, (const T*)ws->fr_s,
-                     (const SelStat*)ws->tile_stat, ctl);
+  const dim3 grid(ntiles), block(kPushBlock);
+  if (timed)
+    hipExtLaunchKernelGGL(k_push<T>, grid, block, 0, a.stream, ev0, ev1, 0u, (T*)ws->F, g->col,
+                          ws->fr_lstart, ws->fr_base, (const T*)ws->fr_s,
+                          (const SelStat*)ws->tile_stat, ctl);
+  else
+    hipLaunchKernelGGL(k_push<T>, grid, block, 0, a.stream, (T*)ws->F, g->col, ws->fr_lstart,
+                       ws->fr_base, (const T*)ws->fr_s, (const SelStat*)ws->tile_stat, ctl);
+  hipError_t err;
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  if (ev1 && (err = hipEventRecord(ev1, a.stream)) != hipSuccess) return err;
   hipLaunchKernelGGL(k_reduce<T>, dim3(reduce_grid(g->n)), dim3(kReduceBlock), 0, a.stream,
                      (const T*)ws->F, g->n, (const SelStat*)ws->tile_stat, ntiles, ws->blk_part,
                      ctl);
