@@ -64,7 +64,7 @@ def parse_args():
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the CPU-oracle sample (0 disables it)")
     p.add_argument("--no-extras", action="store_true",
-                   help="headline solve only (no FP32, batched or serving sections)")
+                   help="headline solve only (no FP32, method, high-E, batched or serving sections)")
     p.add_argument("--serve-seconds", type=float, default=6.0,
                    help="length of each serving phase")
     p.add_argument("--serve-kmax", type=int, default=16)
@@ -140,6 +140,62 @@ def fp32_refine_section(di, g, X, d, tol):
     sec, st = time_solves(solve, 10)
     return {"s_per_solve": sec, "cycles": int(st.cycles), "refinements": int(st.refinements),
             "resid_l1": float(st.resid_l1)}
+
+
+def methods_section(di, g, X, d, tol):
+    """The paper's method comparison on the GPU, same graph and tolerance:
+    DI-SOP and DI-CYC, each moving fluid by the pull and by the push. With
+    every node holding fluid diffused each cycle, DI-CYC's history after
+    m + 1 cycles is the power iteration's iterate after m steps, so the
+    DI-CYC rows are also the GPU's PI (pull) and PI' (push)."""
+    rows = []
+    for name, method in (("DI-SOP", di.DI_SOP), ("DI-CYC", di.DI_CYC)):
+        for kname, kernel in (("pull", di.DI_KERNEL_PULL), ("push", di.DI_KERNEL_PUSH)):
+            o = di.di_opts_default()
+            o.method = method
+            o.kernel = kernel
+
+            def solve():
+                status, st = di.di_solve_dev(g.handle, None, d, tol, o, X)
+                if status != di.DI_OK:
+                    raise RuntimeError(di.di_last_error())
+                return st
+
+            sec, st = time_solves(solve, 5)
+            rows.append({"method": name, "kernel": kname, "ms_per_solve": sec * 1e3,
+                         "cycles": int(st.cycles), "nb_iter": float(st.nb_iter),
+                         "resid_l1": float(st.resid_l1)})
+    return rows
+
+
+def high_e_section(di, graphgen, d):
+    """Section 2.8's graph (Table 9) by its synthetic stand-in, on P and its
+    transpose: DI-SOP and DI-CYC to the paper's target error 1/N, where
+    most nodes converge exactly in finitely many steps."""
+    import torch
+    n = 9664
+    out = {"graph": f"high-E stand-in N={n} seed 0 (L/N 1.67, D/N 0.48, E/N 0.91)",
+           "stop": "paper, target 1/N", "rows": []}
+    base = graphgen.high_e_graph(n, seed=0)
+    X = torch.empty(n, dtype=torch.float64, device="cuda")
+    for mat, (src, dst) in (("P", base), ("Pt", graphgen.transpose(*base))):
+        g = di.Graph(n, src, dst)
+        for name, method in (("DI-SOP", di.DI_SOP), ("DI-CYC", di.DI_CYC)):
+            o = di.di_opts_default()
+            o.method = method
+            o.stop = di.DI_STOP_PAPER
+
+            def solve():
+                status, st = di.di_solve_dev(g.handle, None, d, 1.0 / n, o, X)
+                if status != di.DI_OK:
+                    raise RuntimeError(di.di_last_error())
+                return st
+
+            sec, st = time_solves(solve, 20)
+            out["rows"].append({"matrix": mat, "method": name, "us_per_solve": sec * 1e6,
+                                "cycles": int(st.cycles), "nb_iter": float(st.nb_iter)})
+        g.close()
+    return out
 
 
 def batched_section(di, graphgen, g, n, d, tol):
@@ -382,6 +438,8 @@ def main():
     line["hbm_frac"] = line["roofline"]["frac"]
     if not args.no_extras and headline:
         line["fp32_refine"] = fp32_refine_section(di, g, X, d, tol)
+        line["methods"] = methods_section(di, g, X, d, tol)
+        line["dataset2_like"] = high_e_section(di, graphgen, d)
         line["batched_ppr"] = batched_section(di, graphgen, g, n, d, tol)
         line["serving"] = serving_section(di, graphgen, d, args.serve_seconds, args.serve_kmax)
     if args.cpu_seconds > 0:

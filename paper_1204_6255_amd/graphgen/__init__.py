@@ -187,3 +187,124 @@ def prefix_subgraph(m: int, src, dst):
     keep = (src < m) & (dst < m)
     return (np.ascontiguousarray(src[keep], dtype=np.int32),
             np.ascontiguousarray(dst[keep], dtype=np.int32))
+
+
+def _powerlaw_exponent(mean: float, kmax: int) -> float:
+    """The exponent a of P(k) proportional to k^-a on [1, kmax] whose mean is
+    `mean` (bisection; the mean falls as a grows)."""
+    k = np.arange(1, kmax + 1, dtype=np.float64)
+    lo, hi = 0.0, 8.0
+    for _ in range(80):
+        a = 0.5 * (lo + hi)
+        p = k ** -a
+        if (k * p).sum() / p.sum() > mean:
+            lo = a
+        else:
+            hi = a
+    return 0.5 * (lo + hi)
+
+
+def high_e_graph(n: int = 9664, seed: int = 0, e_frac: float = 0.91, d_frac: float = 0.48,
+                 links_per_node: float = 1.67, kmax: int = 164, kernel_frac: float = 0.01,
+                 p_core: float = 0.3, p_back: float = 0.05, beta: float = 0.6):
+    """A web-like digraph where most nodes are 0 in-degree nodes in the
+    recursive sense of Section 2.4 (E): the stand-in for the gr0.California
+    graph of Section 2.8, whose Table 9 gives L/N 1.67, D/N 0.48, E/N 0.91,
+    O/N 0, max_in 199, max_out 164 at N = 9664.
+
+    Construction (node positions, shuffled into ids at the end):
+    - the non-E part, (1 - e_frac)·n nodes: a kernel of kernel_frac·n nodes
+      joined in a ring (so every kernel node lies on a cycle), followed by a
+      tail in which every node has a parent link from an earlier non-E node
+      that is not dangling (so it lies downstream of the ring); kernel nodes
+      link inside the non-E part, tail nodes link forward in the tail or,
+      with probability p_back, back into the kernel;
+    - the E part, e_frac·n nodes in a topological order: each links forward
+      inside the E part or, with probability p_core, into the non-E part.
+      Nothing links into the E part from outside it, so its nodes are
+      exactly the recursive 0 in-degree nodes;
+    - d_frac·n dangling nodes drawn among the E part and the tail; the other
+      nodes draw an out-degree from a power law on [1, kmax] whose mean
+      gives links_per_node·n links (the ring and parent links count in it);
+    - each link's destination is drawn among its allowed positions with
+      weight rank^-beta (ranks a seeded permutation), which makes in-degree
+      hubs.
+    No self-loops or duplicate links. Sorted by (src, dst), int32.
+    """
+    if n < 4:
+        raise ValueError("high_e_graph needs n >= 4")
+    rng = np.random.default_rng(seed)
+    n_core = max(2, int(round((1.0 - e_frac) * n)))
+    n_ker = max(2, min(n_core, int(round(kernel_frac * n))))
+    n_e = n - n_core
+    k0, t0 = n_e, n_e + n_ker  # kernel [k0, t0), tail [t0, n)
+    cand = np.concatenate([np.arange(n_e), np.arange(t0, n)])
+    dang = np.zeros(n, dtype=bool)
+    dang[rng.choice(cand, size=min(int(round(d_frac * n)), cand.size), replace=False)] = True
+    active = np.flatnonzero(~dang)
+    forced = {v: {k0 + (v - k0 + 1) % n_ker} for v in range(k0, t0)}
+    feeders = np.flatnonzero(~dang[k0:]) + k0  # ascending; the kernel comes first
+    for u in range(t0, n):
+        c = int(feeders[int(rng.integers(int(np.searchsorted(feeders, u))))])
+        forced.setdefault(c, set()).add(u)
+    n_forced = np.zeros(n, dtype=np.int64)
+    for v, f in forced.items():
+        n_forced[v] = len(f)
+    a = _powerlaw_exponent(links_per_node * n / active.size, kmax)
+    pk = np.arange(1, kmax + 1, dtype=np.float64) ** -a
+    cdf = np.cumsum(pk) / pk.sum()
+    out_deg = np.zeros(n, dtype=np.int64)
+    out_deg[active] = np.minimum(1 + np.searchsorted(cdf, rng.random(active.size), side="right"),
+                                 kmax)
+    out_deg = np.maximum(out_deg, n_forced)
+    # the sum of a heavy-tailed draw strays from its mean: move single links
+    # between random nodes until the total is the target
+    excess = int(out_deg.sum()) - int(round(links_per_node * n))
+    floor = np.maximum(n_forced, 1)
+    excess = max(min(excess, int((out_deg - floor)[active].sum())),
+                 -int((kmax - out_deg)[active].clip(min=0).sum()))
+    while excess != 0:
+        v = int(active[int(rng.integers(active.size))])
+        if excess > 0 and out_deg[v] > floor[v]:
+            out_deg[v] -= 1
+            excess -= 1
+        elif excess < 0 and out_deg[v] < kmax:
+            out_deg[v] += 1
+            excess += 1
+    cw = np.concatenate([[0.0], np.cumsum((rng.permutation(n) + 1.0) ** -beta)])
+
+    def pick(lo, hi):
+        u = cw[lo] + rng.random() * (cw[hi] - cw[lo])
+        return min(max(int(np.searchsorted(cw, u, side="right")) - 1, lo), hi - 1)
+
+    links = set()
+    for v in active.tolist():
+        got = set(forced.get(v, ()))
+        if k0 <= v < t0:
+            ranges = [(k0, n, 1.0)]
+        elif v < n_e:
+            ranges = [(v + 1, n_e, 1.0 - p_core), (k0, n, p_core)]
+        else:
+            ranges = [(v + 1, n, 1.0 - p_back), (k0, t0, p_back)]
+        ranges = [r for r in ranges if r[1] > r[0]]
+        room = sum(hi - lo for lo, hi, _ in ranges) - (1 if any(lo <= v < hi for lo, hi, _ in ranges)
+                                                       else 0)
+        cap = max(min(int(out_deg[v]), room), len(got))
+        total = sum(p for _, _, p in ranges)
+        tries = 0
+        while len(got) < cap and tries < 20 * cap:
+            tries += 1
+            x = rng.random() * total
+            for lo, hi, p in ranges:
+                if x < p:
+                    break
+                x -= p
+            t = pick(lo, hi)
+            if t != v:
+                got.add(t)
+        links.update((v, t) for t in got)
+    arr = np.array(sorted(links), dtype=np.int64).reshape(-1, 2)
+    perm = rng.permutation(n)
+    s, t = perm[arr[:, 0]], perm[arr[:, 1]]
+    order = np.lexsort((t, s))
+    return s[order].astype(np.int32), t[order].astype(np.int32)

@@ -8,7 +8,14 @@
 
 - a graph whose links all point forward (a DAG, every node of the
   Notations' E class), where DI-CYC ends in finitely many cycles with no
-  fluid left (the finite convergence the paper notes for Dataset 2).
+  fluid left (the finite convergence the paper notes for Dataset 2);
+- the stand-in for Dataset 2 (Section 2.8, Table 9: 91% of the nodes in the
+  E class) and its transpose, where every E node of depth h holds no fluid
+  after h + 1 synchronous DI-CYC cycles;
+- DI-CYC run for m + 1 cycles against the oracle's power iteration after m
+  steps: with every node holding fluid diffused each cycle, the GPU's
+  history is the PI iterate (pull: rows gathered, as PI of Section 2.5.1;
+  push: columns scattered, as PI' of Section 2.5.2), started from zero.
 
 Each solve is compared with the CPU oracle's solution within the error
 bound of the stopping rule (residual / (1 - d)), as in the main parity
@@ -20,6 +27,7 @@ import pytest
 
 import oracle
 from paper_1204_6255_amd import di, graphgen
+from _peel import e_depth
 
 pytestmark = pytest.mark.gpu
 
@@ -122,3 +130,88 @@ def test_dag_converges_in_finitely_many_cycles(torch_cuda):
     # DI-SOP reaches the tolerance on the same graph as well
     Xs, sts = gpu_x(torch_cuda, n, src, dst)
     assert np.abs(Xs - ref).sum() <= 1e-9
+
+
+N_CAL = 9664  # Table 9
+
+
+@pytest.mark.parametrize("transposed", [False, True])
+@pytest.mark.parametrize("method", [di.DI_SOP, di.DI_CYC])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_high_e_graph(torch_cuda, transposed, method, kernel):
+    src, dst = graphgen.high_e_graph(N_CAL, seed=0)
+    if transposed:
+        src, dst = graphgen.transpose(src, dst)
+    og, B, ref = oracle_x(N_CAL, src, dst)
+    g = di.Graph(N_CAL, src, dst)
+    o = di.di_opts_default()
+    o.kernel = kernel
+    o.method = method
+    X = torch_cuda.empty(N_CAL, dtype=torch_cuda.float64, device="cuda")
+    status, st = di.di_solve_dev(g.handle, None, D, TOL_PAR, o, X)
+    assert status == di.DI_OK, di.di_last_error()
+    torch_cuda.cuda.synchronize()
+    X = X.cpu().numpy()
+    g.close()
+    assert np.abs(X - ref).sum() <= 1e-9
+    _, r = oracle.residual(og, B, D, X)
+    assert abs(r - st.resid_l1) <= 1e-14
+
+
+@pytest.mark.parametrize("transposed", [False, True])
+def test_high_e_nodes_finish_after_their_depth(torch_cuda, transposed):
+    torch = torch_cuda
+    src, dst = graphgen.high_e_graph(N_CAL, seed=0)
+    if transposed:
+        src, dst = graphgen.transpose(src, dst)
+    depth = e_depth(N_CAL, src, dst)
+    assert (depth >= 0).sum() > N_CAL // 2
+    og = oracle.Graph(N_CAL, src, dst)
+    B = graphgen.uniform_rhs(N_CAL, D)
+    Fo, Ho = B.copy(), np.zeros(N_CAL)
+    g = di.Graph(N_CAL, src, dst)
+    Fd = torch.from_numpy(B.copy()).cuda()
+    Hd = torch.zeros(N_CAL, dtype=torch.float64, device="cuda")
+    e_o = e_g = 0.0
+    for c in range(1, int(depth.max()) + 3):
+        _, _, e_o, _, _ = oracle.di_cycle(og, Fo, Ho, D, oracle.CYC, oracle.SYNC, e_o)
+        status, e_g, _ = di.di_cycles_dev(g.handle, D, di.DI_CYC, Fd, Hd, 1, e_g)
+        assert status == di.DI_OK, di.di_last_error()
+        torch.cuda.synchronize()
+        F, H = Fd.cpu().numpy(), Hd.cpu().numpy()
+        done = (depth >= 0) & (depth < c)
+        assert np.all(F[done] == 0.0), (c, np.abs(F[done]).max())
+        # same schedule as the oracle's SYNC mode, sums in another order
+        assert np.all(np.abs(F - Fo) <= 1e-16 + 1e-13 * np.abs(Fo)), c
+        assert np.all(np.abs(H - Ho) <= 1e-16 + 1e-13 * np.abs(Ho)), c
+        assert abs(e_g - e_o) <= 1e-13 * max(abs(e_o), 1e-300), c
+    g.close()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("m", [0, 3, 17])
+def test_cyc_is_the_power_iteration(torch_cuda, kernel, m):
+    n = 10000
+    src, dst = base(n)
+    og = oracle.Graph(n, src, dst)
+    B = graphgen.uniform_rhs(n, D)
+    x_pi, st_pi = oracle.jacobi(og, B, D, tol=0.0, max_iter=m)
+    assert st_pi.status == oracle.E_NOCONV and st_pi.cycles == m
+    g = di.Graph(n, src, dst)
+    o = di.di_opts_default()
+    o.kernel = kernel
+    o.method = di.DI_CYC
+    o.max_cycles = m + 1
+    X = torch_cuda.empty(n, dtype=torch_cuda.float64, device="cuda")
+    status, st = di.di_solve_dev(g.handle, None, D, 1e-300, o, X)
+    assert status == di.DI_E_NOCONV and st.cycles == m + 1, di.di_last_error()
+    torch_cuda.cuda.synchronize()
+    g.close()
+    X = X.cpu().numpy()
+    # a cycle moves at most every link once (nodes without in-links hold no
+    # fluid after the first cycle, while PI still pays for their links)
+    assert 0 < st.edges_pushed <= (m + 1) * len(src)
+    # all terms are positive: the two summation orders differ by a few ulps
+    # per step, relative to the entry
+    eps = np.finfo(float).eps
+    assert np.all(np.abs(X - x_pi) <= (m + 1) * 4 * (np.log2(n) + 8) * eps * x_pi)

@@ -151,3 +151,45 @@ def test_forward_links_give_a_dag():
     a = graphgen.web_graph(n, seed=2)
     b = graphgen.web_graph(n, seed=2, p_forward=0.0)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_peel_against_the_definition():
+    """The peel helper's E class equals the definition's fixed point."""
+    from _peel import e_depth
+    for seed in range(6):
+        rng = np.random.default_rng(100 + seed)
+        n = int(rng.integers(1, 25))
+        mask = rng.random((n, n)) < rng.uniform(0.02, 0.3)
+        src, dst = (a.astype(np.int32) for a in np.nonzero(mask))
+        assert int((e_depth(n, src, dst) >= 0).sum()) == _brute_stats(n, src, dst)["E"]
+    # a chain 0 -> 1 -> 2 with 3 <-> 4 -> 2: node 2 has a cycle upstream
+    depth = e_depth(5, [0, 1, 3, 4, 4], [1, 2, 4, 3, 2])
+    assert depth.tolist() == [0, 1, -1, -1, -1]
+
+
+def test_high_e_graph_matches_table9():
+    """Section 2.8's graph at N = 9664: L/N 1.67, D/N 0.48, E/N 0.91, no
+    loops, max_in near 199, max_out at most 164."""
+    from _peel import e_depth
+    n = 9664
+    src, dst = graphgen.high_e_graph(n, seed=0)
+    key = src.astype(np.int64) * n + dst
+    assert np.all(np.diff(key) > 0) and np.all(src != dst)
+    assert src.min() >= 0 and dst.max() < n
+    st = graphgen.graph_stats(n, src, dst)
+    assert st.L == round(1.67 * n)
+    assert st.D == round(0.48 * n) and st.O == 0
+    assert st.E == n - round(0.09 * n)
+    assert int((e_depth(n, src, dst) >= 0).sum()) == st.E
+    assert st.max_out <= 164 and 100 <= st.max_in <= 400
+    a = graphgen.high_e_graph(n, seed=0)
+    b = graphgen.high_e_graph(n, seed=1)
+    assert np.array_equal(a[0], src) and np.array_equal(a[1], dst)
+    assert not (a[0].size == b[0].size and np.array_equal(a[1], b[1]))
+    # small sizes keep the construction (a ring of at least 2 nodes)
+    for m in (4, 10, 50):
+        s, t = graphgen.high_e_graph(m, seed=0)
+        sm = graphgen.graph_stats(m, s, t)
+        assert sm.O == 0 and sm.E == m - max(2, round(0.09 * m))
+    with pytest.raises(ValueError):
+        graphgen.high_e_graph(3)
