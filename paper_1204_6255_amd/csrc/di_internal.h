@@ -35,9 +35,15 @@ constexpr int kSelectBlockPush = 256;
 constexpr int kSelectPerThreadPush = 2;
 constexpr int kSelectTilePush = kSelectBlockPush * kSelectPerThreadPush;
 constexpr int kPullBlock = 256;       // threads per pull block
-constexpr int kPullChunk = 2048;      // in-links per pull work item (LDS staged)
+#ifndef DI_PULL_CHUNK
+#define DI_PULL_CHUNK 2048
+#endif
+constexpr int kPullChunk = DI_PULL_CHUNK;  // in-links per pull work item (LDS staged)
 constexpr int kPullMaxRows = 2048;    // rows per pull work item
-constexpr int kPullLongRow = 32;      // rows with more in-links: summed by a wave
+#ifndef DI_PULL_LONG_ROW
+#define DI_PULL_LONG_ROW 32
+#endif
+constexpr int kPullLongRow = DI_PULL_LONG_ROW;  // rows with more in-links: summed by a wave
 constexpr int kPullMaxGrid = 2048;    // pull blocks (grid-stride over items)
 constexpr int kXcds = 8;              // XCDs; workgroups are dealt round-robin
 constexpr int kPushBlock = 256;       // threads per push block
