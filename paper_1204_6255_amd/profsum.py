@@ -9,6 +9,11 @@ output name `run`); FETCH_DIR / WRITE_DIR hold `--pmc FETCH_SIZE` and
 profiles/di_sop_f64_n1m_kernels.txt (per-kernel durations) and
 profiles/k_pull_f64_n1m_traffic.txt (HBM bytes per pull launch, with each
 counter scaled by what it reads for the 256 MiB calibration copy).
+
+    python -m paper_1204_6255_amd.profsum counters OUT_NAME DIR "<command>" [DIR "<command>" ...]
+
+writes profiles/OUT_NAME: the mean per dispatch of every counter that
+`--pmc` runs of the benchmark collected for the pull and the select.
 """
 
 from __future__ import annotations
@@ -90,5 +95,29 @@ def main(argv):
     print("\n".join(lines))
 
 
+def counters_main(argv):
+    """counters OUT_NAME DIR CMD [DIR CMD ...]: mean value per dispatch of
+    every counter collected for k_pull<double> and k_select, one line each."""
+    out_name, rest = argv[0], argv[1:]
+    lines = ["# rocprofv3 counters per dispatch (mean over dispatches), DI-SOP FP64 on the N=1M "
+             "web graph (benchmark workload)"]
+    for d, cmd in zip(rest[0::2], rest[1::2]):
+        lines.append(f"# command: {cmd}")
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                agg[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        for k in sorted(agg):
+            if k.startswith("k_pull") or k.startswith("k_select"):
+                for c, v in sorted(agg[k].items()):
+                    lines.append(f"{k}\t{c}\t{sum(v) / len(v):.0f}\tdispatches={len(v)}")
+    with open(os.path.join(PROFILES, out_name), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
-    main(sys.argv[1:])
+    if sys.argv[1:2] == ["counters"]:
+        counters_main(sys.argv[2:])
+    else:
+        main(sys.argv[1:])
