@@ -319,12 +319,23 @@ def serving_section(di, graphgen, d, seconds, kmax):
         poisson.append({"lambda_per_s": lam, "requests": nreq, "solves_per_s": nreq / el,
                         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                         "p99_ms": 1e3 * float(np.percentile(lat, 99))})
+    # idle: one request at a time (each runs alone on its graph)
+    lat = []
+    for i in range(64):
+        inflight = {}
+        submit(inflight)
+        while inflight:
+            reap(inflight, lat)
+            time.sleep(0.0001)
+    idle = {"requests": len(lat), "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_ms": 1e3 * float(np.percentile(lat, 99))}
     _, info = di.di_serve_info(srv)
     di.di_serve_destroy(srv)
     for G in graphs:
         G.close()
     return {"graphs": ng, "total_nodes": int(sum(Ns)), "k_max": kmax,
-            "precision": "fp32+fp64 refinement", "closed_loop": closed, "poisson": poisson,
+            "precision": "fp32+fp64 refinement (a request alone: fp64 single path)",
+            "closed_loop": closed, "poisson": poisson, "idle_one_at_a_time": idle,
             "admission_stalls": int(info.admission_stalls),
             "hbm_bytes_in_use": int(info.bytes_in_use)}
 

@@ -69,6 +69,7 @@ enum { DI_FP64 = 0, DI_FP32_REFINE = 1, DI_FP32 = 2 };
 enum { DI_STOP_RESID = 0, DI_STOP_PAPER = 1 };
 /* di_opts.flags */
 #define DI_FLAG_KERNEL_TIMING 1u /* time every pull/push launch with HIP events */
+#define DI_FLAG_SERVE_NO_SOLO 2u /* serving: a lone request also runs in a column set */
 
 /* di_opts.kernel: how a cycle moves the claimed fluid along the links */
 enum {
@@ -212,32 +213,42 @@ di_status di_solve_batch_dev(const di_graph* g, int32_t k, const double* B_dev, 
 /* ---- serving ------------------------------------------------------------
  * A server answers personalized PageRank requests (one right-hand side
  * B = (1-d)/|S| on a seed set S, or the uniform (1-d)/n) on resident graphs
- * with continuous batching: a worker thread keeps one batch of KP columns
- * (k_max rounded up to a power of two, at least 8) per graph with work,
- * starts waiting requests in columns as they free up, and finishes each
- * request when its own residual is within its tolerance, as in
- * di_solve_batch. A graph's batch is allocated when the graph first has
- * work and the HBM budget allows it; idle batches of other graphs are
- * released to make room; a request that cannot be placed waits (an
- * admission stall). Requests with another d wait until their graph's batch
- * has drained. Every di_serve_* call is thread-safe. */
+ * with continuous batching. Each request is its own DI-SOP (or DI-CYC) solve
+ * of Sections 2.5.4-2.5.5 and finishes when its own residual is within its
+ * tolerance, as in di_solve_batch.
+ * - A worker thread keeps, per graph with work, column sets: batches of KP
+ *   columns (a power of two from 8 to k_max rounded up), each on its own
+ *   HIP stream. One set per graph is open; its width follows the graph's
+ *   demand (columns in use plus requests waiting), and a set that no longer
+ *   fits the demand drains and is freed once idle. Waiting requests start in
+ *   free columns as they free up.
+ * - A request that would run alone on its graph takes the graph's solo slot
+ *   instead: the single right-hand side path in FP64 (whatever the server's
+ *   precision), which finishes a lone request several times sooner than a
+ *   column set. DI_FLAG_SERVE_NO_SOLO in opts.flags turns this off.
+ * - Sets and solo slots are allocated when the HBM budget allows them; idle
+ *   ones of other graphs are released to make room; a request that cannot be
+ *   placed waits (an admission stall). Requests with another d wait until
+ *   their graph's open set is idle.
+ * Every di_serve_* call is thread-safe. */
 typedef struct di_server di_server;
 
 typedef struct di_serve_stats {
   int64_t submitted;        /* requests accepted */
   int64_t completed;        /* requests finished (collected or not) */
   int64_t admission_stalls; /* times a graph's requests found no HBM room */
-  int64_t active;           /* columns in use now */
+  int64_t active;           /* columns and solo slots in use now */
   int64_t pending;          /* requests waiting for a column */
-  int64_t bytes_in_use;     /* device bytes held by batches */
+  int64_t bytes_in_use;     /* device bytes held by column sets and solo slots */
   double busy_seconds;      /* worker time spent on work */
 } di_serve_stats;
 
-/* Creates a server that may hold up to hbm_budget_bytes of batch buffers,
- * with k_max in [1, 256] columns per graph. opts (may be NULL: DI-SOP,
- * DI_FP32_REFINE) gives method, precision, max_cycles and inner_tol;
- * stop must be DI_STOP_RESID and kernel AUTO or PULL. The device current
- * at the call is used. */
+/* Creates a server that may hold up to hbm_budget_bytes of column sets and
+ * solo slots, with k_max in [1, 256] columns per set. opts (may be NULL:
+ * DI-SOP, DI_FP32_REFINE) gives method, precision (of the column sets),
+ * max_cycles, inner_tol and flags (DI_FLAG_SERVE_NO_SOLO); stop must be
+ * DI_STOP_RESID and kernel AUTO or PULL. The device current at the call is
+ * used. */
 di_status di_serve_create(size_t hbm_budget_bytes, int32_t k_max, const di_opts* opts,
                           di_server** out);
 

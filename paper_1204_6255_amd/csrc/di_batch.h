@@ -124,6 +124,9 @@ struct ColInit {
 hipError_t launch_bcol_init(const BatchArgs& a, BatchWs* ws, const ColInit& ci);
 // X_out (n doubles, device) = column c of H (+ X64 when refined)
 hipError_t launch_bcol_out(const BatchArgs& a, BatchWs* ws, int c, bool refined, double* X_out);
+// x[idx[q]] = v for q < count, on stream (indices in range: the caller checks).
+hipError_t launch_scatter_value(hipStream_t stream, double* x, const int32_t* idx, int64_t count,
+                                double v);
 // allocation and pooling of batch workspaces (di_batch.cpp)
 di_status batch_ws_create(const di_graph* g, int kp, int prec, bool refine, BatchWs** out);
 size_t batch_ws_bytes(const di_graph* g, int kp, int prec, bool refine);

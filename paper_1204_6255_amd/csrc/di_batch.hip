@@ -869,6 +869,16 @@ __global__ __launch_bounds__(kBBlock) void k_bcol_clear(T* __restrict__ F, T* __
   }
 }
 
+// x[idx[q]] = v for q < count (a personalized right-hand side for a solve
+// that runs alone).
+__global__ __launch_bounds__(256) void k_scatter_value(double* __restrict__ x,
+                                                       const int32_t* __restrict__ idx,
+                                                       int64_t count, double v) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count;
+       q += (int64_t)gridDim.x * blockDim.x)
+    x[idx[q]] = v;
+}
+
 // Block j starts column col[j]: B = val[j] at its seeds
 // seeds[off[j] .. off[j+1]) (or the uniform value written by k_bcol_clear
 // when the list is empty), r = sum |F| in FP64, and a fresh control block
@@ -1165,6 +1175,14 @@ hipError_t launch_bcol_out(const BatchArgs& a, BatchWs* ws, int c, bool refined,
 hipError_t launch_bstore(const BatchArgs& a, BatchWs* ws, double* X_out, int k, bool refined) {
   return dispatch(a,
                   [&]<typename T, int KP>() { return bstore_t<T, KP>(a, ws, X_out, k, refined); });
+}
+
+hipError_t launch_scatter_value(hipStream_t stream, double* x, const int32_t* idx, int64_t count,
+                                double v) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_value, dim3((unsigned)std::min<int64_t>(ceil_div(count, 256), 1024)),
+                     dim3(256), 0, stream, x, idx, count, v);
+  return hipGetLastError();
 }
 
 }  // namespace di

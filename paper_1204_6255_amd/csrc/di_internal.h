@@ -243,6 +243,32 @@ template <typename T>
 hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_h_to_x(const CycleArgs& a, double* X);
+
+// ---- step-driven FP64 solve (di_solve.cpp) ----------------------------------
+// One DI-SOP (or DI-CYC) solve in FP64 with the pull, queued a chunk at a
+// time on the caller's stream so that a caller moving other work (the
+// serving worker) never waits for it:
+//   solo_start queues the start state (F = B, H = 0), the first selection
+//     and the read-back of the control block;
+//   solo_next, once that work has finished, reads the control block: done
+//     != 0 ends the solve (1 converged, 2 max_cycles, 3 non-finite);
+//     otherwise it queues the next chunk of cycles and the read-back;
+//   solo_finish queues X = H and fills the statistics (seconds 0).
+// The workspace is the run's own (not pooled); workspace_bytes is its size.
+struct SoloRun {
+  di_graph* g = nullptr;
+  Workspace* ws = nullptr;
+  CycleArgs a{};
+  int last_sel = 0;
+  int chunk = 8;
+};
+size_t workspace_bytes(const di_graph* g, int prec);
+di_status solo_create(di_graph* g, SoloRun** out);
+void solo_destroy(SoloRun* r);
+di_status solo_start(SoloRun* r, const double* B_dev, double b_uniform, double d, double tol,
+                     int method, int max_cycles, hipStream_t stream);
+di_status solo_next(SoloRun* r, int* done);
+di_status solo_finish(SoloRun* r, double* X_dev, di_stats* st);
 // FP64 residual pass: with H, first X += H and H = 0; then y = d X / out and
 // R = B + P.X - X (B == nullptr: b_uniform everywhere), written to R_out as
 // T, with the records of sum |R| and sum R in blk_part[0, pull_grid] (the

@@ -17,6 +17,11 @@
 // graph's requests find no free column and the HBM budget allows it; idle
 // sets are released to make room; a request that cannot be placed waits (an
 // admission stall).
+//
+// A request that would run alone on its graph (nothing else running or
+// waiting there) takes the graph's solo slot instead: the single right-hand
+// side path in FP64, queued a chunk at a time like a set, which finishes a
+// lone request several times sooner than a column set of eight.
 
 #include <algorithm>
 #include <chrono>
@@ -64,6 +69,21 @@ struct Lane {
 
 struct GraphSlot;
 
+// The solo slot of a graph: one request on the single right-hand side path.
+// `claimed` changes under the server mutex; the rest is the worker's.
+struct Solo {
+  SoloRun* run = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;     // end of the queued work
+  double* out_dev = nullptr;   // the right-hand side, then X (n doubles)
+  size_t bytes = 0;            // counted in the budget while the slot exists
+  bool ready = false;          // run, stream, event and out_dev exist
+  bool claimed = false;        // a request is placed here (started or not)
+  bool launched = false;
+  Lane lane;                   // the running request
+  double d = 0.85;
+};
+
 // One batch workspace of a graph. `active` and `d` change under the server
 // mutex; the rest is the worker's.
 struct ColumnSet {
@@ -87,6 +107,7 @@ struct GraphSlot {
   int32_t id = 0;
   std::deque<Request> pending;
   std::vector<ColumnSet*> sets;
+  Solo* solo = nullptr;
   bool stalled = false;  // counted once per stall episode
 };
 
@@ -162,11 +183,23 @@ size_t set_bytes(const di_server* s, const di_graph* g, int kp) {
 
 bool set_idle(const ColumnSet* cs) { return cs->active == 0 && !cs->launched; }
 
-// Under s->mu: reserves the bytes of a new set for gs, taking idle sets of
-// graphs without waiting requests out of the books (the caller frees them
-// outside the lock). True when the bytes are reserved.
-bool reserve_set(di_server* s, GraphSlot* gs, int kp, std::vector<ColumnSet*>* to_free) {
-  const size_t need = set_bytes(s, gs->g, kp);
+size_t solo_bytes(const di_graph* g) {
+  return workspace_bytes(g, kF64) + (size_t)g->n * sizeof(double);
+}
+
+bool solo_idle(const Solo* so) { return so->ready && !so->claimed && !so->launched; }
+
+// What reserve_bytes takes out of the books for the caller to free outside
+// the lock.
+struct Freed {
+  std::vector<ColumnSet*> sets;
+  std::vector<Solo*> solos;
+};
+
+// Under s->mu: reserves `need` bytes for gs, taking idle sets and idle solo
+// slots of graphs without waiting requests out of the books. True when the
+// bytes are reserved.
+bool reserve_bytes(di_server* s, GraphSlot* gs, size_t need, Freed* freed) {
   if (s->in_use + need > s->budget) {
     for (auto& kv : s->graphs) {
       GraphSlot* o = kv.second;
@@ -175,11 +208,16 @@ bool reserve_set(di_server* s, GraphSlot* gs, int kp, std::vector<ColumnSet*>* t
         ColumnSet* cs = o->sets[q];
         if (cs->ready && set_idle(cs)) {
           s->in_use -= cs->bytes;
-          to_free->push_back(cs);
+          freed->sets.push_back(cs);
           o->sets.erase(o->sets.begin() + (long)q);
         } else {
           ++q;
         }
+      }
+      if (o->solo && s->in_use + need > s->budget && solo_idle(o->solo)) {
+        s->in_use -= o->solo->bytes;
+        freed->solos.push_back(o->solo);
+        o->solo = nullptr;
       }
       if (s->in_use + need <= s->budget) break;
     }
@@ -187,6 +225,15 @@ bool reserve_set(di_server* s, GraphSlot* gs, int kp, std::vector<ColumnSet*>* t
   if (s->in_use + need > s->budget) return false;
   s->in_use += need;
   return true;
+}
+
+void destroy_solo(Solo* so) {
+  if (so->stream) (void)hipStreamSynchronize(so->stream);
+  solo_destroy(so->run);
+  if (so->out_dev) (void)hipFree(so->out_dev);
+  if (so->ev) (void)hipEventDestroy(so->ev);
+  if (so->stream) (void)hipStreamDestroy(so->stream);
+  delete so;
 }
 
 void destroy_set(ColumnSet* cs) {
@@ -323,6 +370,75 @@ di_status finish_columns(di_server* s, ColumnSet* cs) {
   return DI_OK;
 }
 
+di_status create_solo(GraphSlot* gs, Solo* so) {
+  const di_graph* g = gs->g;
+  DI_HIP(hipStreamCreate(&so->stream));
+  DI_HIP(hipEventCreateWithFlags(&so->ev, hipEventDisableTiming));
+  DI_TRY(solo_create(const_cast<di_graph*>(g), &so->run));
+  hipError_t err = hipMalloc((void**)&so->out_dev, (size_t)g->n * sizeof(double));
+  if (err != hipSuccess) {
+    so->out_dev = nullptr;
+    set_error(std::string("hipMalloc: ") + hipGetErrorString(err));
+    return DI_E_NOMEM;
+  }
+  so->ready = true;
+  return DI_OK;
+}
+
+// Starts request r in gs's solo slot: B on the device (the seed values
+// scattered into zeros, or uniform), the start state and the first
+// selection, then the slot's event.
+di_status start_solo(di_server* s, GraphSlot* gs, Request& r) {
+  Solo* so = gs->solo;
+  const di_graph* g = gs->g;
+  const double* B = nullptr;
+  const double bu = (1.0 - r.d) / (double)g->n;
+  if (!r.seeds.empty()) {
+    DI_TRY(ensure_seed_staging(s, r.seeds.size()));
+    DI_HIP(hipMemsetAsync(so->out_dev, 0, (size_t)g->n * sizeof(double), so->stream));
+    DI_HIP(hipMemcpyAsync(s->d_seeds, r.seeds.data(), r.seeds.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, so->stream));
+    DI_HIP(launch_scatter_value(so->stream, so->out_dev, s->d_seeds, (int64_t)r.seeds.size(),
+                                (1.0 - r.d) / (double)r.seeds.size()));
+    // the seed staging is shared and the host copy is pageable: wait
+    DI_HIP(hipStreamSynchronize(so->stream));
+    B = so->out_dev;
+  }
+  const int max_cycles = s->opts.max_cycles > 0 ? s->opts.max_cycles : 100000;
+  DI_TRY(solo_start(so->run, B, bu, r.d, r.tol, s->opts.method, max_cycles, so->stream));
+  DI_HIP(hipEventRecord(so->ev, so->stream));
+  so->lane = Lane{r.ticket, r.t_submit};
+  so->d = r.d;
+  so->launched = true;
+  return DI_OK;
+}
+
+// After the solo slot's queued work finished: the next chunk, or the result.
+di_status step_solo(di_server* s, GraphSlot* gs) {
+  Solo* so = gs->solo;
+  int done = 0;
+  DI_TRY(solo_next(so->run, &done));
+  if (done == 0) {
+    DI_HIP(hipEventRecord(so->ev, so->stream));
+    so->launched = true;
+    return DI_OK;
+  }
+  const di_graph* g = gs->g;
+  Result res;
+  res.X.resize((size_t)g->n);
+  res.status = solo_finish(so->run, so->out_dev, &res.stats);
+  DI_HIP(hipMemcpyAsync(res.X.data(), so->out_dev, (size_t)g->n * sizeof(double),
+                        hipMemcpyDeviceToHost, so->stream));
+  DI_HIP(hipStreamSynchronize(so->stream));
+  res.stats.seconds = now_s() - so->lane.t_submit;  // latency: submission to completion
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->results[so->lane.ticket] = std::move(res);
+  s->completed += 1;
+  so->lane = Lane{};
+  so->claimed = false;
+  return DI_OK;
+}
+
 // Queues cs's next work on its stream: the residual passes of the columns
 // whose FP32 pass ended (states from the last read-back), a chunk of
 // cycles, and the read-back of the column states.
@@ -376,6 +492,11 @@ void fail_all(di_server* s, di_status st, const std::string& msg) {
         }
       cs->active = 0;
     }
+    if (gs->solo && gs->solo->lane.ticket) {
+      s->results[gs->solo->lane.ticket].status = st;
+      gs->solo->lane = Lane{};
+    }
+    if (gs->solo) gs->solo->claimed = false;
     for (Request& r : gs->pending) s->results[r.ticket].status = st;
     gs->pending.clear();
   }
@@ -383,6 +504,7 @@ void fail_all(di_server* s, di_status st, const std::string& msg) {
 
 bool graph_busy(const GraphSlot* gs) {
   if (!gs->pending.empty()) return true;
+  if (gs->solo && (gs->solo->claimed || gs->solo->launched)) return true;
   for (const ColumnSet* cs : gs->sets)
     if (cs->launched || cs->active > 0) return true;
   return false;
@@ -402,14 +524,34 @@ struct Placement {
 // takes requests of its own d; an idle open set takes the d of the next
 // request. Idle sets of other graphs released to make room go to *to_free.
 void place_requests(di_server* s, GraphSlot* gs, std::vector<Placement>* out,
-                    ColumnSet** fresh, std::vector<ColumnSet*>* to_free) {
+                    ColumnSet** fresh, Freed* freed, std::vector<Request>* solo_req,
+                    bool* solo_fresh) {
   *fresh = nullptr;
+  *solo_fresh = false;
   if (gs->pending.empty()) return;
   ColumnSet* open = nullptr;
   int demand = (int)gs->pending.size();
   for (ColumnSet* cs : gs->sets) {
     demand += cs->active;
     if (!cs->draining) open = cs;
+  }
+  if (gs->solo && gs->solo->claimed) demand += 1;
+  // a request alone on its graph runs in the solo slot
+  if (demand == 1 && !(s->opts.flags & DI_FLAG_SERVE_NO_SOLO)) {
+    bool have = gs->solo != nullptr;
+    if (!have && reserve_bytes(s, gs, solo_bytes(gs->g), freed)) {
+      gs->solo = new Solo;
+      gs->solo->bytes = solo_bytes(gs->g);
+      *solo_fresh = true;
+      have = true;
+    }
+    if (have) {
+      gs->solo->claimed = true;
+      solo_req->push_back(std::move(gs->pending.front()));
+      gs->pending.pop_front();
+      gs->stalled = false;
+      return;
+    }
   }
   const int want = std::min(pow2_at_least(demand), s->kp);
   if (open && open->ready && open->active == 0) open->d = gs->pending.front().d;
@@ -432,7 +574,7 @@ void place_requests(di_server* s, GraphSlot* gs, std::vector<Placement>* out,
   }
   if (!resize && open) return;  // the open set is full: wait for its columns
   if ((int)gs->sets.size() >= kMaxSetsPerGraph) return;
-  if (!reserve_set(s, gs, want, to_free)) {
+  if (!reserve_bytes(s, gs, set_bytes(s, gs->g, want), freed)) {
     if (!gs->stalled) {
       s->stalls += 1;
       gs->stalled = true;
@@ -520,18 +662,45 @@ void worker_loop(di_server* s) {
         progressed = true;
       }
       if (st != DI_OK) break;
+      // the solo slot (only the worker creates, launches and frees it)
+      if (gs->solo && gs->solo->launched) {
+        const hipError_t q = hipEventQuery(gs->solo->ev);
+        if (q == hipErrorNotReady) {
+          (void)hipGetLastError();
+        } else {
+          gs->solo->launched = false;
+          if (q != hipSuccess) {
+            set_error(std::string("serving worker: ") + hipGetErrorString(q));
+            st = DI_E_DEVICE;
+            break;
+          }
+          st = step_solo(s, gs);
+          if (st != DI_OK) break;
+          progressed = true;
+        }
+      }
       // place waiting requests
       std::vector<Placement> places;
       ColumnSet* fresh = nullptr;
       std::vector<ColumnSet*> to_free;
+      Freed freed;
+      std::vector<Request> solo_req;
+      bool solo_fresh = false;
       {
         std::lock_guard<std::mutex> lk(s->mu);
         retire_drained(s, gs, &to_free);
-        place_requests(s, gs, &places, &fresh, &to_free);
+        place_requests(s, gs, &places, &fresh, &freed, &solo_req, &solo_fresh);
         sets = gs->sets;
       }
       for (ColumnSet* cs : to_free) destroy_set(cs);
-      if (fresh) st = create_set_ws(s, fresh);
+      for (ColumnSet* cs : freed.sets) destroy_set(cs);
+      for (Solo* so : freed.solos) destroy_solo(so);
+      if (solo_fresh) st = create_solo(gs, gs->solo);
+      if (st == DI_OK && !solo_req.empty()) {
+        st = start_solo(s, gs, solo_req.front());
+        progressed = true;
+      }
+      if (st == DI_OK && fresh) st = create_set_ws(s, fresh);
       for (size_t q = 0; st == DI_OK && q < places.size(); ++q)
         st = start_requests(s, places[q].cs, places[q].reqs);
       // queue the next work of every set with columns in use
@@ -541,17 +710,30 @@ void worker_loop(di_server* s) {
         st = launch_set(s, cs);
         progressed = true;
       }
-      if (st != DI_OK) break;
+      if (st != DI_OK) {
+        // placed requests may not hold a column or the solo slot yet
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (Placement& p : places)
+          for (Request& r : p.reqs) s->results[r.ticket].status = st;
+        for (Request& r : solo_req) s->results[r.ticket].status = st;
+        break;
+      }
     }
     if (st != DI_OK) {
       // drain what was queued before failing the requests
       std::lock_guard<std::mutex> lk(s->mu);
-      for (auto& kv : s->graphs)
+      for (auto& kv : s->graphs) {
         for (ColumnSet* cs : kv.second->sets)
           if (cs->launched) {
             (void)hipEventSynchronize(cs->ev);
             cs->launched = false;
           }
+        Solo* so = kv.second->solo;
+        if (so && so->launched) {
+          (void)hipEventSynchronize(so->ev);
+          so->launched = false;
+        }
+      }
     }
     if (st != DI_OK) fail_all(s, st, "serving worker: " + std::string(di_last_error()));
     if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -738,6 +920,7 @@ di_status di_serve_info(di_server* s, di_serve_stats* out) {
   int64_t active = 0, pending = 0;
   for (auto& kv : s->graphs) {
     for (const di::ColumnSet* cs : kv.second->sets) active += cs->active;
+    if (kv.second->solo && kv.second->solo->claimed) active += 1;
     pending += (int64_t)kv.second->pending.size();
   }
   out->active = active;
@@ -759,6 +942,7 @@ void di_serve_destroy(di_server* s) {
   if (hipGetDevice(&cur) == hipSuccess && cur != s->device) (void)hipSetDevice(s->device);
   for (auto& kv : s->graphs) {
     for (di::ColumnSet* cs : kv.second->sets) di::destroy_set(cs);
+    if (kv.second->solo) di::destroy_solo(kv.second->solo);
     delete kv.second;
   }
   void* ptrs[] = {s->d_flag, s->d_buni, s->d_col, s->d_off, s->d_val, s->d_tol, s->d_seeds};

@@ -179,6 +179,23 @@ struct RunTimes {
   Ctl state{};                // the final control block
 };
 
+// The cycles to queue next, after the read-back of the state h at
+// selection last_sel: from the contraction of r per cycle so far, the
+// cycles still needed to reach the target, within [2, 64] (the first chunk
+// keeps its size).
+int next_chunk(const CycleArgs& a, const Ctl& h, int last_sel, int chunk) {
+  if (last_sel == 0) return chunk;
+  int next = 16;
+  const double target = a.tol_rel >= 0.0 ? std::max(a.tol_in, a.tol_rel * h.r_start) : a.tol;
+  if (a.stop == DI_STOP_RESID && h.cycles >= 1 && h.r_first > 0.0 && h.r > 0.0 &&
+      h.r < h.r_first && target > 0.0) {
+    const double rate = std::log(h.r / h.r_first) / (double)h.cycles;
+    const double need = std::log(target / h.r) / rate;
+    if (std::isfinite(need)) next = (int)std::ceil(need) + 1;
+  }
+  return std::max(2, std::min(next, 64));
+}
+
 // Queues cycles until the device reports a stop: the selection of cycle 0,
 // then (move c, selection c + 1) pairs in chunks. The newest control copy
 // after selection c is copy (c + 1) & 1; it is left in rt->state.
@@ -201,19 +218,7 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
       set_error("internal: the device did not stop after max_cycles");
       return DI_E_DEVICE;
     }
-    if (last_sel > 0) {
-      // cycles still needed, from the contraction of r per cycle so far
-      int next = 16;
-      const double target =
-          a.tol_rel >= 0.0 ? std::max(a.tol_in, a.tol_rel * h.r_start) : a.tol;
-      if (a.stop == DI_STOP_RESID && h.cycles >= 1 && h.r_first > 0.0 && h.r > 0.0 &&
-          h.r < h.r_first && target > 0.0) {
-        const double rate = std::log(h.r / h.r_first) / (double)h.cycles;
-        const double need = std::log(target / h.r) / rate;
-        if (std::isfinite(need)) next = (int)std::ceil(need) + 1;
-      }
-      chunk = std::max(2, std::min(next, 64));
-    }
+    chunk = next_chunk(a, h, last_sel, chunk);
     const int todo = std::max(1, std::min(chunk, a.max_cycles - last_sel));
     if (timing) DI_TRY(ensure_events(ws, 2 + 2 * (size_t)(last_sel + todo)));
     for (int q = 0; q < todo; ++q) {
@@ -560,6 +565,96 @@ di_status residual_dev(const di_graph* gc, const double* B_dev, double d, const 
 }
 
 }  // namespace
+
+// ---- step-driven FP64 solve -------------------------------------------------
+
+size_t workspace_bytes(const di_graph* g, int prec) {
+  const size_t n = (size_t)g->n;
+  const size_t s = prec == kF64 ? sizeof(double) : sizeof(float);
+  const size_t ntiles =
+      (size_t)std::max(select_tiles(g->n, kPull), select_tiles(g->n, kPush));
+  const size_t nparts = (size_t)std::max(kPullMaxGrid, kReduceGrid) + 1;
+  return 3 * n * s + ((n + 63) / 64) * sizeof(unsigned long long) + ntiles * sizeof(SelStat) +
+         nparts * sizeof(Part) + (size_t)std::max<int64_t>(g->n_segs, 1) * sizeof(double) +
+         2 * sizeof(Ctl);
+}
+
+di_status solo_create(di_graph* g, SoloRun** out) {
+  SoloRun* r = new (std::nothrow) SoloRun;
+  if (!r) return DI_E_NOMEM;
+  r->g = g;
+  di_status st = alloc_workspace(g, kF64, &r->ws);
+  if (st != DI_OK) {
+    delete r;
+    return st;
+  }
+  *out = r;
+  return DI_OK;
+}
+
+void solo_destroy(SoloRun* r) {
+  if (!r) return;
+  free_workspace(r->ws);
+  delete r;
+}
+
+di_status solo_start(SoloRun* r, const double* B_dev, double b_uniform, double d, double tol,
+                     int method, int max_cycles, hipStream_t stream) {
+  CycleArgs& a = r->a;
+  a = CycleArgs{};
+  a.g = r->g;
+  a.ws = r->ws;
+  a.d = d;
+  a.tol = tol;
+  a.tol_in = tol;
+  a.tol_rel = -1.0;
+  a.method = method;
+  a.stop = DI_STOP_RESID;
+  a.max_cycles = max_cycles;
+  a.direction = kPull;
+  a.stream = stream;
+  a.first_parts = part_count(a) + 1;
+  r->last_sel = 0;
+  r->chunk = 8;
+  DI_HIP(launch_reset_ctl(a));
+  DI_HIP(launch_start<double>(a, B_dev, b_uniform));
+  DI_HIP(launch_select<double>(a, 0, 1));
+  DI_HIP(hipMemcpyAsync(r->ws->host_ctl, r->ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost,
+                        stream));
+  return DI_OK;
+}
+
+di_status solo_next(SoloRun* r, int* done) {
+  CycleArgs& a = r->a;
+  const Ctl& h = r->ws->host_ctl[(r->last_sel + 1) & 1];
+  *done = h.done;
+  if (h.done) return DI_OK;
+  if (r->last_sel >= a.max_cycles) {
+    set_error("internal: the device did not stop after max_cycles");
+    return DI_E_DEVICE;
+  }
+  r->chunk = next_chunk(a, h, r->last_sel, r->chunk);
+  const int todo = std::max(1, std::min(r->chunk, a.max_cycles - r->last_sel));
+  for (int q = 0; q < todo; ++q) {
+    const int c = r->last_sel;
+    DI_HIP(launch_move<double>(a, c, nullptr, nullptr));
+    DI_HIP(launch_select<double>(a, c + 1, 0));
+    r->last_sel = c + 1;
+  }
+  DI_HIP(hipMemcpyAsync(r->ws->host_ctl, r->ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost,
+                        a.stream));
+  return DI_OK;
+}
+
+di_status solo_finish(SoloRun* r, double* X_dev, di_stats* st) {
+  const Ctl h = r->ws->host_ctl[(r->last_sel + 1) & 1];
+  DI_HIP(launch_h_to_x<double>(r->a, X_dev));
+  RunTimes rt;
+  std::memset(st, 0, sizeof(*st));
+  fill_stats(r->g, h, r->a.d, (int)sizeof(double), kPull, rt, 0, st);
+  return h.done == 1 ? DI_OK : (h.done == 2 ? DI_E_NOCONV : DI_E_INVAL);
+}
+
 }  // namespace di
 
 extern "C" {

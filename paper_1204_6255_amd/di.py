@@ -25,6 +25,7 @@ DI_SOP, DI_CYC = 0, 1
 DI_FP64, DI_FP32_REFINE, DI_FP32 = 0, 1, 2
 DI_STOP_RESID, DI_STOP_PAPER = 0, 1
 DI_FLAG_KERNEL_TIMING = 1
+DI_FLAG_SERVE_NO_SOLO = 2
 DI_KERNEL_AUTO, DI_KERNEL_PULL, DI_KERNEL_PUSH = 0, 1, 2
 
 STATUS_NAMES = {

@@ -151,6 +151,7 @@ def test_admission_by_hbm_budget(torch_cuda):
     _, _, g2, og2 = graph(20000, 1)
     o = di.di_opts_default()
     o.precision = di.DI_FP32_REFINE
+    o.flags = di.DI_FLAG_SERVE_NO_SOLO  # column sets only: their admission is tested
     # batch bytes of the larger graph, plus a little: never both at once
     # (KP = 8: 3 float arrays + 3 double arrays of n * 8, plus small records)
     budget = 20000 * 8 * (3 * 4 + 3 * 8) + 20000 * 8 + (1 << 20)
@@ -171,6 +172,61 @@ def test_admission_by_hbm_budget(torch_cuda):
     _, info = di.di_serve_info(srv.h)
     assert info.admission_stalls >= 1
     assert info.bytes_in_use <= budget
+    srv.close()
+
+
+def test_lone_request_runs_solo(torch_cuda):
+    """A request alone on its graph takes the single right-hand side path in
+    FP64 (no residual passes, whatever the server's precision); with
+    DI_FLAG_SERVE_NO_SOLO it runs in a column set. Both meet the bar, and a
+    solo request and column sets on the same graph overlap correctly."""
+    _, _, g, og = graph(10000, 0)
+    seeds = graphgen.ppr_seed_sets(10000, 1, 4243)[0]
+    o = di.di_opts_default()
+    o.precision = di.DI_FP32_REFINE
+    srv = Server(8 * GIB, 16, o)
+    assert di.di_serve_add_graph(srv.h, g.handle, 0) == di.DI_OK
+    st, t = di.di_serve_submit(srv.h, 0, seeds, D, 1e-9)
+    st, X_solo, s_solo = wait(srv, t, 10000)
+    assert st == di.DI_OK, di.di_last_error()
+    check(og, seeds, 1e-9, X_solo)
+    assert s_solo.refinements == 0 and s_solo.cycles > 0 and s_solo.seconds > 0
+    # the same request's FP64 single solve gives the same cycles
+    B = graphgen.ppr_rhs(10000, seeds, D)
+    X1 = np.empty(10000)
+    status, st1 = di.di_solve(g.handle, B, D, 1e-9, di.di_opts_default(), X1)
+    assert status == di.DI_OK and st1.cycles == s_solo.cycles
+    assert np.array_equal(X1, X_solo)  # same kernels, deterministic pull
+    # uniform B through the solo slot
+    st, t = di.di_serve_submit(srv.h, 0, None, D, 1.4e-10)
+    st, Xu, su = wait(srv, t, 10000)
+    assert st == di.DI_OK and su.refinements == 0
+    check(og, [], 1.4e-10, Xu)
+    # a solo request, then a burst on the same graph while it runs
+    reqs = [(seeds, 1e-9)] + [(s, 1e-6 if j % 2 else 1e-9)
+                              for j, s in enumerate(graphgen.ppr_seed_sets(10000, 9, 600))]
+    tickets = []
+    for s_, tol in reqs:
+        st, tk = di.di_serve_submit(srv.h, 0, s_, D, tol)
+        assert st == di.DI_OK
+        tickets.append(tk)
+    for (s_, tol), tk in zip(reqs, tickets):
+        st, X, _ = wait(srv, tk, 10000)
+        assert st == di.DI_OK
+        check(og, s_, tol, X)
+    _, info = di.di_serve_info(srv.h)
+    assert info.completed == info.submitted == 12 and info.active == 0 and info.pending == 0
+    srv.close()
+    # the same lone request in a column set
+    o.flags = di.DI_FLAG_SERVE_NO_SOLO
+    srv = Server(8 * GIB, 16, o)
+    assert di.di_serve_add_graph(srv.h, g.handle, 0) == di.DI_OK
+    st, t = di.di_serve_submit(srv.h, 0, seeds, D, 1e-9)
+    st, X_set, s_set = wait(srv, t, 10000)
+    assert st == di.DI_OK
+    check(og, seeds, 1e-9, X_set)
+    assert s_set.refinements >= 1
+    assert np.abs(X_set - X_solo).sum() <= 2e-9 / (1 - D)
     srv.close()
 
 
