@@ -65,6 +65,9 @@ def parse_args():
                    help="budget of the CPU-oracle sample (0 disables it)")
     p.add_argument("--no-extras", action="store_true",
                    help="headline solve only (no FP32, method, high-E, batched or serving sections)")
+    p.add_argument("--only", choices=["fp32_refine", "methods", "dataset2_like", "batched_ppr",
+                                      "serving"], default=None,
+                   help="run this one section after the headline solve (for profiling)")
     p.add_argument("--serve-seconds", type=float, default=6.0,
                    help="length of each serving phase")
     p.add_argument("--serve-kmax", type=int, default=16)
@@ -448,11 +451,17 @@ def main():
         del a, b
     line["hbm_frac"] = line["roofline"]["frac"]
     if not args.no_extras and headline:
-        line["fp32_refine"] = fp32_refine_section(di, g, X, d, tol)
-        line["methods"] = methods_section(di, g, X, d, tol)
-        line["dataset2_like"] = high_e_section(di, graphgen, d)
-        line["batched_ppr"] = batched_section(di, graphgen, g, n, d, tol)
-        line["serving"] = serving_section(di, graphgen, d, args.serve_seconds, args.serve_kmax)
+        sections = {
+            "fp32_refine": lambda: fp32_refine_section(di, g, X, d, tol),
+            "methods": lambda: methods_section(di, g, X, d, tol),
+            "dataset2_like": lambda: high_e_section(di, graphgen, d),
+            "batched_ppr": lambda: batched_section(di, graphgen, g, n, d, tol),
+            "serving": lambda: serving_section(di, graphgen, d, args.serve_seconds,
+                                               args.serve_kmax),
+        }
+        for name, run in sections.items():
+            if args.only is None or args.only == name:
+                line[name] = run()
     if args.cpu_seconds > 0:
         src, dst = graphgen.web_graph(n, seed=0, alpha=args.alpha, kmax=args.kmax)
         line["cpu_baseline"] = cpu_baseline(n, src, dst, d, tol, args.cpu_seconds)

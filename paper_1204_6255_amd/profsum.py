@@ -14,6 +14,11 @@ counter scaled by what it reads for the 256 MiB calibration copy).
 
 writes profiles/OUT_NAME: the mean per dispatch of every counter that
 `--pmc` runs of the benchmark collected for the pull and the select.
+
+    python -m paper_1204_6255_amd.profsum trace OUT_NAME DIR "<title>" "<command>"
+
+writes profiles/OUT_NAME: the per-kernel table of any `--kernel-trace
+--stats` run (csv, output name `run`).
 """
 
 from __future__ import annotations
@@ -116,8 +121,25 @@ def counters_main(argv):
     print("\n".join(lines))
 
 
+def trace_main(argv):
+    """trace OUT_NAME DIR TITLE CMD: the per-kernel table of a
+    `--kernel-trace --stats` run."""
+    out_name, d, title, cmd = argv[:4]
+    lines = [f"# rocprofv3 kernel summary: {title}", f"# command: {cmd}",
+             "# columns: kernel, calls, total_us, average_us, min_us, max_us, percent"]
+    for r in kernel_stats(d):
+        lines.append(f"{short(r['Name'])}\t{r['Calls']}\t{float(r['TotalDurationNs']) / 1e3:.1f}\t"
+                     f"{float(r['AverageNs']) / 1e3:.2f}\t{float(r['MinNs']) / 1e3:.2f}\t"
+                     f"{float(r['MaxNs']) / 1e3:.2f}\t{float(r['Percentage']):.1f}")
+    with open(os.path.join(PROFILES, out_name), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1:2] == ["counters"]:
         counters_main(sys.argv[2:])
+    elif sys.argv[1:2] == ["trace"]:
+        trace_main(sys.argv[2:])
     else:
         main(sys.argv[1:])
