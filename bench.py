@@ -99,7 +99,7 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(n, src, dst, d, tol, budget_s):
+def cpu_baseline(n, src, dst, d, tol, budget_s, with_baselines=True):
     import numpy as np
     import oracle
     from paper_1204_6255_amd import graphgen
@@ -113,11 +113,27 @@ def cpu_baseline(n, src, dst, d, tol, budget_s):
         times.append(st.seconds)
         if time.perf_counter() - t_start >= budget_s or len(times) >= 50:
             break
-    return {
+    out = {
         "value": float(np.mean(times)), "unit": "s", "cores": 1, "kind": "oracle",
         "sample": f"{len(times)} full solves of the same N={n} graph to sum|F| <= {tol:g} "
                   f"(sequential DI-SOP, one thread, FP64)",
     }
+    # the oracle's baselines, one solve each to the same residual: the power
+    # (Jacobi) iteration and the Gauss-Seidel sweep (its residual checks are
+    # outside its timer)
+    if with_baselines:
+        others = {}
+        _, st = oracle.jacobi(og, B, d, tol=tol)
+        others["PI (power/Jacobi iteration)"] = {"s": st.seconds, "iterations": int(st.cycles),
+                                                 "nb_iter": st.nb_iter}
+        _, st = oracle.gs(og, B, d, stop=oracle.STOP_RESID, tol=tol)
+        others["GS (sequential sweep)"] = {"s": st.seconds, "sweeps": int(st.cycles),
+                                           "nb_iter": st.nb_iter}
+        _, _, st = oracle.diter(og, B, d, oracle.CYC, oracle.SEQUENTIAL, tol=tol)
+        others["DI-CYC (sequential)"] = {"s": st.seconds, "cycles": int(st.cycles),
+                                         "nb_iter": st.nb_iter}
+        out["oracle_baselines"] = others
+    return out
 
 
 def time_solves(fn, reps):
@@ -147,12 +163,12 @@ def fp32_refine_section(di, g, X, d, tol):
 
 def methods_section(di, g, X, d, tol):
     """The paper's method comparison on the GPU, same graph and tolerance:
-    DI-SOP and DI-CYC, each moving fluid by the pull and by the push. With
-    every node holding fluid diffused each cycle, DI-CYC's history after
-    m + 1 cycles is the power iteration's iterate after m steps, so the
-    DI-CYC rows are also the GPU's PI (pull) and PI' (push)."""
+    DI-SOP, DI-CYC and PI, each moving fluid by the pull (rows gathered, as
+    PI) and by the push (columns scattered, as PI'). PI diffuses every node
+    every cycle, so its history after m + 1 cycles is the power iteration's
+    iterate after m steps, at the power iteration's cost."""
     rows = []
-    for name, method in (("DI-SOP", di.DI_SOP), ("DI-CYC", di.DI_CYC)):
+    for name, method in (("DI-SOP", di.DI_SOP), ("DI-CYC", di.DI_CYC), ("PI", di.DI_PI)):
         for kname, kernel in (("pull", di.DI_KERNEL_PULL), ("push", di.DI_KERNEL_PUSH)):
             o = di.di_opts_default()
             o.method = method

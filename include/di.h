@@ -61,8 +61,16 @@ typedef enum di_status {
   DI_E_NOTFOUND = -9   /* unknown graph id or ticket (serving) */
 } di_status;
 
-/* di_opts.method */
-enum { DI_SOP = 0, DI_CYC = 1 };
+/* di_opts.method: which nodes each (frontier-synchronous) cycle diffuses.
+ *   DI_SOP: F_i >= (r/L)*out_i with r = sum|F| at the cycle's start
+ *           (Section 2.5.5);
+ *   DI_CYC: every node with F_i != 0 (Section 2.5.4);
+ *   DI_PI:  every node, fluid or not. The history after c cycles is then the
+ *           power iteration's c-th iterate from zero, sum_{k<c} P^k B, and
+ *           sum|F| = |P^c B|_1 its residual: the unnormalized power (Jacobi)
+ *           iteration of Sections 2.5.1-2.5.2 with its cost (every link
+ *           moves every cycle). Single right-hand side only. */
+enum { DI_SOP = 0, DI_CYC = 1, DI_PI = 2 };
 /* di_opts.precision */
 enum { DI_FP64 = 0, DI_FP32_REFINE = 1, DI_FP32 = 2 };
 /* di_opts.stop */
@@ -83,7 +91,7 @@ enum {
 typedef struct di_graph di_graph;
 
 typedef struct di_opts {
-  int32_t method;     /* DI_SOP (default) or DI_CYC (select every |F_i| > 0) */
+  int32_t method;     /* DI_SOP (default), DI_CYC or DI_PI (see above) */
   int32_t precision;  /* DI_FP64 (default), DI_FP32_REFINE, DI_FP32 */
   int32_t stop;       /* DI_STOP_RESID (default): stop when sum|F| <= tol;
                          DI_STOP_PAPER: stop after a cycle when

@@ -332,7 +332,7 @@ di_status check_batch(const di_graph* g, int32_t k, double d, const double* tol,
     return DI_E_INVAL;
   }
   if (o.method != DI_SOP && o.method != DI_CYC) {
-    set_error("unknown method");
+    set_error("batched solves run DI_SOP or DI_CYC");
     return DI_E_INVAL;
   }
   if (o.stop != DI_STOP_RESID) {

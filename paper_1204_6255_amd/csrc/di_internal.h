@@ -79,7 +79,7 @@ struct Ctl {
   int fallback;      // DI-CYC cycles run after an empty DI-SOP cycle
   int done;          // 0 running, 1 converged, 2 max_cycles, 3 non-finite,
                      // 4 inner stop (the FP32 pass of a refined solve ended)
-  int cyc_mode;      // next cycle selects every |F_i| > 0
+  int cyc_mode;      // next cycle selects: 0 by the DI-SOP threshold, 1 every |F_i| > 0, 2 every node
   unsigned long long edges_total;  // link operations (pushes along j != i)
   unsigned long long front_total;  // diffused nodes with links to push
   unsigned long long sel_total;    // diffused nodes

@@ -256,10 +256,10 @@ __device__ inline Ctl next_ctl(Ctl c, const Part& v, int first, double d, double
     // a DI-SOP cycle that diffused nothing (possible only through rounding
     // at a tie) is followed by one DI-CYC cycle
     const bool empty = v.sel == 0 && v.pabs > 0.0;
-    c.cyc_mode = (method == DI_CYC || empty) ? 1 : 0;
-    if (method != DI_CYC && empty) c.fallback += 1;
+    c.cyc_mode = method == DI_PI ? 2 : ((method == DI_CYC || empty) ? 1 : 0);
+    if (method == DI_SOP && empty) c.fallback += 1;
   } else {
-    c.cyc_mode = method == DI_CYC ? 1 : 0;
+    c.cyc_mode = method == DI_PI ? 2 : (method == DI_CYC ? 1 : 0);
   }
   const double r = v.pabs;
   c.r = r;
@@ -425,7 +425,9 @@ __global__ __launch_bounds__(BLOCK) void k_select(
       }
     return;
   }
-  const bool cyc = s_cyc != 0;
+  // 0: the DI-SOP threshold; 1: every node holding fluid (DI-CYC);
+  // 2: every node (the power iteration's cost: all links move)
+  const int mode = s_cyc;
   const double rl = s_r / (double)L;
 
   for (; tile < ntiles; tile += gridDim.x) {
@@ -463,8 +465,8 @@ __global__ __launch_bounds__(BLOCK) void k_select(
           f[m] = s_hval[lo];
         }
         const double a = fabs(f[m]);
-        const double thr = (cyc || out == 0) ? 0.0 : rl * (double)out;
-        if (a > 0.0 && a >= thr) {
+        const double thr = (mode != 0 || out == 0) ? 0.0 : rl * (double)out;
+        if (mode == 2 || (a > 0.0 && a >= thr)) {
           const double t = loop ? f[m] * (double)out / ((double)out - d) : f[m];
           H[i] = (T)(hv[m] + t);
           F[i] = (T)0;

@@ -770,7 +770,7 @@ di_status serve_create(size_t budget, int32_t k_max, const di_opts* opts, di_ser
   if (opts) o = *opts;
   if (!opts) o.precision = DI_FP32_REFINE;
   if (o.method != DI_SOP && o.method != DI_CYC) {
-    set_error("unknown method");
+    set_error("serving runs DI_SOP or DI_CYC");
     return DI_E_INVAL;
   }
   if (o.precision != DI_FP64 && o.precision != DI_FP32 && o.precision != DI_FP32_REFINE) {

@@ -305,7 +305,7 @@ di_status check_common(const di_graph* g, double d, double tol, const di_opts& o
     set_error("tol must be > 0 (>= 0 with DI_STOP_PAPER)");
     return DI_E_INVAL;
   }
-  if (o.method != DI_SOP && o.method != DI_CYC) {
+  if (o.method != DI_SOP && o.method != DI_CYC && o.method != DI_PI) {
     set_error("unknown method");
     return DI_E_INVAL;
   }
@@ -480,7 +480,7 @@ di_status guarded(Fn&& body) {
 di_status cycles_dev(const di_graph* gc, double d, int32_t method, double* F_dev, double* H_dev,
                      int32_t cycles, double* e_inout, void* stream_v, di_stats* stats) {
   if (!gc || !F_dev || !H_dev || cycles < 0 || !(d > 0.0 && d < 1.0) ||
-      (method != DI_SOP && method != DI_CYC)) {
+      (method != DI_SOP && method != DI_CYC && method != DI_PI)) {
     set_error("di_cycles_dev: invalid argument");
     return DI_E_INVAL;
   }

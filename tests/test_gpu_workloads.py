@@ -215,3 +215,41 @@ def test_cyc_is_the_power_iteration(torch_cuda, kernel, m):
     # per step, relative to the entry
     eps = np.finfo(float).eps
     assert np.all(np.abs(X - x_pi) <= (m + 1) * 4 * (np.log2(n) + 8) * eps * x_pi)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_pi_method_is_the_power_iteration(torch_cuda, kernel, tol):
+    """DI_PI diffuses every node every cycle: after c cycles H is the power
+    iteration's iterate x_{c-1} (from x_0 = B) and sum|F| = |P^c B|_1 its
+    residual, so it stops exactly where the oracle's power iteration stops,
+    one cycle later by count, with every link moved every cycle."""
+    n = 10000
+    src, dst = base(n)
+    og = oracle.Graph(n, src, dst)
+    B = graphgen.uniform_rhs(n, D)
+    x_pi, st_pi = oracle.jacobi(og, B, D, tol=tol)
+    assert st_pi.status == oracle.OK
+    g = di.Graph(n, src, dst)
+    o = di.di_opts_default()
+    o.kernel = kernel
+    o.method = di.DI_PI
+    X = torch_cuda.empty(n, dtype=torch_cuda.float64, device="cuda")
+    status, st = di.di_solve_dev(g.handle, None, D, tol, o, X)
+    assert status == di.DI_OK, di.di_last_error()
+    torch_cuda.cuda.synchronize()
+    X = X.cpu().numpy()
+    m = st_pi.cycles
+    assert st.cycles == m + 1
+    assert st.edges_pushed == st.cycles * np.count_nonzero(src != dst)
+    eps = np.finfo(float).eps
+    assert np.all(np.abs(X - x_pi) <= (m + 1) * 4 * (np.log2(n) + 8) * eps * x_pi)
+    # the oracle's residual is a difference of nearly equal iterates (its
+    # rounding is relative to x); the GPU's is the fluid itself
+    assert abs(st.resid_l1 - st_pi.resid_l1) <= 1e-4 * st_pi.resid_l1
+    # the batched path and serving take DI_SOP and DI_CYC only
+    status, _, _ = di.di_solve_batch(g.handle, 2, None, D, [tol, tol], o)
+    assert status == di.DI_E_INVAL
+    st_s, h = di.di_serve_create(1 << 30, 8, o)
+    assert st_s == di.DI_E_INVAL
+    g.close()
