@@ -152,10 +152,15 @@ struct PoolGuard {
   }
 };
 
+// events[0] and [1] bracket a solve (the host reads them after a stream
+// synchronization); the others time single pull/push launches and are only
+// read for their timestamps, so they skip the system-scope fence (a cache
+// writeback that would otherwise land inside the timed launch).
 di_status ensure_events(Workspace* ws, size_t count) {
   while (ws->events.size() < count) {
     hipEvent_t e;
-    DI_HIP(hipEventCreate(&e));
+    if (ws->events.size() < 2) DI_HIP(hipEventCreate(&e));
+    else DI_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     ws->events.push_back(e);
   }
   return DI_OK;
