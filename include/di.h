@@ -69,8 +69,17 @@ typedef enum di_status {
  *           power iteration's c-th iterate from zero, sum_{k<c} P^k B, and
  *           sum|F| = |P^c B|_1 its residual: the unnormalized power (Jacobi)
  *           iteration of Sections 2.5.1-2.5.2 with its cost (every link
- *           moves every cycle). Single right-hand side only. */
-enum { DI_SOP = 0, DI_CYC = 1, DI_PI = 2 };
+ *           moves every cycle). Single right-hand side only.
+ *   DI_GS_ASYNC: not a D-iteration: the Gauss-Seidel baseline of Section
+ *           2.5.3 as an asynchronous GPU relaxation. x starts at B; each
+ *           sweep updates every row in place, x_i = (B_i + sum over in-links
+ *           j != i of d x_j / out_j) / (1 - d/out_i if i has a self-loop),
+ *           from whatever x_j is visible (so results vary in the last bits
+ *           from run to run). It stops when d * sum|x_new - x_old| <= tol,
+ *           which bounds the residual, and reports the exact FP64 residual.
+ *           di_solve / di_solve_dev only, FP64, DI_STOP_RESID, pull. A
+ *           "cycle" in di_stats is a sweep. */
+enum { DI_SOP = 0, DI_CYC = 1, DI_PI = 2, DI_GS_ASYNC = 3 };
 /* di_opts.precision */
 enum { DI_FP64 = 0, DI_FP32_REFINE = 1, DI_FP32 = 2 };
 /* di_opts.stop */
@@ -91,7 +100,7 @@ enum {
 typedef struct di_graph di_graph;
 
 typedef struct di_opts {
-  int32_t method;     /* DI_SOP (default), DI_CYC or DI_PI (see above) */
+  int32_t method;     /* DI_SOP (default), DI_CYC, DI_PI or DI_GS_ASYNC (see above) */
   int32_t precision;  /* DI_FP64 (default), DI_FP32_REFINE, DI_FP32 */
   int32_t stop;       /* DI_STOP_RESID (default): stop when sum|F| <= tol;
                          DI_STOP_PAPER: stop after a cycle when

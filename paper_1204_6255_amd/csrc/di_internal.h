@@ -244,6 +244,12 @@ hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t
 template <typename T>
 hipError_t launch_h_to_x(const CycleArgs& a, double* X);
 
+// Asynchronous Gauss-Seidel (DI_GS_ASYNC), FP64, x in ws->H and y = d x / out
+// in ws->F: x = B; then one sweep = the in-place sweep, the heavy rows and
+// the stop test on ctl[0] (every kernel returns at once after the stop).
+hipError_t launch_gs_init(const CycleArgs& a, const double* B, double b_uniform);
+hipError_t launch_gs_sweep(const CycleArgs& a, const double* B, double b_uniform);
+
 // ---- step-driven FP64 solve (di_solve.cpp) ----------------------------------
 // One DI-SOP (or DI-CYC) solve in FP64 with the pull, queued a chunk at a
 // time on the caller's stream so that a caller moving other work (the

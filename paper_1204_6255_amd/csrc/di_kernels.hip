@@ -893,6 +893,179 @@ __global__ __launch_bounds__(kReduceBlock) void k_refine_heavy(
   if (threadIdx.x == 0) blk_part[slot] = v;
 }
 
+// ---- asynchronous Gauss-Seidel (the GS baseline's GPU variant) -------------
+// Section 2.5.3's sweep updates the rows in order, each from the newest
+// values. On the GPU the rows of a sweep update in parallel and in place:
+// row i computes x_i = (B_i + sum of y_j over its in-links j != i) /
+// (1 - d/out_i if i has a self-loop, else 1), where y_j = d x_j / out_j is
+// whatever value of row j is visible at that moment, and writes x_i and
+// y_i. Every y_j is written once per sweep, so a read sees its value from
+// before the sweep or its final value; the residual after the sweep is then
+// R_i = sum over j != i of p_ij (x_j - x_j as read), hence |R|_1 <= d times
+// the sum of |x_i(after) - x_i(before)|, which is the stop test. x starts at
+// B.
+
+__device__ inline double gs_diag(uint32_t w, double d) {
+  const int out = (int)(w & kOutMask);
+  return (w & kLoopBit) ? 1.0 - d / (double)out : 1.0;
+}
+
+// x = B, y = d x / out (0 for dangling nodes).
+__global__ void k_gs_init(double* __restrict__ x, double* __restrict__ y,
+                          const uint32_t* __restrict__ info, const double* __restrict__ B,
+                          double b_uniform, double d, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double xi = B ? B[i] : b_uniform;
+    const int out = (int)(info[i] & kOutMask);
+    x[i] = xi;
+    y[i] = out > 0 ? d * xi / (double)out : 0.0;
+  }
+}
+
+// One sweep over the light rows (in place); heavy-row segments leave their
+// sums in seg_val. Each block writes one record: sum |dx| and sum dx of its
+// rows. y is read and written by every block: no restrict.
+__global__ __launch_bounds__(kPullBlock) void k_gs_sweep(
+    double* __restrict__ x, double* y, const double* __restrict__ B, double b_uniform,
+    double d, const uint32_t* __restrict__ info, const int64_t* __restrict__ csc_ptr,
+    const int32_t* __restrict__ csc_idx, const int64_t* __restrict__ it_r0,
+    const int64_t* __restrict__ it_r1, const int64_t* __restrict__ it_l0,
+    const int64_t* __restrict__ it_l1, const int32_t* __restrict__ it_seg, int64_t n_items,
+    double* __restrict__ seg_val, Part* __restrict__ blk_part, const Ctl* __restrict__ ctl) {
+  constexpr int U = kPullChunk / kPullBlock;
+  __shared__ double s_val[kPullChunk];
+  __shared__ double s_red[kPullBlock / 64];
+  __shared__ Part s_part[kPullBlock / 64];
+  if (ctl->done) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  Part acc_part{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int64_t l0 = it_l0[it], l1 = it_l1[it], r0 = it_r0[it], r1 = it_r1[it];
+    const int seg = it_seg[it];
+    const int nl = (int)(l1 - l0);
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kPullBlock;
+      v[u] = p < nl ? y[csc_idx[l0 + p]] : 0.0;
+    }
+    if (seg >= 0) {
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += v[u];
+      acc = block_sum(acc, s_red);
+      if (tid == 0) seg_val[seg] = acc;
+      continue;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kPullBlock;
+      if (p < nl) s_val[p] = v[u];
+    }
+    __syncthreads();
+    for (int64_t row = r0 + tid; row - lane < r1; row += kPullBlock) {
+      const bool valid = row < r1;
+      int a = 0, b = 0;
+      if (valid) {
+        a = (int)(csc_ptr[row] - l0);
+        b = (int)(csc_ptr[row + 1] - l0);
+      }
+      const bool longrow = valid && (b - a) > kPullLongRow;
+      double acc = 0.0;
+      if (valid && !longrow)
+        for (int q = a; q < b; ++q) acc += s_val[q];
+      unsigned long long mask = __ballot(longrow);
+      while (mask) {
+        const int src = __ffsll(mask) - 1;
+        mask &= mask - 1;
+        const int la = __shfl(a, src, 64), lb = __shfl(b, src, 64);
+        double part = 0.0;
+        for (int q = la + lane; q < lb; q += 64) part += s_val[q];
+        part = wave_sum(part);
+        if (lane == src) acc = part;
+      }
+      if (valid) {
+        const uint32_t w = info[row];
+        const double bi = B ? B[row] : b_uniform;
+        const double xo = x[row];
+        const double xn = (bi + acc) / gs_diag(w, d);
+        const int out = (int)(w & kOutMask);
+        x[row] = xn;
+        y[row] = out > 0 ? d * xn / (double)out : 0.0;
+        acc_part.pabs += fabs(xn - xo);
+        acc_part.psum += xn - xo;
+      }
+    }
+    __syncthreads();
+  }
+  acc_part = block_sum_part(acc_part, s_part);
+  if (tid == 0) blk_part[blockIdx.x] = acc_part;
+}
+
+// The heavy rows of a sweep, from their segment sums in order. One block;
+// writes the record blk_part[slot].
+__global__ __launch_bounds__(kReduceBlock) void k_gs_heavy(
+    double* __restrict__ x, double* __restrict__ y, const double* __restrict__ B,
+    double b_uniform, double d, const uint32_t* __restrict__ info,
+    const int32_t* __restrict__ heavy_row, const int64_t* __restrict__ heavy_seg,
+    int64_t n_heavy, const double* __restrict__ seg_val, Part* __restrict__ blk_part, int slot,
+    const Ctl* __restrict__ ctl) {
+  __shared__ Part lds[kReduceBlock / 64];
+  if (ctl->done) return;
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  for (int64_t h = threadIdx.x; h < n_heavy; h += blockDim.x) {
+    const int64_t row = heavy_row[h];
+    const double acc = ordered_sum(seg_val, heavy_seg[h], heavy_seg[h + 1], 1);
+    const uint32_t w = info[row];
+    const double bi = B ? B[row] : b_uniform;
+    const double xo = x[row];
+    const double xn = (bi + acc) / gs_diag(w, d);
+    const int out = (int)(w & kOutMask);
+    x[row] = xn;
+    y[row] = out > 0 ? d * xn / (double)out : 0.0;
+    v.pabs += fabs(xn - xo);
+    v.psum += xn - xo;
+  }
+  v = block_sum_part(v, lds);
+  if (threadIdx.x == 0) blk_part[slot] = v;
+}
+
+// The stop test after a sweep: sums the records in order; done = 1 when
+// d * sum |dx| <= tol (then |B + P.x - x|_1 <= tol), 2 at max_cycles, 3
+// when the sum is not finite.
+__global__ __launch_bounds__(kReduceBlock) void k_gs_decide(const Part* __restrict__ blk_part,
+                                                            int nparts, double d, double tol,
+                                                            int64_t links, int max_cycles,
+                                                            Ctl* __restrict__ ctl) {
+  __shared__ Part lds[kReduceBlock / 64];
+  __shared__ int s_done;
+  if (threadIdx.x == 0) s_done = ctl->done;
+  __syncthreads();
+  if (s_done) return;
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  for (int p = threadIdx.x; p < nparts; p += blockDim.x) part_add(v, blk_part[p]);
+  v = block_sum_part(v, lds);
+  if (threadIdx.x == 0) {
+    Ctl c = *ctl;
+    c.cycles += 1;
+    c.edges_total += (unsigned long long)links;
+    c.r = v.pabs;
+    if (c.cycles == 1) c.r_first = v.pabs;
+    if (!isfinite(v.pabs)) {
+      c.final_r = v.pabs;
+      c.done = 3;
+    } else if (d * v.pabs <= tol) {
+      c.final_r = d * v.pabs;
+      c.done = 1;
+    } else if (c.cycles >= max_cycles) {
+      c.final_r = d * v.pabs;
+      c.done = 2;
+    }
+    *ctl = c;
+  }
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 inline unsigned int grid_for(int64_t n, int block, int64_t cap) {
@@ -1055,6 +1228,33 @@ template hipError_t launch_move<double>(const CycleArgs&, int, hipEvent_t, hipEv
 template hipError_t launch_move<float>(const CycleArgs&, int, hipEvent_t, hipEvent_t);
 template hipError_t launch_h_to_x<double>(const CycleArgs&, double*);
 template hipError_t launch_h_to_x<float>(const CycleArgs&, double*);
+hipError_t launch_gs_init(const CycleArgs& a, const double* B, double b_uniform) {
+  hipLaunchKernelGGL(k_gs_init, dim3(grid_for(a.g->n, 256, 4096)), dim3(256), 0, a.stream,
+                     (double*)a.ws->H, (double*)a.ws->F, a.g->info, B, b_uniform, a.d, a.g->n);
+  return hipGetLastError();
+}
+
+hipError_t launch_gs_sweep(const CycleArgs& a, const double* B, double b_uniform) {
+  const di_graph* g = a.g;
+  Workspace* ws = a.ws;
+  const int grid = pull_grid(g);
+  hipLaunchKernelGGL(k_gs_sweep, dim3(grid), dim3(kPullBlock), 0, a.stream, (double*)ws->H,
+                     (double*)ws->F, B, b_uniform, a.d, g->info, g->csc_ptr, g->csc_idx, g->it_r0,
+                     g->it_r1, g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->seg_val,
+                     ws->blk_part, (const Ctl*)ws->ctl);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_gs_heavy, dim3(1), dim3(kReduceBlock), 0, a.stream, (double*)ws->H,
+                     (double*)ws->F, B, b_uniform, a.d, g->info, g->heavy_row, g->heavy_seg,
+                     g->n_heavy, (const double*)ws->seg_val, ws->blk_part, grid,
+                     (const Ctl*)ws->ctl);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_gs_decide, dim3(1), dim3(kReduceBlock), 0, a.stream,
+                     (const Part*)ws->blk_part, grid + 1, a.d, a.tol, (int64_t)g->Lp,
+                     a.max_cycles, ws->ctl);
+  return hipGetLastError();
+}
+
 template hipError_t launch_refine<double>(const CycleArgs&, double*, double*, const double*, double,
                                           double*);
 template hipError_t launch_refine<float>(const CycleArgs&, double*, float*, const double*, double,

@@ -310,8 +310,13 @@ di_status check_common(const di_graph* g, double d, double tol, const di_opts& o
     set_error("tol must be > 0 (>= 0 with DI_STOP_PAPER)");
     return DI_E_INVAL;
   }
-  if (o.method != DI_SOP && o.method != DI_CYC && o.method != DI_PI) {
+  if (o.method != DI_SOP && o.method != DI_CYC && o.method != DI_PI && o.method != DI_GS_ASYNC) {
     set_error("unknown method");
+    return DI_E_INVAL;
+  }
+  if (o.method == DI_GS_ASYNC &&
+      (o.precision != DI_FP64 || o.stop != DI_STOP_RESID || o.kernel == DI_KERNEL_PUSH)) {
+    set_error("DI_GS_ASYNC runs in FP64 with the pull and stops on the residual");
     return DI_E_INVAL;
   }
   if (o.stop != DI_STOP_RESID && o.stop != DI_STOP_PAPER) {
@@ -345,6 +350,96 @@ void add_run(Ctl* tot, const Ctl& h) {
   tot->front_total += h.front_total;
   tot->sel_total += h.sel_total;
   tot->e += h.e;
+}
+
+// Asynchronous Gauss-Seidel: sweeps queued in chunks (sized from the
+// contraction of sum |dx| per sweep), the control block read back after
+// each chunk. At the stop the FP64 residual of x is computed exactly; when
+// rounding leaves it above tol, sweeping goes on.
+di_status gs_solve(di_graph* g, const double* B_dev, double d, double tol, const di_opts& o,
+                   double* X_dev, di_stats* st, Workspace* ws, hipStream_t stream) {
+  CycleArgs a{};
+  a.g = g;
+  a.ws = ws;
+  a.d = d;
+  a.tol = tol;
+  a.tol_in = tol;
+  a.tol_rel = -1.0;
+  a.method = o.method;
+  a.stop = DI_STOP_RESID;
+  a.max_cycles = o.max_cycles > 0 ? o.max_cycles : 100000;
+  a.direction = kPull;
+  a.stream = stream;
+  a.first_parts = part_count(a) + 1;
+  const double bu = (1.0 - d) / (double)g->n;
+  DI_TRY(ensure_events(ws, 2));
+  DI_TRY(ensure_refine_buffers(g, ws));
+  DI_HIP(launch_reset_ctl(a));
+  DI_HIP(hipEventRecord(ws->events[0], stream));
+  DI_HIP(launch_gs_init(a, B_dev, bu));
+  int queued = 0, chunk = 8, checks = 0;
+  double resid = 0.0;
+  Ctl h{};
+  for (;;) {
+    const int todo = std::max(1, std::min(chunk, a.max_cycles - queued));
+    for (int q = 0; q < todo; ++q) DI_HIP(launch_gs_sweep(a, B_dev, bu));
+    queued += todo;
+    DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    DI_HIP(hipStreamSynchronize(stream));
+    h = ws->host_ctl[0];
+    if (h.done == 3) break;
+    if (h.done == 1 || h.done == 2) {
+      DI_HIP(launch_refine<double>(a, (double*)ws->H, (double*)nullptr, B_dev, bu,
+                                   (double*)ws->sent));
+      DI_TRY(residual_norm(a, pull_grid(g) + 1, &resid, nullptr));
+      if (h.done == 1 && resid > tol && checks < 8) {
+        ++checks;  // the bound holds in exact arithmetic: sweep on
+        ws->host_ctl[0].done = 0;
+        DI_HIP(hipMemcpyAsync(ws->ctl, ws->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+        chunk = 2;
+        continue;
+      }
+      break;
+    }
+    if (queued >= a.max_cycles) {
+      set_error("internal: the device did not stop after max_cycles");
+      return DI_E_DEVICE;
+    }
+    chunk = 16;
+    if (h.cycles >= 2 && h.r > 0.0 && h.r < h.r_first) {
+      const double rate = std::log(h.r / h.r_first) / (double)(h.cycles - 1);
+      const double need = std::log(tol / (d * h.r)) / rate;
+      if (std::isfinite(need)) chunk = std::max(2, std::min((int)std::ceil(need) + 1, 64));
+    }
+  }
+  DI_HIP(hipMemcpyAsync(X_dev, ws->H, (size_t)g->n * sizeof(double), hipMemcpyDeviceToDevice,
+                        stream));
+  DI_HIP(hipEventRecord(ws->events[1], stream));
+  DI_HIP(hipEventSynchronize(ws->events[1]));
+  float ms = 0.f;
+  DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
+  di_stats t;
+  std::memset(&t, 0, sizeof(t));
+  t.cycles = h.cycles;
+  t.edges_pushed = (int64_t)h.edges_total;
+  t.nb_iter = g->L > 0 ? (double)h.edges_total / (double)g->L : 0.0;
+  t.resid_l1 = h.done == 3 ? h.final_r : resid;
+  t.err_bound = t.resid_l1 / (1.0 - d);
+  t.seconds = ms * 1e-3;
+  // per sweep: in-link ids and y gathers, and per row its offsets, x read
+  // and written, y written, B and the node word; plus the residual passes
+  const double N = (double)g->n, Lp = (double)g->Lp;
+  t.bytes_moved = (double)h.cycles * (Lp * 12.0 + N * 44.0) + (double)(checks + 1) * (Lp * 12.0 + N * 80.0);
+  if (st) *st = t;
+  if (h.done == 3) {
+    set_error("the iterate became non-finite (non-finite B?)");
+    return DI_E_INVAL;
+  }
+  if (h.done == 2 || resid > tol) {
+    set_error("max_cycles reached before the tolerance");
+    return DI_E_NOCONV;
+  }
+  return DI_OK;
 }
 
 template <typename T>
@@ -462,8 +557,10 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
     if (!ws->X64) DI_TRY(dmalloc((void**)&ws->X64, nbytes));
     X_dev = ws->X64;
   }
-  di_status rs = prec == kF64 ? solve_t<double>(g, B_dev, d, tol, o, X_dev, st, ws, stream)
-                              : solve_t<float>(g, B_dev, d, tol, o, X_dev, st, ws, stream);
+  di_status rs = o.method == DI_GS_ASYNC
+                     ? gs_solve(g, B_dev, d, tol, o, X_dev, st, ws, stream)
+                     : (prec == kF64 ? solve_t<double>(g, B_dev, d, tol, o, X_dev, st, ws, stream)
+                                     : solve_t<float>(g, B_dev, d, tol, o, X_dev, st, ws, stream));
   if (rs != DI_OK && rs != DI_E_NOCONV) return rs;
   if (X_on_host) DI_HIP(hipMemcpy(X, X_dev, nbytes, hipMemcpyDeviceToHost));
   return rs;

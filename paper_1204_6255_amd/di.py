@@ -21,7 +21,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "di.h")
 DI_OK, DI_PENDING = 0, 1
 DI_E_INVAL, DI_E_UNSORTED, DI_E_DUP, DI_E_RANGE = -1, -2, -3, -4
 DI_E_NOMEM, DI_E_NOCONV, DI_E_DEVICE, DI_E_BUSY, DI_E_NOTFOUND = -5, -6, -7, -8, -9
-DI_SOP, DI_CYC, DI_PI = 0, 1, 2
+DI_SOP, DI_CYC, DI_PI, DI_GS_ASYNC = 0, 1, 2, 3
 DI_FP64, DI_FP32_REFINE, DI_FP32 = 0, 1, 2
 DI_STOP_RESID, DI_STOP_PAPER = 0, 1
 DI_FLAG_KERNEL_TIMING = 1

@@ -253,3 +253,77 @@ def test_pi_method_is_the_power_iteration(torch_cuda, kernel, tol):
     st_s, h = di.di_serve_create(1 << 30, 8, o)
     assert st_s == di.DI_E_INVAL
     g.close()
+
+
+def star_graph(n):
+    """Node 0 links to every other node and every other node links to 0:
+    a row of n - 1 in-links, split into segments by the pull items."""
+    src = np.concatenate([np.zeros(n - 1, np.int64), np.arange(1, n)]).astype(np.int32)
+    dst = np.concatenate([np.arange(1, n), np.zeros(n - 1, np.int64)]).astype(np.int32)
+    order = np.lexsort((dst, src))
+    return src[order], dst[order]
+
+
+def with_loops(n, src, dst, every=7):
+    keep = src != dst
+    s = np.concatenate([src[keep], np.arange(0, n, every, dtype=np.int32)])
+    t = np.concatenate([dst[keep], np.arange(0, n, every, dtype=np.int32)])
+    order = np.lexsort((t, s))
+    return s[order].astype(np.int32), t[order].astype(np.int32)
+
+
+@pytest.mark.parametrize("case", ["web10k", "ppr", "signed", "loops", "star", "transposed"])
+def test_gs_async(torch_cuda, case):
+    """The Gauss-Seidel baseline as an asynchronous GPU relaxation: its
+    reported residual is exact and within tol, X is within tol / (1 - d) of
+    the oracle's solution, and it needs no more sweeps than the power
+    iteration (plus the sweeps the stop test's bound costs)."""
+    n = 10000
+    if case == "star":
+        n = 30001
+        src, dst = star_graph(n)
+    else:
+        src, dst = base(n)
+        if case == "loops":
+            src, dst = with_loops(n, src, dst)
+        elif case == "transposed":
+            src, dst = graphgen.transpose(src, dst)
+    og = oracle.Graph(n, src, dst)
+    if case == "ppr":
+        B = graphgen.ppr_rhs(n, graphgen.ppr_seed_sets(n, 1)[0], D)
+    elif case == "signed":
+        B = np.random.default_rng(3).standard_normal(n) * 1e-4
+    else:
+        B = graphgen.uniform_rhs(n, D)
+    ref, _, ost = oracle.diter(og, B, D, oracle.SOP, oracle.SEQUENTIAL, tol=1e-13)
+    assert ost.status == oracle.OK
+    g = di.Graph(n, src, dst)
+    o = di.di_opts_default()
+    o.method = di.DI_GS_ASYNC
+    Bd = torch_cuda.from_numpy(np.ascontiguousarray(B)).cuda()
+    X = torch_cuda.empty(n, dtype=torch_cuda.float64, device="cuda")
+    status, st = di.di_solve_dev(g.handle, Bd, D, TOL_PAR, o, X)
+    assert status == di.DI_OK, di.di_last_error()
+    torch_cuda.cuda.synchronize()
+    X = X.cpu().numpy()
+    _, r = oracle.residual(og, B, D, X)
+    # both residuals are sums of cancelling terms; the oracle adds a row's
+    # in-links one after another, whose rounding grows with the in-degree
+    indeg = np.bincount(dst[src != dst], minlength=n) + 2
+    scale = np.abs(B) + np.abs(X) + oracle.apply_p(og, D, np.abs(X))
+    bound = np.finfo(float).eps * float((indeg * scale).sum())
+    assert st.resid_l1 <= TOL_PAR and abs(r - st.resid_l1) <= 1e-6 * r + bound
+    assert np.abs(X - ref).sum() <= TOL_PAR / (1 - D) + 1e-12
+    _, sj = oracle.jacobi(og, B, D, tol=TOL_PAR)
+    assert 1 <= st.cycles <= sj.cycles + 3
+    assert st.edges_pushed == st.cycles * np.count_nonzero(src != dst)
+    # FP64 pull only; not a D-iteration, so no batches, serving or cycles
+    o.precision = di.DI_FP32_REFINE
+    status, _ = di.di_solve_dev(g.handle, Bd, D, TOL_PAR, o, X := torch_cuda.empty(
+        n, dtype=torch_cuda.float64, device="cuda"))
+    assert status == di.DI_E_INVAL
+    F = torch_cuda.from_numpy(np.ascontiguousarray(B)).cuda()
+    H = torch_cuda.zeros(n, dtype=torch_cuda.float64, device="cuda")
+    status, _, _ = di.di_cycles_dev(g.handle, D, di.DI_GS_ASYNC, F, H, 1)
+    assert status == di.DI_E_INVAL
+    g.close()
