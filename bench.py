@@ -65,8 +65,8 @@ def parse_args():
                    help="budget of the CPU-oracle sample (0 disables it)")
     p.add_argument("--no-extras", action="store_true",
                    help="headline solve only (no FP32, method, high-E, batched or serving sections)")
-    p.add_argument("--only", choices=["fp32_refine", "methods", "dataset2_like", "batched_ppr",
-                                      "serving"], default=None,
+    p.add_argument("--only", choices=["fp32_refine", "methods", "literal_alpha_1m", "config_10k",
+                                      "dataset2_like", "batched_ppr", "serving"], default=None,
                    help="run this one section after the headline solve (for profiling)")
     p.add_argument("--serve-seconds", type=float, default=6.0,
                    help="length of each serving phase")
@@ -99,12 +99,61 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(n, src, dst, d, tol, budget_s, with_baselines=True):
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_methods(oracle, og, B, d, tol):
+    """The oracle's five methods on one graph: resid mode to tol (time,
+    iterations, nb_iter), and nb_iter in the paper's mode (target 1/N)."""
+    n = og.n
+    out = {}
+    for name, variant in (("DI-SOP", oracle.SOP), ("DI-CYC", oracle.CYC)):
+        _, _, st = oracle.diter(og, B, d, variant, oracle.SEQUENTIAL, tol=tol)
+        _, _, sp = oracle.diter(og, B, d, variant, oracle.SEQUENTIAL, stop=oracle.STOP_PAPER,
+                                tol=1.0 / n)
+        out[name] = {"s": st.seconds, "cycles": int(st.cycles), "nb_iter": st.nb_iter,
+                     "paper_mode_nb_iter": sp.nb_iter}
+    _, st = oracle.jacobi(og, B, d, tol=tol)
+    _, sp = oracle.pi(og, d)
+    _, sq = oracle.pi(og, d, by_columns=True)
+    out["PI (power/Jacobi iteration)"] = {"s": st.seconds, "iterations": int(st.cycles),
+                                          "nb_iter": st.nb_iter,
+                                          "paper_mode_nb_iter": sp.nb_iter,
+                                          "paper_mode_nb_iter_PI'": sq.nb_iter}
+    _, st = oracle.gs(og, B, d, stop=oracle.STOP_RESID, tol=tol)
+    _, sp = oracle.gs(og, B, d, stop=oracle.STOP_PAPER, tol=1.0 / n)
+    out["GS (sequential sweep)"] = {"s": st.seconds, "sweeps": int(st.cycles),
+                                    "nb_iter": st.nb_iter, "paper_mode_nb_iter": sp.nb_iter}
+    return out
+
+
+def cpu_baseline(n, d, tol, budget_s, alpha, kmax, solutions=None, with_baselines=True):
+    """The oracle on the host: repeated DI-SOP solves of the benchmark graph
+    (the baseline value), its other methods once each, the N = 10k
+    configuration, and the L1 error of every GPU solution collected by the
+    other sections against an oracle solve to 1e-13."""
     import numpy as np
     import oracle
     from paper_1204_6255_amd import graphgen
 
-    og = oracle.Graph(n, src, dst)
+    graphs = {}
+
+    def graph(key):
+        if key not in graphs:
+            m, a = {"1m": (n, alpha), "1m_a2.1": (n, graphgen.ALPHA_LITERAL)}[key]
+            s_, t_ = graphgen.web_graph(m, seed=0, alpha=a, kmax=kmax)
+            graphs[key] = oracle.Graph(m, s_, t_)
+        return graphs[key]
+
+    og = graph("1m")
     B = graphgen.uniform_rhs(n, d)
     times = []
     t_start = time.perf_counter()
@@ -117,22 +166,36 @@ def cpu_baseline(n, src, dst, d, tol, budget_s, with_baselines=True):
         "value": float(np.mean(times)), "unit": "s", "cores": 1, "kind": "oracle",
         "sample": f"{len(times)} full solves of the same N={n} graph to sum|F| <= {tol:g} "
                   f"(sequential DI-SOP, one thread, FP64)",
+        "host_cpu": host_cpu(), "host_nproc": os.cpu_count(),
     }
-    # the oracle's baselines, one solve each to the same residual: the power
-    # (Jacobi) iteration and the Gauss-Seidel sweep (its residual checks are
-    # outside its timer)
-    if with_baselines:
-        others = {}
-        _, st = oracle.jacobi(og, B, d, tol=tol)
-        others["PI (power/Jacobi iteration)"] = {"s": st.seconds, "iterations": int(st.cycles),
-                                                 "nb_iter": st.nb_iter}
-        _, st = oracle.gs(og, B, d, stop=oracle.STOP_RESID, tol=tol)
-        others["GS (sequential sweep)"] = {"s": st.seconds, "sweeps": int(st.cycles),
-                                           "nb_iter": st.nb_iter}
-        _, _, st = oracle.diter(og, B, d, oracle.CYC, oracle.SEQUENTIAL, tol=tol)
-        others["DI-CYC (sequential)"] = {"s": st.seconds, "cycles": int(st.cycles),
-                                         "nb_iter": st.nb_iter}
-        out["oracle_baselines"] = others
+    if not with_baselines:
+        return out
+    out["oracle_baselines"] = oracle_methods(oracle, og, B, d, tol)
+    # the N = 10k configuration at both readings of the out-degree exponent
+    small = {}
+    for a in (graphgen.ALPHA_L_MATCHED, graphgen.ALPHA_LITERAL):
+        s_, t_ = graphgen.web_graph(10_000, seed=0, alpha=a, kmax=kmax)
+        small[f"alpha={a}"] = oracle_methods(oracle, oracle.Graph(10_000, s_, t_),
+                                             graphgen.uniform_rhs(10_000, d), d, tol)
+    out["oracle_n10k"] = small
+    # error of every collected GPU solution against the oracle's
+    if solutions:
+        refs, errs = {}, {}
+        for name, (gkey, bkey, X) in solutions.items():
+            if (gkey, bkey) not in refs:
+                og_ = graph(gkey)
+                if bkey == "uniform":
+                    Bk = graphgen.uniform_rhs(og_.n, d)
+                else:
+                    k, j = bkey
+                    Bk = graphgen.ppr_rhs(og_.n, graphgen.ppr_seed_sets(og_.n, k)[j], d)
+                refs[(gkey, bkey)], _, _ = oracle.diter(og_, Bk, d, oracle.SOP,
+                                                        oracle.SEQUENTIAL, tol=1e-13)
+            errs[name] = float(np.abs(X - refs[(gkey, bkey)]).sum())
+        out["error_vs_oracle_l1"] = errs
+        out["error_vs_oracle_note"] = ("L1 distance to the oracle's DI-SOP solve to 1e-13 "
+                                       "(itself within 1e-13/(1-d) of the exact X); a solve to "
+                                       "tol is within tol/(1-d)")
     return out
 
 
@@ -146,7 +209,7 @@ def time_solves(fn, reps):
     return (time.perf_counter() - t0) / reps, out[-1]
 
 
-def fp32_refine_section(di, g, X, d, tol):
+def fp32_refine_section(di, g, X, d, tol, solutions):
     o = di.di_opts_default()
     o.precision = di.DI_FP32_REFINE
 
@@ -157,11 +220,12 @@ def fp32_refine_section(di, g, X, d, tol):
         return st
 
     sec, st = time_solves(solve, 10)
+    solutions["DI-SOP pull fp32+refine"] = ("1m", "uniform", X.cpu().numpy())
     return {"s_per_solve": sec, "cycles": int(st.cycles), "refinements": int(st.refinements),
             "resid_l1": float(st.resid_l1)}
 
 
-def methods_section(di, g, X, d, tol):
+def methods_section(di, g, X, d, tol, solutions):
     """The paper's method comparison on the GPU, same graph and tolerance:
     DI-SOP, DI-CYC and PI, each moving fluid by the pull (rows gathered, as
     PI) and by the push (columns scattered, as PI'). PI diffuses every node
@@ -184,6 +248,23 @@ def methods_section(di, g, X, d, tol):
             rows.append({"method": name, "kernel": kname, "ms_per_solve": sec * 1e3,
                          "cycles": int(st.cycles), "nb_iter": float(st.nb_iter),
                          "resid_l1": float(st.resid_l1)})
+            solutions[f"{name} {kname} fp64"] = ("1m", "uniform", X.cpu().numpy())
+    # PI in FP32 with FP64 residual passes
+    o = di.di_opts_default()
+    o.method = di.DI_PI
+    o.precision = di.DI_FP32_REFINE
+
+    def pi32():
+        status, st = di.di_solve_dev(g.handle, None, d, tol, o, X)
+        if status != di.DI_OK:
+            raise RuntimeError(di.di_last_error())
+        return st
+
+    sec, st = time_solves(pi32, 5)
+    rows.append({"method": "PI", "kernel": "pull", "precision": "fp32+fp64 refinement",
+                 "ms_per_solve": sec * 1e3, "cycles": int(st.cycles), "nb_iter": float(st.nb_iter),
+                 "refinements": int(st.refinements), "resid_l1": float(st.resid_l1)})
+    solutions["PI pull fp32+refine"] = ("1m", "uniform", X.cpu().numpy())
     # the Gauss-Seidel baseline as an asynchronous in-place relaxation
     o = di.di_opts_default()
     o.method = di.DI_GS_ASYNC
@@ -198,7 +279,61 @@ def methods_section(di, g, X, d, tol):
     rows.append({"method": "GS-async (GPU variant)", "kernel": "pull", "ms_per_solve": sec * 1e3,
                  "cycles": int(st.cycles), "nb_iter": float(st.nb_iter),
                  "resid_l1": float(st.resid_l1)})
+    solutions["GS-async pull fp64"] = ("1m", "uniform", X.cpu().numpy())
     return rows
+
+
+def literal_alpha_section(di, graphgen, n, d, tol, kmax, solutions):
+    """The N = 1M graph at the literal out-degree exponent 2.1 (about 2.8
+    links per node): DI-SOP in FP64 and FP32 with FP64 refinement."""
+    import torch
+    src, dst = graphgen.web_graph(n, seed=0, alpha=graphgen.ALPHA_LITERAL, kmax=kmax)
+    st_g = graphgen.graph_stats(n, src, dst)
+    g = di.Graph(n, src, dst)
+    del src, dst
+    X = torch.empty(n, dtype=torch.float64, device="cuda")
+    out = {"alpha": graphgen.ALPHA_LITERAL, "links": int(st_g.L), "dangling": int(st_g.D),
+           "zero_in": int(st_g.zero_in), "rows": []}
+    for pname, prec in (("fp64", di.DI_FP64), ("fp32+refine", di.DI_FP32_REFINE)):
+        o = di.di_opts_default()
+        o.precision = prec
+
+        def solve():
+            status, st = di.di_solve_dev(g.handle, None, d, tol, o, X)
+            if status != di.DI_OK:
+                raise RuntimeError(di.di_last_error())
+            return st
+
+        sec, st = time_solves(solve, 10)
+        out["rows"].append({"precision": pname, "ms_per_solve": sec * 1e3, "cycles": int(st.cycles),
+                            "nb_iter": float(st.nb_iter), "resid_l1": float(st.resid_l1),
+                            "gedges_per_s": st.edges_pushed / sec / 1e9})
+        solutions[f"alpha 2.1 DI-SOP {pname}"] = ("1m_a2.1", "uniform", X.cpu().numpy())
+    g.close()
+    return out
+
+
+def small_graph_section(di, graphgen, d, tol):
+    """The N = 10k configuration (launch-latency bound), both exponents."""
+    import torch
+    out = []
+    for a in (graphgen.ALPHA_L_MATCHED, graphgen.ALPHA_LITERAL):
+        src, dst = graphgen.web_graph(10_000, seed=0, alpha=a)
+        g = di.Graph(10_000, src, dst)
+        X = torch.empty(10_000, dtype=torch.float64, device="cuda")
+        o = di.di_opts_default()
+
+        def solve():
+            status, st = di.di_solve_dev(g.handle, None, d, tol, o, X)
+            if status != di.DI_OK:
+                raise RuntimeError(di.di_last_error())
+            return st
+
+        sec, st = time_solves(solve, 20)
+        out.append({"alpha": a, "links": int(len(src)), "ms_per_solve": sec * 1e3,
+                    "cycles": int(st.cycles), "nb_iter": float(st.nb_iter)})
+        g.close()
+    return out
 
 
 def high_e_section(di, graphgen, d):
@@ -231,7 +366,7 @@ def high_e_section(di, graphgen, d):
     return out
 
 
-def batched_section(di, graphgen, g, n, d, tol):
+def batched_section(di, graphgen, g, n, d, tol, solutions):
     import numpy as np
     import torch
     out = {"precision": "fp32+fp64 refinement", "tol": tol, "seed_sets": "1..100 nodes, seed 1000+j"}
@@ -263,6 +398,9 @@ def batched_section(di, graphgen, g, n, d, tol):
             return st
 
         sec, st = time_solves(batch, 2)
+        Xh = Xd[:2].cpu().numpy()
+        for j in range(2):
+            solutions[f"batched k={k} column {j}"] = ("1m", (k, j), Xh[j].copy())
         runs.append({"k": k, "s_per_batch": sec, "solves_per_s": k / sec,
                      "vs_single_fp64": (k / sec) * sec1,
                      "max_cycles": max(x.cycles for x in st),
@@ -433,6 +571,20 @@ def main():
     achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
     traffic = read_traffic() if headline else None
     edges = float(np.mean([r.edges_pushed for r in runs]))
+    solutions = {"DI-SOP pull fp64 (headline)": ("1m", "uniform", X.cpu().numpy())}
+    # an achievable copy rate on this device, beside the published peak:
+    # 512 MiB read and 512 MiB written per copy, timed with events
+    ca = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * ca.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del ca, cb
 
     line = {
         "metric": "s to L1 resid\u22641e-9 and % HBM peak at N=1M; batched PPR solves/s, p50/p99 ms",
@@ -457,6 +609,7 @@ def main():
         "cycles": int(last.cycles),
         "nb_iter": float(last.nb_iter),
         "gedges_per_s": edges / sec / 1e9,
+        "bytes_per_edge": float(last.bytes_moved) / max(float(last.edges_pushed), 1.0),
         "resid_l1": float(last.resid_l1),
         "err_bound": float(last.err_bound),
         "roofline": {
@@ -470,6 +623,7 @@ def main():
             "traffic": traffic if opts.kernel != di.DI_KERNEL_PUSH else None,
             "bytes_per_launch": per_launch_bytes,
             "us_per_launch": per_launch_s * 1e6,
+            "achievable_copy_gbps": copy_gbps,
         },
     }
     if args.calibration_copy:
@@ -482,10 +636,13 @@ def main():
     line["hbm_frac"] = line["roofline"]["frac"]
     if not args.no_extras and headline:
         sections = {
-            "fp32_refine": lambda: fp32_refine_section(di, g, X, d, tol),
-            "methods": lambda: methods_section(di, g, X, d, tol),
+            "fp32_refine": lambda: fp32_refine_section(di, g, X, d, tol, solutions),
+            "methods": lambda: methods_section(di, g, X, d, tol, solutions),
+            "literal_alpha_1m": lambda: literal_alpha_section(di, graphgen, n, d, tol, args.kmax,
+                                                              solutions),
+            "config_10k": lambda: small_graph_section(di, graphgen, d, tol),
             "dataset2_like": lambda: high_e_section(di, graphgen, d),
-            "batched_ppr": lambda: batched_section(di, graphgen, g, n, d, tol),
+            "batched_ppr": lambda: batched_section(di, graphgen, g, n, d, tol, solutions),
             "serving": lambda: serving_section(di, graphgen, d, args.serve_seconds,
                                                args.serve_kmax),
         }
@@ -493,8 +650,9 @@ def main():
             if args.only is None or args.only == name:
                 line[name] = run()
     if args.cpu_seconds > 0:
-        src, dst = graphgen.web_graph(n, seed=0, alpha=args.alpha, kmax=args.kmax)
-        line["cpu_baseline"] = cpu_baseline(n, src, dst, d, tol, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(n, d, tol, args.cpu_seconds, args.alpha, args.kmax,
+                                            solutions if headline else None,
+                                            with_baselines=headline)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
