@@ -19,6 +19,12 @@ writes profiles/OUT_NAME: the mean per dispatch of every counter that
 
 writes profiles/OUT_NAME: the per-kernel table of any `--kernel-trace
 --stats` run (csv, output name `run`).
+
+    python -m paper_1204_6255_amd.profsum traffic OUT_NAME KERNEL FETCH_DIR WRITE_DIR "<title>" \
+        "<fetch command>" "<write command>"
+
+writes profiles/OUT_NAME: HBM bytes per launch of KERNEL (short name) from
+`--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs with --calibration-copy.
 """
 
 from __future__ import annotations
@@ -44,6 +50,17 @@ def kernel_stats(d: str):
         return list(csv.DictReader(f))
 
 
+def calibration_kib(d: str) -> float:
+    """The counter value of the run's last copy dispatch: the calibration copy
+    bench.py makes after its timed region (earlier copies are uploads)."""
+    last_id, value = -1, None
+    with open(os.path.join(d, "run_counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if short(r["Kernel_Name"]) == "__amd_rocclr_copyBuffer" and int(r["Dispatch_Id"]) > last_id:
+                last_id, value = int(r["Dispatch_Id"]), float(r["Counter_Value"])
+    return value
+
+
 def counters(d: str):
     agg = collections.defaultdict(list)
     with open(os.path.join(d, "run_counter_collection.csv")) as f:
@@ -64,9 +81,9 @@ def main(argv):
     with open(os.path.join(PROFILES, "di_sop_f64_n1m_kernels.txt"), "w") as f:
         f.write("\n".join(out) + "\n")
     fe, wr = counters(fetch_dir), counters(write_dir)
-    copy = "__amd_rocclr_copyBuffer"
-    ff = COPY_KIB / max(fe[copy])
-    fw = COPY_KIB / max(wr[copy])
+    cf, cw = calibration_kib(fetch_dir), calibration_kib(write_dir)
+    ff = COPY_KIB / cf
+    fw = COPY_KIB / cw
     pull = [k for k in fe if short(k) == "k_pull<double>"][0]
     f_kib = sum(fe[pull]) / len(fe[pull])
     w_kib = sum(wr[pull]) / len(wr[pull])
@@ -79,9 +96,9 @@ def main(argv):
         f"# write command: {write_cmd}",
         "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the factor that makes",
         "# the same counter read 256 MiB for the 256 MiB torch copy (__amd_rocclr_copyBuffer)",
-        "# run in the same command (--calibration-copy).",
-        f"copy_fetch_kib: {max(fe[copy]):.1f}",
-        f"copy_write_kib: {max(wr[copy]):.1f}",
+        "# run last in the same command (--calibration-copy).",
+        f"copy_fetch_kib: {cf:.1f}",
+        f"copy_write_kib: {cw:.1f}",
         f"fetch_scale: {ff:.4f}",
         f"write_scale: {fw:.4f}",
         f"pull_dispatches: {len(fe[pull])}",
@@ -121,6 +138,38 @@ def counters_main(argv):
     print("\n".join(lines))
 
 
+def traffic_main(argv):
+    """traffic OUT_NAME KERNEL FETCH_DIR WRITE_DIR TITLE FETCH_CMD WRITE_CMD:
+    HBM bytes per launch of one kernel (its short name, e.g. k_pull<float>),
+    each counter scaled by what it reads for the calibration copy."""
+    out_name, kernel, fetch_dir, write_dir, title, fetch_cmd, write_cmd = argv[:7]
+    fe, wr = counters(fetch_dir), counters(write_dir)
+    cf, cw = calibration_kib(fetch_dir), calibration_kib(write_dir)
+    ff = COPY_KIB / cf
+    fw = COPY_KIB / cw
+    name = [k for k in fe if short(k) == kernel][0]
+    f_kib = sum(fe[name]) / len(fe[name])
+    w_kib = sum(wr[name]) / len(wr[name])
+    lines = [
+        f"# HBM traffic of {kernel} per launch, {title}",
+        f"# fetch command: {fetch_cmd}",
+        f"# write command: {write_cmd}",
+        "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the factor that makes",
+        "# the same counter read 256 MiB for the 256 MiB torch copy run last in the same command.",
+        f"copy_fetch_kib: {cf:.1f}",
+        f"copy_write_kib: {cw:.1f}",
+        f"fetch_scale: {ff:.4f}",
+        f"write_scale: {fw:.4f}",
+        f"dispatches: {len(fe[name])}",
+        f"fetch_kib_mean: {f_kib:.1f}",
+        f"write_kib_mean: {w_kib:.1f}",
+        f"traffic_bytes_per_launch: {(f_kib * ff + w_kib * fw) * 1024:.0f}",
+    ]
+    with open(os.path.join(PROFILES, out_name), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def trace_main(argv):
     """trace OUT_NAME DIR TITLE CMD: the per-kernel table of a
     `--kernel-trace --stats` run."""
@@ -141,5 +190,7 @@ if __name__ == "__main__":
         counters_main(sys.argv[2:])
     elif sys.argv[1:2] == ["trace"]:
         trace_main(sys.argv[2:])
+    elif sys.argv[1:2] == ["traffic"]:
+        traffic_main(sys.argv[2:])
     else:
         main(sys.argv[1:])
