@@ -925,7 +925,16 @@ __global__ void k_gs_init(double* __restrict__ x, double* __restrict__ y,
 
 // One sweep over the light rows (in place); heavy-row segments leave their
 // sums in seg_val. Each block writes one record: sum |dx| and sum dx of its
-// rows. y is read and written by every block: no restrict.
+// rows. y is read and written by every block concurrently: its accesses are
+// relaxed device-scope atomics (well defined, and any value a read returns
+// is one the bound above allows).
+__device__ inline double y_read(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void y_write(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(kPullBlock) void k_gs_sweep(
     double* __restrict__ x, double* y, const double* __restrict__ B, double b_uniform,
     double d, const uint32_t* __restrict__ info, const int64_t* __restrict__ csc_ptr,
@@ -948,7 +957,7 @@ __global__ __launch_bounds__(kPullBlock) void k_gs_sweep(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = tid + u * kPullBlock;
-      v[u] = p < nl ? y[csc_idx[l0 + p]] : 0.0;
+      v[u] = p < nl ? y_read(y + csc_idx[l0 + p]) : 0.0;
     }
     if (seg >= 0) {
       double acc = 0.0;
@@ -992,7 +1001,7 @@ __global__ __launch_bounds__(kPullBlock) void k_gs_sweep(
         const double xn = (bi + acc) / gs_diag(w, d);
         const int out = (int)(w & kOutMask);
         x[row] = xn;
-        y[row] = out > 0 ? d * xn / (double)out : 0.0;
+        y_write(y + row, out > 0 ? d * xn / (double)out : 0.0);
         acc_part.pabs += fabs(xn - xo);
         acc_part.psum += xn - xo;
       }
