@@ -20,12 +20,19 @@
 //           bitmap, staged through LDS in work items of at most kPullChunk
 //           links; each block writes one record (sums over its rows and the
 //           folded tile statistics). A row with more in-links is split into
-//           segments whose sums are added to F[row] with a few FP64 atomics.
+//           segments whose sums the next selection completes in a fixed
+//           order (with more than kHeavyLds such rows, the segments are
+//           added to F[row] with FP64 atomics instead).
 //           push: each selected node's out-links (CSR) receive
 //           transit*d/out_i by device-scope float atomics (one push block
 //           per select tile), then a reduction writes the records.
-// Kernels return at once after the stop, so the host may queue cycles ahead
-// of the stop test.
+// The selection rule is DI-SOP's, DI-CYC's (every node holding fluid) or
+// the power iteration's (every node). Kernels return at once after the stop,
+// so the host may queue cycles ahead of the stop test.
+//
+// Also here: the FP64 residual pass of a refined solve (R = B + P.X - X,
+// through the same work items), and the asynchronous Gauss-Seidel baseline
+// (an in-place relaxation over the same items).
 
 #include "di_internal.h"
 #include <hip/hip_ext.h>

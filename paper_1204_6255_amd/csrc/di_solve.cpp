@@ -5,6 +5,10 @@
 // convergence at the cost of empty launches. After each chunk the host reads
 // the control block (a pinned copy) and sizes the next chunk from the
 // observed contraction of r per cycle.
+//
+// Also here: the FP32 + FP64 refinement loop, the residual entry point, the
+// asynchronous Gauss-Seidel baseline's driver, and a step-driven FP64 solve
+// that the serving worker advances a chunk at a time.
 
 #include <algorithm>
 #include <cmath>
