@@ -327,3 +327,55 @@ def test_gs_async(torch_cuda, case):
     status, _, _ = di.di_cycles_dev(g.handle, D, di.DI_GS_ASYNC, F, H, 1)
     assert status == di.DI_E_INVAL
     g.close()
+
+
+def test_pi_and_gs_edge_cases(torch_cuda):
+    torch = torch_cuda
+    n = 10000
+    src, dst = base(n)
+    og, B, ref = oracle_x(n, src, dst)
+    g = di.Graph(n, src, dst)
+    # PI with FP32 fluid and FP64 residual passes
+    o = di.di_opts_default()
+    o.method = di.DI_PI
+    o.precision = di.DI_FP32_REFINE
+    X = torch.empty(n, dtype=torch.float64, device="cuda")
+    status, st = di.di_solve_dev(g.handle, None, D, TOL_PAR, o, X)
+    assert status == di.DI_OK and st.refinements >= 1, di.di_last_error()
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    _, r = oracle.residual(og, B, D, Xh)
+    assert st.resid_l1 <= TOL_PAR and abs(r - st.resid_l1) <= 1e-15 + 1e-6 * r
+    assert np.abs(Xh - ref).sum() <= TOL_PAR / (1 - D) + 1e-12
+    # GS-async: max_cycles gives NOCONV with the sweeps' x and its residual
+    o = di.di_opts_default()
+    o.method = di.DI_GS_ASYNC
+    o.max_cycles = 3
+    status, st = di.di_solve_dev(g.handle, None, D, 1e-12, o, X)
+    assert status == di.DI_E_NOCONV and st.cycles == 3
+    torch.cuda.synchronize()
+    _, r = oracle.residual(og, B, D, X.cpu().numpy())
+    assert abs(r - st.resid_l1) <= 1e-15 + 1e-6 * r and r > 1e-12
+    # host arrays, personalized B
+    o.max_cycles = 0
+    Bp = graphgen.ppr_rhs(n, graphgen.ppr_seed_sets(n, 1, 77)[0], D)
+    Xp = np.empty(n)
+    status, st = di.di_solve(g.handle, Bp, D, TOL_PAR, o, Xp)
+    assert status == di.DI_OK
+    refp, _, _ = oracle.diter(og, Bp, D, oracle.SOP, oracle.SEQUENTIAL, tol=1e-13)
+    assert np.abs(Xp - refp).sum() <= TOL_PAR / (1 - D) + 1e-12
+    # B = 0: x = 0 after one sweep, residual 0
+    status, st = di.di_solve(g.handle, np.zeros(n), D, TOL_PAR, o, Xp)
+    assert status == di.DI_OK and st.cycles == 1 and st.resid_l1 == 0.0 and not Xp.any()
+    g.close()
+    # one node without links: x = B
+    g1 = di.Graph(1, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    X1 = np.empty(1)
+    status, st = di.di_solve(g1.handle, None, D, 1e-12, o, X1)
+    assert status == di.DI_OK and abs(X1[0] - (1 - D)) <= 1e-16 and st.resid_l1 == 0.0
+    # a self-loop-only node: x = B / (1 - d)
+    g2 = di.Graph(1, np.zeros(1, np.int32), np.zeros(1, np.int32))
+    status, st = di.di_solve(g2.handle, None, D, 1e-12, o, X1)
+    assert status == di.DI_OK and abs(X1[0] - 1.0) <= 1e-15
+    g1.close()
+    g2.close()
