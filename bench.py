@@ -572,6 +572,15 @@ def main():
     traffic = read_traffic() if headline else None
     edges = float(np.mean([r.edges_pushed for r in runs]))
     solutions = {"DI-SOP pull fp64 (headline)": ("1m", "uniform", X.cpu().numpy())}
+    # the same solve through the host-array entry (B and X cross PCIe)
+    Xh = np.empty(n)
+    di.di_solve(g.handle, None, d, tol, opts, Xh)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        status, _ = di.di_solve(g.handle, None, d, tol, opts, Xh)
+        if status != di.DI_OK:
+            raise RuntimeError(di.di_last_error())
+    pcie_s = (time.perf_counter() - t0) / 5
     # an achievable copy rate on this device, beside the published peak:
     # 512 MiB read and 512 MiB written per copy, timed with events
     ca = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -610,6 +619,7 @@ def main():
         "nb_iter": float(last.nb_iter),
         "gedges_per_s": edges / sec / 1e9,
         "bytes_per_edge": float(last.bytes_moved) / max(float(last.edges_pushed), 1.0),
+        "host_arrays_s": pcie_s,
         "resid_l1": float(last.resid_l1),
         "err_bound": float(last.err_bound),
         "roofline": {
