@@ -373,3 +373,46 @@ def test_duplicate_check_on_unsorted_lists():
     with pytest.raises(ValueError):
         oracle.Graph(3, src, dst)
     oracle.Graph(3, np.array([0, 0], np.int32), np.array([2, 1], np.int32))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_power_iterates_against_matrix_powers(seed):
+    """The unnormalized power (Jacobi) iteration starts at B and after m
+    steps holds sum_{k<=m} P^k B (Section 2.5.1's update without the
+    normalization); its residual is then |P^(m+1) B|_1. Checked against
+    dense matrix powers, self-loops included."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(8, 30))
+    src, dst = _random_graph(rng, n)
+    g = oracle.Graph(n, src, dst)
+    P = dense_p(n, src, dst, D)
+    B = rng.random(n)
+    for m in (0, 1, 5, 12):
+        x, st = oracle.jacobi(g, B, D, tol=0.0, max_iter=m)
+        assert st.status == oracle.E_NOCONV and st.cycles == m
+        ref = sum(np.linalg.matrix_power(P, k) @ B for k in range(m + 1))
+        assert np.allclose(x, ref, rtol=1e-13, atol=1e-15)
+        r_ref = np.abs(np.linalg.matrix_power(P, m + 1) @ B).sum()
+        assert abs(st.resid_l1 - r_ref) <= 1e-13 * max(r_ref, 1e-300) + 1e-15
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_gauss_seidel_sweep_against_the_splitting(seed):
+    """One ascending Gauss-Seidel sweep from x0 = B is the textbook
+    splitting of A = I - P into its lower part L, diagonal D and upper part U:
+    x1 = (D + L)^-1 (B - U x0). Checked with a dense triangular solve,
+    self-loops (a diagonal of P) included."""
+    rng = np.random.default_rng(400 + seed)
+    n = int(rng.integers(8, 30))
+    src, dst = _random_graph(rng, n)
+    g = oracle.Graph(n, src, dst)
+    A = np.eye(n) - dense_p(n, src, dst, D)
+    B = rng.random(n)
+    lower = np.tril(A)
+    upper = np.triu(A, 1)
+    x = B.copy()
+    for sweeps in (1, 2, 3):
+        x = np.linalg.solve(lower, B - upper @ x)
+        xs, st = oracle.gs(g, B, D, tol=0.0, max_sweeps=sweeps)
+        assert st.status == oracle.E_NOCONV and st.cycles == sweeps
+        assert np.allclose(xs, x, rtol=1e-12, atol=1e-15)
