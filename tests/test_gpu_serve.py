@@ -291,3 +291,33 @@ def test_serving_errors(torch_cuda):
     assert di.di_serve_add_graph(small.h, g.handle, 0) == di.DI_E_NOMEM
     small.close()
     srv.close()
+
+
+def test_all_nodes_seed_set_is_uniform_pagerank(torch_cuda):
+    """A seed set of every node gives B = (1-d)/N, the uniform right-hand
+    side: served alone and in a column set, the answer equals the uniform
+    request's, and a batch column with that B equals a uniform column."""
+    n = 10000
+    _, _, g, og = graph(n, 0)
+    every = np.arange(n, dtype=np.int32)
+    for flags in (0, di.DI_FLAG_SERVE_NO_SOLO):
+        o = di.di_opts_default()
+        o.precision = di.DI_FP32_REFINE
+        o.flags = flags
+        srv = Server(8 * GIB, 8, o)
+        di.di_serve_add_graph(srv.h, g.handle, 0)
+        st, t1 = di.di_serve_submit(srv.h, 0, every, D, 1e-9)
+        st, X1, _ = wait(srv, t1, n)
+        assert st == di.DI_OK
+        st, t2 = di.di_serve_submit(srv.h, 0, None, D, 1e-9)
+        st, X2, _ = wait(srv, t2, n)
+        assert st == di.DI_OK
+        assert np.array_equal(X1, X2)
+        check(og, [], 1e-9, X1)
+        srv.close()
+    B = np.stack([graphgen.ppr_rhs(n, every, D), graphgen.uniform_rhs(n, D)])
+    o = di.di_opts_default()
+    o.precision = di.DI_FP32_REFINE
+    status, Xb, _ = di.di_solve_batch(g.handle, 2, B, D, [1e-9, 1e-9], o)
+    assert status == di.DI_OK
+    assert np.array_equal(Xb[0], Xb[1])
