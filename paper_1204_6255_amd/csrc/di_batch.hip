@@ -300,12 +300,16 @@ __global__ __launch_bounds__(kBBlock) void k_bselect(
     unsigned long long word = 0;
     for (int t0 = 0; t0 < NT; t0 += NB) {
       uint32_t wis[NB];
-      Pack<T, V> fs[NB];
+      Pack<T, V> fs[NB], hs[NB];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int64_t i = w * 64 + (t0 + u) * P + grp;
         wis[u] = i < n ? info[i] : 0u;
         fs[u] = (i < n && lane_run) ? ld<T, V>(F + i * KP + gl * V) : zero_pack<T, V>();
+        // narrow batches load H with F (one round of loads instead of a
+        // dependent one); wide ones load it only where a column selects
+        if constexpr (KE <= 32)
+          hs[u] = (i < n && lane_run) ? ld<T, V>(H + i * KP + gl * V) : zero_pack<T, V>();
       }
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
@@ -345,7 +349,9 @@ __global__ __launch_bounds__(kBBlock) void k_bselect(
           if (any_sel) {
             st<T, V>(F + i * KP + gl * V, f);
             T* Hi = H + i * KP + gl * V;
-            Pack<T, V> h = ld<T, V>(Hi);
+            Pack<T, V> h;
+            if constexpr (KE <= 32) h = hs[u];
+            else h = ld<T, V>(Hi);
 #pragma unroll
             for (int v = 0; v < V; ++v)
               if (tr[v] != 0.0) h.v[v] = (T)(to_d(h.v[v]) + tr[v]);
