@@ -23,7 +23,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# DI_ORACLE_LIB names another build of oracle.c (the sanitizer test's)
+_LIB_PATH = os.environ.get("DI_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 SOP, CYC = 0, 1

@@ -18,5 +18,18 @@ def build(verbose: bool = False) -> str:
     return out
 
 
+def build_sanitized(out: str, verbose: bool = False) -> str:
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc, host code only), aborting on the first report."""
+    cmd = ["gcc", "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
+           "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-o", out, os.path.join(HERE, "oracle.c"), "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
