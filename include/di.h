@@ -142,6 +142,15 @@ typedef struct di_stats {
   double move_bytes;        /* algorithmic bytes of those pull/push launches */
 } di_stats;
 
+/* One cycle of a traced solve (di_solve_trace_dev). */
+typedef struct di_cycle_rec {
+  double r;          /* sum |F| at the cycle's start: the r its selection used
+                        (Section 2.5.5) */
+  int64_t links;     /* link operations of the cycle */
+  int32_t selected;  /* nodes diffused */
+  int32_t senders;   /* diffused nodes with links to move */
+} di_cycle_rec;
+
 /* Fills *opts with the defaults listed in di_opts. */
 void di_opts_default(di_opts* opts);
 
@@ -184,6 +193,16 @@ di_status di_solve(const di_graph* g, const double* B, double d, double tol, con
  * queued on opts->stream and the call returns once it has finished. */
 di_status di_solve_dev(const di_graph* g, const double* B_dev, double d, double tol,
                        const di_opts* opts, double* X_dev, di_stats* stats);
+
+/* di_solve_dev with a per-cycle trace: record c of trace[0, capacity) (host,
+ * caller-allocated) describes cycle c of the solve (DI_FP32_REFINE numbers
+ * the cycles of its passes one after another). *count (host) receives the
+ * number of records written, min(cycles, capacity). capacity 0 writes none.
+ * DI-SOP, DI-CYC and PI; DI_E_INVAL for DI_GS_ASYNC (its sweeps are not
+ * cycles) or a negative capacity. Otherwise as di_solve_dev. */
+di_status di_solve_trace_dev(const di_graph* g, const double* B_dev, double d, double tol,
+                             const di_opts* opts, double* X_dev, di_stats* stats,
+                             di_cycle_rec* trace, int32_t capacity, int32_t* count);
 
 /* Runs exactly `cycles` frontier-synchronous FP64 cycles of DI-SOP
  * (method DI_SOP) or DI-CYC (DI_CYC) on the state (F, H) in place, with no

@@ -129,6 +129,8 @@ struct Workspace {
   double* X64 = nullptr;        // host entry points: device copy of X
   double* B64 = nullptr;        // host entry points: device copy of B
   std::vector<hipEvent_t> events;
+  di_cycle_rec* trace = nullptr;  // per-cycle records of a traced solve
+  int trace_cap = 0;
 };
 
 }  // namespace di
@@ -218,6 +220,8 @@ struct CycleArgs {
   int max_cycles;  // the solve stops after this many cycles
   int direction;   // kPull or kPush
   hipStream_t stream;
+  di_cycle_rec* trace;  // device records of this run's cycles (or null)
+  int trace_cap;        // records it has room for
 };
 
 int select_tiles(int64_t n, int direction);

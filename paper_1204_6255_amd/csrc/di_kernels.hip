@@ -323,7 +323,8 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     const int64_t* __restrict__ hc_seg0, const int64_t* __restrict__ hc_seg1,
     const int64_t* __restrict__ hc_off, const double* __restrict__ seg_val, int64_t n_heavy,
     int64_t n_hchunks, int heavy_atomic, Ctl* __restrict__ ctl, int parity, int first, double d,
-    double tol, double tol_in, double tol_rel, int method, int stop, int max_cycles) {
+    double tol, double tol_in, double tol_rel, int method, int stop, int max_cycles,
+    di_cycle_rec* __restrict__ trace, int trace_cap) {
   constexpr int TILE = BLOCK * M;
   constexpr int NW = BLOCK / 64;
   constexpr int HPT = PULL ? kHeavyLds / BLOCK : 1;  // heavy rows per thread
@@ -415,7 +416,14 @@ __global__ __launch_bounds__(BLOCK) void k_select(
   v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
   if (tid == 0) {
     const Ctl c = next_ctl(c0, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
-    if (blockIdx.x == 0) ctl[parity ^ 1] = c;
+    if (blockIdx.x == 0) {
+      ctl[parity ^ 1] = c;
+      // the cycle just counted: the r its selection used and the statistics
+      // of that selection (folded into the records)
+      if (trace && !first && !c0.done && c.cycles - 1 < trace_cap)
+        trace[c.cycles - 1] = di_cycle_rec{c.r_last, (int64_t)v.ops, (int32_t)v.sel,
+                                           (int32_t)v.nfront};
+    }
     s_done = c.done;
     s_was_done = c0.done;
     s_cyc = c.cyc_mode;
@@ -1151,7 +1159,7 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        nparts, g->heavy_row, g->hc_seg0, g->hc_seg1, g->hc_off,
                        (const double*)ws->seg_val, g->n_heavy, g->n_hchunks, (int)g->heavy_atomic,
                        ws->ctl, parity, first, a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop,
-                       a.max_cycles);
+                       a.max_cycles, a.trace, a.trace_cap);
   } else {
     hipLaunchKernelGGL((k_select<T, false, kSelectBlockPush, kSelectPerThreadPush>), dim3(grid),
                        dim3(kSelectBlockPush), 0, a.stream, (T*)ws->F, (T*)ws->H, g->info,
@@ -1160,7 +1168,8 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        (const Part*)ws->blk_part, nparts, (const int32_t*)nullptr,
                        (const int64_t*)nullptr, (const int64_t*)nullptr, (const int64_t*)nullptr,
                        (const double*)nullptr, (int64_t)0, (int64_t)0, 0, ws->ctl, parity, first,
-                       a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop, a.max_cycles);
+                       a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop, a.max_cycles, a.trace,
+                       a.trace_cap);
   }
   return hipGetLastError();
 }

@@ -25,7 +25,7 @@ void free_workspace(Workspace* ws) {
   void* ptrs[] = {ws->F,         ws->H,         ws->sent,     ws->front_bits,
                   ws->fr_lstart, ws->fr_base,   ws->fr_s,     ws->tile_stat,
                   ws->blk_part,  ws->seg_val,   ws->ctl,      ws->X64,      ws->B64,
-                  ws->Y64};
+                  ws->Y64,       ws->trace};
   for (void* p : ptrs) (void)hipFree(p);
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   if (ws->host_part) (void)hipHostFree(ws->host_part);
@@ -448,7 +448,7 @@ di_status gs_solve(di_graph* g, const double* B_dev, double d, double tol, const
 
 template <typename T>
 di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const di_opts& o,
-                  double* X_dev, di_stats* st, Workspace* ws, hipStream_t stream) {
+                  double* X_dev, di_stats* st, Workspace* ws, hipStream_t stream, int trace_cap) {
   CycleArgs a{};
   a.g = g;
   a.ws = ws;
@@ -462,6 +462,8 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   a.direction = direction_of(o);
   a.stream = stream;
   a.first_parts = part_count(a) + 1;
+  a.trace = trace_cap > 0 ? ws->trace : nullptr;
+  a.trace_cap = trace_cap;
   const bool timing = (o.flags & DI_FLAG_KERNEL_TIMING) != 0;
   const double b_uniform = (1.0 - d) / (double)g->n;
   if (a.direction == kPush) DI_TRY(ensure_push_buffers(g, ws));
@@ -492,6 +494,9 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   di_status result = DI_OK;
   for (;;) {
     a.max_cycles = max_cycles - tot.cycles;
+    // the passes' cycles are numbered one after another in the trace
+    a.trace = trace_cap > tot.cycles ? ws->trace + tot.cycles : nullptr;
+    a.trace_cap = std::max(0, trace_cap - tot.cycles);
     DI_TRY(run_cycles<T>(a, timing, ws->events[0], &rt));
     const Ctl h = rt.state;
     add_run(&tot, h);
@@ -525,7 +530,8 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
 }
 
 di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double d, double tol,
-                    const di_opts* opts, double* X, bool X_on_host, di_stats* st) {
+                    const di_opts* opts, double* X, bool X_on_host, di_stats* st,
+                    di_cycle_rec* trace = nullptr, int trace_cap = 0, int32_t* trace_count = nullptr) {
   di_opts o;
   di_opts_default(&o);
   if (opts) o = *opts;
@@ -561,10 +567,27 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
     if (!ws->X64) DI_TRY(dmalloc((void**)&ws->X64, nbytes));
     X_dev = ws->X64;
   }
+  if (trace_cap > ws->trace_cap) {
+    if (ws->trace) (void)hipFree(ws->trace);
+    ws->trace = nullptr;
+    ws->trace_cap = 0;
+    DI_TRY(dmalloc((void**)&ws->trace, (size_t)trace_cap * sizeof(di_cycle_rec)));
+    ws->trace_cap = trace_cap;
+  }
+  di_stats local;
+  if (!st) st = &local;
   di_status rs = o.method == DI_GS_ASYNC
                      ? gs_solve(g, B_dev, d, tol, o, X_dev, st, ws, stream)
-                     : (prec == kF64 ? solve_t<double>(g, B_dev, d, tol, o, X_dev, st, ws, stream)
-                                     : solve_t<float>(g, B_dev, d, tol, o, X_dev, st, ws, stream));
+                     : (prec == kF64
+                            ? solve_t<double>(g, B_dev, d, tol, o, X_dev, st, ws, stream, trace_cap)
+                            : solve_t<float>(g, B_dev, d, tol, o, X_dev, st, ws, stream, trace_cap));
+  if (trace_count && (rs == DI_OK || rs == DI_E_NOCONV)) {
+    const int written = std::min(trace_cap, (int)st->cycles);
+    if (written > 0)
+      DI_HIP(hipMemcpy(trace, ws->trace, (size_t)written * sizeof(di_cycle_rec),
+                       hipMemcpyDeviceToHost));
+    *trace_count = written;
+  }
   if (rs != DI_OK && rs != DI_E_NOCONV) return rs;
   if (X_on_host) DI_HIP(hipMemcpy(X, X_dev, nbytes, hipMemcpyDeviceToHost));
   return rs;
@@ -774,6 +797,24 @@ di_status di_solve_dev(const di_graph* g, const double* B_dev, double d, double 
                        const di_opts* opts, double* X_dev, di_stats* stats) {
   return di::guarded(
       [&] { return di::solve_any(g, B_dev, false, d, tol, opts, X_dev, false, stats); });
+}
+
+di_status di_solve_trace_dev(const di_graph* g, const double* B_dev, double d, double tol,
+                             const di_opts* opts, double* X_dev, di_stats* stats,
+                             di_cycle_rec* trace, int32_t capacity, int32_t* count) {
+  return di::guarded([&] {
+    if (count) *count = 0;
+    if (capacity < 0 || (capacity > 0 && !trace) || !count) {
+      di::set_error("trace needs capacity >= 0, a trace array when capacity > 0, and count");
+      return DI_E_INVAL;
+    }
+    if (opts && opts->method == DI_GS_ASYNC) {
+      di::set_error("DI_GS_ASYNC has no cycles to trace");
+      return DI_E_INVAL;
+    }
+    return di::solve_any(g, B_dev, false, d, tol, opts, X_dev, false, stats, trace, capacity,
+                         count);
+  });
 }
 
 di_status di_cycles_dev(const di_graph* g, double d, int32_t method, double* F_dev, double* H_dev,

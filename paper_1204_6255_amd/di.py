@@ -70,6 +70,15 @@ class di_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class di_cycle_rec(ctypes.Structure):
+    _fields_ = [
+        ("r", ctypes.c_double),
+        ("links", ctypes.c_int64),
+        ("selected", ctypes.c_int32),
+        ("senders", ctypes.c_int32),
+    ]
+
+
 class di_serve_stats(ctypes.Structure):
     _fields_ = [
         ("submitted", ctypes.c_int64),
@@ -118,6 +127,9 @@ def lib():
     L.di_solve.restype = i32
     L.di_solve_dev.argtypes = [vp, vp, dbl, dbl, P(di_opts), vp, P(di_stats)]
     L.di_solve_dev.restype = i32
+    L.di_solve_trace_dev.argtypes = [vp, vp, dbl, dbl, P(di_opts), vp, P(di_stats),
+                                     P(di_cycle_rec), i32, P(i32)]
+    L.di_solve_trace_dev.restype = i32
     L.di_cycles_dev.argtypes = [vp, dbl, i32, vp, vp, i32, P(dbl), vp, P(di_stats)]
     L.di_cycles_dev.restype = i32
     L.di_residual_dev.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
@@ -229,6 +241,22 @@ def di_solve_dev(h, B_dev, d: float, tol: float, opts: di_opts | None, X_dev) ->
     status = lib().di_solve_dev(h, _ptr(B_dev), float(d), float(tol), ctypes.byref(opts), _ptr(X_dev),
                                 ctypes.byref(st))
     return status, st
+
+
+def di_solve_trace_dev(h, B_dev, d: float, tol: float, opts: di_opts | None, X_dev,
+                       capacity: int) -> tuple[int, di_stats, list[di_cycle_rec]]:
+    """di_solve_dev that also returns the first `capacity` per-cycle records."""
+    if opts is None:
+        opts = di_opts_default()
+    if not opts.stream:
+        opts.stream = _current_stream()
+    st = di_stats()
+    recs = (di_cycle_rec * max(int(capacity), 1))()
+    count = ctypes.c_int32(0)
+    status = lib().di_solve_trace_dev(h, _ptr(B_dev), float(d), float(tol), ctypes.byref(opts),
+                                      _ptr(X_dev), ctypes.byref(st), recs, int(capacity),
+                                      ctypes.byref(count))
+    return status, st, list(recs[:count.value])
 
 
 def di_cycles_dev(h, d: float, method: int, F_dev, H_dev, cycles: int, e: float = 0.0, stream=None):

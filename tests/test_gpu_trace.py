@@ -1,0 +1,152 @@
+"""Per-cycle trace of a solve (di_solve_trace_dev): each record against the
+hand-worked cycles of the 4-node example and against the oracle's
+frontier-synchronous cycles (Section 2.5.5 selection, one r per cycle)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1204_6255_amd import di, graphgen
+from tests.test_oracle_pins import _read_worked_example
+
+pytestmark = pytest.mark.gpu
+
+D = 0.85
+TOL = 1.4e-10
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def traced(torch, g, B, capacity, d=D, tol=TOL, allow=(di.DI_OK,), **fields):
+    o = di.di_opts_default()
+    for k, v in fields.items():
+        setattr(o, k, v)
+    X = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    Bd = None if B is None else torch.from_numpy(np.ascontiguousarray(B, np.float64)).cuda()
+    status, st, recs = di.di_solve_trace_dev(g.handle, Bd, d, tol, o, X, capacity)
+    assert status in allow, (di.STATUS_NAMES.get(status), di.di_last_error())
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), st, recs
+
+
+def test_trace_worked_example(torch_cuda):
+    """The records of the first cycles equal the hand-worked ones: r is the
+    sum of F before the cycle, selected and link operations as worked."""
+    from fractions import Fraction
+    spec, runs = _read_worked_example()
+    n = int(spec["n"][0])
+    d = float(Fraction(spec["d"][0]))
+    links = [tuple(int(x) for x in s.split(":")) for s in spec["links"]]
+    src = np.array([a for a, _ in links], np.int32)
+    dst = np.array([b for _, b in links], np.int32)
+    B = np.array([float(Fraction(v)) for v in spec["B"]])
+    g = di.Graph(n, src, dst)
+    worked = runs["sync"]
+    # a tolerance far below the worked cycles: the capacity cuts the trace
+    _, st, recs = traced(torch_cuda, g, B, len(worked), d=d, tol=1e-14)
+    assert st.cycles > len(worked)
+    assert len(recs) == len(worked)
+    F_prev = B
+    for c, (rec, w) in enumerate(zip(recs, worked)):
+        assert abs(rec.r - np.abs(F_prev).sum()) <= 1e-16, c
+        assert rec.selected == len(w["selected"]), c
+        assert rec.links == w["link_ops"], c
+        F_prev = np.array(w["F"])
+
+
+@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH])
+@pytest.mark.parametrize("alpha", [graphgen.ALPHA_L_MATCHED, graphgen.ALPHA_LITERAL])
+def test_trace_matches_oracle_cycles(torch_cuda, alpha, kernel):
+    """Every record of a whole solve on a 10k web graph equals the oracle's
+    frontier-synchronous cycle from the same state: the same nodes diffused,
+    the same link operations, r to rounding."""
+    n = 10000
+    src, dst = graphgen.web_graph(n, seed=0, alpha=alpha, kmax=500)
+    B = graphgen.uniform_rhs(n, D)
+    g = di.Graph(n, src, dst)
+    _, st, recs = traced(torch_cuda, g, B, 4096, kernel=kernel)
+    assert len(recs) == st.cycles > 10
+    assert sum(r.links for r in recs) == st.edges_pushed
+    og = oracle.Graph(n, src, dst)
+    # links each node moves when diffused (self-loops stay)
+    moves = np.bincount(src[src != dst], minlength=n) > 0
+    F, H, e = B.copy(), np.zeros(n), 0.0
+    for c, rec in enumerate(recs):
+        cnt, sel, e, ops, r = oracle.di_cycle(og, F, H, D, oracle.SOP, oracle.SYNC, e)
+        assert abs(rec.r - r) <= 1e-13 * r, (c, rec.r, r)
+        assert rec.selected == cnt == int(sel.sum()), c
+        assert rec.links == ops, c
+        assert rec.senders == int(np.count_nonzero(sel & moves)), c
+    # the solve stopped at the first cycle whose start is within tol
+    assert np.abs(F).sum() <= TOL < recs[-1].r
+
+
+def test_trace_capacity_prefix(torch_cuda):
+    """A short trace is the prefix of the full one (the pull is
+    bit-reproducible); capacity 0 writes nothing and still solves."""
+    n = 10000
+    src, dst = graphgen.web_graph(n, seed=1)
+    g = di.Graph(n, src, dst)
+    X_full, st, full = traced(torch_cuda, g, None, 4096)
+    X_part, _, part = traced(torch_cuda, g, None, 7)
+    X_none, st0, none = traced(torch_cuda, g, None, 0)
+    assert len(part) == 7 and none == []
+    for a, b in zip(part, full):
+        assert (a.r, a.links, a.selected, a.senders) == (b.r, b.links, b.selected, b.senders)
+    assert np.array_equal(X_part, X_full) and np.array_equal(X_none, X_full)
+    assert st0.cycles == st.cycles
+
+
+def test_trace_fp32_refine_numbers_passes_in_order(torch_cuda):
+    """FP32 with FP64 refinement: the passes' cycles follow one another in
+    the trace, and every record's r is that of an FP32 pass (each pass
+    starts from the residual recomputed in FP64, so r jumps up at most to
+    the previous pass's stop)."""
+    n = 10000
+    src, dst = graphgen.web_graph(n, seed=2)
+    g = di.Graph(n, src, dst)
+    _, st, recs = traced(torch_cuda, g, None, 4096, tol=1e-9, precision=di.DI_FP32_REFINE)
+    assert st.refinements >= 1
+    assert len(recs) == st.cycles
+    assert sum(r.links for r in recs) == st.edges_pushed
+    r = np.array([x.r for x in recs])
+    assert r[0] == pytest.approx(1.0 - D, rel=1e-6)
+    # within a pass r falls (F >= 0 loses a share of each diffusion); it can
+    # rise only where a pass starts from the FP64 residual
+    rises = np.nonzero(r[1:] > r[:-1])[0] + 1
+    assert len(rises) <= st.refinements
+    # no cycle started below the inner stop (half the tolerance)
+    assert r.min() > 0.5e-9
+
+
+def test_trace_pi_diffuses_every_node(torch_cuda):
+    """DI_PI: every cycle diffuses all n nodes and moves every link."""
+    n = 5000
+    src, dst = graphgen.web_graph(n, seed=4)
+    g = di.Graph(n, src, dst)
+    _, st, recs = traced(torch_cuda, g, None, 4096, tol=1e-8, method=di.DI_PI)
+    assert len(recs) == st.cycles
+    moved = int(np.count_nonzero(src != dst))
+    for rec in recs:
+        assert rec.selected == n
+        assert rec.links == moved
+    r = np.array([x.r for x in recs])
+    assert np.all(r[1:] < r[:-1])
+
+
+def test_trace_rejects(torch_cuda):
+    torch = torch_cuda
+    n = 100
+    src, dst = graphgen.web_graph(n, seed=5)
+    g = di.Graph(n, src, dst)
+    X = torch.empty(n, dtype=torch.float64, device="cuda")
+    o = di.di_opts_default()
+    o.method = di.DI_GS_ASYNC
+    status, _, recs = di.di_solve_trace_dev(g.handle, None, D, 1e-9, o, X, 16)
+    assert status == di.DI_E_INVAL and recs == []
+    status, _, _ = di.di_solve_trace_dev(g.handle, None, D, 1e-9, None, X, -1)
+    assert status == di.DI_E_INVAL
