@@ -46,13 +46,62 @@ __device__ inline double to_d(float x) { return (double)x; }
 __device__ inline void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
-// Butterfly sum over the 64 lanes of a wave: every lane gets the total, and
-// the order of additions is fixed.
+// Lane exchanges by DPP, an operand modifier of the vector ALU (no LDS
+// round trip). Each control used here permutes lanes within groups of 2, 4,
+// 8 or 16, so every lane has a source; the whole wave must be active.
+template <int CTRL>
+__device__ inline uint32_t dpp32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, typename V>
+__device__ inline V dpp(V v) {
+  static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit lanes");
+  if constexpr (sizeof(V) == 4) {
+    return __builtin_bit_cast(V, dpp32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = dpp32<CTRL>((uint32_t)u), hi = dpp32<CTRL>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(V, lo | (hi << 32));
+  }
+}
+// The value of lane `src` (uniform across the wave), in every lane.
+template <typename V>
+__device__ inline V read_lane(V v, int src) {
+  static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit lanes");
+  if constexpr (sizeof(V) == 4) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+    return __builtin_bit_cast(V, lo | (hi << 32));
+  }
+}
+// Sum over each 16-lane row, held by every lane of the row: partners at
+// xor 1 and xor 2 (quad permutations), then the mirrored lane in the other
+// half of each 8- and 16-lane group. Partners add the same two numbers, so
+// they agree exactly; the order of additions is fixed.
+template <typename V>
+__device__ inline V row_sum16(V v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return v;
+}
+// Sum over the 64 lanes of a wave, the same number in every lane (the four
+// row sums added in a fixed order).
 template <typename V>
 __device__ inline V wave_sum(V v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v = row_sum16(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+// Sum of lanes [0, NW) of a wave whose other lanes hold zero (NW <= 16), in
+// every lane.
+template <int NW, typename V>
+__device__ inline V low_lanes_sum(V v) {
+  static_assert(NW >= 1 && NW <= 16, "at most one row");
+  return read_lane(row_sum16(v), 0);
 }
 
 // Block sum (blockDim.x a multiple of 64, at most 1024); the result is
@@ -114,9 +163,8 @@ __device__ Part block_sum_part(Part v, Part* lds) {
   return t;
 }
 
-// Block sum of a Part for a block of NW waves: butterflies within each
-// wave, then wave 0 folds the NW wave sums (lanes < NW, butterfly). Fixed
-// order; valid in thread 0. The link and frontier counts are summed only
+// Block sum of a Part for a block of NW waves: wave sums, then wave 0 folds
+// the NW wave sums (lanes < NW). Fixed order; valid in thread 0. The link and frontier counts are summed only
 // when `counts` (they feed the control block, which block 0 writes).
 template <int NW>
 __device__ Part block_sum_part_w0(Part v, Part* lds, bool counts) {
@@ -135,16 +183,13 @@ __device__ Part block_sum_part_w0(Part v, Part* lds, bool counts) {
   Part t{0.0, 0.0, 0.0, 0ull, 0u, 0u};
   if (wave == 0) {
     if (lane < NW) t = lds[lane];
-#pragma unroll
-    for (int off = NW / 2; off >= 1; off >>= 1) {
-      t.pabs += __shfl_xor(t.pabs, off, 64);
-      t.psum += __shfl_xor(t.psum, off, 64);
-      t.e += __shfl_xor(t.e, off, 64);
-      t.sel += __shfl_xor(t.sel, off, 64);
-      if (counts) {
-        t.ops += __shfl_xor(t.ops, off, 64);
-        t.nfront += __shfl_xor(t.nfront, off, 64);
-      }
+    t.pabs = low_lanes_sum<NW>(t.pabs);
+    t.psum = low_lanes_sum<NW>(t.psum);
+    t.e = low_lanes_sum<NW>(t.e);
+    t.sel = low_lanes_sum<NW>(t.sel);
+    if (counts) {
+      t.ops = low_lanes_sum<NW>(t.ops);
+      t.nfront = low_lanes_sum<NW>(t.nfront);
     }
   }
   return t;
@@ -563,17 +608,10 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     __syncthreads();
     if (wave == 0) {
       SelStat st;
-      st.sel = lane < NW ? s_sel[lane] : 0u;
-      st.nfront = lane < NW ? s_front[lane] : 0u;
-      st.ops = lane < NW ? s_ops[lane] : 0ull;
-      st.e = lane < NW ? s_e[lane] : 0.0;
-#pragma unroll
-      for (int off = NW / 2; off >= 1; off >>= 1) {
-        st.sel += __shfl_xor(st.sel, off, 64);
-        st.nfront += __shfl_xor(st.nfront, off, 64);
-        st.ops += __shfl_xor(st.ops, off, 64);
-        st.e += __shfl_xor(st.e, off, 64);
-      }
+      st.sel = low_lanes_sum<NW>(lane < NW ? s_sel[lane] : 0u);
+      st.nfront = low_lanes_sum<NW>(lane < NW ? s_front[lane] : 0u);
+      st.ops = low_lanes_sum<NW>(lane < NW ? s_ops[lane] : 0ull);
+      st.e = low_lanes_sum<NW>(lane < NW ? s_e[lane] : 0.0);
       if (lane == 0) tile_stat[tile] = st;
     }
     if (tile + gridDim.x < ntiles) __syncthreads();  // LDS reused by the next tile
@@ -688,7 +726,7 @@ __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
     }
     __syncthreads();
     // rows r0 + tid + k * kPullBlock; a row with more than kPullLongRow links
-    // is summed by its whole wave (strided lanes, then a butterfly)
+    // is summed by its whole wave (strided lanes, then a wave sum)
     const int lane = tid & 63;
     for (int64_t row = row0; row - lane < r1; row += kPullBlock) {
       const bool valid = row < r1;
@@ -711,7 +749,7 @@ __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
       while (mask) {
         const int src = __ffsll(mask) - 1;
         mask &= mask - 1;
-        const int la = __shfl(a, src, 64), lb = __shfl(b, src, 64);
+        const int la = read_lane(a, src), lb = read_lane(b, src);
         double part = 0.0;
         for (int q = la + lane; q < lb; q += 64) part += s_val[q];
         part = wave_sum(part);
@@ -862,7 +900,7 @@ __global__ __launch_bounds__(kPullBlock) void k_refine_r(
       while (mask) {
         const int src = __ffsll(mask) - 1;
         mask &= mask - 1;
-        const int la = __shfl(a, src, 64), lb = __shfl(b, src, 64);
+        const int la = read_lane(a, src), lb = read_lane(b, src);
         double part = 0.0;
         for (int q = la + lane; q < lb; q += 64) part += s_val[q];
         part = wave_sum(part);
@@ -1003,7 +1041,7 @@ __global__ __launch_bounds__(kPullBlock) void k_gs_sweep(
       while (mask) {
         const int src = __ffsll(mask) - 1;
         mask &= mask - 1;
-        const int la = __shfl(a, src, 64), lb = __shfl(b, src, 64);
+        const int la = read_lane(a, src), lb = read_lane(b, src);
         double part = 0.0;
         for (int q = la + lane; q < lb; q += 64) part += s_val[q];
         part = wave_sum(part);
