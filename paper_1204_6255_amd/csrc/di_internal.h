@@ -119,7 +119,7 @@ struct Workspace {
   int64_t* fr_lstart = nullptr; // push: per-block frontier, local link offset
   int64_t* fr_base = nullptr;   // push: CSR offset of the entry's links
   void* fr_s = nullptr;         // push: amount sent along each link
-  SelStat* tile_stat = nullptr; // per select tile
+  SelStat* tile_stat = nullptr; // select statistics (select_stat_records)
   Part* blk_part = nullptr;     // per pull/reduce/start block
   double* seg_val = nullptr;    // pull: sums of the heavy-row segments
   Ctl* ctl = nullptr;           // two copies (see Ctl)
@@ -225,6 +225,8 @@ struct CycleArgs {
 };
 
 int select_tiles(int64_t n, int direction);
+// select statistics records: one per wave (pull direction) or per tile (push)
+int select_stat_records(int64_t n, int direction);
 int select_grid(int64_t n, int direction);
 int pull_grid(const di_graph* g);
 int reduce_grid(int64_t n);

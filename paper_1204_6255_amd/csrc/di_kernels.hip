@@ -555,6 +555,15 @@ __global__ __launch_bounds__(BLOCK) void k_select(
         const int64_t first_node = base - lane + (int64_t)m * BLOCK;  // multiple of 64
         if (lane == 0 && first_node < n) front_bits[first_node >> 6] = word;
       }
+      // one statistics record per wave (the pull folds them), so the block
+      // has no reduction and no barrier behind its stores
+      SelStat st;
+      st.sel = wave_sum(my_sel);
+      st.nfront = wave_sum(my_front);
+      st.ops = wave_sum(my_ops);
+      st.e = wave_sum(my_e);
+      if (lane == 0) tile_stat[tile * NW + wave] = st;
+      continue;
     } else {
       // tile-local exclusive scan of (entries, links) over (thread, m) order
       unsigned int cnt_incl = my_front;
@@ -594,7 +603,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
         }
       }
     }
-    // the tile's statistics: wave butterflies, then wave 0 folds the waves
+    // the tile's statistics: wave sums, then wave 0 folds the waves
     my_sel = wave_sum(my_sel);
     my_front = wave_sum(my_front);
     my_ops = wave_sum(my_ops);
@@ -1145,6 +1154,11 @@ int select_tiles(int64_t n, int direction) {
   return (int)(t < 1 ? 1 : t);
 }
 
+int select_stat_records(int64_t n, int direction) {
+  const int t = select_tiles(n, direction);
+  return direction == kPull ? t * (kSelectBlockPull / 64) : t;
+}
+
 int select_grid(int64_t n, int direction) {
   const int t = select_tiles(n, direction);
   return direction == kPull ? (t < kSelectGridPull ? t : kSelectGridPull) : t;
@@ -1217,7 +1231,7 @@ hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t
   const di_graph* g = a.g;
   Workspace* ws = a.ws;
   const Ctl* ctl = ws->ctl + ((cycle + 1) & 1);
-  const int64_t ntiles = select_tiles(g->n, a.direction);
+  const int64_t ntiles = select_stat_records(g->n, a.direction);
   // Timing events travel in the kernel's own dispatch and take its start and
   // end times (an event recorded beside a launch also times the gap to it).
   const bool timed = ev0 || ev1;

@@ -53,7 +53,7 @@ di_status alloc_workspace(const di_graph* g, int prec, Workspace** out) {
   const size_t n = (size_t)g->n;
   const size_t s = prec == kF64 ? sizeof(double) : sizeof(float);
   const size_t ntiles =
-      (size_t)std::max(select_tiles(g->n, kPull), select_tiles(g->n, kPush));
+      (size_t)std::max(select_stat_records(g->n, kPull), select_stat_records(g->n, kPush));
   // one record per pull/reduce block, plus the heavy-row record of a
   // residual pass
   const size_t nparts = (size_t)std::max(kPullMaxGrid, kReduceGrid) + 1;
@@ -701,7 +701,7 @@ size_t workspace_bytes(const di_graph* g, int prec) {
   const size_t n = (size_t)g->n;
   const size_t s = prec == kF64 ? sizeof(double) : sizeof(float);
   const size_t ntiles =
-      (size_t)std::max(select_tiles(g->n, kPull), select_tiles(g->n, kPush));
+      (size_t)std::max(select_stat_records(g->n, kPull), select_stat_records(g->n, kPush));
   const size_t nparts = (size_t)std::max(kPullMaxGrid, kReduceGrid) + 1;
   return 3 * n * s + ((n + 63) / 64) * sizeof(unsigned long long) + ntiles * sizeof(SelStat) +
          nparts * sizeof(Part) + (size_t)std::max<int64_t>(g->n_segs, 1) * sizeof(double) +
