@@ -264,15 +264,15 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       g->n_heavy = (int64_t)hrow.size();
       g->n_segs = nseg;
       // completion chunks of at most kHeavyChunkSegs segment sums
-      std::vector<int64_t> hc0, hc1, hoff;
+      std::vector<int32_t> hc0, hc1, hoff;
       for (size_t h = 0; h < hrow.size(); ++h) {
-        hoff.push_back((int64_t)hc0.size());
+        hoff.push_back((int32_t)hc0.size());
         for (int64_t q = hseg[h]; q < hseg[h + 1]; q += di::kHeavyChunkSegs) {
-          hc0.push_back(q);
-          hc1.push_back(std::min<int64_t>(q + di::kHeavyChunkSegs, hseg[h + 1]));
+          hc0.push_back((int32_t)q);
+          hc1.push_back((int32_t)std::min<int64_t>(q + di::kHeavyChunkSegs, hseg[h + 1]));
         }
       }
-      hoff.push_back((int64_t)hc0.size());
+      hoff.push_back((int32_t)hc0.size());
       g->n_hchunks = (int64_t)hc0.size();
       g->heavy_atomic = g->n_heavy > di::kHeavyLds || g->n_hchunks > di::kHeavyLds;
       st = upload(&g->csc_ptr, cptr);

@@ -170,9 +170,9 @@ struct di_graph {
   // completion chunks: chunk k sums segments [hc_seg0[k], hc_seg1[k]) of one
   // heavy row; row h owns chunks [hc_off[h], hc_off[h + 1])
   int64_t n_hchunks = 0;
-  int64_t* hc_seg0 = nullptr;
-  int64_t* hc_seg1 = nullptr;
-  int64_t* hc_off = nullptr;
+  int32_t* hc_seg0 = nullptr;
+  int32_t* hc_seg1 = nullptr;
+  int32_t* hc_off = nullptr;
   std::mutex mu;
   std::vector<di::Workspace*> pool;
   std::vector<di::BatchWs*> bpool;  // batched solves (di_batch.h)

@@ -365,8 +365,8 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     unsigned long long* __restrict__ front_bits, int64_t* __restrict__ fr_lstart,
     int64_t* __restrict__ fr_base, T* __restrict__ fr_s, SelStat* __restrict__ tile_stat,
     const Part* __restrict__ blk_part, int nparts, const int32_t* __restrict__ heavy_row,
-    const int64_t* __restrict__ hc_seg0, const int64_t* __restrict__ hc_seg1,
-    const int64_t* __restrict__ hc_off, const double* __restrict__ seg_val, int64_t n_heavy,
+    const int32_t* __restrict__ hc_seg0, const int32_t* __restrict__ hc_seg1,
+    const int32_t* __restrict__ hc_off, const double* __restrict__ seg_val, int64_t n_heavy,
     int64_t n_hchunks, int heavy_atomic, Ctl* __restrict__ ctl, int parity, int first, double d,
     double tol, double tol_in, double tol_rel, int method, int stop, int max_cycles,
     di_cycle_rec* __restrict__ trace, int trace_cap) {
@@ -374,9 +374,10 @@ __global__ __launch_bounds__(BLOCK) void k_select(
   constexpr int NW = BLOCK / 64;
   constexpr int HPT = PULL ? kHeavyLds / BLOCK : 1;  // heavy rows per thread
   // heavy rows completed here (not first, not heavy_atomic): the chunk sums,
-  // then (same space) the completed values; and the row ids
+  // the row ids and the completed values
   __shared__ int32_t s_hrow[PULL ? kHeavyLds : 1];
   __shared__ double s_hval[PULL ? kHeavyLds : 1];
+  __shared__ double s_hnew[PULL ? kHeavyLds : 1];
   __shared__ Part s_part[NW];
   __shared__ unsigned long long s_ops[NW];
   __shared__ double s_e[NW];
@@ -386,8 +387,28 @@ __global__ __launch_bounds__(BLOCK) void k_select(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ntiles = (n + TILE - 1) / TILE;
 
-  // first round of loads: the first tile's nodes, the records, the heavy
-  // rows and the control block are independent of one another
+  // After a pull the records leave out the heavy rows (the start records
+  // cover every row): add their values, completing them with their segment
+  // sums in a fixed order unless the pull added those atomically.
+  const bool heavy_here = PULL && !first && !heavy_atomic;
+  // Heavy row `tid` and completion chunk `tid` (slot 0): their graph data is
+  // loaded first, so that the loads depending on it (the chunk's segment
+  // sums, the row's F) are issued while the node loads are in flight.
+  const bool hrow0 = heavy_here && tid < n_heavy;
+  const bool hchunk0 = heavy_here && tid < n_hchunks;
+  int32_t hr0 = 0, ho0 = 0, ho1 = 0, hq0 = 0, hq1 = 0;
+  if (hrow0) {
+    hr0 = heavy_row[tid];
+    ho0 = hc_off[tid];
+    ho1 = hc_off[tid + 1];
+  }
+  if (hchunk0) {
+    hq0 = hc_seg0[tid];
+    hq1 = hc_seg1[tid];
+  }
+
+  // first round of loads: the first tile's nodes, the records and the
+  // control block are independent of one another
   int64_t tile = blockIdx.x;
   double f[M], hv[M];
   uint32_t w[M];
@@ -401,22 +422,23 @@ __global__ __launch_bounds__(BLOCK) void k_select(
   }
   Ctl c0;
   if (tid == 0) c0 = ctl[parity];
+  double sv[kHeavyChunkSegs], fh0 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kHeavyChunkSegs; ++u)
+    sv[u] = hchunk0 && hq0 + u < hq1 ? seg_val[hq0 + u] : 0.0;
+  if (hrow0) fh0 = to_d(F[hr0]);
   Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
   for (int p = tid; p < nparts; p += BLOCK) part_add(v, blk_part[p]);
-  // After a pull the records leave out the heavy rows (the start records
-  // cover every row): add their values, completing them with their segment
-  // sums in a fixed order unless the pull added those atomically.
-  const bool heavy_here = PULL && !first && !heavy_atomic;
   if (heavy_here) {
-    // chunk sums (one round of loads), then each row's chunks in order
-    int32_t hr[HPT];
-    double hf[HPT];
+    // chunk sums (slot 0 from the registers), then each row's chunks in order
+    if (hchunk0) {
+      double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) {
-      const int64_t h = tid + (int64_t)k * BLOCK;
-      hr[k] = h < n_heavy ? heavy_row[h] : 0;
+      for (int u = 0; u < kHeavyChunkSegs; ++u)
+        if (hq0 + u < hq1) acc += sv[u];
+      s_hval[tid] = acc;
     }
-    for (int64_t k = tid; k < n_hchunks; k += BLOCK) {
+    for (int64_t k = tid + BLOCK; k < n_hchunks; k += BLOCK) {
       const int64_t q0 = hc_seg0[k], q1 = hc_seg1[k];
       double acc = 0.0;
 #pragma unroll
@@ -424,9 +446,14 @@ __global__ __launch_bounds__(BLOCK) void k_select(
         if (q0 + u < q1) acc += seg_val[q0 + u];
       s_hval[k] = acc;
     }
+    int32_t hr[HPT];
+    double hf[HPT];
+    hr[0] = hr0;
+    hf[0] = fh0;
 #pragma unroll
-    for (int k = 0; k < HPT; ++k) {
+    for (int k = 1; k < HPT; ++k) {
       const int64_t h = tid + (int64_t)k * BLOCK;
+      hr[k] = h < n_heavy ? heavy_row[h] : 0;
       hf[k] = h < n_heavy ? to_d(F[hr[k]]) : 0.0;
     }
     __syncthreads();
@@ -434,20 +461,14 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     for (int k = 0; k < HPT; ++k) {
       const int64_t h = tid + (int64_t)k * BLOCK;
       if (h < n_heavy) {
+        const int64_t q0 = k == 0 ? ho0 : hc_off[h], q1 = k == 0 ? ho1 : hc_off[h + 1];
         double acc = 0.0;
-        for (int64_t q = hc_off[h]; q < hc_off[h + 1]; ++q) acc += s_hval[q];
+        for (int64_t q = q0; q < q1; ++q) acc += s_hval[q];
         hf[k] = to_d((T)(hf[k] + acc));
         v.pabs += fabs(hf[k]);
         v.psum += hf[k];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < HPT; ++k) {
-      const int64_t h = tid + (int64_t)k * BLOCK;
-      if (h < n_heavy) {
         s_hrow[h] = hr[k];
-        s_hval[h] = hf[k];
+        s_hnew[h] = hf[k];
       }
     }
   } else if (PULL && !first) {
@@ -481,7 +502,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     if (heavy_here && !s_was_done)
       for (int64_t h = tid; h < n_heavy; h += BLOCK) {
         const int32_t row = s_hrow[h];
-        if ((row / TILE) % gridDim.x == blockIdx.x) F[row] = (T)s_hval[h];
+        if ((row / TILE) % gridDim.x == blockIdx.x) F[row] = (T)s_hnew[h];
       }
     return;
   }
@@ -522,7 +543,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
             if (s_hrow[mid] < i) lo = mid + 1;
             else hi = mid;
           }
-          f[m] = s_hval[lo];
+          f[m] = s_hnew[lo];
         }
         const double a = fabs(f[m]);
         const double thr = (mode != 0 || out == 0) ? 0.0 : rl * (double)out;
@@ -1218,7 +1239,7 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        g->row_ptr, g->n, g->L, (T*)nullptr, (unsigned long long*)nullptr,
                        ws->fr_lstart, ws->fr_base, (T*)ws->fr_s, ws->tile_stat,
                        (const Part*)ws->blk_part, nparts, (const int32_t*)nullptr,
-                       (const int64_t*)nullptr, (const int64_t*)nullptr, (const int64_t*)nullptr,
+                       (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
                        (const double*)nullptr, (int64_t)0, (int64_t)0, 0, ws->ctl, parity, first,
                        a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop, a.max_cycles, a.trace,
                        a.trace_cap);
