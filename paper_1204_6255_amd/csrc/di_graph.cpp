@@ -49,15 +49,16 @@ void free_workspace(Workspace* ws);
 namespace {
 
 void free_graph_device(di_graph* g) {
-  void* ptrs[] = {g->row_ptr, g->col,    g->info,   g->csc_ptr,  g->csc_idx, g->it_r0,
-                  g->it_r1,   g->it_l0,  g->it_l1,  g->it_seg,   g->heavy_row, g->heavy_seg,
-                  g->hc_seg0, g->hc_seg1, g->hc_off};
+  void* ptrs[] = {g->row_ptr, g->col,    g->info,   g->csc_ptr,  g->csc_idx, g->row_lo,
+                  g->it_r0,   g->it_r1,  g->it_l0,  g->it_l1,    g->it_seg,  g->heavy_row,
+                  g->heavy_seg, g->hc_seg0, g->hc_seg1, g->hc_off};
   for (void* p : ptrs) (void)hipFree(p);
   g->row_ptr = nullptr;
   g->col = nullptr;
   g->info = nullptr;
   g->csc_ptr = nullptr;
   g->csc_idx = nullptr;
+  g->row_lo = nullptr;
   g->it_r0 = g->it_r1 = g->it_l0 = g->it_l1 = nullptr;
   g->it_seg = nullptr;
   g->heavy_row = nullptr;
@@ -226,8 +227,11 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       std::vector<int64_t> r0v, r1v, l0v, l1v, hseg;
       std::vector<int32_t> segv, hrow;
       int64_t nseg = 0, open_r0 = -1, cur_links = 0, cur_rows = 0;
+      std::vector<uint16_t> rlo((size_t)n, 0);
       auto flush = [&](int64_t end_row) {
         if (open_r0 < 0) return;
+        for (int64_t r = open_r0; r < end_row; ++r)
+          rlo[(size_t)r] = (uint16_t)(cptr[r] - cptr[open_r0]);
         r0v.push_back(open_r0);
         r1v.push_back(end_row);
         l0v.push_back(cptr[open_r0]);
@@ -277,6 +281,7 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       g->heavy_atomic = g->n_heavy > di::kHeavyLds || g->n_hchunks > di::kHeavyLds;
       st = upload(&g->csc_ptr, cptr);
       if (st == DI_OK) st = upload(&g->csc_idx, cidx);
+      if (st == DI_OK) st = upload(&g->row_lo, rlo);
       if (st == DI_OK) st = upload(&g->it_r0, r0v);
       if (st == DI_OK) st = upload(&g->it_r1, r1v);
       if (st == DI_OK) st = upload(&g->it_l0, l0v);

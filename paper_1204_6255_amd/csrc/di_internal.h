@@ -151,6 +151,9 @@ struct di_graph {
   // in-links (rows of P) without self-loops: CSC
   int64_t* csc_ptr = nullptr;  // n + 1
   int32_t* csc_idx = nullptr;  // Lp
+  // n: first in-link of a light row within its pull item, csc_ptr[j] - l0
+  // (at most kPullChunk: 16 bits); 0 for heavy rows
+  uint16_t* row_lo = nullptr;
   // pull work items: light items cover rows [r0, r1) and their in-links
   // [l0, l1); a segment item (seg >= 0) covers links [l0, l1) of the heavy
   // row r0 and writes its sum to seg_val[seg] (or adds it to F[r0]

@@ -665,7 +665,7 @@ template <typename T>
 __global__ __launch_bounds__(kPullBlock)
 __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
     T* __restrict__ F, const T* __restrict__ sent,
-    const unsigned long long* __restrict__ front_bits, const int64_t* __restrict__ csc_ptr,
+    const unsigned long long* __restrict__ front_bits, const uint16_t* __restrict__ row_lo,
     const int32_t* __restrict__ csc_idx, const int64_t* __restrict__ it_r0,
     const int64_t* __restrict__ it_r1, const int64_t* __restrict__ it_l0,
     const int64_t* __restrict__ it_l1, const int32_t* __restrict__ it_seg, int64_t n_items,
@@ -717,8 +717,8 @@ __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
     int a0 = 0, b0 = 0;
     if (seg < 0 && row0 < r1) {
       f0 = to_d(F[row0]);
-      a0 = (int)(csc_ptr[row0] - l0);
-      b0 = (int)(csc_ptr[row0 + 1] - l0);
+      a0 = row_lo[row0];
+      b0 = row0 + 1 < r1 ? (int)row_lo[row0 + 1] : nl;
     }
     int32_t idx[U];
 #pragma unroll
@@ -768,8 +768,8 @@ __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
         b = b0;
       } else if (valid) {
         f = to_d(F[row]);
-        a = (int)(csc_ptr[row] - l0);
-        b = (int)(csc_ptr[row + 1] - l0);
+        a = row_lo[row];
+        b = row + 1 < r1 ? (int)row_lo[row + 1] : nl;
       }
       const bool longrow = valid && (b - a) > kPullLongRow;
       double acc = 0.0;
@@ -1260,13 +1260,13 @@ hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t
     const dim3 grid(pull_grid(g)), block(kPullBlock);
     if (timed)
       hipExtLaunchKernelGGL(k_pull<T>, grid, block, 0, a.stream, ev0, ev1, 0u, (T*)ws->F,
-                            (const T*)ws->sent, ws->front_bits, g->csc_ptr, g->csc_idx, g->it_r0,
+                            (const T*)ws->sent, ws->front_bits, g->row_lo, g->csc_idx, g->it_r0,
                             g->it_r1, g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->seg_val,
                             (int)g->heavy_atomic, (const SelStat*)ws->tile_stat, ntiles,
                             ws->blk_part, ctl);
     else
       hipLaunchKernelGGL(k_pull<T>, grid, block, 0, a.stream, (T*)ws->F, (const T*)ws->sent,
-                         ws->front_bits, g->csc_ptr, g->csc_idx, g->it_r0, g->it_r1, g->it_l0,
+                         ws->front_bits, g->row_lo, g->csc_idx, g->it_r0, g->it_r1, g->it_l0,
                          g->it_l1, g->it_seg, g->n_items, ws->seg_val, (int)g->heavy_atomic,
                          (const SelStat*)ws->tile_stat, ntiles, ws->blk_part, ctl);
     return hipGetLastError();

@@ -277,7 +277,9 @@ void fill_stats(const di_graph* g, const Ctl& h, double d, int s_bytes, int dire
   const double s = s_bytes, N = (double)g->n, C = (double)h.cycles;
   double move;
   if (direction == kPull) {
-    move = C * ((double)g->Lp * (4.0 + s) + N * (8.0 + 2.0 * s));
+    // per in-link its source id and the gathered value; per row its 16-bit
+    // in-link offset and F read and written
+    move = C * ((double)g->Lp * (4.0 + s) + N * (2.0 + 2.0 * s));
   } else {
     move = (double)h.edges_total * (4.0 + 2.0 * s) + (double)h.front_total * (16.0 + s) + C * N * s;
   }
