@@ -30,6 +30,7 @@ void free_workspace(Workspace* ws) {
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   if (ws->host_part) (void)hipHostFree(ws->host_part);
   for (hipEvent_t e : ws->events) (void)hipEventDestroy(e);
+  if (ws->copied) (void)hipEventDestroy(ws->copied);
   delete ws;
 }
 
@@ -209,37 +210,49 @@ int next_chunk(const CycleArgs& a, const Ctl& h, int last_sel, int chunk) {
 // then (move c, selection c + 1) pairs in chunks. The newest control copy
 // after selection c is copy (c + 1) & 1; it is left in rt->state.
 // ev_begin was recorded before the start kernels.
+// Each read-back of the control block is followed by kLookahead more queued
+// cycles, so the device works while the host waits for the copy and queues
+// the next chunk. Once the device has stopped, their launches return at once.
+constexpr int kLookahead = 1;
 template <typename T>
 di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTimes* rt) {
   Workspace* ws = a.ws;
   DI_TRY(ensure_events(ws, 2));
+  if (!ws->copied) DI_HIP(hipEventCreateWithFlags(&ws->copied, hipEventDisableTiming));
   hipEvent_t ev_end = ws->events[1];
-  int last_sel = 0;
+  int last_sel = 0;  // selections queued after the first
+  auto queue_cycle = [&]() -> di_status {
+    const int c = last_sel;
+    if (timing) DI_TRY(ensure_events(ws, 4 + 2 * (size_t)c));
+    hipEvent_t e0 = timing ? ws->events[2 + 2 * (size_t)c] : nullptr;
+    hipEvent_t e1 = timing ? ws->events[3 + 2 * (size_t)c] : nullptr;
+    DI_HIP(launch_move<T>(a, c, e0, e1));
+    DI_HIP(launch_select<T>(a, c + 1, 0));
+    last_sel = c + 1;
+    return DI_OK;
+  };
   DI_HIP(launch_select<T>(a, 0, 1));
   int chunk = 8;
+  int at = 0;  // the selection the last read-back follows
   for (;;) {
+    at = last_sel;
     DI_HIP(hipEventRecord(ev_end, a.stream));
     DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost, a.stream));
-    DI_HIP(hipStreamSynchronize(a.stream));
-    const Ctl& h = ws->host_ctl[(last_sel + 1) & 1];
+    DI_HIP(hipEventRecord(ws->copied, a.stream));
+    for (int q = 0; q < kLookahead && last_sel < a.max_cycles; ++q) DI_TRY(queue_cycle());
+    DI_HIP(hipEventSynchronize(ws->copied));
+    const Ctl& h = ws->host_ctl[(at + 1) & 1];
     if (h.done) break;
-    if (last_sel >= a.max_cycles) {
+    if (at >= a.max_cycles) {
       set_error("internal: the device did not stop after max_cycles");
       return DI_E_DEVICE;
     }
-    chunk = next_chunk(a, h, last_sel, chunk);
-    const int todo = std::max(1, std::min(chunk, a.max_cycles - last_sel));
-    if (timing) DI_TRY(ensure_events(ws, 2 + 2 * (size_t)(last_sel + todo)));
-    for (int q = 0; q < todo; ++q) {
-      const int c = last_sel;
-      hipEvent_t e0 = timing ? ws->events[2 + 2 * (size_t)c] : nullptr;
-      hipEvent_t e1 = timing ? ws->events[3 + 2 * (size_t)c] : nullptr;
-      DI_HIP(launch_move<T>(a, c, e0, e1));
-      DI_HIP(launch_select<T>(a, c + 1, 0));
-      last_sel = c + 1;
-    }
+    chunk = next_chunk(a, h, at, chunk);
+    // the cycles queued behind the read-back count toward the chunk
+    const int todo = std::min(chunk - (last_sel - at), a.max_cycles - last_sel);
+    for (int q = 0; q < todo; ++q) DI_TRY(queue_cycle());
   }
-  rt->state = ws->host_ctl[(last_sel + 1) & 1];
+  rt->state = ws->host_ctl[(at + 1) & 1];
   float ms = 0.f;
   DI_HIP(hipEventElapsedTime(&ms, ev_begin, ev_end));
   rt->seconds = ms * 1e-3;
