@@ -299,6 +299,32 @@ def test_signed_right_hand_side(torch_cuda):
     assert np.abs(X - X_ref).sum() <= 1e-9
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_max_cycles_stops_on_an_exact_prefix(torch_cuda, kernel):
+    """A solve stopped by max_cycles returns the history of exactly that many
+    cycles, at and around the host's read-back points (the first after 8
+    cycles), although the host keeps a cycle queued behind each read-back."""
+    torch = torch_cuda
+    n = 10000
+    src, dst = web(n)
+    g = di.Graph(n, src, dst)
+    B = graphgen.uniform_rhs(n, D)
+    for m in (1, 2, 8, 9, 10, 23):
+        X, st, status = gpu_solve(torch, g, None, tol=1e-15, allow=(di.DI_E_NOCONV,), max_cycles=m,
+                                  kernel=kernel)
+        assert status == di.DI_E_NOCONV and st.cycles == m, (m, st.cycles)
+        F = torch.from_numpy(B.copy()).cuda()
+        H = torch.zeros(n, dtype=torch.float64, device="cuda")
+        status, _, stc = di.di_cycles_dev(g.handle, D, di.DI_SOP, F, H, m)
+        assert status == di.DI_OK and stc.cycles == m
+        torch.cuda.synchronize()
+        Hh = H.cpu().numpy()
+        if kernel == di.DI_KERNEL_PULL:
+            assert np.array_equal(X, Hh), m
+        else:  # atomic order differs between runs
+            assert np.abs(X - Hh).sum() <= 1e-13, m
+
+
 def test_errors_on_device(torch_cuda):
     torch = torch_cuda
     n = 1000
