@@ -14,12 +14,13 @@
 //           rows, so all blocks hold the same r bit for bit; thread 0 of
 //           each block takes the same stop decision and block 0 writes the
 //           next copy of the control block. Then the block selects and
-//           claims the nodes of its tiles.
+//           claims the nodes of its tiles; in the pull direction each wave
+//           leaves one statistics record.
 //   move    pull (default): each node sums sent[i] over its in-links (CSC
-//           without self-loops) whose sender bit is set in the frontier
-//           bitmap, staged through LDS in work items of at most kPullChunk
-//           links; each block writes one record (sums over its rows and the
-//           folded tile statistics). A row with more in-links is split into
+//           without self-loops, a 16-bit in-link offset per row) whose
+//           sender bit is set in the frontier bitmap, staged through LDS in
+//           work items of at most kPullChunk links; each block writes one
+//           record (sums over its rows and the folded select statistics). A row with more in-links is split into
 //           segments whose sums the next selection completes in a fixed
 //           order (with more than kHeavyLds such rows, the segments are
 //           added to F[row] with FP64 atomics instead).
@@ -33,6 +34,8 @@
 // Also here: the FP64 residual pass of a refined solve (R = B + P.X - X,
 // through the same work items), and the asynchronous Gauss-Seidel baseline
 // (an in-place relaxation over the same items).
+// Wave and block sums use DPP lane exchanges and readlane (no LDS), always
+// in one fixed order.
 
 #include "di_internal.h"
 #include <hip/hip_ext.h>
