@@ -95,3 +95,32 @@ def test_serving_without_gpu_reports_device_error():
 def test_batch_rejects_bad_arguments_before_device_work():
     st, _, _ = di.di_solve_batch(None, 2, None, 0.85, [1e-9, 1e-9])
     assert st == di.DI_E_INVAL
+
+
+def test_cycle_record_layout():
+    # double r, int64 links, int32 selected, int32 senders
+    assert ctypes.sizeof(di.di_cycle_rec) == 24
+
+
+def test_trace_rejects_bad_arguments_before_device_work():
+    L = di.lib()
+    recs = (di.di_cycle_rec * 4)()
+    count = ctypes.c_int32(-1)
+    st = di.di_stats()
+    o = di.di_opts_default()
+    # no graph
+    assert L.di_solve_trace_dev(None, None, 0.85, 1e-9, ctypes.byref(o), None, ctypes.byref(st),
+                                recs, 4, ctypes.byref(count)) == di.DI_E_INVAL
+    assert count.value == 0
+    # negative capacity, records missing for a positive capacity, no count
+    assert L.di_solve_trace_dev(None, None, 0.85, 1e-9, ctypes.byref(o), None, ctypes.byref(st),
+                                recs, -1, ctypes.byref(count)) == di.DI_E_INVAL
+    assert L.di_solve_trace_dev(None, None, 0.85, 1e-9, ctypes.byref(o), None, ctypes.byref(st),
+                                None, 4, ctypes.byref(count)) == di.DI_E_INVAL
+    assert L.di_solve_trace_dev(None, None, 0.85, 1e-9, ctypes.byref(o), None, ctypes.byref(st),
+                                recs, 4, None) == di.DI_E_INVAL
+    # the asynchronous Gauss-Seidel baseline has no cycles to trace
+    o.method = di.DI_GS_ASYNC
+    assert L.di_solve_trace_dev(None, None, 0.85, 1e-9, ctypes.byref(o), None, ctypes.byref(st),
+                                recs, 4, ctypes.byref(count)) == di.DI_E_INVAL
+    assert "Gauss" in di.di_last_error() or "DI_GS_ASYNC" in di.di_last_error()
