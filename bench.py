@@ -490,7 +490,9 @@ def serving_section(di, graphgen, d, seconds, kmax):
         poisson.append({"lambda_per_s": lam, "requests": nreq, "solves_per_s": nreq / el,
                         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
                         "p99_ms": 1e3 * float(np.percentile(lat, 99))})
-    # idle: one request at a time (each runs alone on its graph)
+    # idle: one request at a time (each runs alone on its graph); the same
+    # requests in every run, whatever the earlier phases submitted
+    counter[0] = 20_000_000
     lat = []
     for i in range(64):
         inflight = {}
