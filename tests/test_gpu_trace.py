@@ -85,6 +85,29 @@ def test_trace_matches_oracle_cycles(torch_cuda, alpha, kernel):
     assert np.abs(F).sum() <= TOL < recs[-1].r
 
 
+@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH])
+def test_trace_dicyc_matches_oracle_cycles(torch_cuda, kernel):
+    """DI-CYC: every record equals the oracle's frontier-synchronous DI-CYC
+    cycle (every node holding fluid diffused) from the same state."""
+    n = 10000
+    src, dst = graphgen.web_graph(n, seed=3)
+    B = graphgen.uniform_rhs(n, D)
+    g = di.Graph(n, src, dst)
+    _, st, recs = traced(torch_cuda, g, B, 4096, kernel=kernel, method=di.DI_CYC)
+    assert len(recs) == st.cycles > 10
+    og = oracle.Graph(n, src, dst)
+    moves = np.bincount(src[src != dst], minlength=n) > 0
+    F, H, e = B.copy(), np.zeros(n), 0.0
+    for c, rec in enumerate(recs):
+        held = int(np.count_nonzero(F))
+        cnt, sel, e, ops, r = oracle.di_cycle(og, F, H, D, oracle.CYC, oracle.SYNC, e)
+        assert abs(rec.r - r) <= 1e-13 * r, (c, rec.r, r)
+        assert rec.selected == cnt == held, c
+        assert rec.links == ops, c
+        assert rec.senders == int(np.count_nonzero(sel & moves)), c
+    assert np.abs(F).sum() <= TOL < recs[-1].r
+
+
 def test_trace_capacity_prefix(torch_cuda):
     """A short trace is the prefix of the full one (the pull is
     bit-reproducible); capacity 0 writes nothing and still solves."""
