@@ -161,6 +161,27 @@ def test_trace_pi_diffuses_every_node(torch_cuda):
     assert np.all(r[1:] < r[:-1])
 
 
+@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH])
+def test_trace_pi_r_is_the_norm_of_matrix_powers(torch_cuda, kernel):
+    """DI_PI diffuses every node each cycle, so the fluid at the start of cycle
+    c is P^c.B: each record's r equals |P^c B|_1, computed with the oracle's
+    product by P."""
+    n = 5000
+    src, dst = graphgen.web_graph(n, seed=6)
+    rng = np.random.default_rng(6)
+    B = rng.random(n) * (1.0 - D) / n
+    g = di.Graph(n, src, dst)
+    _, st, recs = traced(torch_cuda, g, B, 4096, tol=1e-10, method=di.DI_PI, kernel=kernel)
+    assert len(recs) == st.cycles > 20
+    og = oracle.Graph(n, src, dst)
+    x = B.copy()
+    for c, rec in enumerate(recs):
+        want = np.abs(x).sum()
+        # sums of up to a hub's in-degree of terms, in another order, per cycle
+        assert abs(rec.r - want) <= (c + 1) * 1e-13 * want, (c, rec.r, want)
+        x = oracle.apply_p(og, D, x)
+
+
 def test_trace_rejects(torch_cuda):
     torch = torch_cuda
     n = 100
