@@ -108,6 +108,26 @@ def test_trace_dicyc_matches_oracle_cycles(torch_cuda, kernel):
     assert np.abs(F).sum() <= TOL < recs[-1].r
 
 
+def test_trace_matches_oracle_cycles_at_1m(torch_cuda):
+    """The benchmark's configuration (N = 1M web graph, uniform B, default
+    options): every cycle of the whole solve diffuses exactly the oracle's
+    frontier-synchronous selection, with r to rounding."""
+    n = 1_000_000
+    src, dst = graphgen.web_graph(n, seed=0)
+    B = graphgen.uniform_rhs(n, D)
+    g = di.Graph(n, src, dst)
+    _, st, recs = traced(torch_cuda, g, None, 4096)
+    assert len(recs) == st.cycles > 50
+    og = oracle.Graph(n, src, dst)
+    F, H, e = B.copy(), np.zeros(n), 0.0
+    for c, rec in enumerate(recs):
+        cnt, sel, e, ops, r = oracle.di_cycle(og, F, H, D, oracle.SOP, oracle.SYNC, e)
+        # the oracle adds N terms one after another: within (N - 1) u of the sum
+        assert abs(rec.r - r) <= (n - 1) * 0.5 * np.finfo(float).eps * r, (c, rec.r, r)
+        assert rec.selected == cnt and rec.links == ops, c
+    assert np.abs(F).sum() <= TOL < recs[-1].r
+
+
 def test_trace_capacity_prefix(torch_cuda):
     """A short trace is the prefix of the full one (the pull is
     bit-reproducible); capacity 0 writes nothing and still solves."""
