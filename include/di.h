@@ -196,10 +196,14 @@ di_status di_solve_dev(const di_graph* g, const double* B_dev, double d, double 
 
 /* di_solve_dev with a per-cycle trace: record c of trace[0, capacity) (host,
  * caller-allocated) describes cycle c of the solve (DI_FP32_REFINE numbers
- * the cycles of its passes one after another). *count (host) receives the
- * number of records written, min(cycles, capacity). capacity 0 writes none.
+ * the cycles of its passes one after another). *count (host, required)
+ * receives the number of records written, min(cycles, capacity); it is 0
+ * when the call fails other than with DI_E_NOCONV. capacity 0 writes none
+ * (trace may then be NULL). The records pass through a device buffer of
+ * capacity records that the graph's pooled workspace keeps.
  * DI-SOP, DI-CYC and PI; DI_E_INVAL for DI_GS_ASYNC (its sweeps are not
- * cycles) or a negative capacity. Otherwise as di_solve_dev. */
+ * cycles), a negative capacity, a NULL trace with capacity > 0 or a NULL
+ * count. Otherwise as di_solve_dev. */
 di_status di_solve_trace_dev(const di_graph* g, const double* B_dev, double d, double tol,
                              const di_opts* opts, double* X_dev, di_stats* stats,
                              di_cycle_rec* trace, int32_t capacity, int32_t* count);
