@@ -36,12 +36,28 @@ def hipcc() -> str:
 
 
 def build_di(verbose: bool = False) -> str:
+    """Compiles each source to an object in _build/ (in parallel) and links
+    libdi.so in-tree."""
+    from concurrent.futures import ThreadPoolExecutor
+
     out = os.path.join(HERE, "libdi.so")
-    srcs = []
-    for s in HIP_SOURCES:
-        p = os.path.join(CSRC, s)
-        srcs += (["-x", "hip", p] if s.endswith(".hip") else ["-x", "hip", p])
-    cmd = [hipcc(), *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-o", out + ".tmp", *srcs]
+    bdir = os.path.join(ROOT, "_build", "di")
+    os.makedirs(bdir, exist_ok=True)
+    common = [f for f in HIPCC_FLAGS if f not in ("-shared",)]
+
+    def compile_one(name):
+        obj = os.path.join(bdir, name + ".o")
+        cmd = [hipcc(), *common, f"-I{INCLUDE}", f"-I{CSRC}", "-c", "-x", "hip",
+               os.path.join(CSRC, name), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    jobs = max(1, min(len(HIP_SOURCES), int(os.environ.get("MAX_JOBS", "8"))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(compile_one, HIP_SOURCES))
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-fPIC", "-shared", "-o", out + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -51,7 +51,7 @@ namespace {
 void free_graph_device(di_graph* g) {
   void* ptrs[] = {g->row_ptr, g->col,    g->info,   g->csc_ptr,  g->csc_idx, g->row_lo,
                   g->it_r0,   g->it_r1,  g->it_l0,  g->it_l1,    g->it_seg,  g->heavy_row,
-                  g->heavy_seg, g->hc_seg0, g->hc_seg1, g->hc_off};
+                  g->heavy_seg, g->hc_seg0, g->hc_seg1, g->hc_off, g->seg_heavy};
   for (void* p : ptrs) (void)hipFree(p);
   g->row_ptr = nullptr;
   g->col = nullptr;
@@ -64,6 +64,7 @@ void free_graph_device(di_graph* g) {
   g->heavy_row = nullptr;
   g->heavy_seg = nullptr;
   g->hc_seg0 = g->hc_seg1 = g->hc_off = nullptr;
+  g->seg_heavy = nullptr;
 }
 
 template <typename V>
@@ -225,7 +226,7 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       // and kPullMaxRows rows; a row with more in-links is split into
       // segments of kPullChunk links, summed separately
       std::vector<int64_t> r0v, r1v, l0v, l1v, hseg;
-      std::vector<int32_t> segv, hrow;
+      std::vector<int32_t> segv, hrow, seg_heavy;
       int64_t nseg = 0, open_r0 = -1, cur_links = 0, cur_rows = 0;
       std::vector<uint16_t> rlo((size_t)n, 0);
       auto flush = [&](int64_t end_row) {
@@ -253,6 +254,7 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
             l0v.push_back(lo);
             l1v.push_back(std::min<int64_t>(lo + di::kPullChunk, cptr[j + 1]));
             segv.push_back((int32_t)nseg++);
+            seg_heavy.push_back((int32_t)(hrow.size() - 1));
           }
           continue;
         }
@@ -292,6 +294,7 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
       if (st == DI_OK) st = upload(&g->hc_seg0, hc0);
       if (st == DI_OK) st = upload(&g->hc_seg1, hc1);
       if (st == DI_OK) st = upload(&g->hc_off, hoff);
+      if (st == DI_OK) st = upload(&g->seg_heavy, seg_heavy);
       // the node words carry the heavy flags
       if (st == DI_OK)
         DI_HIP(hipMemcpy(g->info, info.data(), info.size() * sizeof(uint32_t), hipMemcpyHostToDevice));

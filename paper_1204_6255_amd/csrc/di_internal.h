@@ -122,6 +122,15 @@ struct Workspace {
   SelStat* tile_stat = nullptr; // select statistics (select_stat_records)
   Part* blk_part = nullptr;     // per pull/reduce/start block
   double* seg_val = nullptr;    // pull: sums of the heavy-row segments
+  // pull: the heavy rows' fluid kept by the last selection, two copies by
+  // cycle parity (the selection of cycle c reads copy c & 1 and writes copy
+  // (c + 1) & 1), so no selection block reads a value another block of the
+  // same launch writes; n_heavy values of the fluid type each
+  void* hret = nullptr;
+  // pull with heavy_atomic: the segment sums of each heavy row, added with
+  // FP64 atomics by the pull of cycle c into copy (c + 1) & 1 and read by
+  // the next selection; the pull of cycle c clears copy c & 1
+  double* hacc = nullptr;
   Ctl* ctl = nullptr;           // two copies (see Ctl)
   Ctl* host_ctl = nullptr;      // pinned copy of both, for the stop check
   double* Y64 = nullptr;        // refinement: d X_j / out_j
@@ -169,6 +178,7 @@ struct di_graph {
   int64_t n_heavy = 0;
   int64_t n_segs = 0;
   bool heavy_atomic = false;      // n_heavy or n_hchunks > kHeavyLds
+  int32_t* seg_heavy = nullptr;   // n_segs: the heavy row (index) of each segment
   int32_t* heavy_row = nullptr;   // n_heavy, ascending
   int64_t* heavy_seg = nullptr;   // n_heavy + 1: segment range of each
   // completion chunks: chunk k sums segments [hc_seg0[k], hc_seg1[k]) of one

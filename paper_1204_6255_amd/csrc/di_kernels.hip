@@ -216,7 +216,12 @@ __device__ inline void fold_tile_stats(const SelStat* __restrict__ tile_stat, in
   }
 }
 
-__global__ void k_reset_ctl(Ctl* ctl) {
+// Both control-block copies cleared, and both copies of the heavy rows'
+// atomic segment sums (n2 doubles) set to zero.
+__global__ void k_reset_ctl(Ctl* ctl, double* __restrict__ hacc, int64_t n2) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n2;
+       q += (int64_t)gridDim.x * blockDim.x)
+    hacc[q] = 0.0;
   if (blockIdx.x == 0 && threadIdx.x < 2) {
     Ctl c;
     c.r = 0.0;
@@ -370,7 +375,8 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     const Part* __restrict__ blk_part, int nparts, const int32_t* __restrict__ heavy_row,
     const int32_t* __restrict__ hc_seg0, const int32_t* __restrict__ hc_seg1,
     const int32_t* __restrict__ hc_off, const double* __restrict__ seg_val, int64_t n_heavy,
-    int64_t n_hchunks, int heavy_atomic, Ctl* __restrict__ ctl, int parity, int first, double d,
+    int64_t n_hchunks, int heavy_atomic, T* __restrict__ hret, const double* __restrict__ hacc,
+    Ctl* __restrict__ ctl, int parity, int first, double d,
     double tol, double tol_in, double tol_rel, int method, int stop, int max_cycles,
     di_cycle_rec* __restrict__ trace, int trace_cap) {
   constexpr int TILE = BLOCK * M;
@@ -392,8 +398,14 @@ __global__ __launch_bounds__(BLOCK) void k_select(
 
   // After a pull the records leave out the heavy rows (the start records
   // cover every row): add their values, completing them with their segment
-  // sums in a fixed order unless the pull added those atomically.
+  // sums in a fixed order (or the sums the pull added atomically). A heavy
+  // row's kept fluid is read from the copy of this cycle's parity, which no
+  // block of this launch writes: the owner of the row's tile writes the
+  // other copy (and F, which no selection reads for a heavy row).
   const bool heavy_here = PULL && !first && !heavy_atomic;
+  const T* hret_cur = hret + (int64_t)parity * n_heavy;
+  T* hret_next = hret + (int64_t)(parity ^ 1) * n_heavy;
+  const double* hacc_cur = hacc + (int64_t)parity * n_heavy;
   // Heavy row `tid` and completion chunk `tid` (slot 0): their graph data is
   // loaded first, so that the loads depending on it (the chunk's segment
   // sums, the row's F) are issued while the node loads are in flight.
@@ -429,7 +441,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
 #pragma unroll
   for (int u = 0; u < kHeavyChunkSegs; ++u)
     sv[u] = hchunk0 && hq0 + u < hq1 ? seg_val[hq0 + u] : 0.0;
-  if (hrow0) fh0 = to_d(F[hr0]);
+  if (hrow0) fh0 = to_d(hret_cur[tid]);
   Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
   for (int p = tid; p < nparts; p += BLOCK) part_add(v, blk_part[p]);
   if (heavy_here) {
@@ -457,7 +469,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     for (int k = 1; k < HPT; ++k) {
       const int64_t h = tid + (int64_t)k * BLOCK;
       hr[k] = h < n_heavy ? heavy_row[h] : 0;
-      hf[k] = h < n_heavy ? to_d(F[hr[k]]) : 0.0;
+      hf[k] = h < n_heavy ? to_d(hret_cur[h]) : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -475,12 +487,16 @@ __global__ __launch_bounds__(BLOCK) void k_select(
       }
     }
   } else if (PULL && !first) {
-    // heavy_atomic: the pull added the segment sums to F
+    // heavy_atomic: the pull added the segment sums into hacc
     for (int64_t h = tid; h < n_heavy; h += BLOCK) {
-      const double fh = to_d(F[heavy_row[h]]);
+      const double fh = to_d((T)(to_d(hret_cur[h]) + hacc_cur[h]));
       v.pabs += fabs(fh);
       v.psum += fh;
     }
+  } else if (PULL && !heavy_atomic) {
+    // first selection: heavy rows are read with their tiles; their ids serve
+    // the owner's lookup of the row's index
+    for (int64_t h = tid; h < n_heavy; h += BLOCK) s_hrow[h] = heavy_row[h];
   }
   v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
   if (tid == 0) {
@@ -506,6 +522,12 @@ __global__ __launch_bounds__(BLOCK) void k_select(
       for (int64_t h = tid; h < n_heavy; h += BLOCK) {
         const int32_t row = s_hrow[h];
         if ((row / TILE) % gridDim.x == blockIdx.x) F[row] = (T)s_hnew[h];
+      }
+    if (PULL && !first && heavy_atomic && !s_was_done)
+      for (int64_t h = tid; h < n_heavy; h += BLOCK) {
+        const int32_t row = heavy_row[h];
+        if ((row / TILE) % gridDim.x == blockIdx.x)
+          F[row] = (T)(to_d(hret_cur[h]) + hacc_cur[h]);
       }
     return;
   }
@@ -538,15 +560,21 @@ __global__ __launch_bounds__(BLOCK) void k_select(
       if (i < n) {
         const int out = (int)(w[m] & kOutMask);
         const bool loop = (w[m] & kLoopBit) != 0;
-        const bool heavy = heavy_here && (w[m] & kHeavyBit) != 0;
-        if (heavy) {  // the completed value, found by binary search in LDS
+        // a heavy row: its index by binary search over the ascending ids (in
+        // LDS, or in global memory when there are too many for LDS); after a
+        // pull its fluid is the completed value
+        const bool heavy = PULL && (w[m] & kHeavyBit) != 0;
+        int hidx = 0;
+        if (heavy) {
           int lo = 0, hi = (int)n_heavy - 1;
           while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (s_hrow[mid] < i) lo = mid + 1;
+            if ((heavy_atomic ? heavy_row[mid] : s_hrow[mid]) < i) lo = mid + 1;
             else hi = mid;
           }
-          f[m] = s_hnew[lo];
+          hidx = lo;
+          if (!first)
+            f[m] = heavy_atomic ? to_d((T)(to_d(hret_cur[lo]) + hacc_cur[lo])) : s_hnew[lo];
         }
         const double a = fabs(f[m]);
         const double thr = (mode != 0 || out == 0) ? 0.0 : rl * (double)out;
@@ -554,6 +582,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
           const double t = loop ? f[m] * (double)out / ((double)out - d) : f[m];
           H[i] = (T)(hv[m] + t);
           F[i] = (T)0;
+          if (heavy) hret_next[hidx] = (T)0;
           ++my_sel;
           if (out == 0) {
             my_e += t;
@@ -568,6 +597,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
           }
         } else if (heavy) {
           F[i] = (T)f[m];  // the completed value stays
+          hret_next[hidx] = (T)f[m];
         }
         if (PULL && npush[m] > 0) sent[i] = (T)snd[m];
       }
@@ -672,8 +702,10 @@ __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
     const int32_t* __restrict__ csc_idx, const int64_t* __restrict__ it_r0,
     const int64_t* __restrict__ it_r1, const int64_t* __restrict__ it_l0,
     const int64_t* __restrict__ it_l1, const int32_t* __restrict__ it_seg, int64_t n_items,
-    double* __restrict__ seg_val, int heavy_atomic, const SelStat* __restrict__ tile_stat,
-    int64_t ntiles, Part* __restrict__ blk_part, const Ctl* __restrict__ ctl) {
+    double* __restrict__ seg_val, int heavy_atomic, const int32_t* __restrict__ seg_heavy,
+    double* __restrict__ hacc_next, double* __restrict__ hacc_clear, int64_t n_heavy,
+    const SelStat* __restrict__ tile_stat, int64_t ntiles, Part* __restrict__ blk_part,
+    const Ctl* __restrict__ ctl) {
   constexpr int U = kPullChunk / kPullBlock;
   __shared__ double s_val[kPullChunk];
   __shared__ double s_red[kPullBlock / 64];
@@ -702,6 +734,10 @@ __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
   }
   double acc_abs = 0.0, acc_sum = 0.0;  // the block's rows: sum |F|, sum F
   if (ctl->done) return;
+  // heavy_atomic: the copy the last selection read is cleared for the next
+  // pull's additions
+  if (heavy_atomic && blockIdx.x == 0)
+    for (int64_t h = tid; h < n_heavy; h += kPullBlock) hacc_clear[h] = 0.0;
   for (int64_t it = it_begin; it < it_end; it += it_step) {
     const int64_t l0 = nl0, l1 = nl1, r0 = nr0, r1 = nr1;
     const int seg = nseg;
@@ -741,14 +777,15 @@ __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU))) void k_pull(
       v[u] = (word[u] >> (idx[u] & 63)) & 1ull ? to_d(sent[idx[u]]) : 0.0;
     if (seg >= 0) {
       // a segment of a heavy row: its sum is completed by the next
-      // selection (or, with too many heavy rows, added to F[r0] atomically)
+      // selection (or, with too many heavy rows, added atomically to the
+      // row's sum of this cycle)
       double acc = 0.0;
 #pragma unroll
       for (int u = 0; u < U; ++u) acc += v[u];
       acc = block_sum(acc, s_red);
       if (tid == 0) {
         if (!heavy_atomic) seg_val[seg] = acc;
-        else if (acc != 0.0) atomic_add(&F[r0], (T)acc);
+        else if (acc != 0.0) atomic_add(&hacc_next[seg_heavy[seg]], acc);
       }
       continue;
     }
@@ -1201,7 +1238,9 @@ int part_count(const CycleArgs& a) {
 }
 
 hipError_t launch_reset_ctl(const CycleArgs& a) {
-  hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, a.stream, a.ws->ctl);
+  const int64_t n2 = a.ws->hacc ? 2 * a.g->n_heavy : 0;
+  hipLaunchKernelGGL(k_reset_ctl, dim3(grid_for(n2, 256, 64)), dim3(256), 0, a.stream, a.ws->ctl,
+                     a.ws->hacc, n2);
   return hipGetLastError();
 }
 
@@ -1234,7 +1273,8 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        (int64_t*)nullptr, (T*)nullptr, ws->tile_stat, (const Part*)ws->blk_part,
                        nparts, g->heavy_row, g->hc_seg0, g->hc_seg1, g->hc_off,
                        (const double*)ws->seg_val, g->n_heavy, g->n_hchunks, (int)g->heavy_atomic,
-                       ws->ctl, parity, first, a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop,
+                       (T*)ws->hret, (const double*)ws->hacc, ws->ctl, parity, first, a.d, a.tol,
+                       a.tol_in, a.tol_rel, a.method, a.stop,
                        a.max_cycles, a.trace, a.trace_cap);
   } else {
     hipLaunchKernelGGL((k_select<T, false, kSelectBlockPush, kSelectPerThreadPush>), dim3(grid),
@@ -1243,7 +1283,8 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        ws->fr_lstart, ws->fr_base, (T*)ws->fr_s, ws->tile_stat,
                        (const Part*)ws->blk_part, nparts, (const int32_t*)nullptr,
                        (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
-                       (const double*)nullptr, (int64_t)0, (int64_t)0, 0, ws->ctl, parity, first,
+                       (const double*)nullptr, (int64_t)0, (int64_t)0, 0, (T*)nullptr,
+                       (const double*)nullptr, ws->ctl, parity, first,
                        a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop, a.max_cycles, a.trace,
                        a.trace_cap);
   }
@@ -1261,16 +1302,22 @@ hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t
   const bool timed = ev0 || ev1;
   if (a.direction == kPull) {
     const dim3 grid(pull_grid(g)), block(kPullBlock);
+    // the selection of cycle c read hacc copy c & 1; this pull adds into copy
+    // (c + 1) & 1 and clears copy c & 1
+    double* hacc_next = ws->hacc + (int64_t)((cycle + 1) & 1) * g->n_heavy;
+    double* hacc_clear = ws->hacc + (int64_t)(cycle & 1) * g->n_heavy;
     if (timed)
       hipExtLaunchKernelGGL(k_pull<T>, grid, block, 0, a.stream, ev0, ev1, 0u, (T*)ws->F,
                             (const T*)ws->sent, ws->front_bits, g->row_lo, g->csc_idx, g->it_r0,
                             g->it_r1, g->it_l0, g->it_l1, g->it_seg, g->n_items, ws->seg_val,
-                            (int)g->heavy_atomic, (const SelStat*)ws->tile_stat, ntiles,
+                            (int)g->heavy_atomic, (const int32_t*)g->seg_heavy, hacc_next,
+                            hacc_clear, g->n_heavy, (const SelStat*)ws->tile_stat, ntiles,
                             ws->blk_part, ctl);
     else
       hipLaunchKernelGGL(k_pull<T>, grid, block, 0, a.stream, (T*)ws->F, (const T*)ws->sent,
                          ws->front_bits, g->row_lo, g->csc_idx, g->it_r0, g->it_r1, g->it_l0,
                          g->it_l1, g->it_seg, g->n_items, ws->seg_val, (int)g->heavy_atomic,
+                         (const int32_t*)g->seg_heavy, hacc_next, hacc_clear, g->n_heavy,
                          (const SelStat*)ws->tile_stat, ntiles, ws->blk_part, ctl);
     return hipGetLastError();
   }

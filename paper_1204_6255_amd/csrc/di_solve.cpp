@@ -25,7 +25,7 @@ void free_workspace(Workspace* ws) {
   void* ptrs[] = {ws->F,         ws->H,         ws->sent,     ws->front_bits,
                   ws->fr_lstart, ws->fr_base,   ws->fr_s,     ws->tile_stat,
                   ws->blk_part,  ws->seg_val,   ws->ctl,      ws->X64,      ws->B64,
-                  ws->Y64,       ws->trace};
+                  ws->Y64,       ws->trace,     ws->hret,     ws->hacc};
   for (void* p : ptrs) (void)hipFree(p);
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   if (ws->host_part) (void)hipHostFree(ws->host_part);
@@ -67,6 +67,9 @@ di_status alloc_workspace(const di_graph* g, int prec, Workspace** out) {
   if (st == DI_OK) st = dmalloc((void**)&ws->blk_part, nparts * sizeof(Part));
   if (st == DI_OK)
     st = dmalloc((void**)&ws->seg_val, (size_t)std::max<int64_t>(g->n_segs, 1) * sizeof(double));
+  const size_t nh = (size_t)std::max<int64_t>(g->n_heavy, 1);
+  if (st == DI_OK) st = dmalloc(&ws->hret, 2 * nh * s);
+  if (st == DI_OK) st = dmalloc((void**)&ws->hacc, 2 * nh * sizeof(double));
   if (st == DI_OK) st = dmalloc((void**)&ws->ctl, 2 * sizeof(Ctl));
   if (st == DI_OK) {
     hipError_t err = hipHostMalloc((void**)&ws->host_ctl, 2 * sizeof(Ctl), hipHostMallocDefault);
@@ -718,9 +721,10 @@ size_t workspace_bytes(const di_graph* g, int prec) {
   const size_t ntiles =
       (size_t)std::max(select_stat_records(g->n, kPull), select_stat_records(g->n, kPush));
   const size_t nparts = (size_t)std::max(kPullMaxGrid, kReduceGrid) + 1;
+  const size_t nh = (size_t)std::max<int64_t>(g->n_heavy, 1);
   return 3 * n * s + ((n + 63) / 64) * sizeof(unsigned long long) + ntiles * sizeof(SelStat) +
          nparts * sizeof(Part) + (size_t)std::max<int64_t>(g->n_segs, 1) * sizeof(double) +
-         2 * sizeof(Ctl);
+         2 * nh * (s + sizeof(double)) + 2 * sizeof(Ctl);
 }
 
 di_status solo_create(di_graph* g, SoloRun** out) {
