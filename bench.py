@@ -45,8 +45,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pull_f64_n1m_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1204_6255_amd", "csrc", "di_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1204_6255_amd", "csrc")
+# per move kernel: its committed counter summary and the source it was taken on
+TRAFFIC = {
+    "window": (os.path.join(ROOT, "profiles", "k_wcycle_f64_n1m_traffic.txt"),
+               os.path.join(CSRC, "di_window.hip")),
+    "pull": (os.path.join(ROOT, "profiles", "k_pull_f64_n1m_traffic.txt"),
+             os.path.join(CSRC, "di_kernels.hip")),
+}
 
 
 def parse_args():
@@ -60,39 +66,42 @@ def parse_args():
     p.add_argument("--precision", choices=["fp64", "fp32", "fp32r"], default="fp64",
                    help="fluid precision (fp32r: FP32 with FP64 residual passes)")
     p.add_argument("--tol", type=float, default=1e-9)
-    p.add_argument("--kernel", choices=["auto", "pull", "push"], default="auto")
+    p.add_argument("--kernel", choices=["auto", "pull", "push", "window"], default="auto")
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="budget of the CPU-oracle sample (0 disables it)")
     p.add_argument("--no-extras", action="store_true",
                    help="headline solve only (no FP32, method, high-E, batched or serving sections)")
     p.add_argument("--only", choices=["fp32_refine", "methods", "literal_alpha_1m", "config_10k",
-                                      "dataset2_like", "batched_ppr", "serving"], default=None,
+                                      "dataset2_like", "prefix_sweep", "batched_ppr", "serving"],
+                   default=None,
                    help="run this one section after the headline solve (for profiling)")
     p.add_argument("--serve-seconds", type=float, default=6.0,
                    help="length of each serving phase")
     p.add_argument("--serve-kmax", type=int, default=16)
     p.add_argument("--calibration-copy", action="store_true",
-                   help="after the timed region, copy 256 MiB once (a plain copy of known size "
-                        "for scaling memory counters)")
+                   help="after the timed region, fill 1 GiB and then sum it (a write-only and a "
+                        "read-only kernel of known size, for scaling memory counters)")
     return p.parse_args()
 
 
-def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
+def kernel_source_hash(path) -> str:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic():
-    """Measured HBM bytes per pull launch from the committed counter summary,
-    or None when it is missing or was taken on other kernel source."""
+def read_traffic(kind):
+    """Measured HBM bytes per launch of the move kernel (`window` or `pull`)
+    from the committed counter summary, or None when it is missing or was
+    taken on other kernel source."""
+    path, source = TRAFFIC[kind]
     try:
         fields = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
                     fields[k.strip()] = v.strip()
-        if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        if fields.get("kernel_source_sha256_16") != kernel_source_hash(source):
             return None
         return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -178,6 +187,24 @@ def cpu_baseline(n, d, tol, budget_s, alpha, kmax, solutions=None, with_baseline
         small[f"alpha={a}"] = oracle_methods(oracle, oracle.Graph(10_000, s_, t_),
                                              graphgen.uniform_rhs(10_000, d), d, tol)
     out["oracle_n10k"] = small
+    # the oracle's side of the prefix sweep (Tables 2-3): sequential DI-SOP
+    # nb_iter per N, both stop modes
+    s_full, t_full = graphgen.web_graph(n, seed=0, alpha=alpha, kmax=kmax)
+    sweep = []
+    for m in PREFIX_SIZES:
+        if m > n:
+            break
+        s_, t_ = graphgen.prefix_subgraph(m, s_full, t_full)
+        og_ = og if m == n else oracle.Graph(m, s_, t_)
+        Bm = graphgen.uniform_rhs(m, d)
+        _, _, st = oracle.diter(og_, Bm, d, oracle.SOP, oracle.SEQUENTIAL, tol=tol)
+        _, _, sp = oracle.diter(og_, Bm, d, oracle.SOP, oracle.SEQUENTIAL, stop=oracle.STOP_PAPER,
+                                tol=1.0 / m)
+        sweep.append({"N": m, "resid_s": st.seconds, "resid_nb_iter": st.nb_iter,
+                      "resid_cycles": int(st.cycles), "paper_nb_iter": sp.nb_iter,
+                      "paper_cycles": int(sp.cycles)})
+    out["oracle_prefix_sweep"] = sweep
+    del s_full, t_full
     # error of every collected GPU solution against the oracle's
     if solutions:
         refs, errs = {}, {}
@@ -366,6 +393,46 @@ def high_e_section(di, graphgen, d):
     return out
 
 
+PREFIX_SIZES = (1_000, 10_000, 100_000, 1_000_000)
+
+
+def prefix_sweep_section(di, graphgen, n, d, tol, alpha, kmax):
+    """Section 2.6's scaling method on the synthetic stand-in: the subgraphs
+    induced on the first N ids of the benchmark graph, N = 10^3 .. 10^6,
+    with the statistics of Table 1, and DI-SOP's GPU time, cycles and cost
+    (nb_iter) per N in both stop modes (the GPU's side of Tables 2-3; the
+    oracle's nb_iter for the same subgraphs is in cpu_baseline)."""
+    import torch
+    src, dst = graphgen.web_graph(n, seed=0, alpha=alpha, kmax=kmax)
+    rows = []
+    for m in PREFIX_SIZES:
+        if m > n:
+            break
+        s, t = graphgen.prefix_subgraph(m, src, dst)
+        row = graphgen.graph_stats(m, s, t).table1_row()
+        g = di.Graph(m, s, t)
+        X = torch.empty(m, dtype=torch.float64, device="cuda")
+        for mode, stop, tl in (("resid", di.DI_STOP_RESID, tol), ("paper", di.DI_STOP_PAPER, 1.0 / m)):
+            o = di.di_opts_default()
+            o.stop = stop
+
+            def solve():
+                status, st = di.di_solve_dev(g.handle, None, d, tl, o, X)
+                if status != di.DI_OK:
+                    raise RuntimeError(di.di_last_error())
+                return st
+
+            sec, st = time_solves(solve, 10 if m < n else 5)
+            row[f"gpu_{mode}"] = {"ms_per_solve": sec * 1e3, "cycles": int(st.cycles),
+                                  "nb_iter": float(st.nb_iter),
+                                  "resid_l1": float(st.resid_l1),
+                                  "gedges_per_s": st.edges_pushed / sec / 1e9}
+        rows.append(row)
+        g.close()
+    return {"graph": f"prefixes of the N={n} benchmark graph (ids < N, induced)",
+            "tol_resid": tol, "paper_target": "1/N", "rows": rows}
+
+
 def batched_section(di, graphgen, g, n, d, tol, solutions):
     import numpy as np
     import torch
@@ -535,7 +602,10 @@ def main():
     del src, dst
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     opts = di.di_opts_default()
-    opts.kernel = {"auto": di.DI_KERNEL_AUTO, "pull": di.DI_KERNEL_PULL, "push": di.DI_KERNEL_PUSH}[args.kernel]
+    opts.kernel = {"auto": di.DI_KERNEL_AUTO, "pull": di.DI_KERNEL_PULL, "push": di.DI_KERNEL_PUSH,
+                   "window": di.DI_KERNEL_WINDOW}[args.kernel]
+    # the move kernel DI_KERNEL_AUTO takes
+    kind = {"auto": "window", "pull": "pull", "push": "push", "window": "window"}[args.kernel]
     opts.precision = {"fp64": di.DI_FP64, "fp32": di.DI_FP32, "fp32r": di.DI_FP32_REFINE}[args.precision]
     headline = (n == 1_000_000 and args.kmax == 500 and args.precision == "fp64"
                 and args.alpha == 1.68 and args.kernel != "push")
@@ -565,13 +635,15 @@ def main():
     torch.cuda.synchronize()
     opts.flags = 0
 
+    # method bytes (what DI-SOP itself moves: per link moved, per diffused
+    # node, and the selection's pass over F and the node words) per launch
     move_bytes = sum(r.move_bytes for r in runs)
     move_secs = sum(r.move_seconds for r in runs)
     launches = sum(r.move_launches for r in runs)
     per_launch_bytes = move_bytes / max(launches, 1)
     per_launch_s = move_secs / max(launches, 1)
     achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
-    traffic = read_traffic() if headline else None
+    traffic = read_traffic(kind) if headline and kind in TRAFFIC else None
     edges = float(np.mean([r.edges_pushed for r in runs]))
     solutions = {"DI-SOP pull fp64 (headline)": ("1m", "uniform", X.cpu().numpy())}
     # the same solve through the host-array entry (B and X cross PCIe)
@@ -615,7 +687,7 @@ def main():
                         f"[1,{args.kmax}], 15% dangling, 70% links within +-500, rest Zipf(1); "
                         f"d={d}, B=(1-d)/N, stop at sum|F|<={tol:g}, {args.precision}",
             "n": n, "links": int(stats.L), "dangling": int(stats.D),
-            "kernel": "push" if opts.kernel == di.DI_KERNEL_PUSH else "pull",
+            "kernel": kind,
         },
         "cycles": int(last.cycles),
         "nb_iter": float(last.nb_iter),
@@ -626,25 +698,42 @@ def main():
         "err_bound": float(last.err_bound),
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_pull" if opts.kernel != di.DI_KERNEL_PUSH else "k_push")
+            "kernel": {"window": "k_wcycle", "pull": "k_pull", "push": "k_push"}[kind]
                       + ("<double>" if args.precision == "fp64" else "<float>"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic if opts.kernel != di.DI_KERNEL_PUSH else None,
-            "bytes_per_launch": per_launch_bytes,
+            "traffic": traffic,
+            "method_bytes_per_launch": per_launch_bytes,
             "us_per_launch": per_launch_s * 1e6,
+            "launches": launches,
+            "traffic_over_method_bytes": (traffic / per_launch_bytes
+                                          if traffic and per_launch_bytes > 0 else None),
             "achievable_copy_gbps": copy_gbps,
+            "method_bytes": "per cycle N*(s+4) (selection reads F and the node word) + "
+                            "(8+4s) per diffused node + (4+2s) per link moved, s = 8 (FP64); "
+                            "the window launch selects and moves in one" if kind == "window" else
+                            "(4+2s) per link moved, s = 8 (FP64)",
         },
     }
+    if kind == "pull":
+        # the pull reads every in-link each cycle: its dense scan, apart
+        # from the method's bytes
+        scan = float(stats.L) * 12.0 + n * 18.0
+        line["roofline"]["pull_scan_model"] = {
+            "bytes_per_launch": scan, "gbps": scan / per_launch_s / 1e9 if per_launch_s else 0.0,
+            "frac": scan / per_launch_s / 1e9 / HBM_PEAK_GBS if per_launch_s else 0.0}
     if args.calibration_copy:
-        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
+        # a write-only fill and a read-only sum of 1 GiB each (beyond the
+        # 256 MB Infinity Cache), the last two kernels of the run
+        a = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
-        b.copy_(a)
+        a.fill_(1.0)
         torch.cuda.synchronize()
-        del a, b
+        line["calibration_sum"] = float(a.sum().item())
+        torch.cuda.synchronize()
+        del a
     line["hbm_frac"] = line["roofline"]["frac"]
     if not args.no_extras and headline:
         sections = {
@@ -654,6 +743,8 @@ def main():
                                                               solutions),
             "config_10k": lambda: small_graph_section(di, graphgen, d, tol),
             "dataset2_like": lambda: high_e_section(di, graphgen, d),
+            "prefix_sweep": lambda: prefix_sweep_section(di, graphgen, n, d, tol, args.alpha,
+                                                         args.kmax),
             "batched_ppr": lambda: batched_section(di, graphgen, g, n, d, tol, solutions),
             "serving": lambda: serving_section(di, graphgen, d, args.serve_seconds,
                                                args.serve_kmax),

@@ -93,8 +93,13 @@ enum {
   DI_KERNEL_AUTO = 0, /* the library's choice (currently DI_KERNEL_PULL) */
   DI_KERNEL_PULL = 1, /* every node sums what its in-links send (CSC);
                          no atomics, bit-reproducible */
-  DI_KERNEL_PUSH = 2  /* every diffused node adds to its out-neighbours
+  DI_KERNEL_PUSH = 2, /* every diffused node adds to its out-neighbours
                          (CSR) with device-scope float atomics */
+  DI_KERNEL_WINDOW = 3 /* one launch per cycle selects and pushes a tile of
+                         nodes: links within 512 ids into an LDS window, the
+                         far links into LDS hub rows or device-scope atomics;
+                         reads only the links it moves. Atomic order varies,
+                         so results agree with the pull to rounding */
 };
 
 typedef struct di_graph di_graph;
@@ -140,6 +145,12 @@ typedef struct di_stats {
                                the fluid (with DI_FLAG_KERNEL_TIMING) */
   double bytes_moved;       /* algorithmic bytes of the whole solve */
   double move_bytes;        /* algorithmic bytes of those pull/push launches */
+  double seconds_to_1e9;    /* device time from the first cycle to the first
+                               cycle start with an L1 residual <= 1e-9 (an
+                               FP64 one: with DI_FP32_REFINE, a residual
+                               pass), by the device wall clock; -1 when the
+                               solve never got there (or for batched and
+                               served solves, which do not record it) */
 } di_stats;
 
 /* One cycle of a traced solve (di_solve_trace_dev). */

@@ -304,6 +304,7 @@ di_status batch_group(di_graph* g, int k, const double* B_dev, double d, const d
       t.move_seconds = move_seconds;
       t.bytes_moved = select_b + pull_b + refine_b;
       t.move_bytes = move_launches > 0 ? pull_b : 0.0;
+      t.seconds_to_1e9 = -1.0;  // not recorded for batched columns
     }
   }
   return result;
@@ -343,7 +344,7 @@ di_status check_batch(const di_graph* g, int32_t k, double d, const double* tol,
     set_error("unknown precision");
     return DI_E_INVAL;
   }
-  if (o.kernel == DI_KERNEL_PUSH) {
+  if (o.kernel == DI_KERNEL_PUSH || o.kernel == DI_KERNEL_WINDOW) {
     set_error("batched solves move the fluid by the pull kernel only");
     return DI_E_INVAL;
   }

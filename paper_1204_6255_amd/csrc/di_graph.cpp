@@ -51,7 +51,8 @@ namespace {
 void free_graph_device(di_graph* g) {
   void* ptrs[] = {g->row_ptr, g->col,    g->info,   g->csc_ptr,  g->csc_idx, g->row_lo,
                   g->it_r0,   g->it_r1,  g->it_l0,  g->it_l1,    g->it_seg,  g->heavy_row,
-                  g->heavy_seg, g->hc_seg0, g->hc_seg1, g->hc_off, g->seg_heavy};
+                  g->heavy_seg, g->hc_seg0, g->hc_seg1, g->hc_off, g->seg_heavy,
+                  g->wp_col,  g->wp_near, g->hub_node, g->hub_tile};
   for (void* p : ptrs) (void)hipFree(p);
   g->row_ptr = nullptr;
   g->col = nullptr;
@@ -65,7 +66,13 @@ void free_graph_device(di_graph* g) {
   g->heavy_seg = nullptr;
   g->hc_seg0 = g->hc_seg1 = g->hc_off = nullptr;
   g->seg_heavy = nullptr;
+  g->wp_col = nullptr;
+  g->wp_near = nullptr;
+  g->hub_node = nullptr;
+  g->hub_tile = nullptr;
 }
+
+
 
 template <typename V>
 di_status upload(V** dst, const std::vector<V>& src) {
@@ -80,6 +87,76 @@ di_status upload(V** dst, const std::vector<V>& src) {
   }
   if (!src.empty()) DI_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
   return DI_OK;
+}
+
+// Window-push layout (di_window.hip): each row's out-links with the near
+// links (|i - j| <= kWinHalo) first and the far links after them, a far link
+// into a hub row coded -1 - slot; the hubs are the nodes with the most far
+// in-links (at least kWinHubMinFar; ties to the lower id), at most kWinHubs,
+// slots ascending by id.
+di_status build_window(di_graph* g, const std::vector<int64_t>& row_ptr,
+                       const std::vector<int32_t>& col) {
+  const int64_t n = g->n;
+  const int64_t W = di::kWinHalo;
+  std::vector<int64_t> farin((size_t)n, 0);
+  std::vector<uint32_t> nnear((size_t)n, 0);
+  int64_t near_links = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int64_t j = col[e];
+      if (j - i <= W && i - j <= W) {
+        ++nnear[i];
+        ++near_links;
+      } else {
+        ++farin[j];
+      }
+    }
+  std::vector<int32_t> hubs;
+  for (int64_t j = 0; j < n; ++j)
+    if (farin[j] >= di::kWinHubMinFar) hubs.push_back((int32_t)j);
+  if ((int64_t)hubs.size() > di::kWinHubs) {
+    std::nth_element(hubs.begin(), hubs.begin() + di::kWinHubs, hubs.end(),
+                     [&](int32_t x, int32_t y) {
+                       return farin[x] != farin[y] ? farin[x] > farin[y] : x < y;
+                     });
+    hubs.resize(di::kWinHubs);
+  }
+  std::sort(hubs.begin(), hubs.end());
+  std::vector<int32_t> slot((size_t)n, -1);
+  for (size_t k = 0; k < hubs.size(); ++k) slot[(size_t)hubs[k]] = (int32_t)k;
+  std::vector<int32_t> wcol(col.size());
+  std::vector<uint32_t> wnear((size_t)n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t q = row_ptr[i];
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int64_t j = col[e];
+      if (j - i <= W && i - j <= W) wcol[(size_t)q++] = (int32_t)j;
+    }
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int64_t j = col[e];
+      if (!(j - i <= W && i - j <= W))
+        wcol[(size_t)q++] = slot[(size_t)j] >= 0 ? -1 - slot[(size_t)j] : (int32_t)j;
+    }
+    wnear[(size_t)i] = nnear[(size_t)i] | (slot[(size_t)i] >= 0 ? di::kHubBit : 0u);
+  }
+  const int64_t ntiles = (n + di::kWinTile - 1) / di::kWinTile;
+  std::vector<int32_t> htile((size_t)ntiles + 1, 0);
+  for (int32_t h : hubs) htile[(size_t)(h / di::kWinTile) + 1] += 1;
+  for (int64_t t = 0; t < ntiles; ++t) htile[(size_t)t + 1] += htile[(size_t)t];
+  // the window kernel keeps a tile's link offsets in 32 bits
+  g->window_ok = true;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t a = t * di::kWinTile, b = std::min<int64_t>(a + di::kWinTile, n);
+    if (row_ptr[(size_t)b] - row_ptr[(size_t)a] >= (int64_t(1) << 31)) g->window_ok = false;
+  }
+  g->n_hubs = (int64_t)hubs.size();
+  g->n_wtiles = ntiles;
+  g->near_links = near_links;
+  di_status st = upload(&g->wp_col, wcol);
+  if (st == DI_OK) st = upload(&g->wp_near, wnear);
+  if (st == DI_OK) st = upload(&g->hub_node, hubs);
+  if (st == DI_OK) st = upload(&g->hub_tile, htile);
+  return st;
 }
 
 }  // namespace
@@ -203,6 +280,7 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
     st = upload(&g->row_ptr, row_ptr);
     if (st == DI_OK) st = upload(&g->col, col);
     if (st == DI_OK) st = upload(&g->info, info);
+    if (st == DI_OK) st = build_window(g, row_ptr, col);
     std::vector<int64_t>().swap(row_ptr);
     std::vector<int32_t>().swap(col);
     if (st == DI_OK) {

@@ -61,6 +61,34 @@ constexpr uint32_t kOutMask = 0x3fffffffu;
 constexpr int kHeavyLds = 4096;
 constexpr int kHeavyChunkSegs = 16;   // segment sums per completion chunk
 
+// Window push (the default move): one launch per cycle selects the nodes of
+// a tile of kWinTile consecutive ids, claims them and pushes their links.
+// A link i -> j is "near" when |i - j| <= kWinHalo: it lands in the tile's
+// LDS window [a - kWinHalo, a + kWinTile + kWinHalo); the parts of the
+// window outside the tile (the halos) are handed to the neighbouring tiles'
+// next cycle. A far link goes to one of the kWinHubs hub rows (the nodes
+// with the most far in-links, accumulated per block in LDS) or else, by a
+// device-scope atomic, to the far accumulator of the next cycle.
+#ifndef DI_WIN_BLOCK
+#define DI_WIN_BLOCK 512
+#endif
+#ifndef DI_WIN_PER_THREAD
+#define DI_WIN_PER_THREAD 4
+#endif
+#ifndef DI_WIN_GRID
+#define DI_WIN_GRID 1024
+#endif
+constexpr int kWinBlock = DI_WIN_BLOCK;
+constexpr int kWinPerThread = DI_WIN_PER_THREAD;
+constexpr int kWinTile = kWinBlock * kWinPerThread;
+constexpr int kWinHalo = 512;
+constexpr int kWinHubs = 1024;
+constexpr int kWinMaxGrid = DI_WIN_GRID;  // blocks (grid-stride over tiles)
+constexpr int kWinHubMinFar = 16;  // far in-links a node needs to be a hub
+static_assert(kWinHalo <= kWinTile, "a near link must land in the tile or a neighbour");
+// wp_near: near-link count in bits 0..30, hub flag in bit 31
+constexpr uint32_t kHubBit = 0x80000000u;
+
 // Control block: two copies. The select kernel of cycle c reads copy c & 1
 // (the state after cycle c - 1) and its block 0 writes copy (c + 1) & 1; the
 // pull (or push) of cycle c reads copy (c + 1) & 1.
@@ -83,6 +111,10 @@ struct Ctl {
   unsigned long long edges_total;  // link operations (pushes along j != i)
   unsigned long long front_total;  // diffused nodes with links to push
   unsigned long long sel_total;    // diffused nodes
+  // device wall clock (wall_clock64) at the run's first selection, and at
+  // the first selection whose r, an L1 residual, was <= 1e-9 (0: not yet)
+  unsigned long long t_start;
+  unsigned long long t_1e9;
 };
 
 // Per select tile: what its nodes did in the cycle.
@@ -131,6 +163,16 @@ struct Workspace {
   // FP64 atomics by the pull of cycle c into copy (c + 1) & 1 and read by
   // the next selection; the pull of cycle c clears copy c & 1
   double* hacc = nullptr;
+  // window push: far accumulators (two copies by parity, n values each),
+  // halos (two copies, per tile 2 * kWinHalo values: left then right), hub
+  // partials (two copies, per block kWinHubs values) and per-block records
+  // (two copies); all of the fluid type except the records
+  void* wA = nullptr;
+  void* whalo = nullptr;
+  void* whub = nullptr;
+  Part* wrec = nullptr;
+  int* wflag = nullptr;         // device flag (any negative right-hand side)
+  int* host_flag = nullptr;     // pinned copy
   Ctl* ctl = nullptr;           // two copies (see Ctl)
   Ctl* host_ctl = nullptr;      // pinned copy of both, for the stop check
   double* Y64 = nullptr;        // refinement: d X_j / out_j
@@ -179,6 +221,18 @@ struct di_graph {
   int64_t n_segs = 0;
   bool heavy_atomic = false;      // n_heavy or n_hchunks > kHeavyLds
   int32_t* seg_heavy = nullptr;   // n_segs: the heavy row (index) of each segment
+  // window push: out-links per row (offsets row_ptr) with the near links
+  // (|i - j| <= kWinHalo, ids) first and the far links after them (ids, or
+  // -1 - slot for a hub); wp_near per node (near count | kHubBit); hub ids
+  // ascending (slot = index) and the slots of each window tile
+  int32_t* wp_col = nullptr;
+  uint32_t* wp_near = nullptr;
+  int64_t n_hubs = 0;
+  int32_t* hub_node = nullptr;
+  int32_t* hub_tile = nullptr;   // n_wtiles + 1
+  int64_t n_wtiles = 0;
+  int64_t near_links = 0;        // near links (statistics)
+  bool window_ok = false;        // every tile's links fit 32-bit offsets
   int32_t* heavy_row = nullptr;   // n_heavy, ascending
   int64_t* heavy_seg = nullptr;   // n_heavy + 1: segment range of each
   // completion chunks: chunk k sums segments [hc_seg0[k], hc_seg1[k]) of one
@@ -218,7 +272,7 @@ di_status check_device(int* device_out);
 void free_workspace(Workspace* ws);
 
 // ---- kernel launchers (di_kernels.hip) ------------------------------------
-enum Direction { kPull = 0, kPush = 1 };
+enum Direction { kPull = 0, kPush = 1, kWindow = 2 };
 
 struct CycleArgs {
   const di_graph* g;
@@ -232,7 +286,9 @@ struct CycleArgs {
   int method;      // DI_SOP or DI_CYC
   int stop;        // DI_STOP_RESID or DI_STOP_PAPER
   int max_cycles;  // the solve stops after this many cycles
-  int direction;   // kPull or kPush
+  int direction;   // kPull, kPush or kWindow
+  int folded;      // kWindow: the fluid may be signed, so a fold pass after
+                   // every cycle gathers it into F and sums |F| exactly
   hipStream_t stream;
   di_cycle_rec* trace;  // device records of this run's cycles (or null)
   int trace_cap;        // records it has room for
@@ -263,6 +319,31 @@ template <typename T>
 hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_h_to_x(const CycleArgs& a, double* X);
+
+// ---- window push (di_window.hip) --------------------------------------------
+// Cycle c is one launch of the window kernel: its selection reads the
+// records of cycle c - 1 (or, for c = 0, the start records in blk_part) and
+// the fluid F + far accumulator + halos + hub partials of parity c & 1; it
+// pushes into parity (c + 1) & 1. Without `folded` the next r is summed from
+// the kept and pushed amounts (exact for a fluid that stays >= 0); with it a
+// fold pass after each cycle gathers the fluid into F and sums |F|.
+int win_grid(const di_graph* g);
+// F = B (or the uniform value), H = 0, both far accumulators 0, and the
+// start records (part_count(a) + 1 of them) in blk_part.
+template <typename T>
+hipError_t launch_wstart(const CycleArgs& a, const double* B, double b_uniform);
+// the same for a state (F, H) already in the workspace
+template <typename T>
+hipError_t launch_wstart_state(const CycleArgs& a);
+template <typename T>
+hipError_t launch_wcycle(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1);
+// After the stop at cycle c (parity c & 1): gathers the fluid into F (unless
+// the run folded every cycle) and writes its exact sums, one record per
+// window block, to blk_part[0, win_grid).
+template <typename T>
+hipError_t launch_wfinal(const CycleArgs& a, int parity, int add);
+// *flag = 1 when some B_i < 0 (flag cleared first)
+hipError_t launch_any_negative(const double* B, int64_t n, int* flag, hipStream_t stream);
 
 // Asynchronous Gauss-Seidel (DI_GS_ASYNC), FP64, x in ws->H and y = d x / out
 // in ws->F: x = B; then one sweep = the in-place sweep, the heavy rows and

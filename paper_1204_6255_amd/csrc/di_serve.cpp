@@ -359,6 +359,7 @@ di_status finish_columns(di_server* s, ColumnSet* cs) {
     t.err_bound = b.final_r / (1.0 - cs->d);
     t.e = b.e;
     t.seconds = now_s() - ln.t_submit;  // latency: submission to completion
+    t.seconds_to_1e9 = -1.0;            // not recorded for served requests
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->results[ln.ticket] = std::move(res);
@@ -431,6 +432,7 @@ di_status step_solo(di_server* s, GraphSlot* gs) {
                         hipMemcpyDeviceToHost, so->stream));
   DI_HIP(hipStreamSynchronize(so->stream));
   res.stats.seconds = now_s() - so->lane.t_submit;  // latency: submission to completion
+  res.stats.seconds_to_1e9 = -1.0;                  // not recorded for served requests
   std::lock_guard<std::mutex> lk(s->mu);
   s->results[so->lane.ticket] = std::move(res);
   s->completed += 1;
@@ -777,7 +779,7 @@ di_status serve_create(size_t budget, int32_t k_max, const di_opts* opts, di_ser
     set_error("unknown precision");
     return DI_E_INVAL;
   }
-  if (o.stop != DI_STOP_RESID || o.kernel == DI_KERNEL_PUSH) {
+  if (o.stop != DI_STOP_RESID || o.kernel == DI_KERNEL_PUSH || o.kernel == DI_KERNEL_WINDOW) {
     set_error("serving stops on the residual and moves fluid by the pull kernel only");
     return DI_E_INVAL;
   }

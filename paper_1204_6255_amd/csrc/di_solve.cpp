@@ -25,9 +25,11 @@ void free_workspace(Workspace* ws) {
   void* ptrs[] = {ws->F,         ws->H,         ws->sent,     ws->front_bits,
                   ws->fr_lstart, ws->fr_base,   ws->fr_s,     ws->tile_stat,
                   ws->blk_part,  ws->seg_val,   ws->ctl,      ws->X64,      ws->B64,
-                  ws->Y64,       ws->trace,     ws->hret,     ws->hacc};
+                  ws->Y64,       ws->trace,     ws->hret,     ws->hacc,
+                  ws->wA,        ws->whalo,     ws->whub,     ws->wrec,     ws->wflag};
   for (void* p : ptrs) (void)hipFree(p);
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
+  if (ws->host_flag) (void)hipHostFree(ws->host_flag);
   if (ws->host_part) (void)hipHostFree(ws->host_part);
   for (hipEvent_t e : ws->events) (void)hipEventDestroy(e);
   if (ws->copied) (void)hipEventDestroy(ws->copied);
@@ -95,6 +97,28 @@ di_status ensure_push_buffers(const di_graph* g, Workspace* ws) {
   DI_TRY(dmalloc((void**)&ws->fr_base, slots * sizeof(int64_t)));
   DI_TRY(dmalloc(&ws->fr_s, slots * s));
   DI_TRY(dmalloc((void**)&ws->fr_lstart, slots * sizeof(int64_t)));
+  return DI_OK;
+}
+
+// Window-push buffers, allocated on first use: far accumulators, halos, hub
+// partials and records, two copies each, and the sign flag.
+di_status ensure_window_buffers(const di_graph* g, Workspace* ws) {
+  if (ws->wA) return DI_OK;
+  const size_t s = ws->prec == kF64 ? sizeof(double) : sizeof(float);
+  const size_t G = (size_t)win_grid(g);
+  DI_TRY(dmalloc(&ws->whalo, 2 * (size_t)std::max<int64_t>(g->n_wtiles, 1) * 2 * kWinHalo * s));
+  DI_TRY(dmalloc(&ws->whub, 2 * G * kWinHubs * s));
+  DI_TRY(dmalloc((void**)&ws->wrec, 2 * G * sizeof(Part)));
+  DI_TRY(dmalloc((void**)&ws->wflag, sizeof(int)));
+  if (!ws->host_flag) {
+    hipError_t err = hipHostMalloc((void**)&ws->host_flag, sizeof(int), hipHostMallocDefault);
+    if (err != hipSuccess) {
+      ws->host_flag = nullptr;
+      set_error(std::string("hipHostMalloc: ") + hipGetErrorString(err));
+      return DI_E_NOMEM;
+    }
+  }
+  DI_TRY(dmalloc(&ws->wA, 2 * (size_t)g->n * s));  // last: marks the set complete
   return DI_OK;
 }
 
@@ -190,7 +214,21 @@ struct RunTimes {
   double move_seconds = 0.0;  // summed pull/push kernel time (timing flag)
   int move_launches = 0;
   Ctl state{};                // the final control block
+  // device wall clock at the first run's first selection and at the first
+  // selection (of any run) with an FP64 residual <= 1e-9
+  unsigned long long t_start = 0, t_1e9 = 0;
 };
+
+// Rate of the device wall clock (wall_clock64), in Hz; 0 if unknown.
+double wall_clock_hz() {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0.0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.0;
+  }
+  return (double)khz * 1e3;
+}
 
 // The cycles to queue next, after the read-back of the state h at
 // selection last_sel: from the contraction of r per cycle so far, the
@@ -224,17 +262,38 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
   if (!ws->copied) DI_HIP(hipEventCreateWithFlags(&ws->copied, hipEventDisableTiming));
   hipEvent_t ev_end = ws->events[1];
   int last_sel = 0;  // selections queued after the first
+  const bool window = a.direction == kWindow;
+  // timing events: pull/push direction, pair c brackets the move of cycle c;
+  // window push, pair c brackets the launch of cycle c
+  auto events_of = [&](int c, hipEvent_t* e0, hipEvent_t* e1) -> di_status {
+    *e0 = *e1 = nullptr;
+    if (!timing) return DI_OK;
+    DI_TRY(ensure_events(ws, 4 + 2 * (size_t)c));
+    *e0 = ws->events[2 + 2 * (size_t)c];
+    *e1 = ws->events[3 + 2 * (size_t)c];
+    return DI_OK;
+  };
   auto queue_cycle = [&]() -> di_status {
     const int c = last_sel;
-    if (timing) DI_TRY(ensure_events(ws, 4 + 2 * (size_t)c));
-    hipEvent_t e0 = timing ? ws->events[2 + 2 * (size_t)c] : nullptr;
-    hipEvent_t e1 = timing ? ws->events[3 + 2 * (size_t)c] : nullptr;
-    DI_HIP(launch_move<T>(a, c, e0, e1));
-    DI_HIP(launch_select<T>(a, c + 1, 0));
+    hipEvent_t e0, e1;
+    if (window) {
+      DI_TRY(events_of(c + 1, &e0, &e1));
+      DI_HIP(launch_wcycle<T>(a, c + 1, e0, e1));
+    } else {
+      DI_TRY(events_of(c, &e0, &e1));
+      DI_HIP(launch_move<T>(a, c, e0, e1));
+      DI_HIP(launch_select<T>(a, c + 1, 0));
+    }
     last_sel = c + 1;
     return DI_OK;
   };
-  DI_HIP(launch_select<T>(a, 0, 1));
+  if (window) {
+    hipEvent_t e0, e1;
+    DI_TRY(events_of(0, &e0, &e1));
+    DI_HIP(launch_wcycle<T>(a, 0, e0, e1));
+  } else {
+    DI_HIP(launch_select<T>(a, 0, 1));
+  }
   int chunk = 8;
   int at = 0;  // the selection the last read-back follows
   for (;;) {
@@ -256,11 +315,14 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
     for (int q = 0; q < todo; ++q) DI_TRY(queue_cycle());
   }
   rt->state = ws->host_ctl[(at + 1) & 1];
+  if (rt->t_start == 0) rt->t_start = rt->state.t_start;
+  if (rt->t_1e9 == 0) rt->t_1e9 = rt->state.t_1e9;
   float ms = 0.f;
   DI_HIP(hipEventElapsedTime(&ms, ev_begin, ev_end));
   rt->seconds = ms * 1e-3;
   if (timing) {
-    const int real = std::min(rt->state.cycles, last_sel);
+    // the launches that moved fluid: cycles 0 .. cycles - 1
+    const int real = std::min(rt->state.cycles, window ? last_sel + 1 : last_sel);
     for (int c = 0; c < real; ++c) {
       float pm = 0.f;
       DI_HIP(hipEventElapsedTime(&pm, ws->events[2 + 2 * (size_t)c], ws->events[3 + 2 * (size_t)c]));
@@ -271,15 +333,18 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
   return DI_OK;
 }
 
-// Algorithmic bytes (s = bytes per fluid value).
-//   select, per cycle: N (2s + 4) (F and the node word read, sent or frontier
-//     written) + 3s per diffused node (H read and written, F written);
-//   pull, per cycle: Lp (4 + s) (in-link id, sender's amount) + N (8 + 2s)
-//     (in-link offsets, F read and written);
-//   push, per cycle: links pushed (4 + 2s) (out-link id, atomic read-modify-
-//     write) + frontier entries (16 + s), and the reduction N s.
-//   residual pass (refinement): Lp 12 (in-link id, y of the sender) +
+// Algorithmic bytes: what the method itself moves (s = bytes per fluid
+// value), whatever the kernel reads besides:
+//   per cycle, the selection: N (s + 4) (F and the node word read);
+//   per diffused node: 8 + 4s (its link offset, F claimed, H read and
+//     written);
+//   per link moved: 4 + 2s (the link id and the read-modify-write of the
+//     destination's fluid);
+//   per residual pass (refinement): Lp 12 (in-link id, y of the sender) +
 //     N (56 + 3s) (X, H, node word, y, B, in-link offsets, R).
+// move_bytes covers the timed launches that move the fluid: the links moved
+// for the pull and the push, the whole cycle for the window push (which
+// selects and moves in one launch).
 void fill_stats(const di_graph* g, const Ctl& h, double d, int s_bytes, int direction,
                 const RunTimes& rt, int refinements, di_stats* st) {
   st->cycles = h.cycles;
@@ -291,22 +356,20 @@ void fill_stats(const di_graph* g, const Ctl& h, double d, int s_bytes, int dire
   st->paper_err = h.paper_err;
   st->e = h.e;
   const double s = s_bytes, N = (double)g->n, C = (double)h.cycles;
-  double move;
-  if (direction == kPull) {
-    // per in-link its source id and the gathered value; per row its 16-bit
-    // in-link offset and F read and written
-    move = C * ((double)g->Lp * (4.0 + s) + N * (2.0 + 2.0 * s));
-  } else {
-    move = (double)h.edges_total * (4.0 + 2.0 * s) + (double)h.front_total * (16.0 + s) + C * N * s;
-  }
-  const double select = C * N * (2.0 * s + 4.0) + (double)h.sel_total * 3.0 * s;
+  const double links = (double)h.edges_total * (4.0 + 2.0 * s);
+  const double select = C * N * (s + 4.0) + (double)h.sel_total * (8.0 + 4.0 * s);
   const double refine = (double)refinements * ((double)g->Lp * 12.0 + N * (56.0 + 3.0 * s));
+  const double move = direction == kWindow ? links + select : links;
   st->refinements = refinements;
   st->move_bytes = rt.move_launches > 0 ? move : 0.0;
-  st->bytes_moved = move + select + refine;
+  st->bytes_moved = links + select + refine;
   st->seconds = rt.seconds;
   st->move_seconds = rt.move_seconds;
   st->move_launches = rt.move_launches;
+  const double hz = rt.t_1e9 != 0 ? wall_clock_hz() : 0.0;
+  st->seconds_to_1e9 = (hz > 0.0 && rt.t_1e9 >= rt.t_start)
+                           ? (double)(rt.t_1e9 - rt.t_start) / hz
+                           : -1.0;
 }
 
 di_status status_from_done(int done) {
@@ -336,8 +399,8 @@ di_status check_common(const di_graph* g, double d, double tol, const di_opts& o
     set_error("unknown method");
     return DI_E_INVAL;
   }
-  if (o.method == DI_GS_ASYNC &&
-      (o.precision != DI_FP64 || o.stop != DI_STOP_RESID || o.kernel == DI_KERNEL_PUSH)) {
+  if (o.method == DI_GS_ASYNC && (o.precision != DI_FP64 || o.stop != DI_STOP_RESID ||
+                                  o.kernel == DI_KERNEL_PUSH || o.kernel == DI_KERNEL_WINDOW)) {
     set_error("DI_GS_ASYNC runs in FP64 with the pull and stops on the residual");
     return DI_E_INVAL;
   }
@@ -353,14 +416,18 @@ di_status check_common(const di_graph* g, double d, double tol, const di_opts& o
     set_error("DI_FP32_REFINE stops on the residual only (DI_STOP_RESID)");
     return DI_E_INVAL;
   }
-  if (o.kernel < DI_KERNEL_AUTO || o.kernel > DI_KERNEL_PUSH) {
+  if (o.kernel < DI_KERNEL_AUTO || o.kernel > DI_KERNEL_WINDOW) {
     set_error("unknown kernel direction");
     return DI_E_INVAL;
   }
   return DI_OK;
 }
 
-int direction_of(const di_opts& o) { return o.kernel == DI_KERNEL_PUSH ? kPush : kPull; }
+int direction_of(const di_opts& o) {
+  if (o.kernel == DI_KERNEL_PUSH) return kPush;
+  if (o.kernel == DI_KERNEL_WINDOW) return kWindow;
+  return kPull;
+}
 
 constexpr int kMaxRefinements = 100;
 
@@ -452,6 +519,7 @@ di_status gs_solve(di_graph* g, const double* B_dev, double d, double tol, const
   // and written, y written, B and the node word; plus the residual passes
   const double N = (double)g->n, Lp = (double)g->Lp;
   t.bytes_moved = (double)h.cycles * (Lp * 12.0 + N * 44.0) + (double)(checks + 1) * (Lp * 12.0 + N * 80.0);
+  t.seconds_to_1e9 = -1.0;  // GS sweeps are not cycles of a residual
   if (st) *st = t;
   if (h.done == 3) {
     set_error("the iterate became non-finite (non-finite B?)");
@@ -466,7 +534,8 @@ di_status gs_solve(di_graph* g, const double* B_dev, double d, double tol, const
 
 template <typename T>
 di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const di_opts& o,
-                  double* X_dev, di_stats* st, Workspace* ws, hipStream_t stream, int trace_cap) {
+                  double* X_dev, di_stats* st, Workspace* ws, hipStream_t stream, int trace_cap,
+                  bool signed_B) {
   CycleArgs a{};
   a.g = g;
   a.ws = ws;
@@ -484,21 +553,81 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   a.trace_cap = trace_cap;
   const bool timing = (o.flags & DI_FLAG_KERNEL_TIMING) != 0;
   const double b_uniform = (1.0 - d) / (double)g->n;
+  const bool window = a.direction == kWindow;
+  if (window && !g->window_ok) {
+    set_error("the window push needs every tile of the graph to hold fewer than 2^31 links");
+    return DI_E_INVAL;
+  }
   if (a.direction == kPush) DI_TRY(ensure_push_buffers(g, ws));
+  if (window) {
+    DI_TRY(ensure_window_buffers(g, ws));
+    DI_TRY(ensure_refine_buffers(g, ws));
+    a.folded = signed_B ? 1 : 0;
+  }
   DI_TRY(ensure_events(ws, 2));
   DI_HIP(launch_reset_ctl(a));
   DI_HIP(hipEventRecord(ws->events[0], stream));
-  DI_HIP(launch_start<T>(a, B_dev, b_uniform));
+  if (window) DI_HIP(launch_wstart<T>(a, B_dev, b_uniform));
+  else DI_HIP(launch_start<T>(a, B_dev, b_uniform));
   RunTimes rt;
   di_stats tmp;
   std::memset(&tmp, 0, sizeof(tmp));
+  // window push: once a run has stopped at cycle c, its fluid (parity c & 1)
+  // is gathered into F and its residual summed exactly
+  auto window_finish = [&](const Ctl& h, double* r_exact) -> di_status {
+    DI_HIP(launch_wfinal<T>(a, h.cycles & 1, (!a.folded && h.cycles > 0) ? 1 : 0));
+    return residual_norm(a, win_grid(g), r_exact, nullptr);
+  };
+  auto elapsed = [&](double* sec) -> di_status {
+    DI_HIP(hipEventRecord(ws->events[1], stream));
+    DI_HIP(hipEventSynchronize(ws->events[1]));
+    float ms = 0.f;
+    DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
+    *sec = ms * 1e-3;
+    return DI_OK;
+  };
+  const int max_cycles = a.max_cycles;
   if (o.precision != DI_FP32_REFINE) {
-    DI_TRY(run_cycles<T>(a, timing, ws->events[0], &rt));
+    if (!window) {
+      DI_TRY(run_cycles<T>(a, timing, ws->events[0], &rt));
+      DI_HIP(launch_h_to_x<T>(a, X_dev));
+      DI_HIP(hipStreamSynchronize(stream));
+      fill_stats(g, rt.state, d, (int)sizeof(T), a.direction, rt, 0, &tmp);
+      if (st) *st = tmp;
+      return status_from_done(rt.state.done);
+    }
+    Ctl tot{};
+    int restarts = 0;
+    for (;;) {
+      a.max_cycles = max_cycles - tot.cycles;
+      a.trace = trace_cap > tot.cycles ? ws->trace + tot.cycles : nullptr;
+      a.trace_cap = std::max(0, trace_cap - tot.cycles);
+      DI_TRY(run_cycles<T>(a, timing, ws->events[0], &rt));
+      const Ctl h = rt.state;
+      add_run(&tot, h);
+      tot.done = h.done;
+      tot.paper_err = h.paper_err;
+      if (h.done == 3) return status_from_done(3);
+      double r_exact = 0.0;
+      DI_TRY(window_finish(h, &r_exact));
+      tot.final_r = r_exact;
+      // the stop compared the kept-plus-pushed sum with tol; should rounding
+      // leave the exact residual above tol, the solve goes on from the
+      // gathered fluid (first selection on the exact records)
+      if (h.done == 1 && a.stop == DI_STOP_RESID && r_exact > tol && restarts < 4 &&
+          tot.cycles < max_cycles) {
+        ++restarts;
+        a.first_parts = win_grid(g);
+        DI_HIP(launch_reset_ctl(a));
+        continue;
+      }
+      break;
+    }
     DI_HIP(launch_h_to_x<T>(a, X_dev));
-    DI_HIP(hipStreamSynchronize(stream));
-    fill_stats(g, rt.state, d, (int)sizeof(T), a.direction, rt, 0, &tmp);
+    DI_TRY(elapsed(&rt.seconds));
+    fill_stats(g, tot, d, (int)sizeof(T), a.direction, rt, 0, &tmp);
     if (st) *st = tmp;
-    return status_from_done(rt.state.done);
+    return status_from_done(tot.done);
   }
   // FP32 passes with FP64 residual passes between them: X accumulates the
   // passes' histories; each pass solves for the correction of X.
@@ -506,7 +635,6 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   DI_HIP(hipMemsetAsync(X_dev, 0, (size_t)g->n * sizeof(double), stream));
   a.tol_in = 0.5 * tol;
   a.tol_rel = o.inner_tol > 0.0 ? o.inner_tol : 1e-5;
-  const int max_cycles = a.max_cycles;
   Ctl tot{};
   int refinements = 0;
   di_status result = DI_OK;
@@ -523,10 +651,15 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
       break;
     }
     if (h.done == 3) return status_from_done(3);
+    if (window) {  // clears the far accumulators for the next pass
+      double r_pass = 0.0;
+      DI_TRY(window_finish(h, &r_pass));
+    }
     // inner stop or max_cycles: fold H into X and recompute the residual
     DI_HIP(launch_refine<T>(a, X_dev, (T*)ws->H, B_dev, b_uniform, (T*)ws->F));
     ++refinements;
     a.first_parts = pull_grid(g) + 1;
+    a.folded = window ? 1 : 0;  // the residual is a signed fluid
     if (h.done == 2 || refinements >= kMaxRefinements) {
       DI_TRY(residual_norm(a, a.first_parts, &tot.final_r, nullptr));
       result = tot.final_r <= tol ? DI_OK : DI_E_NOCONV;
@@ -537,11 +670,7 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
     }
     DI_HIP(launch_reset_ctl(a));
   }
-  DI_HIP(hipEventRecord(ws->events[1], stream));
-  DI_HIP(hipEventSynchronize(ws->events[1]));
-  float ms = 0.f;
-  DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
-  rt.seconds = ms * 1e-3;
+  DI_TRY(elapsed(&rt.seconds));
   fill_stats(g, tot, d, (int)sizeof(T), a.direction, rt, refinements, &tmp);
   if (st) *st = tmp;
   return result;
@@ -592,13 +721,30 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
     DI_TRY(dmalloc((void**)&ws->trace, (size_t)trace_cap * sizeof(di_cycle_rec)));
     ws->trace_cap = trace_cap;
   }
+  // the window push sums the next r from kept and pushed amounts, which is
+  // exact only for a fluid that stays >= 0: find out whether B has a
+  // negative entry
+  bool signed_B = false;
+  if (B && o.method != DI_GS_ASYNC && direction_of(o) == kWindow) {
+    if (B_on_host) {
+      for (int64_t i = 0; i < g->n && !signed_B; ++i) signed_B = B[i] < 0.0;
+    } else {
+      DI_TRY(ensure_window_buffers(g, ws));
+      DI_HIP(launch_any_negative(B_dev, g->n, ws->wflag, stream));
+      DI_HIP(hipMemcpyAsync(ws->host_flag, ws->wflag, sizeof(int), hipMemcpyDeviceToHost, stream));
+      DI_HIP(hipStreamSynchronize(stream));
+      signed_B = *ws->host_flag != 0;
+    }
+  }
   di_stats local;
   if (!st) st = &local;
-  di_status rs = o.method == DI_GS_ASYNC
-                     ? gs_solve(g, B_dev, d, tol, o, X_dev, st, ws, stream)
-                     : (prec == kF64
-                            ? solve_t<double>(g, B_dev, d, tol, o, X_dev, st, ws, stream, trace_cap)
-                            : solve_t<float>(g, B_dev, d, tol, o, X_dev, st, ws, stream, trace_cap));
+  di_status rs =
+      o.method == DI_GS_ASYNC
+          ? gs_solve(g, B_dev, d, tol, o, X_dev, st, ws, stream)
+          : (prec == kF64 ? solve_t<double>(g, B_dev, d, tol, o, X_dev, st, ws, stream, trace_cap,
+                                            signed_B)
+                          : solve_t<float>(g, B_dev, d, tol, o, X_dev, st, ws, stream, trace_cap,
+                                           signed_B));
   if (trace_count && (rs == DI_OK || rs == DI_E_NOCONV)) {
     const int written = std::min(trace_cap, (int)st->cycles);
     if (written > 0)

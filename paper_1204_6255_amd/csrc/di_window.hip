@@ -1,0 +1,553 @@
+// Window-push D-iteration cycle on gfx950: one launch per cycle, whose work
+// follows the diffused links.
+//
+// A cycle of DI-SOP (Sections 2.3 and 2.5.5) selects, against r = sum_i |F_i|
+// of the fluid at the cycle's start, every node with |F_i| >= (r/L) out_i,
+// claims it (Section 2.5.4: H_i += transit, the fluid leaves F_i, a dangling
+// node absorbs it) and pushes transit * d / out_i along each out-link j != i.
+// Here one block owns a tile of kWinTile consecutive node ids and does all
+// of that for its tile in one launch:
+//   - the fluid of node i at the cycle's start is F_i (what the node kept,
+//     plus what its own tile pushed to it) + the far accumulator A_i (far
+//     links, device-scope atomics) + what the neighbouring tiles left in
+//     their halos (near links across a tile boundary) + for a hub row the
+//     block partials of the previous launch (far links into the hubs);
+//   - near links (|i - j| <= kWinHalo) are added into the tile's LDS window
+//     [a - kWinHalo, a + kWinTile + kWinHalo) with LDS atomics; the window's
+//     middle goes straight to F, its two halos to the neighbours' next cycle;
+//   - far links into one of the graph's hub rows (the nodes with the most
+//     far in-links) are added into per-block LDS accumulators, written out
+//     once per launch; other far links are device-scope atomics into the far
+//     accumulator of the next cycle.
+// So the links a cycle reads are the links it moves (plus each sender's row
+// offset), and every state array has two copies by cycle parity: cycle c
+// reads copy c & 1 and pushes into copy (c + 1) & 1, so no block reads what
+// another block of the same launch writes.
+//
+// r of the next cycle: for a fluid that stays >= 0 (B >= 0), sum_i F_i after
+// the cycle equals what the nodes kept plus what the senders pushed, which
+// every block sums for its own nodes and senders; so the next launch folds
+// the per-block records and needs no pass over F. A signed fluid (an FP64
+// residual as right-hand side) runs a fold pass after every cycle instead,
+// which gathers each node's fluid into F and sums |F| exactly. The fold also
+// runs once after the stop, to leave the whole fluid in F and measure the
+// final residual exactly.
+//
+// The summation order of the LDS and device atomics varies from run to run,
+// so results agree with the pull direction to rounding, not bit for bit.
+
+#include "di_device.h"
+#include <hip/hip_ext.h>
+
+namespace di {
+namespace {
+
+using namespace dev;
+
+constexpr int W = kWinHalo;
+constexpr int K = kWinHubs;
+constexpr int WIN = kWinTile + 2 * kWinHalo;
+constexpr int kUnroll = 4;  // links in flight per thread in the push
+
+__device__ inline void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void lds_add(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Graph and fluid arrays of one launch (state arrays already offset to the
+// launch's parity).
+template <typename T>
+struct WinState {
+  const uint32_t* info;
+  const int64_t* row_ptr;
+  const int32_t* wp_col;
+  const uint32_t* wp_near;
+  const int32_t* hub_node;
+  const int32_t* hub_tile;
+  int64_t n, L, ntiles, nhubs;
+  T* F;
+  T* H;
+  T* A_cur;           // far accumulator read (and cleared) this cycle
+  T* A_next;          // far accumulator this cycle pushes into
+  const T* halo_cur;  // per tile: left halo, then right halo (W values each)
+  T* halo_next;
+  const T* hub_cur;   // per block of the last launch: K hub partials
+  T* hub_next;
+};
+
+// The tile's hub rows: their ids (s_hnode) and, when `add`, what the last
+// launch's G blocks sent them (s_hadd), each summed over the blocks in one
+// order. Returns the number of hubs in the tile.
+template <typename T, int BLOCK>
+__device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool add,
+                                int32_t* s_hnode, T* s_hadd) {
+  constexpr int NW = BLOCK / 64;
+  const int h0 = S.hub_tile[tile], h1 = S.hub_tile[tile + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = wave; k < h1 - h0; k += NW) {
+    double acc = 0.0;
+    if (add)
+      for (int b = lane; b < G; b += 64) acc += to_d(S.hub_cur[(int64_t)b * K + h0 + k]);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      s_hnode[k] = S.hub_node[h0 + k];
+      s_hadd[k] = (T)acc;
+    }
+  }
+  return h1 - h0;
+}
+
+// Fluid of node i (position li in its tile) at the cycle's start: kept +
+// far accumulator + halos + hub partials, added in this order. The far
+// accumulator is cleared as it is read.
+template <typename T>
+__device__ inline T start_value(const WinState<T>& S, T f, int64_t i, int64_t tile, int li,
+                                uint32_t wn, const int32_t* s_hnode, const T* s_hadd, int nh) {
+  const T av = S.A_cur[i];
+  if (av != (T)0) {
+    f = f + av;
+    S.A_cur[i] = (T)0;
+  }
+  if (li < W && tile > 0) f = f + S.halo_cur[(tile - 1) * 2 * W + W + li];
+  if (li >= kWinTile - W && tile + 1 < S.ntiles)
+    f = f + S.halo_cur[(tile + 1) * 2 * W + (li - (kWinTile - W))];
+  if (wn & kHubBit) {
+    int lo = 0, hi = nh - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_hnode[mid] < i) lo = mid + 1;
+      else hi = mid;
+    }
+    f = f + s_hadd[lo];
+  }
+  return f;
+}
+
+// One link i -> code of a push: hub links (code < 0) into the block's hub
+// accumulators, near links (|code - i| <= W) into the window, other far
+// links into the next far accumulator.
+template <typename T>
+__device__ inline void push_link(const WinState<T>& S, int32_t code, int64_t i, int64_t win0, T s,
+                                 T* s_win, T* s_hub) {
+  if (code < 0) lds_add(&s_hub[-1 - code], s);
+  else if (code - i <= W && i - code <= W) lds_add(&s_win[code - win0], s);
+  else atomic_add(&S.A_next[code], s);
+}
+
+// One cycle: the stop test on the last cycle's records, then select, claim
+// and push every tile of the block (grid-stride). first: the records are the
+// start records and F is the whole fluid; folded: F is the whole fluid (a
+// fold pass ran after the last cycle).
+template <typename T, int BLOCK, int M>
+__global__ __launch_bounds__(BLOCK) void k_wcycle(
+    WinState<T> S, const Part* __restrict__ rec_in, int nrec_in, Part* __restrict__ rec_out,
+    Ctl* __restrict__ ctl, int parity, int first, int folded, double d, double tol,
+    double tol_in, double tol_rel, int method, int stop, int max_cycles,
+    di_cycle_rec* __restrict__ trace, int trace_cap) {
+  static_assert(BLOCK * M == kWinTile, "tile shape");
+  constexpr int NW = BLOCK / 64;
+  __shared__ T s_win[WIN];
+  __shared__ T s_hub[K];
+  __shared__ T s_hadd[K];
+  __shared__ int32_t s_hnode[K];
+  __shared__ Part s_part[NW];
+  // the tile's senders, slot k = tid * M + m for node a + tid + m * BLOCK:
+  // position of its first link among the tile's moved links, its first
+  // link's offset from the tile's first link, and the amount it sends
+  __shared__ int32_t s_off[kWinTile];
+  __shared__ int32_t s_rel[kWinTile];
+  __shared__ T s_snd[kWinTile];
+  __shared__ int s_wtot[NW];
+  __shared__ double s_r;
+  __shared__ int s_done, s_cyc;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int G = gridDim.x;
+  const int nhub = (int)(S.nhubs < K ? S.nhubs : K);
+
+  // the last cycle's records, folded in one order by every block
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  for (int p = tid; p < nrec_in; p += BLOCK) part_add(v, rec_in[p]);
+  Ctl c0;
+  if (tid == 0) c0 = ctl[parity];
+  for (int k = tid; k < nhub; k += BLOCK) s_hub[k] = (T)0;
+  v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
+  if (tid == 0) {
+    const Ctl c = next_ctl(c0, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
+    if (blockIdx.x == 0) {
+      ctl[parity ^ 1] = c;
+      if (trace && !first && !c0.done && c.cycles - 1 < trace_cap)
+        trace[c.cycles - 1] = di_cycle_rec{c.r_last, (int64_t)v.ops, (int32_t)v.sel,
+                                           (int32_t)v.nfront};
+    }
+    s_done = c.done;
+    s_cyc = c.cyc_mode;
+    s_r = c.r;
+  }
+  __syncthreads();
+  if (s_done) return;
+  // 0: the DI-SOP threshold; 1: every node holding fluid (DI-CYC); 2: every
+  // node (the power iteration's cost)
+  const int mode = s_cyc;
+  const double rl = s_r / (double)S.L;
+  const bool add = !first && !folded;
+
+  double my_keep = 0.0, my_push = 0.0, my_e = 0.0;
+  unsigned long long my_ops = 0;
+  unsigned int my_sel = 0, my_front = 0;
+
+  for (int64_t tile = blockIdx.x; tile < S.ntiles; tile += G) {
+    const int64_t a = tile * kWinTile;
+    const int64_t win0 = a - W;
+    for (int q = tid; q < WIN; q += BLOCK) s_win[q] = (T)0;
+    const int nh = tile_hubs<T, BLOCK>(S, tile, G, add, s_hnode, s_hadd);
+    __syncthreads();
+    T raw[M], keep[M], snd[M];
+    uint32_t w[M], wn[M];
+    const int64_t ebase = S.row_ptr[a];  // the tile's first link
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t i = a + tid + (int64_t)m * BLOCK;
+      const bool in = i < S.n;
+      raw[m] = in ? S.F[i] : (T)0;
+      w[m] = in ? S.info[i] : 0u;
+      wn[m] = in ? S.wp_near[i] : 0u;
+    }
+    double t[M];
+    bool sel[M];
+    int np[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t i = a + tid + (int64_t)m * BLOCK;
+      const int li = tid + m * BLOCK;
+      T fv = raw[m];
+      if (add && i < S.n) fv = start_value(S, fv, i, tile, li, wn[m], s_hnode, s_hadd, nh);
+      const double f = to_d(fv);
+      const int out = (int)(w[m] & kOutMask);
+      const bool loop = (w[m] & kLoopBit) != 0;
+      const double af = fabs(f);
+      const double thr = (mode != 0 || out == 0) ? 0.0 : rl * (double)out;
+      sel[m] = i < S.n && (mode == 2 || (af > 0.0 && af >= thr));
+      np[m] = 0;
+      t[m] = 0.0;
+      snd[m] = (T)0;
+      keep[m] = fv;
+      if (sel[m]) {
+        t[m] = loop ? f * (double)out / ((double)out - d) : f;
+        keep[m] = (T)0;
+        ++my_sel;
+        if (out == 0) {
+          my_e += t[m];
+        } else {
+          const int npush = out - (loop ? 1 : 0);
+          if (npush > 0) {
+            np[m] = npush;
+            snd[m] = (T)(t[m] * d / (double)out);
+            my_ops += (unsigned long long)npush;
+            ++my_front;
+            my_push += to_d(snd[m]) * (double)npush;
+          }
+        }
+      }
+      my_keep += to_d(keep[m]);
+    }
+    // the history and the senders' link offsets, loaded together
+    T hv[M];
+    int64_t e0[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t i = a + tid + (int64_t)m * BLOCK;
+      hv[m] = sel[m] ? S.H[i] : (T)0;
+      e0[m] = np[m] > 0 ? S.row_ptr[i] : 0;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t i = a + tid + (int64_t)m * BLOCK;
+      if (sel[m]) S.H[i] = (T)(to_d(hv[m]) + t[m]);
+    }
+    // push, parallel over the tile's moved links: a block scan of the
+    // senders' link counts gives each slot the position of its first link;
+    // thread tid moves links tid, tid + BLOCK, ... (the slot of a link by
+    // binary search over the positions: the last slot starting at or before
+    // it, which has links), kUnroll link loads in flight at a time
+    int cnt = 0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) cnt += np[m];
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) s_wtot[wave] = incl;
+    __syncthreads();
+    int pos = incl - cnt, total = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const int x = s_wtot[q];
+      if (q < wave) pos += x;
+      total += x;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int k = tid * M + m;
+      s_off[k] = pos;
+      s_rel[k] = (int32_t)(e0[m] - ebase);
+      s_snd[k] = snd[m];
+      pos += np[m];
+    }
+    __syncthreads();
+    for (int q0 = tid; q0 < total; q0 += kUnroll * BLOCK) {
+      int32_t code[kUnroll];
+      int slot[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int q = q0 + u * BLOCK;
+        slot[u] = -1;
+        code[u] = 0;
+        if (q < total) {
+          int lo = 0, hi = kWinTile - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= q) lo = mid;
+            else hi = mid - 1;
+          }
+          slot[u] = lo;
+          code[u] = S.wp_col[ebase + s_rel[lo] + (q - s_off[lo])];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (slot[u] >= 0) {
+          const int k = slot[u];
+          const int64_t i = a + k / M + (int64_t)(k % M) * BLOCK;
+          push_link(S, code[u], i, win0, s_snd[k], s_win, s_hub);
+        }
+    }
+    __syncthreads();
+    // kept fluid plus the tile's own near pushes; the halos for the
+    // neighbours
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t i = a + tid + (int64_t)m * BLOCK;
+      if (i < S.n) {
+        const T nv = keep[m] + s_win[W + tid + m * BLOCK];
+        if (nv != raw[m]) S.F[i] = nv;
+      }
+    }
+    for (int q = tid; q < W; q += BLOCK) {
+      S.halo_next[tile * 2 * W + q] = s_win[q];
+      S.halo_next[tile * 2 * W + W + q] = s_win[W + kWinTile + q];
+    }
+    __syncthreads();  // the window is cleared by the next tile
+  }
+  for (int k = tid; k < nhub; k += BLOCK) S.hub_next[(int64_t)blockIdx.x * K + k] = s_hub[k];
+  Part rec{my_keep + my_push, my_keep + my_push, my_e, my_ops, my_sel, my_front};
+  rec = block_sum_part(rec, s_part);
+  if (tid == 0) rec_out[blockIdx.x] = rec;
+}
+
+// Gathers each node's fluid into F (when `add`: kept + far accumulator +
+// halos + hub partials, the far accumulator cleared) and writes the exact
+// sums of |F| and F of the block's tiles into rec[blockIdx.x] (the other
+// fields of the record are kept). Returns at once when ctl says the solve
+// has stopped (ctl may be null).
+template <typename T, int BLOCK, int M>
+__global__ __launch_bounds__(BLOCK) void k_wfold(WinState<T> S, Part* __restrict__ rec, int add,
+                                                 const Ctl* __restrict__ ctl) {
+  constexpr int NW = BLOCK / 64;
+  __shared__ T s_hadd[K];
+  __shared__ int32_t s_hnode[K];
+  __shared__ double s_red[NW];
+  if (ctl && ctl->done) return;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x;
+  double pabs = 0.0, psum = 0.0;
+  for (int64_t tile = blockIdx.x; tile < S.ntiles; tile += G) {
+    const int64_t a = tile * kWinTile;
+    int nh = 0;
+    if (add) nh = tile_hubs<T, BLOCK>(S, tile, G, true, s_hnode, s_hadd);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int64_t i = a + tid + (int64_t)m * BLOCK;
+      if (i < S.n) {
+        const T raw = S.F[i];
+        T fv = raw;
+        if (add) {
+          fv = start_value(S, fv, i, tile, tid + m * BLOCK, S.wp_near[i], s_hnode, s_hadd, nh);
+          if (fv != raw) S.F[i] = fv;
+        }
+        pabs += fabs(to_d(fv));
+        psum += to_d(fv);
+      }
+    }
+    __syncthreads();
+  }
+  pabs = block_sum(pabs, s_red);
+  psum = block_sum(psum, s_red);
+  if (tid == 0) {
+    rec[blockIdx.x].pabs = pabs;
+    rec[blockIdx.x].psum = psum;
+  }
+}
+
+// F = B (or the uniform value), H = 0, both far accumulators (2n values) 0,
+// and per-block sums of |F| and F.
+template <typename T>
+__global__ __launch_bounds__(kReduceBlock) void k_wstart(T* __restrict__ F, T* __restrict__ H,
+                                                         T* __restrict__ A2,
+                                                         const double* __restrict__ B,
+                                                         double b_uniform, int64_t n, int state,
+                                                         Part* __restrict__ blk_part) {
+  __shared__ Part lds[kReduceBlock / 64];
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    T f;
+    if (state) {
+      f = F[i];
+    } else {
+      f = B ? (T)B[i] : (T)b_uniform;
+      F[i] = f;
+      H[i] = (T)0;
+    }
+    A2[i] = (T)0;
+    A2[n + i] = (T)0;
+    v.pabs += fabs(to_d(f));
+    v.psum += to_d(f);
+  }
+  v = block_sum_part(v, lds);
+  if (threadIdx.x == 0) {
+    blk_part[blockIdx.x] = v;
+    if (blockIdx.x == 0) blk_part[gridDim.x] = Part{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  }
+}
+
+__global__ void k_clear_flag(int* flag) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+}
+
+// Every thread that sees a negative entry stores 1 (all stores agree).
+__global__ void k_any_negative(const double* __restrict__ B, int64_t n, int* __restrict__ flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    if (B[i] < 0.0) *flag = 1;
+}
+
+template <typename T>
+WinState<T> win_state(const CycleArgs& a, int parity) {
+  const di_graph* g = a.g;
+  Workspace* ws = a.ws;
+  const int G = win_grid(g);
+  const int64_t n = g->n;
+  WinState<T> S;
+  S.info = g->info;
+  S.row_ptr = g->row_ptr;
+  S.wp_col = g->wp_col;
+  S.wp_near = g->wp_near;
+  S.hub_node = g->hub_node;
+  S.hub_tile = g->hub_tile;
+  S.n = n;
+  S.L = g->L;
+  S.ntiles = g->n_wtiles;
+  S.nhubs = g->n_hubs;
+  S.F = (T*)ws->F;
+  S.H = (T*)ws->H;
+  T* A = (T*)ws->wA;
+  S.A_cur = A + (int64_t)parity * n;
+  S.A_next = A + (int64_t)(parity ^ 1) * n;
+  T* halo = (T*)ws->whalo;
+  const int64_t hsz = g->n_wtiles * 2 * W;
+  S.halo_cur = halo + (int64_t)parity * hsz;
+  S.halo_next = halo + (int64_t)(parity ^ 1) * hsz;
+  T* hub = (T*)ws->whub;
+  const int64_t bsz = (int64_t)G * K;
+  S.hub_cur = hub + (int64_t)parity * bsz;
+  S.hub_next = hub + (int64_t)(parity ^ 1) * bsz;
+  return S;
+}
+
+}  // namespace
+
+int win_grid(const di_graph* g) {
+  const int64_t t = g->n_wtiles < 1 ? 1 : g->n_wtiles;
+  return (int)(t < kWinMaxGrid ? t : kWinMaxGrid);
+}
+
+template <typename T>
+hipError_t launch_wstart(const CycleArgs& a, const double* B, double b_uniform) {
+  hipLaunchKernelGGL(k_wstart<T>, dim3(part_count(a)), dim3(kReduceBlock), 0, a.stream,
+                     (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, B, b_uniform, a.g->n, 0,
+                     a.ws->blk_part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_wstart_state(const CycleArgs& a) {
+  hipLaunchKernelGGL(k_wstart<T>, dim3(part_count(a)), dim3(kReduceBlock), 0, a.stream,
+                     (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, (const double*)nullptr, 0.0,
+                     a.g->n, 1, a.ws->blk_part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_wcycle(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1) {
+  const di_graph* g = a.g;
+  Workspace* ws = a.ws;
+  const int G = win_grid(g);
+  const int parity = cycle & 1;
+  const int first = cycle == 0;
+  const WinState<T> S = win_state<T>(a, parity);
+  const Part* rec_in = first ? ws->blk_part : ws->wrec + (int64_t)parity * G;
+  const int nrec_in = first ? a.first_parts : G;
+  Part* rec_out = ws->wrec + (int64_t)(parity ^ 1) * G;
+  const int folded = a.folded ? 1 : 0;
+  auto kern = k_wcycle<T, kWinBlock, kWinPerThread>;
+  if (ev0 || ev1)
+    hipExtLaunchKernelGGL(kern, dim3(G), dim3(kWinBlock), 0, a.stream, ev0, ev1, 0u, S, rec_in,
+                          nrec_in, rec_out, ws->ctl, parity, first, folded, a.d, a.tol, a.tol_in,
+                          a.tol_rel, a.method, a.stop, a.max_cycles, a.trace, a.trace_cap);
+  else
+    hipLaunchKernelGGL(kern, dim3(G), dim3(kWinBlock), 0, a.stream, S, rec_in, nrec_in, rec_out,
+                       ws->ctl, parity, first, folded, a.d, a.tol, a.tol_in, a.tol_rel, a.method,
+                       a.stop, a.max_cycles, a.trace, a.trace_cap);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || !a.folded) return err;
+  // a signed fluid: gather it into F and sum |F| before the next selection
+  const WinState<T> Sn = win_state<T>(a, parity ^ 1);
+  hipLaunchKernelGGL((k_wfold<T, kWinBlock, kWinPerThread>), dim3(G), dim3(kWinBlock), 0,
+                     a.stream, Sn, rec_out, 1, (const Ctl*)(ws->ctl + (parity ^ 1)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_wfinal(const CycleArgs& a, int parity, int add) {
+  const int G = win_grid(a.g);
+  const WinState<T> S = win_state<T>(a, parity);
+  hipLaunchKernelGGL((k_wfold<T, kWinBlock, kWinPerThread>), dim3(G), dim3(kWinBlock), 0,
+                     a.stream, S, a.ws->blk_part, add, (const Ctl*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_any_negative(const double* B, int64_t n, int* flag, hipStream_t stream) {
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, stream, flag);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  int64_t g = (n + 255) / 256;
+  g = g < 1 ? 1 : (g > 2048 ? 2048 : g);
+  hipLaunchKernelGGL(k_any_negative, dim3((unsigned)g), dim3(256), 0, stream, B, n, flag);
+  return hipGetLastError();
+}
+
+template hipError_t launch_wstart<double>(const CycleArgs&, const double*, double);
+template hipError_t launch_wstart<float>(const CycleArgs&, const double*, double);
+template hipError_t launch_wstart_state<double>(const CycleArgs&);
+template hipError_t launch_wstart_state<float>(const CycleArgs&);
+template hipError_t launch_wcycle<double>(const CycleArgs&, int, hipEvent_t, hipEvent_t);
+template hipError_t launch_wcycle<float>(const CycleArgs&, int, hipEvent_t, hipEvent_t);
+template hipError_t launch_wfinal<double>(const CycleArgs&, int, int);
+template hipError_t launch_wfinal<float>(const CycleArgs&, int, int);
+
+}  // namespace di

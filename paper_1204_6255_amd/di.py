@@ -15,7 +15,8 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdi.so")
+# DI_LIB names another build of the library (the host-sanitizer test's)
+LIB_PATH = os.environ.get("DI_LIB") or os.path.join(_HERE, "libdi.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "di.h")
 
 DI_OK, DI_PENDING = 0, 1
@@ -26,7 +27,7 @@ DI_FP64, DI_FP32_REFINE, DI_FP32 = 0, 1, 2
 DI_STOP_RESID, DI_STOP_PAPER = 0, 1
 DI_FLAG_KERNEL_TIMING = 1
 DI_FLAG_SERVE_NO_SOLO = 2
-DI_KERNEL_AUTO, DI_KERNEL_PULL, DI_KERNEL_PUSH = 0, 1, 2
+DI_KERNEL_AUTO, DI_KERNEL_PULL, DI_KERNEL_PUSH, DI_KERNEL_WINDOW = 0, 1, 2, 3
 
 STATUS_NAMES = {
     0: "DI_OK", 1: "DI_PENDING", -1: "DI_E_INVAL", -2: "DI_E_UNSORTED", -3: "DI_E_DUP",
@@ -64,6 +65,7 @@ class di_stats(ctypes.Structure):
         ("move_seconds", ctypes.c_double),
         ("bytes_moved", ctypes.c_double),
         ("move_bytes", ctypes.c_double),
+        ("seconds_to_1e9", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -37,7 +37,7 @@ def test_version_and_defaults():
 def test_struct_layouts_match_header():
     # sizes follow from the field lists in include/di.h
     assert ctypes.sizeof(di.di_opts) == 40
-    assert ctypes.sizeof(di.di_stats) == 4 * 4 + 8 + 9 * 8
+    assert ctypes.sizeof(di.di_stats) == 4 * 4 + 8 + 10 * 8
 
 
 @pytest.mark.parametrize("n,src,dst,expect", [

@@ -133,7 +133,7 @@ def test_cycles_match_oracle_sync_schedule(torch_cuda, case):
 
 # ------------------------------------------------------------- full solves
 
-KERNELS = [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH]
+KERNELS = [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH, di.DI_KERNEL_WINDOW]
 
 
 @pytest.mark.parametrize("kernel", KERNELS)

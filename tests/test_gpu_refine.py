@@ -128,7 +128,7 @@ def oracle_solution(og, B):
     return H
 
 
-@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH])
+@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH, di.DI_KERNEL_WINDOW])
 @pytest.mark.parametrize("rhs", ["uniform", "ppr", "signed"])
 def test_refined_solve_10k(torch_cuda, kernel, rhs):
     n = 10000

@@ -58,7 +58,7 @@ def test_trace_worked_example(torch_cuda):
         F_prev = np.array(w["F"])
 
 
-@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH])
+@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH, di.DI_KERNEL_WINDOW])
 @pytest.mark.parametrize("alpha", [graphgen.ALPHA_L_MATCHED, graphgen.ALPHA_LITERAL])
 def test_trace_matches_oracle_cycles(torch_cuda, alpha, kernel):
     """Every record of a whole solve on a 10k web graph equals the oracle's
@@ -85,7 +85,7 @@ def test_trace_matches_oracle_cycles(torch_cuda, alpha, kernel):
     assert np.abs(F).sum() <= TOL < recs[-1].r
 
 
-@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH])
+@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH, di.DI_KERNEL_WINDOW])
 def test_trace_dicyc_matches_oracle_cycles(torch_cuda, kernel):
     """DI-CYC: every record equals the oracle's frontier-synchronous DI-CYC
     cycle (every node holding fluid diffused) from the same state."""
@@ -181,7 +181,7 @@ def test_trace_pi_diffuses_every_node(torch_cuda):
     assert np.all(r[1:] < r[:-1])
 
 
-@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH])
+@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH, di.DI_KERNEL_WINDOW])
 def test_trace_pi_r_is_the_norm_of_matrix_powers(torch_cuda, kernel):
     """DI_PI diffuses every node each cycle, so the fluid at the start of cycle
     c is P^c.B: each record's r equals |P^c B|_1, computed with the oracle's

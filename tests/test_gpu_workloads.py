@@ -33,7 +33,7 @@ pytestmark = pytest.mark.gpu
 
 D = 0.85
 TOL_PAR = 1.4e-10
-KERNELS = [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH]
+KERNELS = [di.DI_KERNEL_PULL, di.DI_KERNEL_PUSH, di.DI_KERNEL_WINDOW]
 
 
 @pytest.fixture(scope="module")
