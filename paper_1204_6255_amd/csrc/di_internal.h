@@ -86,6 +86,9 @@ constexpr int kWinHubs = 1024;
 constexpr int kWinMaxGrid = DI_WIN_GRID;  // blocks (grid-stride over tiles)
 constexpr int kWinHubMinFar = 16;  // far in-links a node needs to be a hub
 static_assert(kWinHalo <= kWinTile, "a near link must land in the tile or a neighbour");
+// stride of the two far-accumulator copies (whole 256-byte lines, so that
+// both copies take aligned vector accesses)
+inline int64_t win_stride(int64_t n) { return (n + 63) & ~int64_t(63); }
 // wp_near: near-link count in bits 0..30, hub flag in bit 31
 constexpr uint32_t kHubBit = 0x80000000u;
 

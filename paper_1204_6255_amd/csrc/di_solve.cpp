@@ -118,7 +118,7 @@ di_status ensure_window_buffers(const di_graph* g, Workspace* ws) {
       return DI_E_NOMEM;
     }
   }
-  DI_TRY(dmalloc(&ws->wA, 2 * (size_t)g->n * s));  // last: marks the set complete
+  DI_TRY(dmalloc(&ws->wA, 2 * (size_t)win_stride(g->n) * s));  // last: marks the set complete
   return DI_OK;
 }
 

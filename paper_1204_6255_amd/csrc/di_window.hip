@@ -136,42 +136,123 @@ __device__ inline void push_link(const WinState<T>& S, int32_t code, int64_t i, 
   else atomic_add(&S.A_next[code], s);
 }
 
+// Four consecutive values of a node array, as one vector access when all
+// four nodes exist (i0 is a multiple of 4 and every node array starts on a
+// 256-byte boundary).
+template <typename V>
+struct alignas(4 * sizeof(V)) Quad {
+  V v[4];
+};
+template <typename V>
+__device__ inline void load4(const V* p, int64_t i0, int64_t n, V (&out)[4]) {
+  if (i0 + 4 <= n) {
+    const Quad<V> q = *reinterpret_cast<const Quad<V>*>(p + i0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) out[m] = q.v[m];
+  } else {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) out[m] = i0 + m < n ? p[i0 + m] : (V)0;
+  }
+}
+template <typename V>
+__device__ inline void store4(V* p, int64_t i0, int64_t n, const V (&val)[4]) {
+  if (i0 + 4 <= n) {
+    Quad<V> q;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) q.v[m] = val[m];
+    *reinterpret_cast<Quad<V>*>(p + i0) = q;
+  } else {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (i0 + m < n) p[i0 + m] = val[m];
+  }
+}
+
+// Inclusive sums over the lanes of a wave (lane l: lanes 0..l), two at once.
+__device__ inline void wave_scan2(int& x, int& y) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(x, o, 64), v = __shfl_up(y, o, 64);
+    if (lane >= o) {
+      x += u;
+      y += v;
+    }
+  }
+}
+
 // One cycle: the stop test on the last cycle's records, then select, claim
-// and push every tile of the block (grid-stride). first: the records are the
-// start records and F is the whole fluid; folded: F is the whole fluid (a
-// fold pass ran after the last cycle).
+// and push every tile of the block (grid-stride). Thread tid holds the four
+// consecutive nodes a + 4 tid .. a + 4 tid + 3 of tile a. The first tile's
+// loads (and its hub rows' sums) are issued before the stop test, which
+// they do not depend on; nothing is written before it. first: the records
+// are the start records and F is the whole fluid; folded: F is the whole
+// fluid (a fold pass ran after the last cycle).
+// At least four waves per SIMD (at most 128 VGPRs): two 512-thread blocks
+// per compute unit.
 template <typename T, int BLOCK, int M>
-__global__ __launch_bounds__(BLOCK) void k_wcycle(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_wcycle(
     WinState<T> S, const Part* __restrict__ rec_in, int nrec_in, Part* __restrict__ rec_out,
     Ctl* __restrict__ ctl, int parity, int first, int folded, double d, double tol,
     double tol_in, double tol_rel, int method, int stop, int max_cycles,
     di_cycle_rec* __restrict__ trace, int trace_cap) {
-  static_assert(BLOCK * M == kWinTile, "tile shape");
+  static_assert(M == 4 && BLOCK * M == kWinTile, "tile shape: four nodes per thread");
+  static_assert(W % 4 == 0, "halo in whole quads");
   constexpr int NW = BLOCK / 64;
   __shared__ T s_win[WIN];
   __shared__ T s_hub[K];
   __shared__ T s_hadd[K];
   __shared__ int32_t s_hnode[K];
   __shared__ Part s_part[NW];
-  // the tile's senders, slot k = tid * M + m for node a + tid + m * BLOCK:
-  // position of its first link among the tile's moved links, its first
-  // link's offset from the tile's first link, and the amount it sends
+  // per node of the tile (node order): position of its first moved link
+  // among the tile's moved links, offset of its first link from the tile's
+  // first link, and the amount it sends along each link
   __shared__ int32_t s_off[kWinTile];
   __shared__ int32_t s_rel[kWinTile];
   __shared__ T s_snd[kWinTile];
-  __shared__ int s_wtot[NW];
+  __shared__ int s_wtot[2 * NW];
   __shared__ double s_r;
   __shared__ int s_done, s_cyc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = gridDim.x;
   const int nhub = (int)(S.nhubs < K ? S.nhubs : K);
+  const bool add = !first && !folded;
+  const int l0 = 4 * tid;  // the thread's first node in the tile
+
+  // a tile's loads: kept fluid, far accumulator, history, node words, the
+  // halo values of the tile's first and last W nodes, the tile's first link
+  T raw[4], av[4], hv[4], hl[4], hr[4];
+  uint32_t w[4], wn[4];
+  int64_t ebase = 0;
+  int nh = 0;
+  auto load_tile = [&](int64_t tile) {
+    const int64_t i0 = tile * kWinTile + l0;
+    load4(S.F, i0, S.n, raw);
+    load4(S.info, i0, S.n, w);
+    load4(S.wp_near, i0, S.n, wn);
+    load4(S.H, i0, S.n, hv);
+    ebase = S.row_ptr[tile * kWinTile];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) av[m] = hl[m] = hr[m] = (T)0;
+    if (add) {
+      load4(S.A_cur, i0, S.n, av);
+      if (l0 < W && tile > 0) load4(S.halo_cur, (tile - 1) * 2 * W + W + l0, INT64_MAX, hl);
+      if (l0 >= kWinTile - W && tile + 1 < S.ntiles)
+        load4(S.halo_cur, (tile + 1) * 2 * W + (l0 - (kWinTile - W)), INT64_MAX, hr);
+    }
+    for (int q = tid; q < WIN; q += BLOCK) s_win[q] = (T)0;
+    nh = tile_hubs<T, BLOCK>(S, tile, G, add, s_hnode, s_hadd);
+  };
+
+  int64_t tile = blockIdx.x;
+  load_tile(tile);
+  for (int k = tid; k < nhub; k += BLOCK) s_hub[k] = (T)0;
 
   // the last cycle's records, folded in one order by every block
   Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
   for (int p = tid; p < nrec_in; p += BLOCK) part_add(v, rec_in[p]);
   Ctl c0;
   if (tid == 0) c0 = ctl[parity];
-  for (int k = tid; k < nhub; k += BLOCK) s_hub[k] = (T)0;
   v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
   if (tid == 0) {
     const Ctl c = next_ctl(c0, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
@@ -191,113 +272,117 @@ __global__ __launch_bounds__(BLOCK) void k_wcycle(
   // node (the power iteration's cost)
   const int mode = s_cyc;
   const double rl = s_r / (double)S.L;
-  const bool add = !first && !folded;
 
   double my_keep = 0.0, my_push = 0.0, my_e = 0.0;
   unsigned long long my_ops = 0;
   unsigned int my_sel = 0, my_front = 0;
 
-  for (int64_t tile = blockIdx.x; tile < S.ntiles; tile += G) {
+  for (;;) {
     const int64_t a = tile * kWinTile;
+    const int64_t i0 = a + l0;
     const int64_t win0 = a - W;
-    for (int q = tid; q < WIN; q += BLOCK) s_win[q] = (T)0;
-    const int nh = tile_hubs<T, BLOCK>(S, tile, G, add, s_hnode, s_hadd);
-    __syncthreads();
-    T raw[M], keep[M], snd[M];
-    uint32_t w[M], wn[M];
-    const int64_t ebase = S.row_ptr[a];  // the tile's first link
+    // fluid at the cycle's start: kept + far accumulator + halos + hubs
+    T fv[4], keep[4], snd[4];
+    double t[4];
+    int deg[4], np[4];
+    bool sel[4];
+    bool any_a = false, any_sel = false;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int64_t i = a + tid + (int64_t)m * BLOCK;
-      const bool in = i < S.n;
-      raw[m] = in ? S.F[i] : (T)0;
-      w[m] = in ? S.info[i] : 0u;
-      wn[m] = in ? S.wp_near[i] : 0u;
-    }
-    double t[M];
-    bool sel[M];
-    int np[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int64_t i = a + tid + (int64_t)m * BLOCK;
-      const int li = tid + m * BLOCK;
-      T fv = raw[m];
-      if (add && i < S.n) fv = start_value(S, fv, i, tile, li, wn[m], s_hnode, s_hadd, nh);
-      const double f = to_d(fv);
+    for (int m = 0; m < 4; ++m) {
+      const int64_t i = i0 + m;
+      fv[m] = raw[m];
+      if (add && i < S.n) {
+        if (av[m] != (T)0) {
+          fv[m] = fv[m] + av[m];
+          any_a = true;
+        }
+        if (l0 < W && tile > 0) fv[m] = fv[m] + hl[m];
+        if (l0 >= kWinTile - W && tile + 1 < S.ntiles) fv[m] = fv[m] + hr[m];
+        if (wn[m] & kHubBit) {
+          int lo = 0, hi = nh - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_hnode[mid] < i) lo = mid + 1;
+            else hi = mid;
+          }
+          fv[m] = fv[m] + s_hadd[lo];
+        }
+      }
+      const double f = to_d(fv[m]);
       const int out = (int)(w[m] & kOutMask);
       const bool loop = (w[m] & kLoopBit) != 0;
+      deg[m] = out - (loop ? 1 : 0);
       const double af = fabs(f);
       const double thr = (mode != 0 || out == 0) ? 0.0 : rl * (double)out;
       sel[m] = i < S.n && (mode == 2 || (af > 0.0 && af >= thr));
       np[m] = 0;
       t[m] = 0.0;
       snd[m] = (T)0;
-      keep[m] = fv;
+      keep[m] = fv[m];
       if (sel[m]) {
+        any_sel = true;
         t[m] = loop ? f * (double)out / ((double)out - d) : f;
         keep[m] = (T)0;
+        hv[m] = (T)(to_d(hv[m]) + t[m]);
         ++my_sel;
         if (out == 0) {
           my_e += t[m];
-        } else {
-          const int npush = out - (loop ? 1 : 0);
-          if (npush > 0) {
-            np[m] = npush;
-            snd[m] = (T)(t[m] * d / (double)out);
-            my_ops += (unsigned long long)npush;
-            ++my_front;
-            my_push += to_d(snd[m]) * (double)npush;
-          }
+        } else if (deg[m] > 0) {
+          np[m] = deg[m];
+          snd[m] = (T)(t[m] * d / (double)out);
+          my_ops += (unsigned long long)np[m];
+          ++my_front;
+          my_push += to_d(snd[m]) * (double)np[m];
         }
       }
       my_keep += to_d(keep[m]);
     }
-    // the history and the senders' link offsets, loaded together
-    T hv[M];
-    int64_t e0[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int64_t i = a + tid + (int64_t)m * BLOCK;
-      hv[m] = sel[m] ? S.H[i] : (T)0;
-      e0[m] = np[m] > 0 ? S.row_ptr[i] : 0;
+    // the far accumulator entries read are cleared; the history of the
+    // diffused nodes
+    if (any_a) {
+      const T zero[4] = {(T)0, (T)0, (T)0, (T)0};
+      store4(S.A_cur, i0, S.n, zero);
     }
+    if (any_sel) store4(S.H, i0, S.n, hv);
+    // block scans of the link counts (node order): every node's first link
+    // relative to the tile's first link, and each sender's position among
+    // the tile's moved links
+    int dsum = 0, nsum = 0;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int64_t i = a + tid + (int64_t)m * BLOCK;
-      if (sel[m]) S.H[i] = (T)(to_d(hv[m]) + t[m]);
+    for (int m = 0; m < 4; ++m) {
+      dsum += deg[m];
+      nsum += np[m];
     }
-    // push, parallel over the tile's moved links: a block scan of the
-    // senders' link counts gives each slot the position of its first link;
-    // thread tid moves links tid, tid + BLOCK, ... (the slot of a link by
-    // binary search over the positions: the last slot starting at or before
-    // it, which has links), kUnroll link loads in flight at a time
-    int cnt = 0;
-#pragma unroll
-    for (int m = 0; m < M; ++m) cnt += np[m];
-    int incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int v = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += v;
+    int dinc = dsum, ninc = nsum;
+    wave_scan2(dinc, ninc);
+    if (lane == 63) {
+      s_wtot[wave] = dinc;
+      s_wtot[NW + wave] = ninc;
     }
-    if (lane == 63) s_wtot[wave] = incl;
     __syncthreads();
-    int pos = incl - cnt, total = 0;
+    int dpos = dinc - dsum, npos = ninc - nsum, total = 0;
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
-      const int x = s_wtot[q];
-      if (q < wave) pos += x;
-      total += x;
+      const int x = s_wtot[q], y = s_wtot[NW + q];
+      if (q < wave) {
+        dpos += x;
+        npos += y;
+      }
+      total += y;
     }
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int k = tid * M + m;
-      s_off[k] = pos;
-      s_rel[k] = (int32_t)(e0[m] - ebase);
-      s_snd[k] = snd[m];
-      pos += np[m];
+    for (int m = 0; m < 4; ++m) {
+      s_off[l0 + m] = npos;
+      s_rel[l0 + m] = dpos;
+      s_snd[l0 + m] = snd[m];
+      dpos += deg[m];
+      npos += np[m];
     }
     __syncthreads();
+    // push, parallel over the tile's moved links: thread tid moves links
+    // tid, tid + BLOCK, ..., each found by binary search over the senders'
+    // positions (the last node starting at or before it, which has links),
+    // kUnroll link loads in flight at a time
     for (int q0 = tid; q0 < total; q0 += kUnroll * BLOCK) {
       int32_t code[kUnroll];
       int slot[kUnroll];
@@ -319,29 +404,26 @@ __global__ __launch_bounds__(BLOCK) void k_wcycle(
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
-        if (slot[u] >= 0) {
-          const int k = slot[u];
-          const int64_t i = a + k / M + (int64_t)(k % M) * BLOCK;
-          push_link(S, code[u], i, win0, s_snd[k], s_win, s_hub);
-        }
+        if (slot[u] >= 0) push_link(S, code[u], a + slot[u], win0, s_snd[slot[u]], s_win, s_hub);
     }
     __syncthreads();
     // kept fluid plus the tile's own near pushes; the halos for the
     // neighbours
+    T nv[4];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int64_t i = a + tid + (int64_t)m * BLOCK;
-      if (i < S.n) {
-        const T nv = keep[m] + s_win[W + tid + m * BLOCK];
-        if (nv != raw[m]) S.F[i] = nv;
-      }
-    }
+    for (int m = 0; m < 4; ++m) nv[m] = keep[m] + s_win[W + l0 + m];
+    store4(S.F, i0, S.n, nv);
     for (int q = tid; q < W; q += BLOCK) {
       S.halo_next[tile * 2 * W + q] = s_win[q];
       S.halo_next[tile * 2 * W + W + q] = s_win[W + kWinTile + q];
     }
-    __syncthreads();  // the window is cleared by the next tile
+    tile += G;
+    if (tile >= S.ntiles) break;
+    __syncthreads();  // the window and the hub ids are reused
+    load_tile(tile);
+    __syncthreads();
   }
+  __syncthreads();  // the hub accumulators are complete
   for (int k = tid; k < nhub; k += BLOCK) S.hub_next[(int64_t)blockIdx.x * K + k] = s_hub[k];
   Part rec{my_keep + my_push, my_keep + my_push, my_e, my_ops, my_sel, my_front};
   rec = block_sum_part(rec, s_part);
@@ -393,14 +475,14 @@ __global__ __launch_bounds__(BLOCK) void k_wfold(WinState<T> S, Part* __restrict
   }
 }
 
-// F = B (or the uniform value), H = 0, both far accumulators (2n values) 0,
+// F = B (or the uniform value), H = 0, both far accumulators (stride sa) 0,
 // and per-block sums of |F| and F.
 template <typename T>
 __global__ __launch_bounds__(kReduceBlock) void k_wstart(T* __restrict__ F, T* __restrict__ H,
                                                          T* __restrict__ A2,
                                                          const double* __restrict__ B,
-                                                         double b_uniform, int64_t n, int state,
-                                                         Part* __restrict__ blk_part) {
+                                                         double b_uniform, int64_t n, int64_t sa,
+                                                         int state, Part* __restrict__ blk_part) {
   __shared__ Part lds[kReduceBlock / 64];
   Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -414,7 +496,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_wstart(T* __restrict__ F, T* _
       H[i] = (T)0;
     }
     A2[i] = (T)0;
-    A2[n + i] = (T)0;
+    A2[sa + i] = (T)0;
     v.pabs += fabs(to_d(f));
     v.psum += to_d(f);
   }
@@ -456,8 +538,8 @@ WinState<T> win_state(const CycleArgs& a, int parity) {
   S.F = (T*)ws->F;
   S.H = (T*)ws->H;
   T* A = (T*)ws->wA;
-  S.A_cur = A + (int64_t)parity * n;
-  S.A_next = A + (int64_t)(parity ^ 1) * n;
+  S.A_cur = A + (int64_t)parity * win_stride(n);
+  S.A_next = A + (int64_t)(parity ^ 1) * win_stride(n);
   T* halo = (T*)ws->whalo;
   const int64_t hsz = g->n_wtiles * 2 * W;
   S.halo_cur = halo + (int64_t)parity * hsz;
@@ -479,8 +561,8 @@ int win_grid(const di_graph* g) {
 template <typename T>
 hipError_t launch_wstart(const CycleArgs& a, const double* B, double b_uniform) {
   hipLaunchKernelGGL(k_wstart<T>, dim3(part_count(a)), dim3(kReduceBlock), 0, a.stream,
-                     (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, B, b_uniform, a.g->n, 0,
-                     a.ws->blk_part);
+                     (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, B, b_uniform, a.g->n,
+                     win_stride(a.g->n), 0, a.ws->blk_part);
   return hipGetLastError();
 }
 
@@ -488,7 +570,7 @@ template <typename T>
 hipError_t launch_wstart_state(const CycleArgs& a) {
   hipLaunchKernelGGL(k_wstart<T>, dim3(part_count(a)), dim3(kReduceBlock), 0, a.stream,
                      (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, (const double*)nullptr, 0.0,
-                     a.g->n, 1, a.ws->blk_part);
+                     a.g->n, win_stride(a.g->n), 1, a.ws->blk_part);
   return hipGetLastError();
 }
 

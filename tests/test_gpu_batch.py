@@ -204,3 +204,37 @@ def test_batch_edge_cases(torch_cuda):
     o.kernel = di.DI_KERNEL_PUSH
     status, _, _ = di.di_solve_batch(g.handle, 1, None, D, [1e-9], o)
     assert status == di.DI_E_INVAL
+
+
+def test_batch_k256_fp32_refine_at_1m(torch_cuda):
+    """The widest batched shape of the benchmark: k = 256 personalized
+    columns on the N = 1M graph in FP32 with FP64 residual passes (the float
+    256-column kernels). Every column's residual, recomputed by the oracle,
+    is within tol; eight columns (both ends of each 128-column half and four
+    others) are within tol/(1-d) of oracle solves."""
+    torch = torch_cuda
+    n, k, tol = 1_000_000, 256, 1e-9
+    src, dst = web(n)
+    og = oracle.Graph(n, src, dst)
+    g = di.Graph(n, src, dst)
+    B = ppr_matrix(n, k)
+    print(f"batch k={k} n={n} fp32+refine", flush=True)
+    Bd = torch.from_numpy(B).cuda()
+    Xd = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    o = di.di_opts_default()
+    o.precision = di.DI_FP32_REFINE
+    status, st = di.di_solve_batch_dev(g.handle, k, Bd, D, np.full(k, tol), o, Xd)
+    assert status == di.DI_OK, di.di_last_error()
+    torch.cuda.synchronize()
+    del Bd
+    print("batch k=256: residuals", flush=True)
+    for c in range(k):
+        Xc = Xd[c].cpu().numpy()
+        _, r = oracle.residual(og, B[c], D, Xc)
+        assert r <= tol, (c, r)
+        assert abs(r - st[c].resid_l1) <= 1e-14 + 1e-6 * tol, (c, r, st[c].resid_l1)
+    print("batch k=256: oracle solves", flush=True)
+    for c in (0, 1, 127, 128, 129, 200, 254, 255):
+        ref = oracle_x(og, B[c])
+        assert np.abs(Xd[c].cpu().numpy() - ref).sum() <= tol / (1 - D) + 1e-12, c
+    g.close()

@@ -259,6 +259,36 @@ def test_fp32_fluid(torch_cuda, kernel):
     assert np.abs(X - X_ref).sum() <= 2e-6 * X_ref.sum()
 
 
+@pytest.mark.parametrize("kernel", [di.DI_KERNEL_PULL, di.DI_KERNEL_WINDOW])
+def test_fp32_fluid_at_1m(torch_cuda, kernel):
+    """Plain FP32 fluid at the benchmark size: within 2e-6 |X|_1 of the
+    oracle's FP64 solution."""
+    n = 1_000_000
+    src, dst = web(n)
+    B = graphgen.uniform_rhs(n, D)
+    og, X_ref = oracle_ref(n, src, dst, B)
+    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), None, tol=1e-7, precision=di.DI_FP32,
+                         kernel=kernel)
+    assert np.abs(X - X_ref).sum() <= 2e-6 * X_ref.sum()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_paper_stop_same_cycle_as_oracle_sync(torch_cuda, kernel):
+    """The paper's stop rule (sum F / (1 - d - d e) <= 1/N, Section 2.5.4):
+    the GPU stops on the same cycle as the oracle's frontier-synchronous run
+    and reports the same estimate to rounding."""
+    n = 10000
+    src, dst = web(n)
+    B = graphgen.uniform_rhs(n, D)
+    og = oracle.Graph(n, src, dst)
+    _, _, so = oracle.diter(og, B, D, oracle.SOP, oracle.SYNC, stop=oracle.STOP_PAPER, tol=1.0 / n)
+    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), None, tol=1.0 / n,
+                         stop=di.DI_STOP_PAPER, kernel=kernel)
+    assert st.cycles == so.cycles
+    assert abs(st.paper_err - so.paper_err) <= 1e-12 * so.paper_err
+    assert abs(st.e - so.e) <= 1e-12 * so.e
+
+
 def test_cyc_method_and_paper_stop(torch_cuda):
     n = 10000
     src, dst = web(n)
