@@ -87,10 +87,15 @@ enum { DI_STOP_RESID = 0, DI_STOP_PAPER = 1 };
 /* di_opts.flags */
 #define DI_FLAG_KERNEL_TIMING 1u /* time every pull/push launch with HIP events */
 #define DI_FLAG_SERVE_NO_SOLO 2u /* serving: a lone request also runs in a column set */
+#define DI_FLAG_NO_TUNE 4u       /* DI_KERNEL_AUTO: the default window configuration,
+                                    without timing candidates on a first solve */
 
 /* di_opts.kernel: how a cycle moves the claimed fluid along the links */
 enum {
-  DI_KERNEL_AUTO = 0, /* the library's choice (currently DI_KERNEL_PULL) */
+  DI_KERNEL_AUTO = 0, /* the library's choice: DI_KERNEL_WINDOW for DI_SOP (with
+                         the graph's tuned configuration, see di_graph_tuning),
+                         DI_KERNEL_PULL for DI_CYC and DI_PI, whose cycles
+                         move nearly every link */
   DI_KERNEL_PULL = 1, /* every node sums what its in-links send (CSC);
                          no atomics, bit-reproducible */
   DI_KERNEL_PUSH = 2, /* every diffused node adds to its out-neighbours
@@ -181,6 +186,22 @@ void di_opts_default(di_opts* opts);
  * split). Arrays are host memory; they are copied. */
 di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                           uint32_t flags, di_graph** out);
+
+/* The window-push configuration of a graph (DI_KERNEL_WINDOW, and
+ * DI_KERNEL_AUTO for DI_SOP): *tile nodes per tile (1024, 2048 or 4096),
+ * *hubs active hub rows (far links into the nodes with the most far
+ * in-links, summed per block in LDS; at most 1024), *grid the largest
+ * number of blocks. *tuned is 1 once the tuner has picked it and 0 for the
+ * default configuration. The tuner runs on the graph's first DI_KERNEL_AUTO
+ * DI-SOP solve (unless DI_FLAG_NO_TUNE): it times ten cycles of the
+ * PageRank right-hand side per candidate (the three tile shapes, then hub
+ * counts, then smaller grids) and keeps the fastest; a graph of the same
+ * n, L and largest in- and out-degree reuses the process's earlier choice.
+ * *us_default and *us_tuned receive its measured time per cycle of the
+ * default and of the chosen configuration (0 before tuning). Any output
+ * pointer may be NULL. */
+di_status di_graph_tuning(const di_graph* g, int32_t* tile, int32_t* hubs, int32_t* grid,
+                          int32_t* tuned, double* us_default, double* us_tuned);
 
 /* Frees the graph and its device memory. NULL is ignored. */
 void di_graph_destroy(di_graph* g);

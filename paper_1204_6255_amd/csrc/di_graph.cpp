@@ -52,8 +52,12 @@ void free_graph_device(di_graph* g) {
   void* ptrs[] = {g->row_ptr, g->col,    g->info,   g->csc_ptr,  g->csc_idx, g->row_lo,
                   g->it_r0,   g->it_r1,  g->it_l0,  g->it_l1,    g->it_seg,  g->heavy_row,
                   g->heavy_seg, g->hc_seg0, g->hc_seg1, g->hc_off, g->seg_heavy,
-                  g->wp_col,  g->wp_near, g->hub_node, g->hub_tile};
+                  g->wp_col,  g->wp_near, g->hub_rank_node, g->hub_id_node, g->hub_id_rank};
   for (void* p : ptrs) (void)hipFree(p);
+  for (int sh = 0; sh < di::kWinShapes; ++sh) {
+    (void)hipFree(g->hub_tile[sh]);
+    g->hub_tile[sh] = nullptr;
+  }
   g->row_ptr = nullptr;
   g->col = nullptr;
   g->info = nullptr;
@@ -68,8 +72,7 @@ void free_graph_device(di_graph* g) {
   g->seg_heavy = nullptr;
   g->wp_col = nullptr;
   g->wp_near = nullptr;
-  g->hub_node = nullptr;
-  g->hub_tile = nullptr;
+  g->hub_rank_node = g->hub_id_node = g->hub_id_rank = nullptr;
 }
 
 
@@ -91,9 +94,8 @@ di_status upload(V** dst, const std::vector<V>& src) {
 
 // Window-push layout (di_window.hip): each row's out-links with the near
 // links (|i - j| <= kWinHalo) first and the far links after them, a far link
-// into a hub row coded -1 - slot; the hubs are the nodes with the most far
-// in-links (at least kWinHubMinFar; ties to the lower id), at most kWinHubs,
-// slots ascending by id.
+// into a ranked hub coded -1 - rank. Hubs are ranked by far in-links (at
+// least kWinHubMinFar, ties to the lower id), at most kWinHubMax of them.
 di_status build_window(di_graph* g, const std::vector<int64_t>& row_ptr,
                        const std::vector<int32_t>& col) {
   const int64_t n = g->n;
@@ -111,19 +113,19 @@ di_status build_window(di_graph* g, const std::vector<int64_t>& row_ptr,
         ++farin[j];
       }
     }
-  std::vector<int32_t> hubs;
+  std::vector<int32_t> ranked;
   for (int64_t j = 0; j < n; ++j)
-    if (farin[j] >= di::kWinHubMinFar) hubs.push_back((int32_t)j);
-  if ((int64_t)hubs.size() > di::kWinHubs) {
-    std::nth_element(hubs.begin(), hubs.begin() + di::kWinHubs, hubs.end(),
-                     [&](int32_t x, int32_t y) {
-                       return farin[x] != farin[y] ? farin[x] > farin[y] : x < y;
-                     });
-    hubs.resize(di::kWinHubs);
+    if (farin[j] >= di::kWinHubMinFar) ranked.push_back((int32_t)j);
+  auto by_far = [&](int32_t x, int32_t y) {
+    return farin[x] != farin[y] ? farin[x] > farin[y] : x < y;
+  };
+  if ((int64_t)ranked.size() > di::kWinHubMax) {
+    std::nth_element(ranked.begin(), ranked.begin() + di::kWinHubMax, ranked.end(), by_far);
+    ranked.resize(di::kWinHubMax);
   }
-  std::sort(hubs.begin(), hubs.end());
-  std::vector<int32_t> slot((size_t)n, -1);
-  for (size_t k = 0; k < hubs.size(); ++k) slot[(size_t)hubs[k]] = (int32_t)k;
+  std::sort(ranked.begin(), ranked.end(), by_far);
+  std::vector<int32_t> rank((size_t)n, -1);
+  for (size_t r = 0; r < ranked.size(); ++r) rank[(size_t)ranked[r]] = (int32_t)r;
   std::vector<int32_t> wcol(col.size());
   std::vector<uint32_t> wnear((size_t)n, 0);
   for (int64_t i = 0; i < n; ++i) {
@@ -135,27 +137,37 @@ di_status build_window(di_graph* g, const std::vector<int64_t>& row_ptr,
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
       const int64_t j = col[e];
       if (!(j - i <= W && i - j <= W))
-        wcol[(size_t)q++] = slot[(size_t)j] >= 0 ? -1 - slot[(size_t)j] : (int32_t)j;
+        wcol[(size_t)q++] = rank[(size_t)j] >= 0 ? -1 - rank[(size_t)j] : (int32_t)j;
     }
-    wnear[(size_t)i] = nnear[(size_t)i] | (slot[(size_t)i] >= 0 ? di::kHubBit : 0u);
+    wnear[(size_t)i] = nnear[(size_t)i] | (rank[(size_t)i] >= 0 ? di::kHubBit : 0u);
   }
-  const int64_t ntiles = (n + di::kWinTile - 1) / di::kWinTile;
-  std::vector<int32_t> htile((size_t)ntiles + 1, 0);
-  for (int32_t h : hubs) htile[(size_t)(h / di::kWinTile) + 1] += 1;
-  for (int64_t t = 0; t < ntiles; ++t) htile[(size_t)t + 1] += htile[(size_t)t];
-  // the window kernel keeps a tile's link offsets in 32 bits
-  g->window_ok = true;
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const int64_t a = t * di::kWinTile, b = std::min<int64_t>(a + di::kWinTile, n);
-    if (row_ptr[(size_t)b] - row_ptr[(size_t)a] >= (int64_t(1) << 31)) g->window_ok = false;
-  }
-  g->n_hubs = (int64_t)hubs.size();
-  g->n_wtiles = ntiles;
+  std::vector<int32_t> id_node(ranked.begin(), ranked.end());
+  std::sort(id_node.begin(), id_node.end());
+  std::vector<int32_t> id_rank(id_node.size());
+  for (size_t k = 0; k < id_node.size(); ++k) id_rank[k] = rank[(size_t)id_node[k]];
+  g->n_hubs = (int64_t)ranked.size();
   g->near_links = near_links;
   di_status st = upload(&g->wp_col, wcol);
   if (st == DI_OK) st = upload(&g->wp_near, wnear);
-  if (st == DI_OK) st = upload(&g->hub_node, hubs);
-  if (st == DI_OK) st = upload(&g->hub_tile, htile);
+  if (st == DI_OK) st = upload(&g->hub_rank_node, ranked);
+  if (st == DI_OK) st = upload(&g->hub_id_node, id_node);
+  if (st == DI_OK) st = upload(&g->hub_id_rank, id_rank);
+  for (int sh = 0; sh < di::kWinShapes && st == DI_OK; ++sh) {
+    const int64_t T = di::kWinTileOf[sh];
+    const int64_t ntiles = (n + T - 1) / T;
+    std::vector<int32_t> htile((size_t)ntiles + 1, 0);
+    for (int32_t h : id_node) htile[(size_t)(h / T) + 1] += 1;
+    for (int64_t t = 0; t < ntiles; ++t) htile[(size_t)t + 1] += htile[(size_t)t];
+    // the window kernel keeps a tile's link offsets in 32 bits
+    bool ok = true;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      const int64_t a = t * T, b = std::min<int64_t>(a + T, n);
+      if (row_ptr[(size_t)b] - row_ptr[(size_t)a] >= (int64_t(1) << 31)) ok = false;
+    }
+    g->n_wtiles[sh] = ntiles;
+    g->window_ok[sh] = ok;
+    st = upload(&g->hub_tile[sh], htile);
+  }
   return st;
 }
 

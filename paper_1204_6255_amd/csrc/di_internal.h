@@ -61,31 +61,30 @@ constexpr uint32_t kOutMask = 0x3fffffffu;
 constexpr int kHeavyLds = 4096;
 constexpr int kHeavyChunkSegs = 16;   // segment sums per completion chunk
 
-// Window push (the default move): one launch per cycle selects the nodes of
-// a tile of kWinTile consecutive ids, claims them and pushes their links.
-// A link i -> j is "near" when |i - j| <= kWinHalo: it lands in the tile's
-// LDS window [a - kWinHalo, a + kWinTile + kWinHalo); the parts of the
-// window outside the tile (the halos) are handed to the neighbouring tiles'
-// next cycle. A far link goes to one of the kWinHubs hub rows (the nodes
-// with the most far in-links, accumulated per block in LDS) or else, by a
-// device-scope atomic, to the far accumulator of the next cycle.
-#ifndef DI_WIN_BLOCK
-#define DI_WIN_BLOCK 512
-#endif
-#ifndef DI_WIN_PER_THREAD
-#define DI_WIN_PER_THREAD 4
-#endif
-#ifndef DI_WIN_GRID
-#define DI_WIN_GRID 1024
-#endif
-constexpr int kWinBlock = DI_WIN_BLOCK;
-constexpr int kWinPerThread = DI_WIN_PER_THREAD;
-constexpr int kWinTile = kWinBlock * kWinPerThread;
+// Window push: one launch per cycle selects the nodes of a tile of
+// consecutive ids (four per thread), claims them and pushes their links. A
+// link i -> j is "near" when |i - j| <= kWinHalo: it lands in the tile's LDS
+// window [a - kWinHalo, a + tile + kWinHalo); the parts of the window outside
+// the tile (the halos) are handed to the neighbouring tiles' next cycle. A
+// far link into one of the first `hubs` hub rows (the nodes ranked by their
+// far in-links) is accumulated per block in LDS; any other far link is a
+// device-scope atomic into the far accumulator of the next cycle.
+constexpr int kWinShapes = 3;  // tile shapes: 256, 512 or 1024 threads, 4 nodes each
+constexpr int kWinTileOf[kWinShapes] = {1024, 2048, 4096};
 constexpr int kWinHalo = 512;
-constexpr int kWinHubs = 1024;
-constexpr int kWinMaxGrid = DI_WIN_GRID;  // blocks (grid-stride over tiles)
-constexpr int kWinHubMinFar = 16;  // far in-links a node needs to be a hub
-static_assert(kWinHalo <= kWinTile, "a near link must land in the tile or a neighbour");
+constexpr int kWinHubMax = 1024;   // hub rows ranked per graph
+constexpr int kWinMaxGrid = 1024;  // blocks (grid-stride over tiles)
+constexpr int kWinHubMinFar = 16;  // far in-links a node needs to be ranked
+static_assert(kWinHalo <= 1024, "a near link must land in the tile or a neighbour");
+
+// A window configuration: tile shape, active hub rows (<= the graph's
+// ranked hubs) and the largest grid.
+struct WinCfg {
+  int shape = 1;
+  int hubs = 256;
+  int grid_cap = kWinMaxGrid;
+};
+
 // stride of the two far-accumulator copies (whole 256-byte lines, so that
 // both copies take aligned vector accesses)
 inline int64_t win_stride(int64_t n) { return (n + 63) & ~int64_t(63); }
@@ -168,7 +167,7 @@ struct Workspace {
   double* hacc = nullptr;
   // window push: far accumulators (two copies by parity, n values each),
   // halos (two copies, per tile 2 * kWinHalo values: left then right), hub
-  // partials (two copies, per block kWinHubs values) and per-block records
+  // partials (two copies, per block kWinHubMax values) and per-block records
   // (two copies); all of the fluid type except the records
   void* wA = nullptr;
   void* whalo = nullptr;
@@ -226,16 +225,24 @@ struct di_graph {
   int32_t* seg_heavy = nullptr;   // n_segs: the heavy row (index) of each segment
   // window push: out-links per row (offsets row_ptr) with the near links
   // (|i - j| <= kWinHalo, ids) first and the far links after them (ids, or
-  // -1 - slot for a hub); wp_near per node (near count | kHubBit); hub ids
-  // ascending (slot = index) and the slots of each window tile
+  // -1 - r for the hub of rank r); wp_near per node (near count | kHubBit);
+  // the ranked hubs: node of each rank, and the hubs by ascending id (node,
+  // rank) with, per tile shape, each tile's range of them
   int32_t* wp_col = nullptr;
   uint32_t* wp_near = nullptr;
   int64_t n_hubs = 0;
-  int32_t* hub_node = nullptr;
-  int32_t* hub_tile = nullptr;   // n_wtiles + 1
-  int64_t n_wtiles = 0;
+  int32_t* hub_rank_node = nullptr;  // n_hubs
+  int32_t* hub_id_node = nullptr;    // n_hubs, ascending
+  int32_t* hub_id_rank = nullptr;    // n_hubs
+  int32_t* hub_tile[di::kWinShapes] = {};  // n_wtiles[s] + 1 each
+  int64_t n_wtiles[di::kWinShapes] = {};
+  bool window_ok[di::kWinShapes] = {};     // every tile's links fit 32-bit offsets
   int64_t near_links = 0;        // near links (statistics)
-  bool window_ok = false;        // every tile's links fit 32-bit offsets
+  // the window configuration picked by the tuner (tuned: it has run), and
+  // its measured time per cycle next to the default configuration's
+  bool win_tuned = false;
+  di::WinCfg win_cfg;
+  double win_us_default = 0.0, win_us_tuned = 0.0;
   int32_t* heavy_row = nullptr;   // n_heavy, ascending
   int64_t* heavy_seg = nullptr;   // n_heavy + 1: segment range of each
   // completion chunks: chunk k sums segments [hc_seg0[k], hc_seg1[k]) of one
@@ -292,6 +299,7 @@ struct CycleArgs {
   int direction;   // kPull, kPush or kWindow
   int folded;      // kWindow: the fluid may be signed, so a fold pass after
                    // every cycle gathers it into F and sums |F| exactly
+  WinCfg wcfg;     // kWindow: tile shape, active hubs, largest grid
   hipStream_t stream;
   di_cycle_rec* trace;  // device records of this run's cycles (or null)
   int trace_cap;        // records it has room for
@@ -330,7 +338,7 @@ hipError_t launch_h_to_x(const CycleArgs& a, double* X);
 // pushes into parity (c + 1) & 1. Without `folded` the next r is summed from
 // the kept and pushed amounts (exact for a fluid that stays >= 0); with it a
 // fold pass after each cycle gathers the fluid into F and sums |F|.
-int win_grid(const di_graph* g);
+int win_grid(const di_graph* g, const WinCfg& c);
 // F = B (or the uniform value), H = 0, both far accumulators 0, and the
 // start records (part_count(a) + 1 of them) in blk_part.
 template <typename T>

@@ -13,8 +13,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 
 #include "di_internal.h"
 
@@ -105,10 +107,11 @@ di_status ensure_push_buffers(const di_graph* g, Workspace* ws) {
 di_status ensure_window_buffers(const di_graph* g, Workspace* ws) {
   if (ws->wA) return DI_OK;
   const size_t s = ws->prec == kF64 ? sizeof(double) : sizeof(float);
-  const size_t G = (size_t)win_grid(g);
-  DI_TRY(dmalloc(&ws->whalo, 2 * (size_t)std::max<int64_t>(g->n_wtiles, 1) * 2 * kWinHalo * s));
-  DI_TRY(dmalloc(&ws->whub, 2 * G * kWinHubs * s));
-  DI_TRY(dmalloc((void**)&ws->wrec, 2 * G * sizeof(Part)));
+  // sized for every configuration: the smallest tile (most halos), the
+  // largest grid and hub count
+  DI_TRY(dmalloc(&ws->whalo, 2 * (size_t)std::max<int64_t>(g->n_wtiles[0], 1) * 2 * kWinHalo * s));
+  DI_TRY(dmalloc(&ws->whub, 2 * (size_t)kWinMaxGrid * kWinHubMax * s));
+  DI_TRY(dmalloc((void**)&ws->wrec, 2 * (size_t)kWinMaxGrid * sizeof(Part)));
   DI_TRY(dmalloc((void**)&ws->wflag, sizeof(int)));
   if (!ws->host_flag) {
     hipError_t err = hipHostMalloc((void**)&ws->host_flag, sizeof(int), hipHostMallocDefault);
@@ -429,6 +432,152 @@ int direction_of(const di_opts& o) {
   return kPull;
 }
 
+// ---- window configuration and its tuner ------------------------------------
+
+// The default window configuration: 2048-node tiles, up to 256 active hubs,
+// the largest grid (a smaller tile when the graph needs it).
+WinCfg default_window_cfg(const di_graph* g) {
+  WinCfg c;
+  c.shape = 1;
+  if (!g->window_ok[c.shape])
+    for (int sh = 0; sh < kWinShapes; ++sh)
+      if (g->window_ok[sh]) c.shape = sh;
+  c.hubs = (int)std::min<int64_t>(256, g->n_hubs);
+  c.grid_cap = kWinMaxGrid;
+  return c;
+}
+
+// The graph's window configuration: the tuned one, else the default.
+WinCfg window_cfg(const di_graph* gc) {
+  di_graph* g = const_cast<di_graph*>(gc);
+  std::lock_guard<std::mutex> lock(g->mu);
+  return g->win_tuned ? g->win_cfg : default_window_cfg(g);
+}
+
+bool window_usable(const di_graph* g) {
+  for (int sh = 0; sh < kWinShapes; ++sh)
+    if (g->window_ok[sh]) return true;
+  return false;
+}
+
+// Configurations already tuned in this process, by graph shape.
+using TuneKey = std::tuple<int64_t, int64_t, int64_t, int64_t>;
+struct TuneEntry {
+  WinCfg cfg;
+  double us_default, us_tuned;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry>& tune_cache() {
+  static std::map<TuneKey, TuneEntry> m;
+  return m;
+}
+
+constexpr int kTuneCycles = 10;  // timed cycles per candidate
+
+// Time per cycle of one window configuration: kTuneCycles DI-SOP cycles
+// from the PageRank right-hand side (after one untimed cycle), timed with
+// events on the solve's stream. Leaves the workspace's state undefined.
+template <typename T>
+di_status time_window_cfg(di_graph* g, Workspace* ws, hipStream_t stream, double d,
+                          const WinCfg& c, double* us) {
+  CycleArgs a{};
+  a.g = g;
+  a.ws = ws;
+  a.d = d;
+  a.tol = 0.0;
+  a.tol_in = 0.0;
+  a.tol_rel = -1.0;
+  a.method = DI_SOP;
+  a.stop = DI_STOP_RESID;
+  a.max_cycles = kTuneCycles + 2;
+  a.direction = kWindow;
+  a.stream = stream;
+  a.first_parts = part_count(a) + 1;
+  a.wcfg = c;
+  DI_TRY(ensure_events(ws, 2));
+  DI_HIP(launch_reset_ctl(a));
+  DI_HIP(launch_wstart<T>(a, nullptr, (1.0 - d) / (double)g->n));
+  DI_HIP(launch_wcycle<T>(a, 0, nullptr, nullptr));
+  DI_HIP(hipEventRecord(ws->events[0], stream));
+  for (int cyc = 1; cyc <= kTuneCycles; ++cyc) DI_HIP(launch_wcycle<T>(a, cyc, nullptr, nullptr));
+  DI_HIP(hipEventRecord(ws->events[1], stream));
+  DI_HIP(hipEventSynchronize(ws->events[1]));
+  float ms = 0.f;
+  DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
+  *us = 1e3 * ms / kTuneCycles;
+  return DI_OK;
+}
+
+// Picks the graph's window configuration by timing candidates, greedily:
+// the tile shapes at the default hub count, then the hub counts at the best
+// shape, then smaller grids; or takes the choice made for a graph of the
+// same shape (n, L, largest in- and out-degree) earlier in the process.
+template <typename T>
+di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) {
+  {
+    std::lock_guard<std::mutex> lock(g->mu);
+    if (g->win_tuned) return DI_OK;
+  }
+  const TuneKey key{g->n, g->L, g->max_in, g->max_out};
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      std::lock_guard<std::mutex> lock2(g->mu);
+      g->win_cfg = it->second.cfg;
+      g->win_us_default = it->second.us_default;
+      g->win_us_tuned = it->second.us_tuned;
+      g->win_tuned = true;
+      return DI_OK;
+    }
+  }
+  const WinCfg def = default_window_cfg(g);
+  WinCfg best = def;
+  double best_us = 0.0, def_us = 0.0;
+  DI_TRY(time_window_cfg<T>(g, ws, stream, d, def, &def_us));
+  best_us = def_us;
+  auto consider = [&](const WinCfg& c) -> di_status {
+    double us = 0.0;
+    DI_TRY(time_window_cfg<T>(g, ws, stream, d, c, &us));
+    if (us < best_us) {
+      best_us = us;
+      best = c;
+    }
+    return DI_OK;
+  };
+  for (int sh = 0; sh < kWinShapes; ++sh)
+    if (sh != def.shape && g->window_ok[sh]) {
+      WinCfg c = def;
+      c.shape = sh;
+      DI_TRY(consider(c));
+    }
+  const WinCfg shaped = best;
+  for (int h : {0, 64, 128, 512, 1024}) {
+    const int hh = (int)std::min<int64_t>(h, g->n_hubs);
+    if (hh == shaped.hubs) continue;
+    WinCfg c = shaped;
+    c.hubs = hh;
+    DI_TRY(consider(c));
+  }
+  const WinCfg hubbed = best;
+  for (int cap : {256, 512})
+    if (cap < g->n_wtiles[hubbed.shape]) {
+      WinCfg c = hubbed;
+      c.grid_cap = cap;
+      DI_TRY(consider(c));
+    }
+  {
+    std::lock_guard<std::mutex> lock(g->mu);
+    g->win_cfg = best;
+    g->win_us_default = def_us;
+    g->win_us_tuned = best_us;
+    g->win_tuned = true;
+  }
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_cache()[key] = TuneEntry{best, def_us, best_us};
+  return DI_OK;
+}
+
 constexpr int kMaxRefinements = 100;
 
 // Adds the counters of one run (control block h) to the totals.
@@ -554,7 +703,8 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   const bool timing = (o.flags & DI_FLAG_KERNEL_TIMING) != 0;
   const double b_uniform = (1.0 - d) / (double)g->n;
   const bool window = a.direction == kWindow;
-  if (window && !g->window_ok) {
+  if (window) a.wcfg = window_cfg(g);
+  if (window && !g->window_ok[a.wcfg.shape]) {
     set_error("the window push needs every tile of the graph to hold fewer than 2^31 links");
     return DI_E_INVAL;
   }
@@ -576,7 +726,7 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   // is gathered into F and its residual summed exactly
   auto window_finish = [&](const Ctl& h, double* r_exact) -> di_status {
     DI_HIP(launch_wfinal<T>(a, h.cycles & 1, (!a.folded && h.cycles > 0) ? 1 : 0));
-    return residual_norm(a, win_grid(g), r_exact, nullptr);
+    return residual_norm(a, win_grid(g, a.wcfg), r_exact, nullptr);
   };
   auto elapsed = [&](double* sec) -> di_status {
     DI_HIP(hipEventRecord(ws->events[1], stream));
@@ -617,7 +767,7 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
       if (h.done == 1 && a.stop == DI_STOP_RESID && r_exact > tol && restarts < 4 &&
           tot.cycles < max_cycles) {
         ++restarts;
-        a.first_parts = win_grid(g);
+        a.first_parts = win_grid(g, a.wcfg);
         DI_HIP(launch_reset_ctl(a));
         continue;
       }
@@ -713,6 +863,21 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
   if (X_on_host) {
     if (!ws->X64) DI_TRY(dmalloc((void**)&ws->X64, nbytes));
     X_dev = ws->X64;
+  }
+  // DI_KERNEL_AUTO: DI-SOP moves a small share of the links each cycle, so it
+  // takes the window push (tuned on the graph's first such solve); DI-CYC and
+  // the power iteration move nearly every link every cycle and take the pull
+  if (o.kernel == DI_KERNEL_AUTO && o.method != DI_GS_ASYNC) {
+    if (o.method == DI_SOP && window_usable(g)) {
+      o.kernel = DI_KERNEL_WINDOW;
+      if (!(o.flags & DI_FLAG_NO_TUNE)) {
+        DI_TRY(ensure_window_buffers(g, ws));
+        DI_TRY(prec == kF64 ? tune_window<double>(g, ws, stream, d)
+                            : tune_window<float>(g, ws, stream, d));
+      }
+    } else {
+      o.kernel = DI_KERNEL_PULL;
+    }
   }
   if (trace_cap > ws->trace_cap) {
     if (ws->trace) (void)hipFree(ws->trace);
@@ -991,6 +1156,24 @@ di_status di_cycles_dev(const di_graph* g, double d, int32_t method, double* F_d
 di_status di_residual_dev(const di_graph* g, const double* B_dev, double d, const double* X_dev,
                           double* R_dev, double* l1, void* stream) {
   return di::guarded([&] { return di::residual_dev(g, B_dev, d, X_dev, R_dev, l1, stream); });
+}
+
+di_status di_graph_tuning(const di_graph* gc, int32_t* tile, int32_t* hubs, int32_t* grid,
+                          int32_t* tuned, double* us_default, double* us_tuned) {
+  if (!gc) {
+    di::set_error("di_graph_tuning: graph is NULL");
+    return DI_E_INVAL;
+  }
+  di_graph* g = const_cast<di_graph*>(gc);
+  const di::WinCfg c = di::window_cfg(g);
+  std::lock_guard<std::mutex> lock(g->mu);
+  if (tile) *tile = di::kWinTileOf[c.shape];
+  if (hubs) *hubs = c.hubs;
+  if (grid) *grid = di::win_grid(g, c);
+  if (tuned) *tuned = g->win_tuned ? 1 : 0;
+  if (us_default) *us_default = g->win_us_default;
+  if (us_tuned) *us_tuned = g->win_us_tuned;
+  return DI_OK;
 }
 
 }  // extern "C"

@@ -5,7 +5,7 @@
 // of the fluid at the cycle's start, every node with |F_i| >= (r/L) out_i,
 // claims it (Section 2.5.4: H_i += transit, the fluid leaves F_i, a dangling
 // node absorbs it) and pushes transit * d / out_i along each out-link j != i.
-// Here one block owns a tile of kWinTile consecutive node ids and does all
+// Here one block owns a tile of consecutive node ids and does all
 // of that for its tile in one launch:
 //   - the fluid of node i at the cycle's start is F_i (what the node kept,
 //     plus what its own tile pushed to it) + the far accumulator A_i (far
@@ -13,7 +13,7 @@
 //     their halos (near links across a tile boundary) + for a hub row the
 //     block partials of the previous launch (far links into the hubs);
 //   - near links (|i - j| <= kWinHalo) are added into the tile's LDS window
-//     [a - kWinHalo, a + kWinTile + kWinHalo) with LDS atomics; the window's
+//     [a - kWinHalo, a + tile + kWinHalo) with LDS atomics; the window's
 //     middle goes straight to F, its two halos to the neighbours' next cycle;
 //   - far links into one of the graph's hub rows (the nodes with the most
 //     far in-links) are added into per-block LDS accumulators, written out
@@ -45,8 +45,7 @@ namespace {
 using namespace dev;
 
 constexpr int W = kWinHalo;
-constexpr int K = kWinHubs;
-constexpr int WIN = kWinTile + 2 * kWinHalo;
+constexpr int KMAX = kWinHubMax;
 constexpr int kUnroll = 4;  // links in flight per thread in the push
 
 __device__ inline void lds_add(double* p, double v) {
@@ -64,9 +63,12 @@ struct WinState {
   const int64_t* row_ptr;
   const int32_t* wp_col;
   const uint32_t* wp_near;
-  const int32_t* hub_node;
-  const int32_t* hub_tile;
-  int64_t n, L, ntiles, nhubs;
+  const int32_t* hub_rank_node;  // node of each hub rank
+  const int32_t* hub_id_node;    // ranked hubs by ascending id ...
+  const int32_t* hub_id_rank;    // ... and their ranks
+  const int32_t* hub_tile;       // each tile's range of hub_id_*
+  int64_t n, L, ntiles;
+  int K;                         // active hubs: ranks below K
   T* F;
   T* H;
   T* A_cur;           // far accumulator read (and cleared) this cycle
@@ -77,9 +79,11 @@ struct WinState {
   T* hub_next;
 };
 
-// The tile's hub rows: their ids (s_hnode) and, when `add`, what the last
-// launch's G blocks sent them (s_hadd), each summed over the blocks in one
-// order. Returns the number of hubs in the tile.
+// The tile's ranked hubs: their ids ascending (s_hnode) and, when `add`,
+// what the last launch's G blocks sent the active ones (rank below K) in
+// their LDS accumulators (s_hadd; 0 for the others, whose far links went to
+// the far accumulator), each summed over the blocks in one order. Returns
+// the number of ranked hubs in the tile.
 template <typename T, int BLOCK>
 __device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool add,
                                 int32_t* s_hnode, T* s_hadd) {
@@ -87,12 +91,13 @@ __device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool 
   const int h0 = S.hub_tile[tile], h1 = S.hub_tile[tile + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = wave; k < h1 - h0; k += NW) {
+    const int r = S.hub_id_rank[h0 + k];
     double acc = 0.0;
-    if (add)
-      for (int b = lane; b < G; b += 64) acc += to_d(S.hub_cur[(int64_t)b * K + h0 + k]);
+    if (add && r < S.K)
+      for (int b = lane; b < G; b += 64) acc += to_d(S.hub_cur[(int64_t)b * S.K + r]);
     acc = wave_sum(acc);
     if (lane == 0) {
-      s_hnode[k] = S.hub_node[h0 + k];
+      s_hnode[k] = S.hub_id_node[h0 + k];
       s_hadd[k] = (T)acc;
     }
   }
@@ -102,7 +107,7 @@ __device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool 
 // Fluid of node i (position li in its tile) at the cycle's start: kept +
 // far accumulator + halos + hub partials, added in this order. The far
 // accumulator is cleared as it is read.
-template <typename T>
+template <typename T, int TILE>
 __device__ inline T start_value(const WinState<T>& S, T f, int64_t i, int64_t tile, int li,
                                 uint32_t wn, const int32_t* s_hnode, const T* s_hadd, int nh) {
   const T av = S.A_cur[i];
@@ -111,8 +116,8 @@ __device__ inline T start_value(const WinState<T>& S, T f, int64_t i, int64_t ti
     S.A_cur[i] = (T)0;
   }
   if (li < W && tile > 0) f = f + S.halo_cur[(tile - 1) * 2 * W + W + li];
-  if (li >= kWinTile - W && tile + 1 < S.ntiles)
-    f = f + S.halo_cur[(tile + 1) * 2 * W + (li - (kWinTile - W))];
+  if (li >= TILE - W && tile + 1 < S.ntiles)
+    f = f + S.halo_cur[(tile + 1) * 2 * W + (li - (TILE - W))];
   if (wn & kHubBit) {
     int lo = 0, hi = nh - 1;
     while (lo < hi) {
@@ -125,15 +130,21 @@ __device__ inline T start_value(const WinState<T>& S, T f, int64_t i, int64_t ti
   return f;
 }
 
-// One link i -> code of a push: hub links (code < 0) into the block's hub
-// accumulators, near links (|code - i| <= W) into the window, other far
-// links into the next far accumulator.
+// One link i -> code of a push: links into an active hub (code = -1 - r,
+// r < K) into the block's hub accumulators, near links (|code - i| <= W)
+// into the window, other far links into the next far accumulator.
 template <typename T>
 __device__ inline void push_link(const WinState<T>& S, int32_t code, int64_t i, int64_t win0, T s,
                                  T* s_win, T* s_hub) {
-  if (code < 0) lds_add(&s_hub[-1 - code], s);
-  else if (code - i <= W && i - code <= W) lds_add(&s_win[code - win0], s);
-  else atomic_add(&S.A_next[code], s);
+  if (code < 0) {
+    const int r = -1 - code;
+    if (r < S.K) lds_add(&s_hub[r], s);
+    else atomic_add(&S.A_next[S.hub_rank_node[r]], s);
+  } else if (code - i <= W && i - code <= W) {
+    lds_add(&s_win[code - win0], s);
+  } else {
+    atomic_add(&S.A_next[code], s);
+  }
 }
 
 // Four consecutive values of a node array, as one vector access when all
@@ -190,32 +201,34 @@ __device__ inline void wave_scan2(int& x, int& y) {
 // fluid (a fold pass ran after the last cycle).
 // At least four waves per SIMD (at most 128 VGPRs): two 512-thread blocks
 // per compute unit.
-template <typename T, int BLOCK, int M>
+template <typename T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_wcycle(
     WinState<T> S, const Part* __restrict__ rec_in, int nrec_in, Part* __restrict__ rec_out,
     Ctl* __restrict__ ctl, int parity, int first, int folded, double d, double tol,
     double tol_in, double tol_rel, int method, int stop, int max_cycles,
     di_cycle_rec* __restrict__ trace, int trace_cap) {
-  static_assert(M == 4 && BLOCK * M == kWinTile, "tile shape: four nodes per thread");
+  constexpr int TILE = 4 * BLOCK;  // four nodes per thread
+  constexpr int WIN = TILE + 2 * W;
+  static_assert(W <= TILE, "a near link lands in the tile or a neighbour");
   static_assert(W % 4 == 0, "halo in whole quads");
   constexpr int NW = BLOCK / 64;
   __shared__ T s_win[WIN];
-  __shared__ T s_hub[K];
-  __shared__ T s_hadd[K];
-  __shared__ int32_t s_hnode[K];
+  __shared__ T s_hub[KMAX];
+  __shared__ T s_hadd[KMAX];
+  __shared__ int32_t s_hnode[KMAX];
   __shared__ Part s_part[NW];
   // per node of the tile (node order): position of its first moved link
   // among the tile's moved links, offset of its first link from the tile's
   // first link, and the amount it sends along each link
-  __shared__ int32_t s_off[kWinTile];
-  __shared__ int32_t s_rel[kWinTile];
-  __shared__ T s_snd[kWinTile];
+  __shared__ int32_t s_off[TILE];
+  __shared__ int32_t s_rel[TILE];
+  __shared__ T s_snd[TILE];
   __shared__ int s_wtot[2 * NW];
   __shared__ double s_r;
   __shared__ int s_done, s_cyc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = gridDim.x;
-  const int nhub = (int)(S.nhubs < K ? S.nhubs : K);
+  const int nhub = S.K;
   const bool add = !first && !folded;
   const int l0 = 4 * tid;  // the thread's first node in the tile
 
@@ -226,19 +239,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   int64_t ebase = 0;
   int nh = 0;
   auto load_tile = [&](int64_t tile) {
-    const int64_t i0 = tile * kWinTile + l0;
+    const int64_t i0 = tile * TILE + l0;
     load4(S.F, i0, S.n, raw);
     load4(S.info, i0, S.n, w);
     load4(S.wp_near, i0, S.n, wn);
     load4(S.H, i0, S.n, hv);
-    ebase = S.row_ptr[tile * kWinTile];
+    ebase = S.row_ptr[tile * TILE];
 #pragma unroll
     for (int m = 0; m < 4; ++m) av[m] = hl[m] = hr[m] = (T)0;
     if (add) {
       load4(S.A_cur, i0, S.n, av);
       if (l0 < W && tile > 0) load4(S.halo_cur, (tile - 1) * 2 * W + W + l0, INT64_MAX, hl);
-      if (l0 >= kWinTile - W && tile + 1 < S.ntiles)
-        load4(S.halo_cur, (tile + 1) * 2 * W + (l0 - (kWinTile - W)), INT64_MAX, hr);
+      if (l0 >= TILE - W && tile + 1 < S.ntiles)
+        load4(S.halo_cur, (tile + 1) * 2 * W + (l0 - (TILE - W)), INT64_MAX, hr);
     }
     for (int q = tid; q < WIN; q += BLOCK) s_win[q] = (T)0;
     nh = tile_hubs<T, BLOCK>(S, tile, G, add, s_hnode, s_hadd);
@@ -278,7 +291,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   unsigned int my_sel = 0, my_front = 0;
 
   for (;;) {
-    const int64_t a = tile * kWinTile;
+    const int64_t a = tile * TILE;
     const int64_t i0 = a + l0;
     const int64_t win0 = a - W;
     // fluid at the cycle's start: kept + far accumulator + halos + hubs
@@ -297,7 +310,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
           any_a = true;
         }
         if (l0 < W && tile > 0) fv[m] = fv[m] + hl[m];
-        if (l0 >= kWinTile - W && tile + 1 < S.ntiles) fv[m] = fv[m] + hr[m];
+        if (l0 >= TILE - W && tile + 1 < S.ntiles) fv[m] = fv[m] + hr[m];
         if (wn[m] & kHubBit) {
           int lo = 0, hi = nh - 1;
           while (lo < hi) {
@@ -392,7 +405,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         slot[u] = -1;
         code[u] = 0;
         if (q < total) {
-          int lo = 0, hi = kWinTile - 1;
+          int lo = 0, hi = TILE - 1;
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_off[mid] <= q) lo = mid;
@@ -415,7 +428,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     store4(S.F, i0, S.n, nv);
     for (int q = tid; q < W; q += BLOCK) {
       S.halo_next[tile * 2 * W + q] = s_win[q];
-      S.halo_next[tile * 2 * W + W + q] = s_win[W + kWinTile + q];
+      S.halo_next[tile * 2 * W + W + q] = s_win[W + TILE + q];
     }
     tile += G;
     if (tile >= S.ntiles) break;
@@ -424,7 +437,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     __syncthreads();
   }
   __syncthreads();  // the hub accumulators are complete
-  for (int k = tid; k < nhub; k += BLOCK) S.hub_next[(int64_t)blockIdx.x * K + k] = s_hub[k];
+  for (int k = tid; k < nhub; k += BLOCK) S.hub_next[(int64_t)blockIdx.x * nhub + k] = s_hub[k];
   Part rec{my_keep + my_push, my_keep + my_push, my_e, my_ops, my_sel, my_front};
   rec = block_sum_part(rec, s_part);
   if (tid == 0) rec_out[blockIdx.x] = rec;
@@ -435,19 +448,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // sums of |F| and F of the block's tiles into rec[blockIdx.x] (the other
 // fields of the record are kept). Returns at once when ctl says the solve
 // has stopped (ctl may be null).
-template <typename T, int BLOCK, int M>
+template <typename T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_wfold(WinState<T> S, Part* __restrict__ rec, int add,
                                                  const Ctl* __restrict__ ctl) {
   constexpr int NW = BLOCK / 64;
-  __shared__ T s_hadd[K];
-  __shared__ int32_t s_hnode[K];
+  constexpr int M = 4, TILE = 4 * BLOCK;
+  __shared__ T s_hadd[KMAX];
+  __shared__ int32_t s_hnode[KMAX];
   __shared__ double s_red[NW];
   if (ctl && ctl->done) return;
   const int tid = threadIdx.x;
   const int G = gridDim.x;
   double pabs = 0.0, psum = 0.0;
   for (int64_t tile = blockIdx.x; tile < S.ntiles; tile += G) {
-    const int64_t a = tile * kWinTile;
+    const int64_t a = tile * TILE;
     int nh = 0;
     if (add) nh = tile_hubs<T, BLOCK>(S, tile, G, true, s_hnode, s_hadd);
     __syncthreads();
@@ -458,7 +472,8 @@ __global__ __launch_bounds__(BLOCK) void k_wfold(WinState<T> S, Part* __restrict
         const T raw = S.F[i];
         T fv = raw;
         if (add) {
-          fv = start_value(S, fv, i, tile, tid + m * BLOCK, S.wp_near[i], s_hnode, s_hadd, nh);
+          fv = start_value<T, TILE>(S, fv, i, tile, tid + m * BLOCK, S.wp_near[i], s_hnode, s_hadd,
+                                    nh);
           if (fv != raw) S.F[i] = fv;
         }
         pabs += fabs(to_d(fv));
@@ -522,40 +537,83 @@ template <typename T>
 WinState<T> win_state(const CycleArgs& a, int parity) {
   const di_graph* g = a.g;
   Workspace* ws = a.ws;
-  const int G = win_grid(g);
+  const int sh = a.wcfg.shape;
   const int64_t n = g->n;
   WinState<T> S;
   S.info = g->info;
   S.row_ptr = g->row_ptr;
   S.wp_col = g->wp_col;
   S.wp_near = g->wp_near;
-  S.hub_node = g->hub_node;
-  S.hub_tile = g->hub_tile;
+  S.hub_rank_node = g->hub_rank_node;
+  S.hub_id_node = g->hub_id_node;
+  S.hub_id_rank = g->hub_id_rank;
+  S.hub_tile = g->hub_tile[sh];
   S.n = n;
   S.L = g->L;
-  S.ntiles = g->n_wtiles;
-  S.nhubs = g->n_hubs;
+  S.ntiles = g->n_wtiles[sh];
+  S.K = a.wcfg.hubs;
   S.F = (T*)ws->F;
   S.H = (T*)ws->H;
   T* A = (T*)ws->wA;
   S.A_cur = A + (int64_t)parity * win_stride(n);
   S.A_next = A + (int64_t)(parity ^ 1) * win_stride(n);
+  // halos and hub partials: copies sized for the smallest tile and the
+  // largest grid and hub count
   T* halo = (T*)ws->whalo;
-  const int64_t hsz = g->n_wtiles * 2 * W;
+  const int64_t hsz = g->n_wtiles[0] * 2 * W;
   S.halo_cur = halo + (int64_t)parity * hsz;
   S.halo_next = halo + (int64_t)(parity ^ 1) * hsz;
   T* hub = (T*)ws->whub;
-  const int64_t bsz = (int64_t)G * K;
+  const int64_t bsz = (int64_t)kWinMaxGrid * KMAX;
   S.hub_cur = hub + (int64_t)parity * bsz;
   S.hub_next = hub + (int64_t)(parity ^ 1) * bsz;
   return S;
 }
 
+// Launches kernel template K<T, BLOCK> for the configuration's tile shape.
+template <template <typename, int> class L, typename T, typename... Args>
+hipError_t by_shape(const WinCfg& c, Args&&... args) {
+  switch (c.shape) {
+    case 0: return L<T, 256>::run(args...);
+    case 1: return L<T, 512>::run(args...);
+    default: return L<T, 1024>::run(args...);
+  }
+}
+
+template <typename T, int BLOCK>
+struct CycleLaunch {
+  static hipError_t run(const CycleArgs& a, int G, hipEvent_t ev0, hipEvent_t ev1,
+                        const WinState<T>& S, const Part* rec_in, int nrec_in, Part* rec_out,
+                        int parity, int first, int folded) {
+    auto kern = k_wcycle<T, BLOCK>;
+    if (ev0 || ev1)
+      hipExtLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), 0, a.stream, ev0, ev1, 0u, S, rec_in,
+                            nrec_in, rec_out, a.ws->ctl, parity, first, folded, a.d, a.tol,
+                            a.tol_in, a.tol_rel, a.method, a.stop, a.max_cycles, a.trace,
+                            a.trace_cap);
+    else
+      hipLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), 0, a.stream, S, rec_in, nrec_in, rec_out,
+                         a.ws->ctl, parity, first, folded, a.d, a.tol, a.tol_in, a.tol_rel,
+                         a.method, a.stop, a.max_cycles, a.trace, a.trace_cap);
+    return hipGetLastError();
+  }
+};
+
+template <typename T, int BLOCK>
+struct FoldLaunch {
+  static hipError_t run(const CycleArgs& a, int G, const WinState<T>& S, Part* rec, int add,
+                        const Ctl* ctl) {
+    hipLaunchKernelGGL((k_wfold<T, BLOCK>), dim3(G), dim3(BLOCK), 0, a.stream, S, rec, add, ctl);
+    return hipGetLastError();
+  }
+};
+
 }  // namespace
 
-int win_grid(const di_graph* g) {
-  const int64_t t = g->n_wtiles < 1 ? 1 : g->n_wtiles;
-  return (int)(t < kWinMaxGrid ? t : kWinMaxGrid);
+int win_grid(const di_graph* g, const WinCfg& c) {
+  const int64_t t = g->n_wtiles[c.shape] < 1 ? 1 : g->n_wtiles[c.shape];
+  const int64_t cap = c.grid_cap < 1 ? 1 : (c.grid_cap > kWinMaxGrid ? kWinMaxGrid : c.grid_cap);
+  return (int)(t < cap ? t : cap);
 }
 
 template <typename T>
@@ -576,41 +634,29 @@ hipError_t launch_wstart_state(const CycleArgs& a) {
 
 template <typename T>
 hipError_t launch_wcycle(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1) {
-  const di_graph* g = a.g;
   Workspace* ws = a.ws;
-  const int G = win_grid(g);
+  const int G = win_grid(a.g, a.wcfg);
   const int parity = cycle & 1;
   const int first = cycle == 0;
   const WinState<T> S = win_state<T>(a, parity);
-  const Part* rec_in = first ? ws->blk_part : ws->wrec + (int64_t)parity * G;
+  const Part* rec_in = first ? ws->blk_part : ws->wrec + (int64_t)parity * kWinMaxGrid;
   const int nrec_in = first ? a.first_parts : G;
-  Part* rec_out = ws->wrec + (int64_t)(parity ^ 1) * G;
+  Part* rec_out = ws->wrec + (int64_t)(parity ^ 1) * kWinMaxGrid;
   const int folded = a.folded ? 1 : 0;
-  auto kern = k_wcycle<T, kWinBlock, kWinPerThread>;
-  if (ev0 || ev1)
-    hipExtLaunchKernelGGL(kern, dim3(G), dim3(kWinBlock), 0, a.stream, ev0, ev1, 0u, S, rec_in,
-                          nrec_in, rec_out, ws->ctl, parity, first, folded, a.d, a.tol, a.tol_in,
-                          a.tol_rel, a.method, a.stop, a.max_cycles, a.trace, a.trace_cap);
-  else
-    hipLaunchKernelGGL(kern, dim3(G), dim3(kWinBlock), 0, a.stream, S, rec_in, nrec_in, rec_out,
-                       ws->ctl, parity, first, folded, a.d, a.tol, a.tol_in, a.tol_rel, a.method,
-                       a.stop, a.max_cycles, a.trace, a.trace_cap);
-  hipError_t err = hipGetLastError();
+  hipError_t err = by_shape<CycleLaunch, T>(a.wcfg, a, G, ev0, ev1, S, rec_in, nrec_in, rec_out,
+                                             parity, first, folded);
   if (err != hipSuccess || !a.folded) return err;
   // a signed fluid: gather it into F and sum |F| before the next selection
   const WinState<T> Sn = win_state<T>(a, parity ^ 1);
-  hipLaunchKernelGGL((k_wfold<T, kWinBlock, kWinPerThread>), dim3(G), dim3(kWinBlock), 0,
-                     a.stream, Sn, rec_out, 1, (const Ctl*)(ws->ctl + (parity ^ 1)));
-  return hipGetLastError();
+  return by_shape<FoldLaunch, T>(a.wcfg, a, G, Sn, rec_out, 1,
+                                 (const Ctl*)(ws->ctl + (parity ^ 1)));
 }
 
 template <typename T>
 hipError_t launch_wfinal(const CycleArgs& a, int parity, int add) {
-  const int G = win_grid(a.g);
+  const int G = win_grid(a.g, a.wcfg);
   const WinState<T> S = win_state<T>(a, parity);
-  hipLaunchKernelGGL((k_wfold<T, kWinBlock, kWinPerThread>), dim3(G), dim3(kWinBlock), 0,
-                     a.stream, S, a.ws->blk_part, add, (const Ctl*)nullptr);
-  return hipGetLastError();
+  return by_shape<FoldLaunch, T>(a.wcfg, a, G, S, a.ws->blk_part, add, (const Ctl*)nullptr);
 }
 
 hipError_t launch_any_negative(const double* B, int64_t n, int* flag, hipStream_t stream) {

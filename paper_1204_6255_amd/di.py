@@ -27,6 +27,7 @@ DI_FP64, DI_FP32_REFINE, DI_FP32 = 0, 1, 2
 DI_STOP_RESID, DI_STOP_PAPER = 0, 1
 DI_FLAG_KERNEL_TIMING = 1
 DI_FLAG_SERVE_NO_SOLO = 2
+DI_FLAG_NO_TUNE = 4
 DI_KERNEL_AUTO, DI_KERNEL_PULL, DI_KERNEL_PUSH, DI_KERNEL_WINDOW = 0, 1, 2, 3
 
 STATUS_NAMES = {
@@ -136,6 +137,8 @@ def lib():
     L.di_cycles_dev.restype = i32
     L.di_residual_dev.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
     L.di_residual_dev.restype = i32
+    L.di_graph_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(dbl), P(dbl)]
+    L.di_graph_tuning.restype = i32
     L.di_serve_create.argtypes = [ctypes.c_size_t, i32, P(di_opts), P(vp)]
     L.di_serve_create.restype = i32
     L.di_serve_add_graph.argtypes = [vp, vp, i32]
@@ -270,6 +273,16 @@ def di_cycles_dev(h, d: float, method: int, F_dev, H_dev, cycles: int, e: float 
                                  ctypes.byref(e_c), stream if stream is not None else _current_stream(),
                                  ctypes.byref(st))
     return status, e_c.value, st
+
+
+def di_graph_tuning(h):
+    """The graph's window configuration: dict(tile, hubs, grid, tuned,
+    us_default, us_tuned)."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    u = [ctypes.c_double() for _ in range(2)]
+    _check(lib().di_graph_tuning(h, *[ctypes.byref(x) for x in v], *[ctypes.byref(x) for x in u]))
+    return {"tile": v[0].value, "hubs": v[1].value, "grid": v[2].value, "tuned": bool(v[3].value),
+            "us_default": u[0].value, "us_tuned": u[1].value}
 
 
 def di_residual_dev(h, B_dev, d: float, X_dev, R_dev=None, stream=None):

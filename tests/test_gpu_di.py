@@ -238,14 +238,22 @@ def test_parity_1m_bench_configuration(torch_cuda):
     X9, st9, _ = gpu_solve(torch_cuda, g, None, tol=1e-9)
     assert st9.resid_l1 <= 1e-9
     assert np.abs(X9 - X_ref).sum() <= st9.err_bound + 1e-12
+    # the default is the tuned window push
+    tun = di.di_graph_tuning(g.handle)
+    assert tun["tuned"] and tun["tile"] in (1024, 2048, 4096) and 0 <= tun["hubs"] <= 1024
+    assert 0 < tun["us_tuned"] <= tun["us_default"]
     # the pull direction is bit-reproducible
-    X2, _, _ = gpu_solve(torch_cuda, g, None)
-    assert np.array_equal(X2, X)
-    # the push direction differs only by the order of atomic additions
+    Xq, stq, _ = gpu_solve(torch_cuda, g, None, kernel=di.DI_KERNEL_PULL)
+    X2, _, _ = gpu_solve(torch_cuda, g, None, kernel=di.DI_KERNEL_PULL)
+    assert np.array_equal(X2, Xq)
+    assert np.abs(Xq - X_ref).sum() <= 1e-9
+    # the push and window directions differ from it only by the order of
+    # atomic additions
+    assert np.abs(X - Xq).sum() <= 1e-12 and st.cycles == stq.cycles
     Xp, stp, _ = gpu_solve(torch_cuda, g, None, kernel=di.DI_KERNEL_PUSH)
     assert np.abs(Xp - X_ref).sum() <= 1e-9
-    assert np.abs(Xp - X).sum() <= 1e-12
-    assert stp.cycles == st.cycles
+    assert np.abs(Xp - Xq).sum() <= 1e-12
+    assert stp.cycles == stq.cycles
 
 
 @pytest.mark.parametrize("kernel", KERNELS)

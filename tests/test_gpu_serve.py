@@ -194,7 +194,9 @@ def test_lone_request_runs_solo(torch_cuda):
     # the same request's FP64 single solve gives the same cycles
     B = graphgen.ppr_rhs(10000, seeds, D)
     X1 = np.empty(10000)
-    status, st1 = di.di_solve(g.handle, B, D, 1e-9, di.di_opts_default(), X1)
+    o1 = di.di_opts_default()
+    o1.kernel = di.DI_KERNEL_PULL
+    status, st1 = di.di_solve(g.handle, B, D, 1e-9, o1, X1)
     assert status == di.DI_OK and st1.cycles == s_solo.cycles
     assert np.array_equal(X1, X_solo)  # same kernels, deterministic pull
     # uniform B through the solo slot

@@ -134,9 +134,10 @@ def test_trace_capacity_prefix(torch_cuda):
     n = 10000
     src, dst = graphgen.web_graph(n, seed=1)
     g = di.Graph(n, src, dst)
-    X_full, st, full = traced(torch_cuda, g, None, 4096)
-    X_part, _, part = traced(torch_cuda, g, None, 7)
-    X_none, st0, none = traced(torch_cuda, g, None, 0)
+    pull = di.DI_KERNEL_PULL
+    X_full, st, full = traced(torch_cuda, g, None, 4096, kernel=pull)
+    X_part, _, part = traced(torch_cuda, g, None, 7, kernel=pull)
+    X_none, st0, none = traced(torch_cuda, g, None, 0, kernel=pull)
     assert len(part) == 7 and none == []
     for a, b in zip(part, full):
         assert (a.r, a.links, a.selected, a.senders) == (b.r, b.links, b.selected, b.senders)
