@@ -360,6 +360,22 @@ void di_serve_destroy(di_server* s);
 di_status di_residual_dev(const di_graph* g, const double* B_dev, double d, const double* X_dev,
                           double* R_dev, double* l1, void* stream);
 
+/* di_residual_dev for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops and harnesses that forbid hipMalloc):
+ * the same pass, arguments and result (|R|_1 bit for bit), with its scratch
+ * (y = d X / out, the heavy-row segment sums, the per-block records and,
+ * when R_dev is NULL, R itself) taken from a fixed 128 MiB device array that
+ * each GPU holds from the first call until the process ends. The call
+ * allocates no device memory.
+ * Limit: 8 n + 8 (heavy-row segments) + about 82 KB of records, plus 8 n
+ * when R_dev is NULL, must fit in 128 MiB (n up to about 16.7M with R_dev,
+ * 8.3M without); a larger graph returns DI_E_INVAL before any device work.
+ * Every call on one GPU uses that GPU's array: calls that overlap on the
+ * same GPU (other host threads, or other streams before this call returns)
+ * race on it and must be serialized by the caller. */
+di_status di_residual_dev_noalloc(const di_graph* g, const double* B_dev, double d,
+                                  const double* X_dev, double* R_dev, double* l1, void* stream);
+
 /* Message describing the calling thread's last failure ("" if none). */
 const char* di_last_error(void);
 

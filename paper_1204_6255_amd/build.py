@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 
 HIP_SOURCES = ["di_kernels.hip", "di_graph.cpp", "di_solve.cpp", "di_batch.hip", "di_batch.cpp", "di_serve.cpp",
-               "di_window.hip"]
+               "di_noalloc.hip", "di_window.hip"]
 ARCH = "gfx950"
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 arithmetic.

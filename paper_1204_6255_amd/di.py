@@ -139,6 +139,8 @@ def lib():
     L.di_residual_dev.restype = i32
     L.di_graph_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(dbl), P(dbl)]
     L.di_graph_tuning.restype = i32
+    L.di_residual_dev_noalloc.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
+    L.di_residual_dev_noalloc.restype = i32
     L.di_serve_create.argtypes = [ctypes.c_size_t, i32, P(di_opts), P(vp)]
     L.di_serve_create.restype = i32
     L.di_serve_add_graph.argtypes = [vp, vp, i32]
@@ -292,6 +294,16 @@ def di_residual_dev(h, B_dev, d: float, X_dev, R_dev=None, stream=None):
     status = lib().di_residual_dev(h, _ptr(B_dev), float(d), _ptr(X_dev), _ptr(R_dev),
                                    ctypes.byref(l1),
                                    stream if stream is not None else _current_stream())
+    return status, l1.value
+
+
+def di_residual_dev_noalloc(h, B_dev, d: float, X_dev, R_dev=None, stream=None):
+    """di_residual_dev without device allocation (its scratch is the
+    library's fixed per-device array). Returns (status, |R|_1)."""
+    l1 = ctypes.c_double(0.0)
+    status = lib().di_residual_dev_noalloc(h, _ptr(B_dev), float(d), _ptr(X_dev), _ptr(R_dev),
+                                           ctypes.byref(l1),
+                                           stream if stream is not None else _current_stream())
     return status, l1.value
 
 
