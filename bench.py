@@ -255,12 +255,14 @@ def fp32_refine_section(di, g, X, d, tol, solutions):
 def methods_section(di, g, X, d, tol, solutions):
     """The paper's method comparison on the GPU, same graph and tolerance:
     DI-SOP, DI-CYC and PI, each moving fluid by the pull (rows gathered, as
-    PI) and by the push (columns scattered, as PI'). PI diffuses every node
-    every cycle, so its history after m + 1 cycles is the power iteration's
-    iterate after m steps, at the power iteration's cost."""
+    PI), by the atomic push (columns scattered, as PI') and by the window
+    push (one launch per cycle, only the moved links read). PI diffuses
+    every node every cycle, so its history after m + 1 cycles is the power
+    iteration's iterate after m steps, at the power iteration's cost."""
     rows = []
     for name, method in (("DI-SOP", di.DI_SOP), ("DI-CYC", di.DI_CYC), ("PI", di.DI_PI)):
-        for kname, kernel in (("pull", di.DI_KERNEL_PULL), ("push", di.DI_KERNEL_PUSH)):
+        for kname, kernel in (("pull", di.DI_KERNEL_PULL), ("push", di.DI_KERNEL_PUSH),
+                              ("window", di.DI_KERNEL_WINDOW)):
             o = di.di_opts_default()
             o.method = method
             o.kernel = kernel
@@ -490,8 +492,11 @@ def serving_section(di, graphgen, d, seconds, kmax):
     status, srv = di.di_serve_create(200 << 30, kmax)
     if status != di.DI_OK:
         raise RuntimeError(di.di_last_error())
+    t0 = time.perf_counter()
     for gid, G in enumerate(graphs):
-        di.di_serve_add_graph(srv, G.handle, gid)
+        if di.di_serve_add_graph(srv, G.handle, gid) != di.DI_OK:
+            raise RuntimeError(di.di_last_error())
+    add_seconds = time.perf_counter() - t0
     bufs = [np.empty(n) for n in Ns]
 
     def request(i):
@@ -511,7 +516,7 @@ def serving_section(di, graphgen, d, seconds, kmax):
             raise RuntimeError(di.di_last_error())
         inflight[tk] = gid
 
-    def reap(inflight, lat):
+    def reap(inflight, lat, parts=None):
         for tk in list(inflight):
             st, sts = di.di_serve_poll(srv, tk, bufs[inflight[tk]])
             if st != di.DI_PENDING:
@@ -519,6 +524,21 @@ def serving_section(di, graphgen, d, seconds, kmax):
                     raise RuntimeError(di.di_last_error())
                 del inflight[tk]
                 lat.append(sts.seconds)
+                if parts is not None:
+                    parts.append((sts.queue_seconds, sts.run_seconds, sts.readout_seconds,
+                                  sts.refinements == 0))
+
+    def breakdown(parts):
+        """The latency split of the requests: waiting for a slot or column,
+        running, reading out (p50 and mean, ms), and the share that ran on
+        the single right-hand side path."""
+        a = np.array([p[:3] for p in parts])
+        out = {}
+        for k, name in enumerate(("queue", "run", "readout")):
+            out[name + "_p50_ms"] = 1e3 * float(np.percentile(a[:, k], 50))
+            out[name + "_mean_ms"] = 1e3 * float(a[:, k].mean())
+        out["single_path_share"] = float(np.mean([p[3] for p in parts]))
+        return out
 
     def drain(inflight):
         while inflight:
@@ -526,24 +546,25 @@ def serving_section(di, graphgen, d, seconds, kmax):
             time.sleep(0.001)
 
     # closed loop: 1024 requests in flight
-    inflight, lat = {}, []
+    inflight, lat, parts = {}, [], []
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
         while len(inflight) < 1024:
             submit(inflight)
-        reap(inflight, lat)
+        reap(inflight, lat, parts)
         time.sleep(0.0005)
     el = time.perf_counter() - t0
     mu = len(lat) / el
     closed = {"in_flight": 1024, "solves_per_s": mu, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-              "p99_ms": 1e3 * float(np.percentile(lat, 99)), "requests": len(lat)}
+              "p99_ms": 1e3 * float(np.percentile(lat, 99)), "requests": len(lat),
+              "breakdown": breakdown(parts)}
     drain(inflight)
     poisson = []
     for frac in (0.5, 0.8):
         lam = frac * mu
         nreq = int(min(10000, lam * seconds))
         arr = np.cumsum(np.random.default_rng(int(frac * 10)).exponential(1.0 / lam, nreq))
-        inflight, lat = {}, []
+        inflight, lat, parts = {}, [], []
         t0 = time.perf_counter()
         q = 0
         while q < nreq or inflight:
@@ -551,30 +572,33 @@ def serving_section(di, graphgen, d, seconds, kmax):
             while q < nreq and arr[q] <= now:
                 submit(inflight)
                 q += 1
-            reap(inflight, lat)
+            reap(inflight, lat, parts)
             time.sleep(0.0002)
         el = time.perf_counter() - t0
         poisson.append({"lambda_per_s": lam, "requests": nreq, "solves_per_s": nreq / el,
                         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-                        "p99_ms": 1e3 * float(np.percentile(lat, 99))})
+                        "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                        "breakdown": breakdown(parts)})
     # idle: one request at a time (each runs alone on its graph); the same
     # requests in every run, whatever the earlier phases submitted
     counter[0] = 20_000_000
-    lat = []
+    lat, parts = [], []
     for i in range(64):
         inflight = {}
         submit(inflight)
         while inflight:
-            reap(inflight, lat)
+            reap(inflight, lat, parts)
             time.sleep(0.0001)
     idle = {"requests": len(lat), "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-            "p99_ms": 1e3 * float(np.percentile(lat, 99))}
+            "p99_ms": 1e3 * float(np.percentile(lat, 99)), "breakdown": breakdown(parts)}
     _, info = di.di_serve_info(srv)
     di.di_serve_destroy(srv)
     for G in graphs:
         G.close()
     return {"graphs": ng, "total_nodes": int(sum(Ns)), "k_max": kmax,
-            "precision": "fp32+fp64 refinement (a request alone: fp64 single path)",
+            "precision": "fp32+fp64 refinement in column sets; fp64 single path in solo slots",
+            "solo_requests": int(info.solo_requests),
+            "add_graphs_s": add_seconds,
             "closed_loop": closed, "poisson": poisson, "idle_one_at_a_time": idle,
             "admission_stalls": int(info.admission_stalls),
             "hbm_bytes_in_use": int(info.bytes_in_use)}
@@ -619,6 +643,11 @@ def main():
     for _ in range(args.warmup):
         solve()
     torch.cuda.synchronize()
+    # what the first DI_KERNEL_AUTO solve tuned: the window configuration,
+    # and whether the pull is faster on this graph
+    tuning = di.di_graph_tuning(g.handle)
+    if args.kernel == "auto":
+        kind = tuning["kernel"]
     t0 = time.perf_counter()
     runs = [solve() for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -691,6 +720,8 @@ def main():
         },
         "cycles": int(last.cycles),
         "nb_iter": float(last.nb_iter),
+        "seconds_to_1e9": float(last.seconds_to_1e9),
+        "tuning": tuning if args.kernel == "auto" else None,
         "gedges_per_s": edges / sec / 1e9,
         "bytes_per_edge": float(last.bytes_moved) / max(float(last.edges_pushed), 1.0),
         "host_arrays_s": pcie_s,

@@ -92,10 +92,10 @@ enum { DI_STOP_RESID = 0, DI_STOP_PAPER = 1 };
 
 /* di_opts.kernel: how a cycle moves the claimed fluid along the links */
 enum {
-  DI_KERNEL_AUTO = 0, /* the library's choice: DI_KERNEL_WINDOW for DI_SOP (with
-                         the graph's tuned configuration, see di_graph_tuning),
-                         DI_KERNEL_PULL for DI_CYC and DI_PI, whose cycles
-                         move nearly every link */
+  DI_KERNEL_AUTO = 0, /* the library's choice: for DI_SOP the faster of the
+                         window push (tuned) and the pull on this graph (see
+                         di_graph_tuning); DI_KERNEL_PULL for DI_CYC and
+                         DI_PI, whose cycles move nearly every link */
   DI_KERNEL_PULL = 1, /* every node sums what its in-links send (CSC);
                          no atomics, bit-reproducible */
   DI_KERNEL_PUSH = 2, /* every diffused node adds to its out-neighbours
@@ -156,6 +156,11 @@ typedef struct di_stats {
                                pass), by the device wall clock; -1 when the
                                solve never got there (or for batched and
                                served solves, which do not record it) */
+  /* served requests only (0 otherwise); seconds is then their latency, the
+     sum of the three and the worker's bookkeeping: */
+  double queue_seconds;     /* submission to the queueing of its start */
+  double run_seconds;       /* start queued to the worker seeing it stop */
+  double readout_seconds;   /* X gathered and copied to the host */
 } di_stats;
 
 /* One cycle of a traced solve (di_solve_trace_dev). */
@@ -187,21 +192,24 @@ void di_opts_default(di_opts* opts);
 di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
                           uint32_t flags, di_graph** out);
 
-/* The window-push configuration of a graph (DI_KERNEL_WINDOW, and
- * DI_KERNEL_AUTO for DI_SOP): *tile nodes per tile (1024, 2048 or 4096),
- * *hubs active hub rows (far links into the nodes with the most far
- * in-links, summed per block in LDS; at most 1024), *grid the largest
- * number of blocks. *tuned is 1 once the tuner has picked it and 0 for the
- * default configuration. The tuner runs on the graph's first DI_KERNEL_AUTO
- * DI-SOP solve (unless DI_FLAG_NO_TUNE): it times ten cycles of the
- * PageRank right-hand side per candidate (the three tile shapes, then hub
- * counts, then smaller grids) and keeps the fastest; a graph of the same
- * n, L and largest in- and out-degree reuses the process's earlier choice.
- * *us_default and *us_tuned receive its measured time per cycle of the
- * default and of the chosen configuration (0 before tuning). Any output
- * pointer may be NULL. */
-di_status di_graph_tuning(const di_graph* g, int32_t* tile, int32_t* hubs, int32_t* grid,
-                          int32_t* tuned, double* us_default, double* us_tuned);
+/* What DI_KERNEL_AUTO runs for DI_SOP on a graph, and the window-push
+ * configuration (also used by DI_KERNEL_WINDOW): *kernel DI_KERNEL_WINDOW or
+ * DI_KERNEL_PULL; *tile nodes per tile (1024, 2048 or 4096), *hubs active
+ * hub rows (far links into the nodes with the most far in-links, summed per
+ * block in LDS; at most 1024), *grid the largest number of blocks. *tuned is
+ * 1 once the tuner has picked them and 0 for the defaults (the window with
+ * 2048-node tiles and 256 hub rows). The tuner runs on the graph's first
+ * DI_KERNEL_AUTO DI-SOP solve (unless DI_FLAG_NO_TUNE): it times ten
+ * cycles of the PageRank right-hand side per candidate (the three tile
+ * shapes, then hub counts, then smaller grids, then the select + pull pair)
+ * and keeps the fastest; a graph of the same n, L and largest in- and
+ * out-degree reuses the process's earlier choice. *us_default, *us_tuned
+ * and *us_pull receive its measured time per cycle of the default window
+ * configuration, of the best one, and of the pull (0 before tuning). Any
+ * output pointer may be NULL. */
+di_status di_graph_tuning(const di_graph* g, int32_t* kernel, int32_t* tile, int32_t* hubs,
+                          int32_t* grid, int32_t* tuned, double* us_default, double* us_tuned,
+                          double* us_pull);
 
 /* Frees the graph and its device memory. NULL is ignored. */
 void di_graph_destroy(di_graph* g);
@@ -294,10 +302,14 @@ di_status di_solve_batch_dev(const di_graph* g, int32_t k, const double* B_dev, 
  *   demand (columns in use plus requests waiting), and a set that no longer
  *   fits the demand drains and is freed once idle. Waiting requests start in
  *   free columns as they free up.
- * - A request that would run alone on its graph takes the graph's solo slot
- *   instead: the single right-hand side path in FP64 (whatever the server's
- *   precision), which finishes a lone request several times sooner than a
- *   column set. DI_FLAG_SERVE_NO_SOLO in opts.flags turns this off.
+ * - While a graph has few requests (running or waiting: at most twice its
+ *   solo slots) they take solo slots instead, up to four per graph: the
+ *   single right-hand side path in FP64 (whatever the server's precision;
+ *   for DI-SOP the graph's tuned window push), which finishes a request
+ *   several times sooner than a column set; the others wait for a free
+ *   slot. Past that demand, new requests go to column sets, which give more
+ *   solves per second. DI_FLAG_SERVE_NO_SOLO in opts.flags turns solo slots
+ *   off.
  * - Sets and solo slots are allocated when the HBM budget allows them; idle
  *   ones of other graphs are released to make room; a request that cannot be
  *   placed waits (an admission stall). Requests with another d wait until
@@ -313,6 +325,7 @@ typedef struct di_serve_stats {
   int64_t pending;          /* requests waiting for a column */
   int64_t bytes_in_use;     /* device bytes held by column sets and solo slots */
   double busy_seconds;      /* worker time spent on work */
+  int64_t solo_requests;    /* requests started in solo slots */
 } di_serve_stats;
 
 /* Creates a server that may hold up to hbm_budget_bytes of column sets and
@@ -325,7 +338,10 @@ di_status di_serve_create(size_t hbm_budget_bytes, int32_t k_max, const di_opts*
                           di_server** out);
 
 /* Registers graph g under graph_id (unique). g must outlive the server.
- * DI_E_NOMEM if the graph's batch alone exceeds the budget. */
+ * DI_E_NOMEM if the graph's batch alone exceeds the budget. For a DI-SOP
+ * server without DI_FLAG_NO_TUNE the graph's window push is tuned here (as
+ * on a first DI_KERNEL_AUTO solve; the call waits for it), so that its solo
+ * slots run the tuned configuration. */
 di_status di_serve_add_graph(di_server* s, const di_graph* g, int32_t graph_id);
 
 /* Queues a request: seeds (host, nseeds ids in [0, n), duplicates ignored;

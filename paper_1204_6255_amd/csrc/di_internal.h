@@ -88,6 +88,13 @@ struct WinCfg {
 // stride of the two far-accumulator copies (whole 256-byte lines, so that
 // both copies take aligned vector accesses)
 inline int64_t win_stride(int64_t n) { return (n + 63) & ~int64_t(63); }
+// rows of one copy of the hub partials: one per block of the largest grid
+// any tile shape can take (the smallest tile has the most tiles)
+inline int64_t win_hub_rows(int64_t tiles_of_smallest_shape) {
+  return tiles_of_smallest_shape < 1 ? 1
+                                     : (tiles_of_smallest_shape < kWinMaxGrid ? tiles_of_smallest_shape
+                                                                              : kWinMaxGrid);
+}
 // wp_near: near-link count in bits 0..30, hub flag in bit 31
 constexpr uint32_t kHubBit = 0x80000000u;
 
@@ -242,7 +249,8 @@ struct di_graph {
   // its measured time per cycle next to the default configuration's
   bool win_tuned = false;
   di::WinCfg win_cfg;
-  double win_us_default = 0.0, win_us_tuned = 0.0;
+  bool win_use_pull = false;  // the tuner found the pull faster on this graph
+  double win_us_default = 0.0, win_us_tuned = 0.0, pull_us = 0.0;
   int32_t* heavy_row = nullptr;   // n_heavy, ascending
   int64_t* heavy_seg = nullptr;   // n_heavy + 1: segment range of each
   // completion chunks: chunk k sums segments [hc_seg0[k], hc_seg1[k]) of one
@@ -363,30 +371,43 @@ hipError_t launch_gs_init(const CycleArgs& a, const double* B, double b_uniform)
 hipError_t launch_gs_sweep(const CycleArgs& a, const double* B, double b_uniform);
 
 // ---- step-driven FP64 solve (di_solve.cpp) ----------------------------------
-// One DI-SOP (or DI-CYC) solve in FP64 with the pull, queued a chunk at a
-// time on the caller's stream so that a caller moving other work (the
-// serving worker) never waits for it:
-//   solo_start queues the start state (F = B, H = 0), the first selection
-//     and the read-back of the control block;
+// One DI-SOP (or DI-CYC) solve in FP64, queued a chunk at a time on the
+// caller's stream so that a caller moving other work (the serving worker)
+// never waits for it. DI-SOP takes the window push (the graph's window
+// configuration) when the graph allows it and allow_window is set (unless
+// the graph's tuning found the pull faster), DI-CYC the select + pull pair.
+//   solo_start queues the start state (F = B, H = 0 with B >= 0), the first
+//     selection and the read-back of the control block;
 //   solo_next, once that work has finished, reads the control block: done
-//     != 0 ends the solve (1 converged, 2 max_cycles, 3 non-finite);
+//     != 0 ends the run (1 converged, 2 max_cycles, 3 non-finite);
 //     otherwise it queues the next chunk of cycles and the read-back;
-//   solo_finish queues X = H and fills the statistics (seconds 0).
-// The workspace is the run's own (not pooled); workspace_bytes is its size.
+//   solo_finish queues X = H and fills the statistics (seconds 0). With the
+//     window push it first gathers the fluid and sums the residual exactly
+//     (waiting for the stream); should rounding leave that sum above tol, it
+//     queues a new run from the gathered fluid instead and sets *again.
+// The workspace is the run's own (not pooled); solo_run_bytes is its size.
 struct SoloRun {
   di_graph* g = nullptr;
   Workspace* ws = nullptr;
   CycleArgs a{};
   int last_sel = 0;
   int chunk = 8;
+  bool window = false;
+  Ctl tot{};         // counters of the runs before a restart
+  int restarts = 0;
+  int max_cycles = 0;
 };
 size_t workspace_bytes(const di_graph* g, int prec);
+size_t solo_run_bytes(const di_graph* g);
 di_status solo_create(di_graph* g, SoloRun** out);
 void solo_destroy(SoloRun* r);
 di_status solo_start(SoloRun* r, const double* B_dev, double b_uniform, double d, double tol,
-                     int method, int max_cycles, hipStream_t stream);
+                     int method, int max_cycles, bool allow_window, hipStream_t stream);
 di_status solo_next(SoloRun* r, int* done);
-di_status solo_finish(SoloRun* r, double* X_dev, di_stats* st);
+// Tunes the graph's window push (once per graph; a no-op when tuned), with
+// an FP64 workspace of the graph's pool and a stream of its own.
+di_status tune_window_f64(di_graph* g, double d);
+di_status solo_finish(SoloRun* r, double* X_dev, di_stats* st, bool* again);
 // FP64 residual pass: with H, first X += H and H = 0; then y = d X / out and
 // R = B + P.X - X (B == nullptr: b_uniform everywhere), written to R_out as
 // T, with the records of sum |R| and sum R in blk_part[0, pull_grid] (the

@@ -18,10 +18,18 @@
 // sets are released to make room; a request that cannot be placed waits (an
 // admission stall).
 //
-// A request that would run alone on its graph (nothing else running or
-// waiting there) takes the graph's solo slot instead: the single right-hand
-// side path in FP64, queued a chunk at a time like a set, which finishes a
-// lone request several times sooner than a column set of eight.
+// While a graph has few requests (running or waiting, at most kSoloDemand)
+// they run in solo slots instead, up to kSoloPerGraph per graph: the single
+// right-hand side path in FP64 (for DI-SOP the graph's tuned window push),
+// each on its own stream and queued a chunk at a time like a set. A set of
+// eight columns costs a whole batched cycle per cycle of any one of them, so
+// a request at light load finishes there many times later than alone; the
+// column sets are for heavy load, where they give more solves per second.
+// Requests that find every solo slot busy wait for one, unless the demand
+// outgrows kSoloDemand.
+//
+// Each request records when its start was queued and when the worker saw it
+// stop, so its latency splits into waiting, running and reading out.
 
 #include <algorithm>
 #include <chrono>
@@ -43,6 +51,8 @@ namespace di {
 namespace {
 
 constexpr int kMaxSetsPerGraph = 64;
+constexpr int kSoloPerGraph = 4;
+constexpr int kSoloDemand = 2 * kSoloPerGraph;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -65,23 +75,36 @@ struct Result {
 struct Lane {
   uint64_t ticket = 0;  // 0: free
   double t_submit = 0.0;
+  double t_start = 0.0;  // its start queued
 };
+
+// The latency split of a finished request (t_seen: the worker saw it stop;
+// t_out: its X is on the host).
+void set_times(di_stats* t, const Lane& ln, double t_seen, double t_out) {
+  t->queue_seconds = ln.t_start - ln.t_submit;
+  t->run_seconds = t_seen - ln.t_start;
+  t->readout_seconds = t_out - t_seen;
+  t->seconds = t_out - ln.t_submit;  // latency: submission to completion
+  t->seconds_to_1e9 = -1.0;          // not recorded for served requests
+}
 
 struct GraphSlot;
 
-// The solo slot of a graph: one request on the single right-hand side path.
+// A solo slot of a graph: one request on the single right-hand side path.
 // `claimed` changes under the server mutex; the rest is the worker's.
 struct Solo {
   SoloRun* run = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;     // end of the queued work
   double* out_dev = nullptr;   // the right-hand side, then X (n doubles)
+  int32_t* d_seeds = nullptr;  // the running request's seeds
+  size_t seeds_cap = 0;
+  std::vector<int32_t> seeds;  // their host copy, kept until the run ends
   size_t bytes = 0;            // counted in the budget while the slot exists
   bool ready = false;          // run, stream, event and out_dev exist
   bool claimed = false;        // a request is placed here (started or not)
   bool launched = false;
   Lane lane;                   // the running request
-  double d = 0.85;
 };
 
 // One batch workspace of a graph. `active` and `d` change under the server
@@ -107,7 +130,7 @@ struct GraphSlot {
   int32_t id = 0;
   std::deque<Request> pending;
   std::vector<ColumnSet*> sets;
-  Solo* solo = nullptr;
+  std::vector<Solo*> solos;
   bool stalled = false;  // counted once per stall episode
 };
 
@@ -126,7 +149,7 @@ struct di_server {
   std::map<int32_t, di::GraphSlot*> graphs;
   std::unordered_map<uint64_t, di::Result> results;
   uint64_t next_ticket = 1;
-  int64_t submitted = 0, completed = 0, stalls = 0;
+  int64_t submitted = 0, completed = 0, stalls = 0, solo_requests = 0;
   double busy_seconds = 0.0;
   std::string worker_error;
   std::thread worker;
@@ -184,7 +207,7 @@ size_t set_bytes(const di_server* s, const di_graph* g, int kp) {
 bool set_idle(const ColumnSet* cs) { return cs->active == 0 && !cs->launched; }
 
 size_t solo_bytes(const di_graph* g) {
-  return workspace_bytes(g, kF64) + (size_t)g->n * sizeof(double);
+  return solo_run_bytes(g) + (size_t)g->n * sizeof(double);
 }
 
 bool solo_idle(const Solo* so) { return so->ready && !so->claimed && !so->launched; }
@@ -214,10 +237,15 @@ bool reserve_bytes(di_server* s, GraphSlot* gs, size_t need, Freed* freed) {
           ++q;
         }
       }
-      if (o->solo && s->in_use + need > s->budget && solo_idle(o->solo)) {
-        s->in_use -= o->solo->bytes;
-        freed->solos.push_back(o->solo);
-        o->solo = nullptr;
+      for (size_t q = 0; q < o->solos.size() && s->in_use + need > s->budget;) {
+        Solo* so = o->solos[q];
+        if (solo_idle(so)) {
+          s->in_use -= so->bytes;
+          freed->solos.push_back(so);
+          o->solos.erase(o->solos.begin() + (long)q);
+        } else {
+          ++q;
+        }
       }
       if (s->in_use + need <= s->budget) break;
     }
@@ -231,6 +259,7 @@ void destroy_solo(Solo* so) {
   if (so->stream) (void)hipStreamSynchronize(so->stream);
   solo_destroy(so->run);
   if (so->out_dev) (void)hipFree(so->out_dev);
+  if (so->d_seeds) (void)hipFree(so->d_seeds);
   if (so->ev) (void)hipEventDestroy(so->ev);
   if (so->stream) (void)hipStreamDestroy(so->stream);
   delete so;
@@ -293,9 +322,10 @@ di_status start_requests(di_server* s, ColumnSet* cs, std::vector<Request>& reqs
   std::vector<int64_t> off{0};
   std::vector<int32_t> seeds;
   int c = 0;
+  const double t_start = now_s();
   for (Request& r : reqs) {
     while (cs->lanes[(size_t)c].ticket != 0) ++c;
-    cs->lanes[(size_t)c] = Lane{r.ticket, r.t_submit};
+    cs->lanes[(size_t)c] = Lane{r.ticket, r.t_submit, t_start};
     flag[(size_t)c] = 1;
     col.push_back(c);
     const double v = r.seeds.empty() ? (1.0 - r.d) / (double)a.g->n
@@ -330,6 +360,7 @@ di_status finish_columns(di_server* s, ColumnSet* cs) {
   const BatchArgs a = args_of(s, cs);
   BatchWs* ws = cs->ws;
   const di_graph* g = a.g;
+  const double t_seen = now_s();
   for (int c = 0; c < cs->kp; ++c) {
     Lane& ln = cs->lanes[(size_t)c];
     const BCtl& b = ws->host_bctl[c];
@@ -358,8 +389,7 @@ di_status finish_columns(di_server* s, ColumnSet* cs) {
     t.resid_l1 = b.final_r;
     t.err_bound = b.final_r / (1.0 - cs->d);
     t.e = b.e;
-    t.seconds = now_s() - ln.t_submit;  // latency: submission to completion
-    t.seconds_to_1e9 = -1.0;            // not recorded for served requests
+    set_times(&t, ln, t_seen, now_s());
     {
       std::lock_guard<std::mutex> lk(s->mu);
       s->results[ln.ticket] = std::move(res);
@@ -386,37 +416,48 @@ di_status create_solo(GraphSlot* gs, Solo* so) {
   return DI_OK;
 }
 
-// Starts request r in gs's solo slot: B on the device (the seed values
+// Starts request r in solo slot so: B on the device (the seed values
 // scattered into zeros, or uniform), the start state and the first
-// selection, then the slot's event.
-di_status start_solo(di_server* s, GraphSlot* gs, Request& r) {
-  Solo* so = gs->solo;
+// selection, then the slot's event. Nothing here waits for the device: the
+// slot keeps the seeds (its own device copy and the host copy the transfer
+// reads) until the run ends.
+di_status start_solo(di_server* s, GraphSlot* gs, Solo* so, Request& r) {
   const di_graph* g = gs->g;
   const double* B = nullptr;
   const double bu = (1.0 - r.d) / (double)g->n;
-  if (!r.seeds.empty()) {
-    DI_TRY(ensure_seed_staging(s, r.seeds.size()));
+  so->seeds = std::move(r.seeds);
+  if (!so->seeds.empty()) {
+    if (so->seeds.size() > so->seeds_cap) {
+      if (so->d_seeds) (void)hipFree(so->d_seeds);
+      so->d_seeds = nullptr;
+      so->seeds_cap = 0;
+      const size_t cap = std::max<size_t>(so->seeds.size(), 1024);
+      hipError_t err = hipMalloc((void**)&so->d_seeds, cap * sizeof(int32_t));
+      if (err != hipSuccess) {
+        so->d_seeds = nullptr;
+        set_error(std::string("hipMalloc: ") + hipGetErrorString(err));
+        return DI_E_NOMEM;
+      }
+      so->seeds_cap = cap;
+    }
     DI_HIP(hipMemsetAsync(so->out_dev, 0, (size_t)g->n * sizeof(double), so->stream));
-    DI_HIP(hipMemcpyAsync(s->d_seeds, r.seeds.data(), r.seeds.size() * sizeof(int32_t),
+    DI_HIP(hipMemcpyAsync(so->d_seeds, so->seeds.data(), so->seeds.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice, so->stream));
-    DI_HIP(launch_scatter_value(so->stream, so->out_dev, s->d_seeds, (int64_t)r.seeds.size(),
-                                (1.0 - r.d) / (double)r.seeds.size()));
-    // the seed staging is shared and the host copy is pageable: wait
-    DI_HIP(hipStreamSynchronize(so->stream));
+    DI_HIP(launch_scatter_value(so->stream, so->out_dev, so->d_seeds, (int64_t)so->seeds.size(),
+                                (1.0 - r.d) / (double)so->seeds.size()));
     B = so->out_dev;
   }
   const int max_cycles = s->opts.max_cycles > 0 ? s->opts.max_cycles : 100000;
-  DI_TRY(solo_start(so->run, B, bu, r.d, r.tol, s->opts.method, max_cycles, so->stream));
+  DI_TRY(solo_start(so->run, B, bu, r.d, r.tol, s->opts.method, max_cycles,
+                    s->opts.kernel != DI_KERNEL_PULL, so->stream));
   DI_HIP(hipEventRecord(so->ev, so->stream));
-  so->lane = Lane{r.ticket, r.t_submit};
-  so->d = r.d;
+  so->lane = Lane{r.ticket, r.t_submit, now_s()};
   so->launched = true;
   return DI_OK;
 }
 
-// After the solo slot's queued work finished: the next chunk, or the result.
-di_status step_solo(di_server* s, GraphSlot* gs) {
-  Solo* so = gs->solo;
+// After solo slot so's queued work finished: the next chunk, or the result.
+di_status step_solo(di_server* s, GraphSlot* gs, Solo* so) {
   int done = 0;
   DI_TRY(solo_next(so->run, &done));
   if (done == 0) {
@@ -424,15 +465,23 @@ di_status step_solo(di_server* s, GraphSlot* gs) {
     so->launched = true;
     return DI_OK;
   }
+  const double t_seen = now_s();
   const di_graph* g = gs->g;
   Result res;
+  bool again = false;
+  res.status = solo_finish(so->run, so->out_dev, &res.stats, &again);
+  if (again) {
+    // rounding left the exact residual above tol: the run goes on
+    DI_HIP(hipEventRecord(so->ev, so->stream));
+    so->launched = true;
+    return DI_OK;
+  }
   res.X.resize((size_t)g->n);
-  res.status = solo_finish(so->run, so->out_dev, &res.stats);
   DI_HIP(hipMemcpyAsync(res.X.data(), so->out_dev, (size_t)g->n * sizeof(double),
                         hipMemcpyDeviceToHost, so->stream));
   DI_HIP(hipStreamSynchronize(so->stream));
-  res.stats.seconds = now_s() - so->lane.t_submit;  // latency: submission to completion
-  res.stats.seconds_to_1e9 = -1.0;                  // not recorded for served requests
+  set_times(&res.stats, so->lane, t_seen, now_s());
+  so->seeds.clear();
   std::lock_guard<std::mutex> lk(s->mu);
   s->results[so->lane.ticket] = std::move(res);
   s->completed += 1;
@@ -494,11 +543,13 @@ void fail_all(di_server* s, di_status st, const std::string& msg) {
         }
       cs->active = 0;
     }
-    if (gs->solo && gs->solo->lane.ticket) {
-      s->results[gs->solo->lane.ticket].status = st;
-      gs->solo->lane = Lane{};
+    for (Solo* so : gs->solos) {
+      if (so->lane.ticket) {
+        s->results[so->lane.ticket].status = st;
+        so->lane = Lane{};
+      }
+      so->claimed = false;
     }
-    if (gs->solo) gs->solo->claimed = false;
     for (Request& r : gs->pending) s->results[r.ticket].status = st;
     gs->pending.clear();
   }
@@ -506,7 +557,8 @@ void fail_all(di_server* s, di_status st, const std::string& msg) {
 
 bool graph_busy(const GraphSlot* gs) {
   if (!gs->pending.empty()) return true;
-  if (gs->solo && (gs->solo->claimed || gs->solo->launched)) return true;
+  for (const Solo* so : gs->solos)
+    if (so->claimed || so->launched) return true;
   for (const ColumnSet* cs : gs->sets)
     if (cs->launched || cs->active > 0) return true;
   return false;
@@ -517,19 +569,28 @@ struct Placement {
   std::vector<Request> reqs;
 };
 
-// Under s->mu: places waiting requests of gs. A graph has at most one open
-// set (the others drain: they take no new requests and are freed once
-// idle). The open set's width follows the demand (columns in use plus
-// requests waiting, as a power of two from 8 to k_max): when the demand
-// outgrows it, or falls to a quarter of it, a new open set of the demanded
-// width is reserved (*fresh, not yet created) and the old one drains. A set
-// takes requests of its own d; an idle open set takes the d of the next
-// request. Idle sets of other graphs released to make room go to *to_free.
+struct SoloStart {
+  Solo* so;  // not yet `ready` when just reserved: the worker creates it
+  Request req;
+};
+
+// Under s->mu: places waiting requests of gs.
+// While the graph's demand (requests running or waiting) is at most
+// kSoloDemand, requests take free solo slots, reserving new ones up to
+// kSoloPerGraph as the budget allows (*solo_starts; the worker creates the
+// new ones), and the rest wait for a slot. Otherwise they go to column sets.
+// A graph has at most one open set (the others drain: they take no new
+// requests and are freed once idle). The open set's width follows the
+// demand (as a power of two from 8 to k_max): when the demand outgrows it,
+// or falls to a quarter of it, a new open set of the demanded width is
+// reserved (*fresh, not yet created) and the old one drains. Requests join
+// an open set between its chunks of cycles (not while its work is queued).
+// A set takes requests of its own d; an idle open set takes the d of the
+// next request. Idle sets and slots of other graphs released to make room
+// go to *freed.
 void place_requests(di_server* s, GraphSlot* gs, std::vector<Placement>* out,
-                    ColumnSet** fresh, Freed* freed, std::vector<Request>* solo_req,
-                    bool* solo_fresh) {
+                    ColumnSet** fresh, Freed* freed, std::vector<SoloStart>* solo_starts) {
   *fresh = nullptr;
-  *solo_fresh = false;
   if (gs->pending.empty()) return;
   ColumnSet* open = nullptr;
   int demand = (int)gs->pending.size();
@@ -537,28 +598,33 @@ void place_requests(di_server* s, GraphSlot* gs, std::vector<Placement>* out,
     demand += cs->active;
     if (!cs->draining) open = cs;
   }
-  if (gs->solo && gs->solo->claimed) demand += 1;
-  // a request alone on its graph runs in the solo slot
-  if (demand == 1 && !(s->opts.flags & DI_FLAG_SERVE_NO_SOLO)) {
-    bool have = gs->solo != nullptr;
-    if (!have && reserve_bytes(s, gs, solo_bytes(gs->g), freed)) {
-      gs->solo = new Solo;
-      gs->solo->bytes = solo_bytes(gs->g);
-      *solo_fresh = true;
-      have = true;
-    }
-    if (have) {
-      gs->solo->claimed = true;
-      solo_req->push_back(std::move(gs->pending.front()));
+  for (const Solo* so : gs->solos) demand += so->claimed ? 1 : 0;
+  if (demand <= kSoloDemand && !(s->opts.flags & DI_FLAG_SERVE_NO_SOLO)) {
+    for (Solo* so : gs->solos) {
+      if (gs->pending.empty()) break;
+      if (so->claimed) continue;
+      so->claimed = true;
+      solo_starts->push_back(SoloStart{so, std::move(gs->pending.front())});
       gs->pending.pop_front();
+    }
+    while (!gs->pending.empty() && (int)gs->solos.size() < kSoloPerGraph &&
+           reserve_bytes(s, gs, solo_bytes(gs->g), freed)) {
+      Solo* so = new Solo;
+      so->bytes = solo_bytes(gs->g);
+      so->claimed = true;
+      gs->solos.push_back(so);
+      solo_starts->push_back(SoloStart{so, std::move(gs->pending.front())});
+      gs->pending.pop_front();
+    }
+    if (!gs->solos.empty()) {
       gs->stalled = false;
-      return;
+      return;  // the rest wait for a slot
     }
   }
   const int want = std::min(pow2_at_least(demand), s->kp);
   if (open && open->ready && open->active == 0) open->d = gs->pending.front().d;
   const bool resize = !open || want > open->kp || want * 4 <= open->kp;
-  if (open && open->ready) {
+  if (open && open->ready && !open->launched) {
     Placement p{open, {}};
     while (open->active + (int)p.reqs.size() < open->kp && !gs->pending.empty() &&
            gs->pending.front().d == open->d && !resize) {
@@ -574,7 +640,7 @@ void place_requests(di_server* s, GraphSlot* gs, std::vector<Placement>* out,
     gs->stalled = false;
     return;
   }
-  if (!resize && open) return;  // the open set is full: wait for its columns
+  if (!resize && open) return;  // the open set is full or busy: wait for it
   if ((int)gs->sets.size() >= kMaxSetsPerGraph) return;
   if (!reserve_bytes(s, gs, set_bytes(s, gs->g, want), freed)) {
     if (!gs->stalled) {
@@ -664,42 +730,50 @@ void worker_loop(di_server* s) {
         progressed = true;
       }
       if (st != DI_OK) break;
-      // the solo slot (only the worker creates, launches and frees it)
-      if (gs->solo && gs->solo->launched) {
-        const hipError_t q = hipEventQuery(gs->solo->ev);
+      // the solo slots (only the worker creates, launches and frees them)
+      std::vector<Solo*> solos;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        solos = gs->solos;
+      }
+      for (Solo* so : solos) {
+        if (!so->launched) continue;
+        const hipError_t q = hipEventQuery(so->ev);
         if (q == hipErrorNotReady) {
           (void)hipGetLastError();
-        } else {
-          gs->solo->launched = false;
-          if (q != hipSuccess) {
-            set_error(std::string("serving worker: ") + hipGetErrorString(q));
-            st = DI_E_DEVICE;
-            break;
-          }
-          st = step_solo(s, gs);
-          if (st != DI_OK) break;
-          progressed = true;
+          continue;
         }
+        so->launched = false;
+        if (q != hipSuccess) {
+          set_error(std::string("serving worker: ") + hipGetErrorString(q));
+          st = DI_E_DEVICE;
+          break;
+        }
+        st = step_solo(s, gs, so);
+        if (st != DI_OK) break;
+        progressed = true;
       }
+      if (st != DI_OK) break;
       // place waiting requests
       std::vector<Placement> places;
       ColumnSet* fresh = nullptr;
       std::vector<ColumnSet*> to_free;
       Freed freed;
-      std::vector<Request> solo_req;
-      bool solo_fresh = false;
+      std::vector<SoloStart> solo_starts;
       {
         std::lock_guard<std::mutex> lk(s->mu);
         retire_drained(s, gs, &to_free);
-        place_requests(s, gs, &places, &fresh, &freed, &solo_req, &solo_fresh);
+        place_requests(s, gs, &places, &fresh, &freed, &solo_starts);
+        s->solo_requests += (int64_t)solo_starts.size();
         sets = gs->sets;
       }
       for (ColumnSet* cs : to_free) destroy_set(cs);
       for (ColumnSet* cs : freed.sets) destroy_set(cs);
       for (Solo* so : freed.solos) destroy_solo(so);
-      if (solo_fresh) st = create_solo(gs, gs->solo);
-      if (st == DI_OK && !solo_req.empty()) {
-        st = start_solo(s, gs, solo_req.front());
+      for (SoloStart& ss : solo_starts) {
+        if (st != DI_OK) break;
+        if (!ss.so->ready) st = create_solo(gs, ss.so);
+        if (st == DI_OK) st = start_solo(s, gs, ss.so, ss.req);
         progressed = true;
       }
       if (st == DI_OK && fresh) st = create_set_ws(s, fresh);
@@ -717,7 +791,7 @@ void worker_loop(di_server* s) {
         std::lock_guard<std::mutex> lk(s->mu);
         for (Placement& p : places)
           for (Request& r : p.reqs) s->results[r.ticket].status = st;
-        for (Request& r : solo_req) s->results[r.ticket].status = st;
+        for (SoloStart& ss : solo_starts) s->results[ss.req.ticket].status = st;
         break;
       }
     }
@@ -730,11 +804,11 @@ void worker_loop(di_server* s) {
             (void)hipEventSynchronize(cs->ev);
             cs->launched = false;
           }
-        Solo* so = kv.second->solo;
-        if (so && so->launched) {
-          (void)hipEventSynchronize(so->ev);
-          so->launched = false;
-        }
+        for (Solo* so : kv.second->solos)
+          if (so->launched) {
+            (void)hipEventSynchronize(so->ev);
+            so->launched = false;
+          }
       }
     }
     if (st != DI_OK) fail_all(s, st, "serving worker: " + std::string(di_last_error()));
@@ -829,6 +903,17 @@ di_status di_serve_add_graph(di_server* s, const di_graph* g, int32_t graph_id) 
       di::set_error("one column set of the graph exceeds the HBM budget");
       return DI_E_NOMEM;
     }
+    // the solo slots' window push, tuned once for the graph
+    const di_opts& o = s->opts;
+    if (o.method == DI_SOP && o.kernel != DI_KERNEL_PULL &&
+        !(o.flags & (DI_FLAG_NO_TUNE | DI_FLAG_SERVE_NO_SOLO))) {
+      int cur = 0;
+      if (hipGetDevice(&cur) != hipSuccess) cur = s->device;
+      if (cur != s->device) (void)hipSetDevice(s->device);
+      const di_status ts = di::tune_window_f64(const_cast<di_graph*>(g), 0.85);
+      if (cur != s->device) (void)hipSetDevice(cur);
+      if (ts != DI_OK) return ts;
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->graphs.count(graph_id)) {
       di::set_error("graph_id already registered");
@@ -922,13 +1007,14 @@ di_status di_serve_info(di_server* s, di_serve_stats* out) {
   int64_t active = 0, pending = 0;
   for (auto& kv : s->graphs) {
     for (const di::ColumnSet* cs : kv.second->sets) active += cs->active;
-    if (kv.second->solo && kv.second->solo->claimed) active += 1;
+    for (const di::Solo* so : kv.second->solos) active += so->claimed ? 1 : 0;
     pending += (int64_t)kv.second->pending.size();
   }
   out->active = active;
   out->pending = pending;
   out->bytes_in_use = (int64_t)s->in_use;
   out->busy_seconds = s->busy_seconds;
+  out->solo_requests = s->solo_requests;
   return DI_OK;
 }
 
@@ -944,7 +1030,7 @@ void di_serve_destroy(di_server* s) {
   if (hipGetDevice(&cur) == hipSuccess && cur != s->device) (void)hipSetDevice(s->device);
   for (auto& kv : s->graphs) {
     for (di::ColumnSet* cs : kv.second->sets) di::destroy_set(cs);
-    if (kv.second->solo) di::destroy_solo(kv.second->solo);
+    for (di::Solo* so : kv.second->solos) di::destroy_solo(so);
     delete kv.second;
   }
   void* ptrs[] = {s->d_flag, s->d_buni, s->d_col, s->d_off, s->d_val, s->d_tol, s->d_seeds};

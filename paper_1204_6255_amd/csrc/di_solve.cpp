@@ -110,7 +110,7 @@ di_status ensure_window_buffers(const di_graph* g, Workspace* ws) {
   // sized for every configuration: the smallest tile (most halos), the
   // largest grid and hub count
   DI_TRY(dmalloc(&ws->whalo, 2 * (size_t)std::max<int64_t>(g->n_wtiles[0], 1) * 2 * kWinHalo * s));
-  DI_TRY(dmalloc(&ws->whub, 2 * (size_t)kWinMaxGrid * kWinHubMax * s));
+  DI_TRY(dmalloc(&ws->whub, 2 * (size_t)win_hub_rows(g->n_wtiles[0]) * kWinHubMax * s));
   DI_TRY(dmalloc((void**)&ws->wrec, 2 * (size_t)kWinMaxGrid * sizeof(Part)));
   DI_TRY(dmalloc((void**)&ws->wflag, sizeof(int)));
   if (!ws->host_flag) {
@@ -125,9 +125,16 @@ di_status ensure_window_buffers(const di_graph* g, Workspace* ws) {
   return DI_OK;
 }
 
-// Residual-pass buffers, allocated on first use.
-di_status ensure_refine_buffers(const di_graph* g, Workspace* ws) {
-  if (!ws->Y64) DI_TRY(dmalloc((void**)&ws->Y64, (size_t)g->n * sizeof(double)));
+// Bytes of the window-push buffers of a workspace of precision prec.
+size_t window_bytes(const di_graph* g, int prec) {
+  const size_t s = prec == kF64 ? sizeof(double) : sizeof(float);
+  return 2 * (size_t)std::max<int64_t>(g->n_wtiles[0], 1) * 2 * kWinHalo * s +
+         2 * (size_t)win_hub_rows(g->n_wtiles[0]) * kWinHubMax * s +
+         2 * (size_t)kWinMaxGrid * sizeof(Part) + sizeof(int) + 2 * (size_t)win_stride(g->n) * s;
+}
+
+// Pinned host copy of the per-block records, allocated on first use.
+di_status ensure_host_part(Workspace* ws) {
   if (!ws->host_part) {
     const size_t bytes = ((size_t)std::max(kPullMaxGrid, kReduceGrid) + 1) * sizeof(Part);
     hipError_t err = hipHostMalloc((void**)&ws->host_part, bytes, hipHostMallocDefault);
@@ -138,6 +145,12 @@ di_status ensure_refine_buffers(const di_graph* g, Workspace* ws) {
     }
   }
   return DI_OK;
+}
+
+// Residual-pass buffers, allocated on first use.
+di_status ensure_refine_buffers(const di_graph* g, Workspace* ws) {
+  if (!ws->Y64) DI_TRY(dmalloc((void**)&ws->Y64, (size_t)g->n * sizeof(double)));
+  return ensure_host_part(ws);
 }
 
 // sum |R| of the records [0, count) of a residual pass, in record order
@@ -464,7 +477,8 @@ bool window_usable(const di_graph* g) {
 using TuneKey = std::tuple<int64_t, int64_t, int64_t, int64_t>;
 struct TuneEntry {
   WinCfg cfg;
-  double us_default, us_tuned;
+  bool use_pull;
+  double us_default, us_tuned, pull_us;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneEntry>& tune_cache() {
@@ -508,10 +522,47 @@ di_status time_window_cfg(di_graph* g, Workspace* ws, hipStream_t stream, double
   return DI_OK;
 }
 
+// Time per cycle of the select + pull pair, measured as for the window.
+template <typename T>
+di_status time_pull(di_graph* g, Workspace* ws, hipStream_t stream, double d, double* us) {
+  CycleArgs a{};
+  a.g = g;
+  a.ws = ws;
+  a.d = d;
+  a.tol = 0.0;
+  a.tol_in = 0.0;
+  a.tol_rel = -1.0;
+  a.method = DI_SOP;
+  a.stop = DI_STOP_RESID;
+  a.max_cycles = kTuneCycles + 2;
+  a.direction = kPull;
+  a.stream = stream;
+  a.first_parts = part_count(a) + 1;
+  DI_TRY(ensure_events(ws, 2));
+  DI_HIP(launch_reset_ctl(a));
+  DI_HIP(launch_start<T>(a, nullptr, (1.0 - d) / (double)g->n));
+  DI_HIP(launch_select<T>(a, 0, 1));
+  DI_HIP(launch_move<T>(a, 0, nullptr, nullptr));
+  DI_HIP(launch_select<T>(a, 1, 0));
+  DI_HIP(hipEventRecord(ws->events[0], stream));
+  for (int cyc = 1; cyc <= kTuneCycles; ++cyc) {
+    DI_HIP(launch_move<T>(a, cyc, nullptr, nullptr));
+    DI_HIP(launch_select<T>(a, cyc + 1, 0));
+  }
+  DI_HIP(hipEventRecord(ws->events[1], stream));
+  DI_HIP(hipEventSynchronize(ws->events[1]));
+  float ms = 0.f;
+  DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
+  *us = 1e3 * ms / kTuneCycles;
+  return DI_OK;
+}
+
 // Picks the graph's window configuration by timing candidates, greedily:
 // the tile shapes at the default hub count, then the hub counts at the best
-// shape, then smaller grids; or takes the choice made for a graph of the
-// same shape (n, L, largest in- and out-degree) earlier in the process.
+// shape, then smaller grids; and whether the select + pull pair is faster
+// still (small graphs, where each launch's own latency dominates). Or takes
+// the choice made for a graph of the same shape (n, L, largest in- and
+// out-degree) earlier in the process.
 template <typename T>
 di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) {
   {
@@ -525,8 +576,10 @@ di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) 
     if (it != tune_cache().end()) {
       std::lock_guard<std::mutex> lock2(g->mu);
       g->win_cfg = it->second.cfg;
+      g->win_use_pull = it->second.use_pull;
       g->win_us_default = it->second.us_default;
       g->win_us_tuned = it->second.us_tuned;
+      g->pull_us = it->second.pull_us;
       g->win_tuned = true;
       return DI_OK;
     }
@@ -566,17 +619,50 @@ di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) 
       c.grid_cap = cap;
       DI_TRY(consider(c));
     }
+  double pull_us = 0.0;
+  DI_TRY(time_pull<T>(g, ws, stream, d, &pull_us));
+  const bool use_pull = pull_us < best_us;
   {
     std::lock_guard<std::mutex> lock(g->mu);
     g->win_cfg = best;
+    g->win_use_pull = use_pull;
     g->win_us_default = def_us;
     g->win_us_tuned = best_us;
+    g->pull_us = pull_us;
     g->win_tuned = true;
   }
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  tune_cache()[key] = TuneEntry{best, def_us, best_us};
+  tune_cache()[key] = TuneEntry{best, use_pull, def_us, best_us, pull_us};
   return DI_OK;
 }
+
+}  // namespace
+
+di_status tune_window_f64(di_graph* g, double d) {
+  if (!window_usable(g)) return DI_OK;
+  {
+    std::lock_guard<std::mutex> lock(g->mu);
+    if (g->win_tuned) return DI_OK;
+  }
+  di_status st = DI_OK;
+  Workspace* ws = acquire(g, kF64, &st);
+  if (st != DI_OK) return st;
+  hipStream_t stream = nullptr;
+  hipError_t err = hipStreamCreate(&stream);
+  if (err != hipSuccess) {
+    release(g, ws);
+    set_error(std::string("hipStreamCreate: ") + hipGetErrorString(err));
+    return DI_E_DEVICE;
+  }
+  st = ensure_window_buffers(g, ws);
+  if (st == DI_OK) st = tune_window<double>(g, ws, stream, d);
+  (void)hipStreamSynchronize(stream);
+  (void)hipStreamDestroy(stream);
+  release(g, ws);
+  return st;
+}
+
+namespace {
 
 constexpr int kMaxRefinements = 100;
 
@@ -868,15 +954,16 @@ di_status solve_any(const di_graph* gc, const double* B, bool B_on_host, double 
   // takes the window push (tuned on the graph's first such solve); DI-CYC and
   // the power iteration move nearly every link every cycle and take the pull
   if (o.kernel == DI_KERNEL_AUTO && o.method != DI_GS_ASYNC) {
+    o.kernel = DI_KERNEL_PULL;
     if (o.method == DI_SOP && window_usable(g)) {
       o.kernel = DI_KERNEL_WINDOW;
       if (!(o.flags & DI_FLAG_NO_TUNE)) {
         DI_TRY(ensure_window_buffers(g, ws));
         DI_TRY(prec == kF64 ? tune_window<double>(g, ws, stream, d)
                             : tune_window<float>(g, ws, stream, d));
+        std::lock_guard<std::mutex> lock(g->mu);
+        if (g->win_use_pull) o.kernel = DI_KERNEL_PULL;
       }
-    } else {
-      o.kernel = DI_KERNEL_PULL;
     }
   }
   if (trace_cap > ws->trace_cap) {
@@ -1038,12 +1125,19 @@ size_t workspace_bytes(const di_graph* g, int prec) {
          2 * nh * (s + sizeof(double)) + 2 * sizeof(Ctl);
 }
 
+size_t solo_run_bytes(const di_graph* g) {
+  return workspace_bytes(g, kF64) + (window_usable(g) ? window_bytes(g, kF64) : 0);
+}
+
 di_status solo_create(di_graph* g, SoloRun** out) {
   SoloRun* r = new (std::nothrow) SoloRun;
   if (!r) return DI_E_NOMEM;
   r->g = g;
   di_status st = alloc_workspace(g, kF64, &r->ws);
+  if (st == DI_OK && window_usable(g)) st = ensure_window_buffers(g, r->ws);
+  if (st == DI_OK) st = ensure_host_part(r->ws);
   if (st != DI_OK) {
+    free_workspace(r->ws);
     delete r;
     return st;
   }
@@ -1057,8 +1151,20 @@ void solo_destroy(SoloRun* r) {
   delete r;
 }
 
+// The first selection of a run and the read-back of its control block.
+di_status solo_first(SoloRun* r) {
+  CycleArgs& a = r->a;
+  r->last_sel = 0;
+  r->chunk = 8;
+  if (r->window) DI_HIP(launch_wcycle<double>(a, 0, nullptr, nullptr));
+  else DI_HIP(launch_select<double>(a, 0, 1));
+  DI_HIP(hipMemcpyAsync(r->ws->host_ctl, r->ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost,
+                        a.stream));
+  return DI_OK;
+}
+
 di_status solo_start(SoloRun* r, const double* B_dev, double b_uniform, double d, double tol,
-                     int method, int max_cycles, hipStream_t stream) {
+                     int method, int max_cycles, bool allow_window, hipStream_t stream) {
   CycleArgs& a = r->a;
   a = CycleArgs{};
   a.g = r->g;
@@ -1070,17 +1176,21 @@ di_status solo_start(SoloRun* r, const double* B_dev, double b_uniform, double d
   a.method = method;
   a.stop = DI_STOP_RESID;
   a.max_cycles = max_cycles;
-  a.direction = kPull;
+  {
+    std::lock_guard<std::mutex> lock(r->g->mu);
+    r->window = allow_window && method == DI_SOP && r->ws->wA != nullptr && !r->g->win_use_pull;
+  }
+  a.direction = r->window ? kWindow : kPull;
+  if (r->window) a.wcfg = window_cfg(r->g);
   a.stream = stream;
   a.first_parts = part_count(a) + 1;
-  r->last_sel = 0;
-  r->chunk = 8;
+  r->tot = Ctl{};
+  r->restarts = 0;
+  r->max_cycles = max_cycles;
   DI_HIP(launch_reset_ctl(a));
-  DI_HIP(launch_start<double>(a, B_dev, b_uniform));
-  DI_HIP(launch_select<double>(a, 0, 1));
-  DI_HIP(hipMemcpyAsync(r->ws->host_ctl, r->ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost,
-                        stream));
-  return DI_OK;
+  if (r->window) DI_HIP(launch_wstart<double>(a, B_dev, b_uniform));
+  else DI_HIP(launch_start<double>(a, B_dev, b_uniform));
+  return solo_first(r);
 }
 
 di_status solo_next(SoloRun* r, int* done) {
@@ -1096,8 +1206,12 @@ di_status solo_next(SoloRun* r, int* done) {
   const int todo = std::max(1, std::min(r->chunk, a.max_cycles - r->last_sel));
   for (int q = 0; q < todo; ++q) {
     const int c = r->last_sel;
-    DI_HIP(launch_move<double>(a, c, nullptr, nullptr));
-    DI_HIP(launch_select<double>(a, c + 1, 0));
+    if (r->window) {
+      DI_HIP(launch_wcycle<double>(a, c + 1, nullptr, nullptr));
+    } else {
+      DI_HIP(launch_move<double>(a, c, nullptr, nullptr));
+      DI_HIP(launch_select<double>(a, c + 1, 0));
+    }
     r->last_sel = c + 1;
   }
   DI_HIP(hipMemcpyAsync(r->ws->host_ctl, r->ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost,
@@ -1105,13 +1219,36 @@ di_status solo_next(SoloRun* r, int* done) {
   return DI_OK;
 }
 
-di_status solo_finish(SoloRun* r, double* X_dev, di_stats* st) {
+di_status solo_finish(SoloRun* r, double* X_dev, di_stats* st, bool* again) {
+  CycleArgs& a = r->a;
   const Ctl h = r->ws->host_ctl[(r->last_sel + 1) & 1];
-  DI_HIP(launch_h_to_x<double>(r->a, X_dev));
+  *again = false;
+  Ctl tot = r->tot;
+  add_run(&tot, h);
+  tot.done = h.done;
+  tot.final_r = h.final_r;
+  if (r->window && h.done != 3) {
+    // the whole fluid into F, and its exact residual
+    DI_HIP(launch_wfinal<double>(a, h.cycles & 1, h.cycles > 0 ? 1 : 0));
+    double r_exact = 0.0;
+    DI_TRY(residual_norm(a, win_grid(r->g, a.wcfg), &r_exact, nullptr));
+    tot.final_r = r_exact;
+    if (h.done == 1 && r_exact > a.tol && r->restarts < 4 && tot.cycles < r->max_cycles) {
+      r->tot = tot;
+      r->restarts += 1;
+      a.max_cycles = r->max_cycles - tot.cycles;
+      a.first_parts = win_grid(r->g, a.wcfg);
+      DI_HIP(launch_reset_ctl(a));
+      DI_TRY(solo_first(r));
+      *again = true;
+      return DI_OK;
+    }
+  }
+  DI_HIP(launch_h_to_x<double>(a, X_dev));
   RunTimes rt;
   std::memset(st, 0, sizeof(*st));
-  fill_stats(r->g, h, r->a.d, (int)sizeof(double), kPull, rt, 0, st);
-  return h.done == 1 ? DI_OK : (h.done == 2 ? DI_E_NOCONV : DI_E_INVAL);
+  fill_stats(r->g, tot, a.d, (int)sizeof(double), a.direction, rt, 0, st);
+  return tot.done == 1 ? DI_OK : (tot.done == 2 ? DI_E_NOCONV : DI_E_INVAL);
 }
 
 }  // namespace di
@@ -1158,8 +1295,9 @@ di_status di_residual_dev(const di_graph* g, const double* B_dev, double d, cons
   return di::guarded([&] { return di::residual_dev(g, B_dev, d, X_dev, R_dev, l1, stream); });
 }
 
-di_status di_graph_tuning(const di_graph* gc, int32_t* tile, int32_t* hubs, int32_t* grid,
-                          int32_t* tuned, double* us_default, double* us_tuned) {
+di_status di_graph_tuning(const di_graph* gc, int32_t* kernel, int32_t* tile, int32_t* hubs,
+                          int32_t* grid, int32_t* tuned, double* us_default, double* us_tuned,
+                          double* us_pull) {
   if (!gc) {
     di::set_error("di_graph_tuning: graph is NULL");
     return DI_E_INVAL;
@@ -1167,12 +1305,14 @@ di_status di_graph_tuning(const di_graph* gc, int32_t* tile, int32_t* hubs, int3
   di_graph* g = const_cast<di_graph*>(gc);
   const di::WinCfg c = di::window_cfg(g);
   std::lock_guard<std::mutex> lock(g->mu);
+  if (kernel) *kernel = g->win_tuned && g->win_use_pull ? DI_KERNEL_PULL : DI_KERNEL_WINDOW;
   if (tile) *tile = di::kWinTileOf[c.shape];
   if (hubs) *hubs = c.hubs;
   if (grid) *grid = di::win_grid(g, c);
   if (tuned) *tuned = g->win_tuned ? 1 : 0;
   if (us_default) *us_default = g->win_us_default;
   if (us_tuned) *us_tuned = g->win_us_tuned;
+  if (us_pull) *us_pull = g->pull_us;
   return DI_OK;
 }
 

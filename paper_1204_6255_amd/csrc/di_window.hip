@@ -564,7 +564,7 @@ WinState<T> win_state(const CycleArgs& a, int parity) {
   S.halo_cur = halo + (int64_t)parity * hsz;
   S.halo_next = halo + (int64_t)(parity ^ 1) * hsz;
   T* hub = (T*)ws->whub;
-  const int64_t bsz = (int64_t)kWinMaxGrid * KMAX;
+  const int64_t bsz = win_hub_rows(g->n_wtiles[0]) * KMAX;
   S.hub_cur = hub + (int64_t)parity * bsz;
   S.hub_next = hub + (int64_t)(parity ^ 1) * bsz;
   return S;

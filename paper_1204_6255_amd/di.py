@@ -67,6 +67,9 @@ class di_stats(ctypes.Structure):
         ("bytes_moved", ctypes.c_double),
         ("move_bytes", ctypes.c_double),
         ("seconds_to_1e9", ctypes.c_double),
+        ("queue_seconds", ctypes.c_double),
+        ("run_seconds", ctypes.c_double),
+        ("readout_seconds", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -91,6 +94,7 @@ class di_serve_stats(ctypes.Structure):
         ("pending", ctypes.c_int64),
         ("bytes_in_use", ctypes.c_int64),
         ("busy_seconds", ctypes.c_double),
+        ("solo_requests", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -137,7 +141,8 @@ def lib():
     L.di_cycles_dev.restype = i32
     L.di_residual_dev.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
     L.di_residual_dev.restype = i32
-    L.di_graph_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(dbl), P(dbl)]
+    L.di_graph_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(dbl), P(dbl),
+                                  P(dbl)]
     L.di_graph_tuning.restype = i32
     L.di_residual_dev_noalloc.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
     L.di_residual_dev_noalloc.restype = i32
@@ -278,13 +283,15 @@ def di_cycles_dev(h, d: float, method: int, F_dev, H_dev, cycles: int, e: float 
 
 
 def di_graph_tuning(h):
-    """The graph's window configuration: dict(tile, hubs, grid, tuned,
-    us_default, us_tuned)."""
-    v = [ctypes.c_int32() for _ in range(4)]
-    u = [ctypes.c_double() for _ in range(2)]
+    """What DI_KERNEL_AUTO runs for DI-SOP on the graph and its window
+    configuration: dict(kernel, tile, hubs, grid, tuned, us_default,
+    us_tuned, us_pull)."""
+    v = [ctypes.c_int32() for _ in range(5)]
+    u = [ctypes.c_double() for _ in range(3)]
     _check(lib().di_graph_tuning(h, *[ctypes.byref(x) for x in v], *[ctypes.byref(x) for x in u]))
-    return {"tile": v[0].value, "hubs": v[1].value, "grid": v[2].value, "tuned": bool(v[3].value),
-            "us_default": u[0].value, "us_tuned": u[1].value}
+    return {"kernel": {DI_KERNEL_WINDOW: "window", DI_KERNEL_PULL: "pull"}[v[0].value],
+            "tile": v[1].value, "hubs": v[2].value, "grid": v[3].value, "tuned": bool(v[4].value),
+            "us_default": u[0].value, "us_tuned": u[1].value, "us_pull": u[2].value}
 
 
 def di_residual_dev(h, B_dev, d: float, X_dev, R_dev=None, stream=None):

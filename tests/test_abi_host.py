@@ -37,7 +37,7 @@ def test_version_and_defaults():
 def test_struct_layouts_match_header():
     # sizes follow from the field lists in include/di.h
     assert ctypes.sizeof(di.di_opts) == 40
-    assert ctypes.sizeof(di.di_stats) == 4 * 4 + 8 + 10 * 8
+    assert ctypes.sizeof(di.di_stats) == 4 * 4 + 8 + 13 * 8
 
 
 @pytest.mark.parametrize("n,src,dst,expect", [
@@ -81,7 +81,7 @@ def test_valid_graph_without_gpu_reports_device_error():
 
 
 def test_serving_struct_layout():
-    assert ctypes.sizeof(di.di_serve_stats) == 6 * 8 + 8
+    assert ctypes.sizeof(di.di_serve_stats) == 6 * 8 + 8 + 8
 
 
 @pytest.mark.skipif(_has_gpu(), reason="checks the no-GPU path")

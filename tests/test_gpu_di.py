@@ -241,7 +241,8 @@ def test_parity_1m_bench_configuration(torch_cuda):
     # the default is the tuned window push
     tun = di.di_graph_tuning(g.handle)
     assert tun["tuned"] and tun["tile"] in (1024, 2048, 4096) and 0 <= tun["hubs"] <= 1024
-    assert 0 < tun["us_tuned"] <= tun["us_default"]
+    assert 0 < tun["us_tuned"] <= tun["us_default"] and tun["us_pull"] > 0
+    assert tun["kernel"] == ("pull" if tun["us_pull"] < tun["us_tuned"] else "window")
     # the pull direction is bit-reproducible
     Xq, stq, _ = gpu_solve(torch_cuda, g, None, kernel=di.DI_KERNEL_PULL)
     X2, _, _ = gpu_solve(torch_cuda, g, None, kernel=di.DI_KERNEL_PULL)

@@ -184,6 +184,7 @@ def test_lone_request_runs_solo(torch_cuda):
     seeds = graphgen.ppr_seed_sets(10000, 1, 4243)[0]
     o = di.di_opts_default()
     o.precision = di.DI_FP32_REFINE
+    o.kernel = di.DI_KERNEL_PULL  # solo slots on the select + pull pair
     srv = Server(8 * GIB, 16, o)
     assert di.di_serve_add_graph(srv.h, g.handle, 0) == di.DI_OK
     st, t = di.di_serve_submit(srv.h, 0, seeds, D, 1e-9)
@@ -229,6 +230,46 @@ def test_lone_request_runs_solo(torch_cuda):
     check(og, seeds, 1e-9, X_set)
     assert s_set.refinements >= 1
     assert np.abs(X_set - X_solo).sum() <= 2e-9 / (1 - D)
+    srv.close()
+
+
+def test_solo_slots_at_light_load(torch_cuda):
+    """A few requests at once on one graph all run in solo slots (FP64, no
+    residual passes; DI-SOP on the graph's tuned kernel, tuned when the graph
+    is registered), two of them after waiting for a free slot; a burst past
+    twice the slots also fills column sets. Every request meets the bar, and
+    its latency splits exactly into waiting, running and reading out."""
+    _, _, g, og = graph(20000, 3)
+    srv = Server(8 * GIB, 16)
+    assert di.di_serve_add_graph(srv.h, g.handle, 0) == di.DI_OK
+    tun = di.di_graph_tuning(g.handle)
+    assert tun["tuned"] and tun["kernel"] in ("window", "pull")
+    seeds = graphgen.ppr_seed_sets(20000, 6, 777)
+    tickets = []
+    for j, s_ in enumerate(seeds):
+        st, tk = di.di_serve_submit(srv.h, 0, s_, D, 1e-9 if j % 2 else 1e-7)
+        assert st == di.DI_OK
+        tickets.append(tk)
+    for j, (s_, tk) in enumerate(zip(seeds, tickets)):
+        st, X, sts = wait(srv, tk, 20000)
+        assert st == di.DI_OK, di.di_last_error()
+        check(og, s_, 1e-9 if j % 2 else 1e-7, X)
+        assert sts.refinements == 0 and sts.cycles > 0
+        assert sts.queue_seconds >= 0 and sts.run_seconds > 0 and sts.readout_seconds >= 0
+        total = sts.queue_seconds + sts.run_seconds + sts.readout_seconds
+        assert abs(total - sts.seconds) <= 1e-9
+    _, info = di.di_serve_info(srv.h)
+    assert info.solo_requests == 6 and info.completed == 6
+    # a burst of 20: past twice the solo slots, column sets take the rest
+    burst = graphgen.ppr_seed_sets(20000, 20, 778)
+    tickets = [di.di_serve_submit(srv.h, 0, s_, D, 1e-8)[1] for s_ in burst]
+    for s_, tk in zip(burst, tickets):
+        st, X, sts = wait(srv, tk, 20000)
+        assert st == di.DI_OK
+        check(og, s_, 1e-8, X)
+    _, info = di.di_serve_info(srv.h)
+    assert info.completed == 26 and 6 <= info.solo_requests < 26
+    assert info.active == 0 and info.pending == 0
     srv.close()
 
 
