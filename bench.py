@@ -8,9 +8,10 @@ resident in HBM before the timed region; one step is one full solve.
 
 Prints one JSON line. `value` is the mean wall time per solve over the
 timed steps. The roofline object is for the kernel that moves the fluid
-(the CSC pull by default): algorithmic bytes per launch over its mean launch
-time, measured with HIP events around each launch in a second pass of the
-same steps (events add stream packets, so they stay out of `value`). The
+(the window push, which also selects, unless the graph's tuning picked the
+CSC pull): the method's bytes per launch over its mean launch time,
+measured with HIP events around each launch in a second pass of the same
+steps (events add stream packets, so they stay out of `value`). The
 cpu_baseline object times the CPU oracle (sequential DI-SOP, one thread)
 on the same graph.
 
@@ -674,7 +675,7 @@ def main():
     achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
     traffic = read_traffic(kind) if headline and kind in TRAFFIC else None
     edges = float(np.mean([r.edges_pushed for r in runs]))
-    solutions = {"DI-SOP pull fp64 (headline)": ("1m", "uniform", X.cpu().numpy())}
+    solutions = {f"DI-SOP {kind} fp64 (headline)": ("1m", "uniform", X.cpu().numpy())}
     # the same solve through the host-array entry (B and X cross PCIe)
     Xh = np.empty(n)
     di.di_solve(g.handle, None, d, tol, opts, Xh)

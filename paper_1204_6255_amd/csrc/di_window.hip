@@ -46,6 +46,7 @@ using namespace dev;
 
 constexpr int W = kWinHalo;
 constexpr int KMAX = kWinHubMax;
+constexpr int kHubBatch = 8;  // hub-partial loads in flight per lane
 constexpr int kUnroll = 4;  // links in flight per thread in the push
 
 __device__ inline void lds_add(double* p, double v) {
@@ -75,17 +76,23 @@ struct WinState {
   T* A_next;          // far accumulator this cycle pushes into
   const T* halo_cur;  // per tile: left halo, then right halo (W values each)
   T* halo_next;
-  const T* hub_cur;   // per block of the last launch: K hub partials
+  // hub partials, by hub rank then block ([r][b], row stride hub_gs): what
+  // block b of the last launch sent hub r (read and cleared by the hub's
+  // tile), and those this launch writes (its nonzero ones only: every entry
+  // is zero between uses)
+  T* hub_cur;
   T* hub_next;
+  int64_t hub_gs;
 };
 
 // The tile's ranked hubs: their ids ascending (s_hnode) and, when `add`,
 // what the last launch's G blocks sent the active ones (rank below K) in
 // their LDS accumulators (s_hadd; 0 for the others, whose far links went to
-// the far accumulator), each summed over the blocks in one order. Returns
-// the number of ranked hubs in the tile.
+// the far accumulator), each summed over the blocks in one order; with
+// `clear` the nonzero partials read are cleared. Returns the number of
+// ranked hubs in the tile.
 template <typename T, int BLOCK>
-__device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool add,
+__device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool add, bool clear,
                                 int32_t* s_hnode, T* s_hadd) {
   constexpr int NW = BLOCK / 64;
   const int h0 = S.hub_tile[tile], h1 = S.hub_tile[tile + 1];
@@ -93,8 +100,25 @@ __device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool 
   for (int k = wave; k < h1 - h0; k += NW) {
     const int r = S.hub_id_rank[h0 + k];
     double acc = 0.0;
-    if (add && r < S.K)
-      for (int b = lane; b < G; b += 64) acc += to_d(S.hub_cur[(int64_t)b * S.K + r]);
+    if (add && r < S.K) {
+      // kHubBatch loads of the row in flight per lane, then their sum (in
+      // ascending block order per lane)
+      T* row = S.hub_cur + (int64_t)r * S.hub_gs;
+      for (int b0 = 0; b0 < G; b0 += 64 * kHubBatch) {
+        T v[kHubBatch];
+#pragma unroll
+        for (int j = 0; j < kHubBatch; ++j) {
+          const int b = b0 + 64 * j + lane;
+          v[j] = b < G ? row[b] : (T)0;
+        }
+#pragma unroll
+        for (int j = 0; j < kHubBatch; ++j)
+          if (v[j] != (T)0) {
+            acc += to_d(v[j]);
+            if (clear) row[b0 + 64 * j + lane] = (T)0;
+          }
+      }
+    }
     acc = wave_sum(acc);
     if (lane == 0) {
       s_hnode[k] = S.hub_id_node[h0 + k];
@@ -102,6 +126,18 @@ __device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool 
     }
   }
   return h1 - h0;
+}
+
+// Puts back the hub sums tile_hubs read (and cleared) for a launch that
+// then found the solve stopped: each active hub's sum into its first
+// partial, which the final fold then adds as the sum itself.
+template <typename T, int BLOCK>
+__device__ inline void restore_tile_hubs(const WinState<T>& S, int64_t tile, const T* s_hadd) {
+  const int h0 = S.hub_tile[tile], h1 = S.hub_tile[tile + 1];
+  for (int k = threadIdx.x; k < h1 - h0; k += BLOCK) {
+    const int r = S.hub_id_rank[h0 + k];
+    if (r < S.K) S.hub_cur[(int64_t)r * S.hub_gs] = s_hadd[k];
+  }
 }
 
 // Fluid of node i (position li in its tile) at the cycle's start: kept +
@@ -254,7 +290,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         load4(S.halo_cur, (tile + 1) * 2 * W + (l0 - (TILE - W)), INT64_MAX, hr);
     }
     for (int q = tid; q < WIN; q += BLOCK) s_win[q] = (T)0;
-    nh = tile_hubs<T, BLOCK>(S, tile, G, add, s_hnode, s_hadd);
+    nh = tile_hubs<T, BLOCK>(S, tile, G, add, true, s_hnode, s_hadd);
   };
 
   int64_t tile = blockIdx.x;
@@ -280,7 +316,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     s_r = c.r;
   }
   __syncthreads();
-  if (s_done) return;
+  if (s_done) {
+    // the first tile's hub partials were read and cleared before the
+    // decision; the final fold still needs them
+    if (add) restore_tile_hubs<T, BLOCK>(S, tile, s_hadd);
+    return;
+  }
   // 0: the DI-SOP threshold; 1: every node holding fluid (DI-CYC); 2: every
   // node (the power iteration's cost)
   const int mode = s_cyc;
@@ -437,7 +478,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     __syncthreads();
   }
   __syncthreads();  // the hub accumulators are complete
-  for (int k = tid; k < nhub; k += BLOCK) S.hub_next[(int64_t)blockIdx.x * nhub + k] = s_hub[k];
+  for (int k = tid; k < nhub; k += BLOCK) {
+    const T v = s_hub[k];
+    if (v != (T)0) S.hub_next[(int64_t)k * S.hub_gs + blockIdx.x] = v;
+  }
   Part rec{my_keep + my_push, my_keep + my_push, my_e, my_ops, my_sel, my_front};
   rec = block_sum_part(rec, s_part);
   if (tid == 0) rec_out[blockIdx.x] = rec;
@@ -463,7 +507,7 @@ __global__ __launch_bounds__(BLOCK) void k_wfold(WinState<T> S, Part* __restrict
   for (int64_t tile = blockIdx.x; tile < S.ntiles; tile += G) {
     const int64_t a = tile * TILE;
     int nh = 0;
-    if (add) nh = tile_hubs<T, BLOCK>(S, tile, G, true, s_hnode, s_hadd);
+    if (add) nh = tile_hubs<T, BLOCK>(S, tile, G, true, true, s_hnode, s_hadd);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -490,11 +534,13 @@ __global__ __launch_bounds__(BLOCK) void k_wfold(WinState<T> S, Part* __restrict
   }
 }
 
-// F = B (or the uniform value), H = 0, both far accumulators (stride sa) 0,
-// and per-block sums of |F| and F.
+// F = B (or the uniform value), H = 0, both far accumulators (stride sa)
+// and both copies of the hub partials (nhub entries) 0, and per-block sums
+// of |F| and F.
 template <typename T>
 __global__ __launch_bounds__(kReduceBlock) void k_wstart(T* __restrict__ F, T* __restrict__ H,
                                                          T* __restrict__ A2,
+                                                         T* __restrict__ hub2, int64_t nhub,
                                                          const double* __restrict__ B,
                                                          double b_uniform, int64_t n, int64_t sa,
                                                          int state, Part* __restrict__ blk_part) {
@@ -515,6 +561,8 @@ __global__ __launch_bounds__(kReduceBlock) void k_wstart(T* __restrict__ F, T* _
     v.pabs += fabs(to_d(f));
     v.psum += to_d(f);
   }
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nhub; k += stride)
+    hub2[k] = (T)0;
   v = block_sum_part(v, lds);
   if (threadIdx.x == 0) {
     blk_part[blockIdx.x] = v;
@@ -532,6 +580,9 @@ __global__ void k_any_negative(const double* __restrict__ B, int64_t n, int* __r
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     if (B[i] < 0.0) *flag = 1;
 }
+
+// Entries of the two copies of the hub partials.
+int64_t hub_entries(const di_graph* g) { return 2 * win_hub_rows(g->n_wtiles[0]) * KMAX; }
 
 template <typename T>
 WinState<T> win_state(const CycleArgs& a, int parity) {
@@ -567,6 +618,7 @@ WinState<T> win_state(const CycleArgs& a, int parity) {
   const int64_t bsz = win_hub_rows(g->n_wtiles[0]) * KMAX;
   S.hub_cur = hub + (int64_t)parity * bsz;
   S.hub_next = hub + (int64_t)(parity ^ 1) * bsz;
+  S.hub_gs = win_hub_rows(g->n_wtiles[0]);
   return S;
 }
 
@@ -619,16 +671,17 @@ int win_grid(const di_graph* g, const WinCfg& c) {
 template <typename T>
 hipError_t launch_wstart(const CycleArgs& a, const double* B, double b_uniform) {
   hipLaunchKernelGGL(k_wstart<T>, dim3(part_count(a)), dim3(kReduceBlock), 0, a.stream,
-                     (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, B, b_uniform, a.g->n,
-                     win_stride(a.g->n), 0, a.ws->blk_part);
+                     (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, (T*)a.ws->whub, hub_entries(a.g),
+                     B, b_uniform, a.g->n, win_stride(a.g->n), 0, a.ws->blk_part);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_wstart_state(const CycleArgs& a) {
   hipLaunchKernelGGL(k_wstart<T>, dim3(part_count(a)), dim3(kReduceBlock), 0, a.stream,
-                     (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, (const double*)nullptr, 0.0,
-                     a.g->n, win_stride(a.g->n), 1, a.ws->blk_part);
+                     (T*)a.ws->F, (T*)a.ws->H, (T*)a.ws->wA, (T*)a.ws->whub, hub_entries(a.g),
+                     (const double*)nullptr, 0.0, a.g->n, win_stride(a.g->n), 1,
+                     a.ws->blk_part);
   return hipGetLastError();
 }
 

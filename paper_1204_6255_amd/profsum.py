@@ -138,15 +138,38 @@ def traffic_main(argv):
 
 
 def trace_main(argv):
-    """trace OUT_NAME DIR TITLE CMD: the per-kernel table of a
-    `--kernel-trace --stats` run."""
+    """trace OUT_NAME DIR TITLE CMD [AFTER_KERNEL]: the per-kernel table of a
+    `--kernel-trace --stats` run. With AFTER_KERNEL (a short name, e.g.
+    k_pull<double>), a second table covers only the dispatches that start
+    after that kernel's last dispatch (for instance after a tuner that times
+    that kernel last), and lists apart those under 12 us (launches that
+    return at the stop test)."""
     out_name, d, title, cmd = argv[:4]
+    after = argv[4] if len(argv) > 4 else None
     lines = [f"# rocprofv3 kernel summary: {title}", f"# command: {cmd}",
              "# columns: kernel, calls, total_us, average_us, min_us, max_us, percent"]
     for r in kernel_stats(d):
         lines.append(f"{short(r['Name'])}\t{r['Calls']}\t{float(r['TotalDurationNs']) / 1e3:.1f}\t"
                      f"{float(r['AverageNs']) / 1e3:.2f}\t{float(r['MinNs']) / 1e3:.2f}\t"
                      f"{float(r['MaxNs']) / 1e3:.2f}\t{float(r['Percentage']):.1f}")
+    if after:
+        with open(os.path.join(d, "run_kernel_trace.csv")) as f:
+            rows = list(csv.DictReader(f))
+        t0 = max(int(r["End_Timestamp"]) for r in rows if short(r["Kernel_Name"]) == after)
+        per = collections.defaultdict(list)
+        for r in rows:
+            if int(r["Start_Timestamp"]) > t0:
+                per[short(r["Kernel_Name"])].append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        lines.append(f"# dispatches after the last {after}: kernel, calls, average_us, min_us, "
+                     "max_us; then the same over the calls of at least 12 us")
+        for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+            full = [x for x in v if x >= 12.0]
+            line = (f"{k}\t{len(v)}\t{sum(v) / len(v):.2f}\t{min(v):.2f}\t{max(v):.2f}")
+            if full:
+                line += (f"\t| {len(full)}\t{sum(full) / len(full):.2f}\t{min(full):.2f}"
+                         f"\t{max(full):.2f}")
+            lines.append(line)
     with open(os.path.join(PROFILES, out_name), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
