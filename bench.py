@@ -79,6 +79,9 @@ def parse_args():
     p.add_argument("--serve-seconds", type=float, default=6.0,
                    help="length of each serving phase")
     p.add_argument("--serve-kmax", type=int, default=16)
+    p.add_argument("--window-cfg", default=None, metavar="TILE,HUBS,GRID",
+                   help="pin the window configuration of the headline graph instead of tuning it "
+                        "(for profiler runs, whose timing would steer the tuner)")
     p.add_argument("--calibration-copy", action="store_true",
                    help="after the timed region, fill 1 GiB and then sum it (a write-only and a "
                         "read-only kernel of known size, for scaling memory counters)")
@@ -625,6 +628,10 @@ def main():
     stats = graphgen.graph_stats(n, src, dst)
     g = di.Graph(n, src, dst)
     del src, dst
+    if args.window_cfg:
+        tile, hubs, grid = (int(v) for v in args.window_cfg.split(","))
+        if di.di_graph_set_window(g.handle, tile, hubs, grid) != di.DI_OK:
+            raise RuntimeError(di.di_last_error())
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     opts = di.di_opts_default()
     opts.kernel = {"auto": di.DI_KERNEL_AUTO, "pull": di.DI_KERNEL_PULL, "push": di.DI_KERNEL_PUSH,

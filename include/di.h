@@ -211,6 +211,16 @@ di_status di_graph_tuning(const di_graph* g, int32_t* kernel, int32_t* tile, int
                           int32_t* grid, int32_t* tuned, double* us_default, double* us_tuned,
                           double* us_pull);
 
+/* Sets the graph's window-push configuration instead of tuning it: tile
+ * nodes per tile (1024, 2048 or 4096, a shape the graph allows), hubs active
+ * hub rows (0 to the graph's ranked hubs, at most 1024), grid_cap the largest
+ * number of blocks (1 to 1024). DI_KERNEL_AUTO then runs DI-SOP with this
+ * window configuration (no tuning, no pull), as does DI_KERNEL_WINDOW.
+ * For profiling and reproducible timing. DI_E_INVAL for a value outside
+ * those ranges, with nothing changed. Not to be called while a solve on the
+ * graph runs. */
+di_status di_graph_set_window(di_graph* g, int32_t tile, int32_t hubs, int32_t grid_cap);
+
 /* Frees the graph and its device memory. NULL is ignored. */
 void di_graph_destroy(di_graph* g);
 

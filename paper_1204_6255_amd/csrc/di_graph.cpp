@@ -52,7 +52,7 @@ void free_graph_device(di_graph* g) {
   void* ptrs[] = {g->row_ptr, g->col,    g->info,   g->csc_ptr,  g->csc_idx, g->row_lo,
                   g->it_r0,   g->it_r1,  g->it_l0,  g->it_l1,    g->it_seg,  g->heavy_row,
                   g->heavy_seg, g->hc_seg0, g->hc_seg1, g->hc_off, g->seg_heavy,
-                  g->wp_col,  g->wp_near, g->hub_rank_node, g->hub_id_node, g->hub_id_rank};
+                  g->wp_col,  g->wp_info, g->hub_rank_node, g->hub_id_node, g->hub_id_rank};
   for (void* p : ptrs) (void)hipFree(p);
   for (int sh = 0; sh < di::kWinShapes; ++sh) {
     (void)hipFree(g->hub_tile[sh]);
@@ -71,7 +71,7 @@ void free_graph_device(di_graph* g) {
   g->hc_seg0 = g->hc_seg1 = g->hc_off = nullptr;
   g->seg_heavy = nullptr;
   g->wp_col = nullptr;
-  g->wp_near = nullptr;
+  g->wp_info = nullptr;
   g->hub_rank_node = g->hub_id_node = g->hub_id_rank = nullptr;
 }
 
@@ -97,21 +97,16 @@ di_status upload(V** dst, const std::vector<V>& src) {
 // into a ranked hub coded -1 - rank. Hubs are ranked by far in-links (at
 // least kWinHubMinFar, ties to the lower id), at most kWinHubMax of them.
 di_status build_window(di_graph* g, const std::vector<int64_t>& row_ptr,
-                       const std::vector<int32_t>& col) {
+                       const std::vector<int32_t>& col, const std::vector<uint32_t>& info) {
   const int64_t n = g->n;
   const int64_t W = di::kWinHalo;
   std::vector<int64_t> farin((size_t)n, 0);
-  std::vector<uint32_t> nnear((size_t)n, 0);
   int64_t near_links = 0;
   for (int64_t i = 0; i < n; ++i)
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
       const int64_t j = col[e];
-      if (j - i <= W && i - j <= W) {
-        ++nnear[i];
-        ++near_links;
-      } else {
-        ++farin[j];
-      }
+      if (j - i <= W && i - j <= W) ++near_links;
+      else ++farin[j];
     }
   std::vector<int32_t> ranked;
   for (int64_t j = 0; j < n; ++j)
@@ -127,7 +122,7 @@ di_status build_window(di_graph* g, const std::vector<int64_t>& row_ptr,
   std::vector<int32_t> rank((size_t)n, -1);
   for (size_t r = 0; r < ranked.size(); ++r) rank[(size_t)ranked[r]] = (int32_t)r;
   std::vector<int32_t> wcol(col.size());
-  std::vector<uint32_t> wnear((size_t)n, 0);
+  std::vector<uint32_t> winfo((size_t)n, 0);
   for (int64_t i = 0; i < n; ++i) {
     int64_t q = row_ptr[i];
     for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -139,7 +134,8 @@ di_status build_window(di_graph* g, const std::vector<int64_t>& row_ptr,
       if (!(j - i <= W && i - j <= W))
         wcol[(size_t)q++] = rank[(size_t)j] >= 0 ? -1 - rank[(size_t)j] : (int32_t)j;
     }
-    wnear[(size_t)i] = nnear[(size_t)i] | (rank[(size_t)i] >= 0 ? di::kHubBit : 0u);
+    winfo[(size_t)i] = (info[(size_t)i] & (di::kOutMask | di::kLoopBit)) |
+                       (rank[(size_t)i] >= 0 ? di::kHubBit : 0u);
   }
   std::vector<int32_t> id_node(ranked.begin(), ranked.end());
   std::sort(id_node.begin(), id_node.end());
@@ -148,7 +144,7 @@ di_status build_window(di_graph* g, const std::vector<int64_t>& row_ptr,
   g->n_hubs = (int64_t)ranked.size();
   g->near_links = near_links;
   di_status st = upload(&g->wp_col, wcol);
-  if (st == DI_OK) st = upload(&g->wp_near, wnear);
+  if (st == DI_OK) st = upload(&g->wp_info, winfo);
   if (st == DI_OK) st = upload(&g->hub_rank_node, ranked);
   if (st == DI_OK) st = upload(&g->hub_id_node, id_node);
   if (st == DI_OK) st = upload(&g->hub_id_rank, id_rank);
@@ -292,7 +288,7 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
     st = upload(&g->row_ptr, row_ptr);
     if (st == DI_OK) st = upload(&g->col, col);
     if (st == DI_OK) st = upload(&g->info, info);
-    if (st == DI_OK) st = build_window(g, row_ptr, col);
+    if (st == DI_OK) st = build_window(g, row_ptr, col, info);
     std::vector<int64_t>().swap(row_ptr);
     std::vector<int32_t>().swap(col);
     if (st == DI_OK) {

@@ -95,8 +95,9 @@ inline int64_t win_hub_rows(int64_t tiles_of_smallest_shape) {
                                      : (tiles_of_smallest_shape < kWinMaxGrid ? tiles_of_smallest_shape
                                                                               : kWinMaxGrid);
 }
-// wp_near: near-link count in bits 0..30, hub flag in bit 31
-constexpr uint32_t kHubBit = 0x80000000u;
+// wp_info: the node word as in info (out-degree, self-loop bit) with bit 30
+// (the pull's heavy-row bit there) the ranked-hub flag
+constexpr uint32_t kHubBit = 0x40000000u;
 
 // Control block: two copies. The select kernel of cycle c reads copy c & 1
 // (the state after cycle c - 1) and its block 0 writes copy (c + 1) & 1; the
@@ -232,11 +233,12 @@ struct di_graph {
   int32_t* seg_heavy = nullptr;   // n_segs: the heavy row (index) of each segment
   // window push: out-links per row (offsets row_ptr) with the near links
   // (|i - j| <= kWinHalo, ids) first and the far links after them (ids, or
-  // -1 - r for the hub of rank r); wp_near per node (near count | kHubBit);
-  // the ranked hubs: node of each rank, and the hubs by ascending id (node,
-  // rank) with, per tile shape, each tile's range of them
+  // -1 - r for the hub of rank r); wp_info per node (info's out-degree and
+  // self-loop bit, and kHubBit); the ranked hubs: node of each rank, and the
+  // hubs by ascending id (node, rank) with, per tile shape, each tile's
+  // range of them
   int32_t* wp_col = nullptr;
-  uint32_t* wp_near = nullptr;
+  uint32_t* wp_info = nullptr;
   int64_t n_hubs = 0;
   int32_t* hub_rank_node = nullptr;  // n_hubs
   int32_t* hub_id_node = nullptr;    // n_hubs, ascending

@@ -1316,4 +1316,31 @@ di_status di_graph_tuning(const di_graph* gc, int32_t* kernel, int32_t* tile, in
   return DI_OK;
 }
 
+di_status di_graph_set_window(di_graph* g, int32_t tile, int32_t hubs, int32_t grid_cap) {
+  if (!g) {
+    di::set_error("di_graph_set_window: graph is NULL");
+    return DI_E_INVAL;
+  }
+  int shape = -1;
+  for (int sh = 0; sh < di::kWinShapes; ++sh)
+    if (di::kWinTileOf[sh] == tile) shape = sh;
+  if (shape < 0 || !g->window_ok[shape]) {
+    di::set_error("di_graph_set_window: tile must be 1024, 2048 or 4096 and allowed by the graph");
+    return DI_E_INVAL;
+  }
+  if (hubs < 0 || hubs > std::min<int64_t>(g->n_hubs, di::kWinHubMax) || grid_cap < 1 ||
+      grid_cap > di::kWinMaxGrid) {
+    di::set_error("di_graph_set_window: hubs or grid_cap out of range");
+    return DI_E_INVAL;
+  }
+  std::lock_guard<std::mutex> lock(g->mu);
+  g->win_cfg.shape = shape;
+  g->win_cfg.hubs = hubs;
+  g->win_cfg.grid_cap = grid_cap;
+  g->win_use_pull = false;
+  g->win_us_default = g->win_us_tuned = g->pull_us = 0.0;
+  g->win_tuned = true;
+  return DI_OK;
+}
+
 }  // extern "C"

@@ -10,14 +10,16 @@
 //   - the fluid of node i at the cycle's start is F_i (what the node kept,
 //     plus what its own tile pushed to it) + the far accumulator A_i (far
 //     links, device-scope atomics) + what the neighbouring tiles left in
-//     their halos (near links across a tile boundary) + for a hub row the
-//     block partials of the previous launch (far links into the hubs);
+//     their halos (near links across a tile boundary) + for a hub row what
+//     the blocks of the previous launch sent it (far links into the hubs);
 //   - near links (|i - j| <= kWinHalo) are added into the tile's LDS window
 //     [a - kWinHalo, a + tile + kWinHalo) with LDS atomics; the window's
 //     middle goes straight to F, its two halos to the neighbours' next cycle;
 //   - far links into one of the graph's hub rows (the nodes with the most
-//     far in-links) are added into per-block LDS accumulators, written out
-//     once per launch; other far links are device-scope atomics into the far
+//     far in-links) are added into per-block LDS accumulators, whose nonzero
+//     values each block writes once per launch into a table by hub and
+//     block; the hub's tile sums its row there at the next cycle's start and
+//     clears it. Other far links are device-scope atomics into the far
 //     accumulator of the next cycle.
 // So the links a cycle reads are the links it moves (plus each sender's row
 // offset), and every state array has two copies by cycle parity: cycle c
@@ -60,10 +62,9 @@ __device__ inline void lds_add(float* p, float v) {
 // launch's parity).
 template <typename T>
 struct WinState {
-  const uint32_t* info;
+  const uint32_t* wp_info;  // node words with the ranked-hub bit
   const int64_t* row_ptr;
   const int32_t* wp_col;
-  const uint32_t* wp_near;
   const int32_t* hub_rank_node;  // node of each hub rank
   const int32_t* hub_id_node;    // ranked hubs by ascending id ...
   const int32_t* hub_id_rank;    // ... and their ranks
@@ -99,6 +100,7 @@ __device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = wave; k < h1 - h0; k += NW) {
     const int r = S.hub_id_rank[h0 + k];
+    const int node = S.hub_id_node[h0 + k];
     double acc = 0.0;
     if (add && r < S.K) {
       // kHubBatch loads of the row in flight per lane, then their sum (in
@@ -121,7 +123,7 @@ __device__ inline int tile_hubs(const WinState<T>& S, int64_t tile, int G, bool 
     }
     acc = wave_sum(acc);
     if (lane == 0) {
-      s_hnode[k] = S.hub_id_node[h0 + k];
+      s_hnode[k] = node;
       s_hadd[k] = (T)acc;
     }
   }
@@ -271,14 +273,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   // a tile's loads: kept fluid, far accumulator, history, node words, the
   // halo values of the tile's first and last W nodes, the tile's first link
   T raw[4], av[4], hv[4], hl[4], hr[4];
-  uint32_t w[4], wn[4];
+  uint32_t w[4];
   int64_t ebase = 0;
   int nh = 0;
   auto load_tile = [&](int64_t tile) {
     const int64_t i0 = tile * TILE + l0;
     load4(S.F, i0, S.n, raw);
-    load4(S.info, i0, S.n, w);
-    load4(S.wp_near, i0, S.n, wn);
+    load4(S.wp_info, i0, S.n, w);
     load4(S.H, i0, S.n, hv);
     ebase = S.row_ptr[tile * TILE];
 #pragma unroll
@@ -293,13 +294,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     nh = tile_hubs<T, BLOCK>(S, tile, G, add, true, s_hnode, s_hadd);
   };
 
+  // the last cycle's records, folded in one order by every block (the
+  // first BLOCK of them loaded before the tile, so that the two overlap)
+  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
+  Part rp = v;
+  if (tid < nrec_in) rp = rec_in[tid];
   int64_t tile = blockIdx.x;
   load_tile(tile);
   for (int k = tid; k < nhub; k += BLOCK) s_hub[k] = (T)0;
-
-  // the last cycle's records, folded in one order by every block
-  Part v{0.0, 0.0, 0.0, 0ull, 0u, 0u};
-  for (int p = tid; p < nrec_in; p += BLOCK) part_add(v, rec_in[p]);
+  part_add(v, rp);
+  for (int p = tid + BLOCK; p < nrec_in; p += BLOCK) part_add(v, rec_in[p]);
   Ctl c0;
   if (tid == 0) c0 = ctl[parity];
   v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         }
         if (l0 < W && tile > 0) fv[m] = fv[m] + hl[m];
         if (l0 >= TILE - W && tile + 1 < S.ntiles) fv[m] = fv[m] + hr[m];
-        if (wn[m] & kHubBit) {
+        if (w[m] & kHubBit) {
           int lo = 0, hi = nh - 1;
           while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -398,6 +402,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       store4(S.A_cur, i0, S.n, zero);
     }
     if (any_sel) store4(S.H, i0, S.n, hv);
+    // the kept fluid starts the tile's part of the window, which the near
+    // pushes then add to (the window was cleared before the last barrier)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s_win[W + l0 + m] = keep[m];
     // block scans of the link counts (node order): every node's first link
     // relative to the tile's first link, and each sender's position among
     // the tile's moved links
@@ -465,7 +473,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     // neighbours
     T nv[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) nv[m] = keep[m] + s_win[W + l0 + m];
+    for (int m = 0; m < 4; ++m) nv[m] = s_win[W + l0 + m];
     store4(S.F, i0, S.n, nv);
     for (int q = tid; q < W; q += BLOCK) {
       S.halo_next[tile * 2 * W + q] = s_win[q];
@@ -516,7 +524,7 @@ __global__ __launch_bounds__(BLOCK) void k_wfold(WinState<T> S, Part* __restrict
         const T raw = S.F[i];
         T fv = raw;
         if (add) {
-          fv = start_value<T, TILE>(S, fv, i, tile, tid + m * BLOCK, S.wp_near[i], s_hnode, s_hadd,
+          fv = start_value<T, TILE>(S, fv, i, tile, tid + m * BLOCK, S.wp_info[i], s_hnode, s_hadd,
                                     nh);
           if (fv != raw) S.F[i] = fv;
         }
@@ -591,10 +599,9 @@ WinState<T> win_state(const CycleArgs& a, int parity) {
   const int sh = a.wcfg.shape;
   const int64_t n = g->n;
   WinState<T> S;
-  S.info = g->info;
+  S.wp_info = g->wp_info;
   S.row_ptr = g->row_ptr;
   S.wp_col = g->wp_col;
-  S.wp_near = g->wp_near;
   S.hub_rank_node = g->hub_rank_node;
   S.hub_id_node = g->hub_id_node;
   S.hub_id_rank = g->hub_id_rank;

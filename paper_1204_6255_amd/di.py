@@ -144,6 +144,8 @@ def lib():
     L.di_graph_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(dbl), P(dbl),
                                   P(dbl)]
     L.di_graph_tuning.restype = i32
+    L.di_graph_set_window.argtypes = [vp, i32, i32, i32]
+    L.di_graph_set_window.restype = i32
     L.di_residual_dev_noalloc.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
     L.di_residual_dev_noalloc.restype = i32
     L.di_serve_create.argtypes = [ctypes.c_size_t, i32, P(di_opts), P(vp)]
@@ -292,6 +294,12 @@ def di_graph_tuning(h):
     return {"kernel": {DI_KERNEL_WINDOW: "window", DI_KERNEL_PULL: "pull"}[v[0].value],
             "tile": v[1].value, "hubs": v[2].value, "grid": v[3].value, "tuned": bool(v[4].value),
             "us_default": u[0].value, "us_tuned": u[1].value, "us_pull": u[2].value}
+
+
+def di_graph_set_window(h, tile: int, hubs: int, grid_cap: int) -> int:
+    """Pins the graph's window-push configuration (no tuning). Returns the
+    status."""
+    return lib().di_graph_set_window(h, int(tile), int(hubs), int(grid_cap))
 
 
 def di_residual_dev(h, B_dev, d: float, X_dev, R_dev=None, stream=None):

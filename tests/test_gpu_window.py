@@ -230,3 +230,34 @@ def test_window_at_the_benchmark_configuration(torch_cuda):
     assert np.abs(X - X_ref).sum() <= 1e-9
     _, r_true = oracle.residual(og, B, D, X)
     assert abs(r_true - st.resid_l1) <= 1e-14
+
+
+def test_pinned_window_configuration(torch_cuda):
+    """di_graph_set_window: out-of-range values are rejected with nothing
+    changed; a pinned configuration is what DI_KERNEL_AUTO then runs (no
+    tuning), including grids smaller than the tile count (blocks take
+    several tiles), and every one gives the oracle's solution and the exact
+    residual."""
+    n = 10000
+    src, dst = graphgen.web_graph(n, seed=4)
+    og = oracle.Graph(n, src, dst)
+    B = graphgen.uniform_rhs(n, D)
+    X_ref, _, _ = oracle.diter(og, B, D, oracle.SOP, tol=1e-13)
+    g = di.Graph(n, src, dst)
+    for bad in [(3000, 0, 8), (1024, -1, 8), (1024, 1025, 8), (1024, 0, 0), (1024, 0, 1025)]:
+        assert di.di_graph_set_window(g.handle, *bad) == di.DI_E_INVAL, bad
+    assert not di.di_graph_tuning(g.handle)["tuned"]
+    for tile, hubs, grid in [(1024, 0, 3), (1024, 64, 1024), (2048, 64, 2), (4096, 16, 1)]:
+        assert di.di_graph_set_window(g.handle, tile, hubs, grid) == di.DI_OK
+        t = di.di_graph_tuning(g.handle)
+        ntiles = (n + tile - 1) // tile
+        assert t["kernel"] == "window" and t["tuned"]
+        assert (t["tile"], t["hubs"], t["grid"]) == (tile, hubs, min(grid, ntiles))
+        print(f"pinned window: tile={tile} hubs={hubs} grid={grid}", flush=True)
+        X, st = di.solve(g, None, D, TOL_PAR)
+        assert np.abs(X - X_ref).sum() <= 1e-9, (tile, hubs, grid)
+        _, r_true = oracle.residual(og, B, D, X)
+        assert st["resid_l1"] <= TOL_PAR and abs(r_true - st["resid_l1"]) <= 1e-14
+        # and the selections follow the oracle's synchronous cycles
+        _, _, recs = traced(torch_cuda, g, B, 4096)
+        check_against_sync_oracle(og, B, recs)
