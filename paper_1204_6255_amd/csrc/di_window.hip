@@ -442,31 +442,30 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     }
     __syncthreads();
     // push, parallel over the tile's moved links: thread tid moves links
-    // tid, tid + BLOCK, ..., each found by binary search over the senders'
-    // positions (the last node starting at or before it, which has links),
-    // kUnroll link loads in flight at a time
+    // tid, tid + BLOCK, ..., kUnroll at a time. A link's sender is the last
+    // node whose first moved link is at or before it (that node has links):
+    // a search of fixed depth over the positions, the kUnroll searches side
+    // by side, then the kUnroll link loads in flight together
     for (int q0 = tid; q0 < total; q0 += kUnroll * BLOCK) {
+      int lo[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) lo[u] = 0;
+#pragma unroll
+      for (int step = TILE / 2; step > 0; step >>= 1) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (s_off[lo[u] + step] <= q0 + u * BLOCK) lo[u] += step;
+      }
       int32_t code[kUnroll];
-      int slot[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int q = q0 + u * BLOCK;
-        slot[u] = -1;
-        code[u] = 0;
-        if (q < total) {
-          int lo = 0, hi = TILE - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= q) lo = mid;
-            else hi = mid - 1;
-          }
-          slot[u] = lo;
-          code[u] = S.wp_col[ebase + s_rel[lo] + (q - s_off[lo])];
-        }
+        code[u] = q < total ? S.wp_col[ebase + s_rel[lo[u]] + (q - s_off[lo[u]])] : 0;
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
-        if (slot[u] >= 0) push_link(S, code[u], a + slot[u], win0, s_snd[slot[u]], s_win, s_hub);
+        if (q0 + u * BLOCK < total)
+          push_link(S, code[u], a + lo[u], win0, s_snd[lo[u]], s_win, s_hub);
     }
     __syncthreads();
     // kept fluid plus the tile's own near pushes; the halos for the
