@@ -264,6 +264,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   __shared__ int s_wtot[2 * NW];
   __shared__ double s_r;
   __shared__ int s_done, s_cyc;
+  __shared__ Ctl s_ctl;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = gridDim.x;
   const int nhub = S.K;
@@ -301,17 +302,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   if (tid < nrec_in) rp = rec_in[tid];
   int64_t tile = blockIdx.x;
   load_tile(tile);
+  // the control block, fetched by the last wave behind its tile loads
+  if (tid == BLOCK - 64) s_ctl = ctl[parity];
   for (int k = tid; k < nhub; k += BLOCK) s_hub[k] = (T)0;
   part_add(v, rp);
   for (int p = tid + BLOCK; p < nrec_in; p += BLOCK) part_add(v, rec_in[p]);
-  Ctl c0;
-  if (tid == 0) c0 = ctl[parity];
   v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
   if (tid == 0) {
-    const Ctl c = next_ctl(c0, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
+    const Ctl c = next_ctl(s_ctl, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
     if (blockIdx.x == 0) {
       ctl[parity ^ 1] = c;
-      if (trace && !first && !c0.done && c.cycles - 1 < trace_cap)
+      if (trace && !first && !s_ctl.done && c.cycles - 1 < trace_cap)
         trace[c.cycles - 1] = di_cycle_rec{c.r_last, (int64_t)v.ops, (int32_t)v.sel,
                                            (int32_t)v.nfront};
     }

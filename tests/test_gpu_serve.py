@@ -339,14 +339,19 @@ def test_serving_errors(torch_cuda):
 def test_all_nodes_seed_set_is_uniform_pagerank(torch_cuda):
     """A seed set of every node gives B = (1-d)/N, the uniform right-hand
     side: served alone and in a column set, the answer equals the uniform
-    request's, and a batch column with that B equals a uniform column."""
+    request's (bit for bit on the deterministic paths: the solo slot's pull
+    and the column sets; to rounding on the solo slot's tuned kernel, whose
+    window push adds far links in a varying order), and a batch column with
+    that B equals a uniform column."""
     n = 10000
     _, _, g, og = graph(n, 0)
     every = np.arange(n, dtype=np.int32)
-    for flags in (0, di.DI_FLAG_SERVE_NO_SOLO):
+    for flags, kernel in ((0, di.DI_KERNEL_PULL), (0, di.DI_KERNEL_AUTO),
+                          (di.DI_FLAG_SERVE_NO_SOLO, di.DI_KERNEL_AUTO)):
         o = di.di_opts_default()
         o.precision = di.DI_FP32_REFINE
         o.flags = flags
+        o.kernel = kernel
         srv = Server(8 * GIB, 8, o)
         di.di_serve_add_graph(srv.h, g.handle, 0)
         st, t1 = di.di_serve_submit(srv.h, 0, every, D, 1e-9)
@@ -355,8 +360,12 @@ def test_all_nodes_seed_set_is_uniform_pagerank(torch_cuda):
         st, t2 = di.di_serve_submit(srv.h, 0, None, D, 1e-9)
         st, X2, _ = wait(srv, t2, n)
         assert st == di.DI_OK
-        assert np.array_equal(X1, X2)
         check(og, [], 1e-9, X1)
+        check(og, [], 1e-9, X2)
+        if flags or kernel == di.DI_KERNEL_PULL or di.di_graph_tuning(g.handle)["kernel"] == "pull":
+            assert np.array_equal(X1, X2)
+        else:
+            assert np.abs(X1 - X2).sum() <= 1e-12
         srv.close()
     B = np.stack([graphgen.ppr_rhs(n, every, D), graphgen.uniform_rhs(n, D)])
     o = di.di_opts_default()
