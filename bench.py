@@ -17,6 +17,10 @@ on the same graph.
 
 The same line also reports, on the same graph unless stated:
   fp32_refine   the same solve with FP32 fluid and FP64 residual passes;
+  methods, literal_alpha_1m, config_10k, transposed_1m, dataset2_like,
+  prefix_sweep  the other methods and kernels, the literal exponent, N = 10k,
+                the transposed graph, the high-E stand-in and the prefix
+                subgraphs (each with the tuner's choice for its graph);
   batched_ppr   personalized PageRank batches (k = 8, 64, 256 seed sets of
                 1..100 nodes, tol 1e-9 each, FP32 + FP64 refinement, one
                 batch per call): solves/s, against single FP64 solves of the
@@ -73,6 +77,7 @@ def parse_args():
     p.add_argument("--no-extras", action="store_true",
                    help="headline solve only (no FP32, method, high-E, batched or serving sections)")
     p.add_argument("--only", choices=["fp32_refine", "methods", "literal_alpha_1m", "config_10k",
+                                      "transposed_1m",
                                       "dataset2_like", "prefix_sweep", "batched_ppr", "serving"],
                    default=None,
                    help="run this one section after the headline solve (for profiling)")
@@ -342,6 +347,7 @@ def literal_alpha_section(di, graphgen, n, d, tol, kmax, solutions):
                             "nb_iter": float(st.nb_iter), "resid_l1": float(st.resid_l1),
                             "gedges_per_s": st.edges_pushed / sec / 1e9})
         solutions[f"alpha 2.1 DI-SOP {pname}"] = ("1m_a2.1", "uniform", X.cpu().numpy())
+    out["tuning"] = di.di_graph_tuning(g.handle)
     g.close()
     return out
 
@@ -364,8 +370,35 @@ def small_graph_section(di, graphgen, d, tol):
 
         sec, st = time_solves(solve, 20)
         out.append({"alpha": a, "links": int(len(src)), "ms_per_solve": sec * 1e3,
-                    "cycles": int(st.cycles), "nb_iter": float(st.nb_iter)})
+                    "cycles": int(st.cycles), "nb_iter": float(st.nb_iter),
+                    "tuning": di.di_graph_tuning(g.handle)})
         g.close()
+    return out
+
+
+def transposed_section(di, graphgen, n, d, tol, alpha, kmax):
+    """Section 2.7's workload: the benchmark graph with every link
+    reversed (Pt), FP64 DI-SOP to the same residual, and what the tuner
+    picked for it (its hub rows are the original's hubs of out-links)."""
+    import torch
+    src, dst = graphgen.web_graph(n, seed=0, alpha=alpha, kmax=kmax)
+    s, t = graphgen.transpose(src, dst)
+    del src, dst
+    g = di.Graph(n, s, t)
+    X = torch.empty(n, dtype=torch.float64, device="cuda")
+    o = di.di_opts_default()
+
+    def solve():
+        status, st = di.di_solve_dev(g.handle, None, d, tol, o, X)
+        if status != di.DI_OK:
+            raise RuntimeError(di.di_last_error())
+        return st
+
+    sec, st = time_solves(solve, 10)
+    out = {"graph": f"transpose of the N={n} benchmark graph", "ms_per_solve": sec * 1e3,
+           "cycles": int(st.cycles), "nb_iter": float(st.nb_iter), "resid_l1": float(st.resid_l1),
+           "tuning": di.di_graph_tuning(g.handle)}
+    g.close()
     return out
 
 
@@ -395,6 +428,7 @@ def high_e_section(di, graphgen, d):
             sec, st = time_solves(solve, 20)
             out["rows"].append({"matrix": mat, "method": name, "us_per_solve": sec * 1e6,
                                 "cycles": int(st.cycles), "nb_iter": float(st.nb_iter)})
+        out.setdefault("tuning", {})[mat] = di.di_graph_tuning(g.handle)
         g.close()
     return out
 
@@ -433,6 +467,7 @@ def prefix_sweep_section(di, graphgen, n, d, tol, alpha, kmax):
                                   "nb_iter": float(st.nb_iter),
                                   "resid_l1": float(st.resid_l1),
                                   "gedges_per_s": st.edges_pushed / sec / 1e9}
+        row["tuning"] = di.di_graph_tuning(g.handle)
         rows.append(row)
         g.close()
     return {"graph": f"prefixes of the N={n} benchmark graph (ids < N, induced)",
@@ -781,6 +816,8 @@ def main():
             "literal_alpha_1m": lambda: literal_alpha_section(di, graphgen, n, d, tol, args.kmax,
                                                               solutions),
             "config_10k": lambda: small_graph_section(di, graphgen, d, tol),
+            "transposed_1m": lambda: transposed_section(di, graphgen, n, d, tol, args.alpha,
+                                                        args.kmax),
             "dataset2_like": lambda: high_e_section(di, graphgen, d),
             "prefix_sweep": lambda: prefix_sweep_section(di, graphgen, n, d, tol, args.alpha,
                                                          args.kmax),
