@@ -6,7 +6,9 @@ through ctypes; the C file states the definitions and readings it follows.
 
 Functions (all FP64, single thread):
   Graph(n, src, dst)              the l_out / l_in iterators of Section 2.1
-  diter(g, B, d, ...)             DI-SOP / DI-CYC (Sections 2.5.4-2.5.5)
+  diter(g, B, d, ...)             DI-SOP / DI-CYC (Sections 2.5.4-2.5.5), in the
+                                  paper's sequential cycle or the labelled
+                                  SYNC and TILED schedules of the GPU
   di_cycle(g, F, H, ...)          one D-iteration cycle, in place
   pi(g, d, ...)                   PI / PI' (Sections 2.5.1-2.5.2)
   jacobi(g, B, d, tol)            unnormalized power (Jacobi) iteration
@@ -28,7 +30,7 @@ _LIB_PATH = os.environ.get("DI_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so
 _lib = None
 
 SOP, CYC = 0, 1
-SEQUENTIAL, SYNC = 0, 1
+SEQUENTIAL, SYNC, TILED = 0, 1, 2
 STOP_RESID, STOP_PAPER = 0, 1
 
 OK, E_INVAL, E_DUP, E_RANGE, E_NOMEM, E_NOCONV = 0, -1, -3, -4, -5, -6
@@ -85,6 +87,11 @@ def _load():
     lib.orc_di_cycle.restype = i64
     lib.orc_diter.argtypes = [vp, vp, dbl, i32, i32, i32, dbl, i64, vp, vp, ctypes.POINTER(_Stats)]
     lib.orc_diter.restype = i32
+    lib.orc_di_cycle2.argtypes = [vp, dbl, i32, i32, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_di_cycle2.restype = i64
+    lib.orc_diter2.argtypes = [vp, vp, dbl, i32, i32, i64, i64, i32, i32, dbl, i64, vp, vp,
+                               ctypes.POINTER(_Stats)]
+    lib.orc_diter2.restype = i32
     lib.orc_pi.argtypes = [vp, dbl, i32, dbl, i64, vp, ctypes.POINTER(_Stats)]
     lib.orc_pi.restype = i32
     lib.orc_jacobi.argtypes = [vp, vp, dbl, dbl, i64, vp, ctypes.POINTER(_Stats)]
@@ -150,34 +157,44 @@ def apply_p(g: Graph, d: float, x):
 
 
 def diter(g: Graph, B, d: float, variant: int = SOP, schedule: int = SEQUENTIAL,
-          stop: int = STOP_RESID, tol: float = 1e-9, max_cycles: int = 1_000_000):
-    """D-iteration solve. Returns (H, F, Stats); H approximates X."""
+          stop: int = STOP_RESID, tol: float = 1e-9, max_cycles: int = 1_000_000,
+          tile: int = 1, reach: int = 0, rounds: int = 1):
+    """D-iteration solve. Returns (H, F, Stats); H approximates X.
+    schedule TILED takes tile, reach and rounds (see di_cycle)."""
     lib = _load()
     B = _f64(B, g.n)
     H = np.empty(g.n)
     F = np.empty(g.n)
     st = _Stats()
-    rc = lib.orc_diter(g.handle, B.ctypes.data, d, variant, schedule, stop, tol, max_cycles,
-                       H.ctypes.data, F.ctypes.data, ctypes.byref(st))
+    rc = lib.orc_diter2(g.handle, B.ctypes.data, d, variant, schedule, tile, reach, rounds, stop,
+                        tol, max_cycles, H.ctypes.data, F.ctypes.data, ctypes.byref(st))
     if rc not in (OK, E_NOCONV):
         raise ValueError(f"orc_diter failed with status {rc}")
     return H, F, _stats(rc, st)
 
 
-def di_cycle(g: Graph, F, H, d: float, variant: int = SOP, schedule: int = SEQUENTIAL, e: float = 0.0):
+def di_cycle(g: Graph, F, H, d: float, variant: int = SOP, schedule: int = SEQUENTIAL, e: float = 0.0,
+             tile: int = 1, reach: int = 0, rounds: int = 1):
     """One cycle in place on float64 arrays F, H.
-    Returns (count, selected mask, e, link_ops, r used)."""
+    Returns (count, selected mask, e, link_ops, r used).
+    schedule TILED: `rounds` frontier-synchronous rounds per cycle (DI-SOP;
+    DI-CYC runs one) over tiles of `tile` ids; an amount sent along i -> j
+    with |i - j| <= reach inside i's tile is seen by the later rounds, any
+    other waits for the next cycle. count counts diffusions over the rounds."""
     lib = _load()
     if F.dtype != np.float64 or H.dtype != np.float64 or not F.flags.c_contiguous or not H.flags.c_contiguous:
         raise ValueError("F and H must be contiguous float64 arrays")
+    if schedule == TILED and (tile < 1 or reach < 0 or rounds < 1):
+        raise ValueError("TILED needs tile >= 1, reach >= 0, rounds >= 1")
     sel = np.zeros(g.n, dtype=np.uint8)
     claim = np.empty(max(g.n, 1))
+    nxt = np.empty(max(g.n, 1))
     e_c = ctypes.c_double(e)
     ops = ctypes.c_int64(0)
     r = ctypes.c_double(0.0)
-    cnt = lib.orc_di_cycle(g.handle, d, variant, schedule, F.ctypes.data, H.ctypes.data,
-                           ctypes.byref(e_c), ctypes.byref(ops), sel.ctypes.data, claim.ctypes.data,
-                           ctypes.byref(r))
+    cnt = lib.orc_di_cycle2(g.handle, d, variant, schedule, tile, reach, rounds, F.ctypes.data,
+                            H.ctypes.data, ctypes.byref(e_c), ctypes.byref(ops), sel.ctypes.data,
+                            claim.ctypes.data, nxt.ctypes.data, ctypes.byref(r))
     return int(cnt), sel.astype(bool), e_c.value, ops.value, r.value
 
 

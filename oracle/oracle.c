@@ -224,6 +224,30 @@ static void di_diffuse(const orc_graph *g, double d, int64_t i, double f, double
   }
 }
 
+/* di_diffuse for schedule 2: the amount sent along i -> j reaches F_j at
+ * once when |i - j| <= reach and j lies in i's tile of `tile` ids, and
+ * next_F_j (the next cycle's) otherwise. */
+static void di_diffuse_routed(const orc_graph *g, double d, int64_t i, double f, double *F,
+                              double *next_F, int64_t tile, int64_t reach, double *H, double *e,
+                              int64_t *link_ops) {
+  double transit;
+  if (g->loop[i]) transit = f * g->out[i] / (g->out[i] - d);
+  else transit = f;
+  H[i] += transit;
+  if (g->out[i] == 0) {
+    *e += transit;
+    return;
+  }
+  double sent = transit * d / g->out[i];
+  for (int64_t q = g->out_ptr[i]; q < g->out_ptr[i + 1]; ++q) {
+    int32_t j = g->out_idx[q];
+    if (j == i) continue;
+    if (j - i <= reach && i - j <= reach && j / tile == i / tile) F[j] += sent;
+    else next_F[j] += sent;
+    ++*link_ops;
+  }
+}
+
 /* Selection predicate. variant 0: DI-SOP, 1: DI-CYC. r is the cycle's
  * r_{n'} = sum_i |F_i|. */
 static int di_selected(const orc_graph *g, int variant, double r, int64_t i, double f) {
@@ -275,24 +299,74 @@ int64_t orc_di_cycle(const orc_graph *g, double d, int variant, int schedule, do
   return count;
 }
 
+/* One cycle of any schedule. Schedules 0 and 1 as orc_di_cycle (tile,
+ * reach and rounds unused). Schedule 2, "tiled": the frontier-synchronous
+ * cycle run in `rounds` rounds over contiguous tiles of `tile` node ids -- a
+ * labelled variant, not the paper's schedule. Each round selects, against
+ * the r of the cycle's start, from every node's current fluid, claims the
+ * selected nodes and diffuses them; what a node sends along a link i -> j
+ * with |i - j| <= reach and j in i's tile reaches F_j at once (so a later
+ * round of the same cycle sees it, as node i's successors see it in the
+ * paper's sequential cycle), what it sends along any other link waits for
+ * the next cycle. DI-CYC (and a fallback cycle) runs one round. next_F is
+ * scratch of n doubles for schedule 2. The count is of diffusions (a node
+ * diffused in two rounds counts twice); selected marks the nodes diffused
+ * at least once. */
+int64_t orc_di_cycle2(const orc_graph *g, double d, int variant, int schedule, int64_t tile,
+                      int64_t reach, int rounds, double *F, double *H, double *e,
+                      int64_t *link_ops, uint8_t *selected, double *claim, double *next_F,
+                      double *r_out) {
+  if (schedule != 2)
+    return orc_di_cycle(g, d, variant, schedule, F, H, e, link_ops, selected, claim, r_out);
+  const int64_t n = g->n;
+  double r = l1_norm(F, n);
+  if (r_out) *r_out = r;
+  int64_t count = 0;
+  if (selected) memset(selected, 0, (size_t)n);
+  for (int64_t i = 0; i < n; ++i) next_F[i] = 0.0;
+  const int nr = variant == 0 ? rounds : 1;
+  for (int k = 0; k < nr; ++k) {
+    for (int64_t i = 0; i < n; ++i) {
+      claim[i] = 0.0;
+      if (di_selected(g, variant, r, i, F[i])) {
+        claim[i] = F[i];
+        if (selected) selected[i] = 1;
+        ++count;
+      }
+    }
+    for (int64_t i = 0; i < n; ++i)
+      if (claim[i] != 0.0) F[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+      if (claim[i] != 0.0)
+        di_diffuse_routed(g, d, i, claim[i], F, next_F, tile, reach, H, e, link_ops);
+  }
+  for (int64_t i = 0; i < n; ++i) F[i] += next_F[i];
+  return count;
+}
+
 /* Full D-iteration solve from F = B, H = 0, e = 0.
- * variant: 0 DI-SOP, 1 DI-CYC. schedule: 0 sequential, 1 sync-frontier.
+ * variant: 0 DI-SOP, 1 DI-CYC. schedule: 0 sequential, 1 sync-frontier, 2
+ * tiled (tile, reach, rounds as in orc_di_cycle2; orc_diter takes 0 or 1).
  * stop 0 ("resid"): stop at the start of a cycle when sum|F| <= tol
  *   (sum|F| = ||B + P.H - H||_1 exactly, since F = B - (I-P).H);
  * stop 1 ("paper"): after each cycle, stop when
  *   sum F / (1 - d - d*e) <= tol (Section 2.5.4 with target 1/N).
  * H receives X; F (nullable) the remaining fluid. */
-int orc_diter(const orc_graph *g, const double *B, double d, int variant, int schedule, int stop,
-              double tol, int64_t max_cycles, double *H, double *F_out, orc_stats *st) {
+int orc_diter2(const orc_graph *g, const double *B, double d, int variant, int schedule,
+               int64_t tile, int64_t reach, int rounds, int stop, double tol, int64_t max_cycles,
+               double *H, double *F_out, orc_stats *st) {
   if (!g || !B || !H || !(d > 0.0 && d < 1.0) || !(tol >= 0.0) || variant < 0 || variant > 1 ||
-      schedule < 0 || schedule > 1)
+      schedule < 0 || schedule > 2 || (schedule == 2 && (tile < 1 || reach < 0 || rounds < 1)))
     return ORC_E_INVAL;
   const int64_t n = g->n;
-  double *F = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-  double *claim = schedule ? (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double)) : NULL;
-  if (!F || (schedule && !claim)) {
+  const size_t bytes = (size_t)(n > 0 ? n : 1) * sizeof(double);
+  double *F = (double *)malloc(bytes);
+  double *claim = schedule ? (double *)malloc(bytes) : NULL;
+  double *next_F = schedule == 2 ? (double *)malloc(bytes) : NULL;
+  if (!F || (schedule && !claim) || (schedule == 2 && !next_F)) {
     free(F);
     free(claim);
+    free(next_F);
     return ORC_E_NOMEM;
   }
   for (int64_t i = 0; i < n; ++i) {
@@ -316,10 +390,12 @@ int orc_diter(const orc_graph *g, const double *B, double d, int variant, int sc
       break;
     }
     double r_used = 0.0;
-    int64_t cnt = orc_di_cycle(g, d, variant, schedule, F, H, &e, &s.link_ops, NULL, claim, &r_used);
+    int64_t cnt = orc_di_cycle2(g, d, variant, schedule, tile, reach, rounds, F, H, &e, &s.link_ops,
+                                NULL, claim, next_F, &r_used);
     ++s.cycles;
     if (cnt == 0 && r_used > 0.0 && variant == 0) {
-      orc_di_cycle(g, d, 1, schedule, F, H, &e, &s.link_ops, NULL, claim, NULL);
+      orc_di_cycle2(g, d, 1, schedule, tile, reach, rounds, F, H, &e, &s.link_ops, NULL, claim,
+                    next_F, NULL);
       ++s.fallback_cycles;
     }
     if (stop == 1) {
@@ -337,7 +413,14 @@ int orc_diter(const orc_graph *g, const double *B, double d, int variant, int sc
   if (st) *st = s;
   free(F);
   free(claim);
+  free(next_F);
   return rc;
+}
+
+int orc_diter(const orc_graph *g, const double *B, double d, int variant, int schedule, int stop,
+              double tol, int64_t max_cycles, double *H, double *F_out, orc_stats *st) {
+  if (schedule < 0 || schedule > 1) return ORC_E_INVAL;
+  return orc_diter2(g, B, d, variant, schedule, 1, 0, 1, stop, tol, max_cycles, H, F_out, st);
 }
 
 /* ---------------------------------------------------------------------

@@ -17,14 +17,19 @@ from tests._dense import dense_p, dense_solve
 
 D = 0.85
 HERE = os.path.dirname(os.path.abspath(__file__))
+# the D-iteration schedules: the paper's sequential cycle, the
+# frontier-synchronous one, and tiled ones (two and three rounds a cycle)
+SCHEDULES = [("seq", oracle.SEQUENTIAL, {}), ("sync", oracle.SYNC, {}),
+             ("tiled-4-2", oracle.TILED, dict(tile=4, reach=2, rounds=2)),
+             ("tiled-16-5", oracle.TILED, dict(tile=16, reach=5, rounds=3))]
 
 
 def _all_methods(g, B, d, tol):
     """Every oracle solve of the unnormalized system, tagged."""
     out = {}
     for var, vname in ((oracle.SOP, "sop"), (oracle.CYC, "cyc")):
-        for sch, sname in ((oracle.SEQUENTIAL, "seq"), (oracle.SYNC, "sync")):
-            H, F, st = oracle.diter(g, B, d, var, sch, tol=tol)
+        for sname, sch, kw in SCHEDULES:
+            H, F, st = oracle.diter(g, B, d, var, sch, tol=tol, **kw)
             assert st.status == oracle.OK
             out[f"di-{vname}-{sname}"] = (H, st)
     x, st = oracle.gs(g, B, d, tol=tol)
@@ -215,10 +220,10 @@ def test_worked_example_selection_and_update():
             assert abs(e - c["e"][0]) < 1e-16
 
 
-@pytest.mark.parametrize("schedule", [oracle.SEQUENTIAL, oracle.SYNC])
+@pytest.mark.parametrize("sname,schedule,kw", SCHEDULES[:3])
 @pytest.mark.parametrize("variant", [oracle.SOP, oracle.CYC])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_invariants_every_cycle(seed, variant, schedule):
+def test_invariants_every_cycle(seed, variant, sname, schedule, kw):
     """F_n = B - (I-P) H_n; conservation of fluid; |F|_1 non-increasing and H
     non-decreasing for B >= 0; H_n + (I-P)^-1 F_n = X; and the stopping
     bound |X - H_n|_1 <= |F_n|_1 / (1-d)."""
@@ -236,7 +241,7 @@ def test_invariants_every_cycle(seed, variant, schedule):
     prev_l1 = F.sum()
     for _ in range(25):
         prev_H = H.copy()
-        _, _, e, _, _ = oracle.di_cycle(g, F, H, D, variant, schedule, e)
+        _, _, e, _, _ = oracle.di_cycle(g, F, H, D, variant, schedule, e, **kw)
         assert np.abs(F - (B - A @ H)).sum() <= 1e-14 * B.sum()
         cons = F.sum() + (1 - D) * H[out > 0].sum() + H[out == 0].sum()
         assert abs(cons - B.sum()) <= 1e-14 * B.sum()
@@ -416,3 +421,77 @@ def test_gauss_seidel_sweep_against_the_splitting(seed):
         xs, st = oracle.gs(g, B, D, tol=0.0, max_sweeps=sweeps)
         assert st.status == oracle.E_NOCONV and st.cycles == sweeps
         assert np.allclose(xs, x, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tiled_schedule_with_one_round_is_the_synchronous_one(seed):
+    """One round per cycle: whatever the tiles, every cycle selects the same
+    nodes, counts the same link operations and leaves the same F and H as
+    the frontier-synchronous cycle (to the order of additions)."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(20, 60))
+    src, dst = _random_graph(rng, n)
+    g = oracle.Graph(n, src, dst)
+    B = rng.random(n)
+    for tile, reach in ((1, 0), (3, 1), (8, 4), (n, n)):
+        Fs, Hs, Ft, Ht = B.copy(), np.zeros(n), B.copy(), np.zeros(n)
+        es = et = 0.0
+        for _ in range(12):
+            cs, sels, es, ops_s, rs = oracle.di_cycle(g, Fs, Hs, D, oracle.SOP, oracle.SYNC, es)
+            ct, selt, et, ops_t, rt = oracle.di_cycle(g, Ft, Ht, D, oracle.SOP, oracle.TILED, et,
+                                                      tile=tile, reach=reach, rounds=1)
+            assert (cs, ops_s) == (ct, ops_t) and np.array_equal(sels, selt)
+            assert abs(rs - rt) <= 1e-15 * rs
+            assert np.abs(Fs - Ft).sum() <= 1e-15 * B.sum()
+            assert np.abs(Hs - Ht).sum() <= 1e-15 * Hs.sum()
+            assert abs(es - et) <= 1e-15 * B.sum()
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3, 5, 12])
+def test_tiled_schedule_on_a_path(tile):
+    """A directed path 0 -> 1 -> ... -> 11 with all fluid on node 0: the
+    fluid stays a single packet, of d^k b at node k. In the synchronous
+    cycle it moves one node per cycle. In the tiled cycle with two rounds,
+    the first round moves it one node and, if that step stayed inside the
+    tile, the second round moves it once more; a step into the next tile
+    waits for the next cycle. So the node it reaches after each cycle
+    follows from the tile boundaries alone, and H holds d^k b for every node
+    it has left. (Each node passes the DI-SOP threshold (r/L) out = r/11:
+    the packet's value is r, and d r >= r/11.)"""
+    n, b = 12, 0.15
+    src = np.arange(n - 1, dtype=np.int32)
+    dst = np.arange(1, n, dtype=np.int32)
+    g = oracle.Graph(n, src, dst)
+    F = np.zeros(n)
+    F[0] = b
+    H = np.zeros(n)
+    e = 0.0
+    pos = 0
+    for cyc in range(12):
+        # the packet's path this cycle: diffused at pos (absorbed if pos is
+        # the dangling end, else sent to pos + 1); when pos + 1 lies in the
+        # same tile, diffused there again in the second round
+        cnt_x, ops_x, nxt, absorbed = 1, 0, pos, pos == n - 1
+        if not absorbed:
+            ops_x, nxt = 1, pos + 1
+            if nxt // tile == pos // tile:
+                cnt_x = 2
+                if nxt == n - 1:
+                    absorbed = True
+                else:
+                    ops_x, nxt = 2, nxt + 1
+        cnt, _, e, ops, _ = oracle.di_cycle(g, F, H, D, oracle.SOP, oracle.TILED, e,
+                                            tile=tile, reach=1, rounds=2)
+        assert (cnt, ops) == (cnt_x, ops_x), (cyc, tile)
+        if absorbed:
+            assert F.sum() == 0.0 and e == pytest.approx(D ** (n - 1) * b, rel=1e-14)
+            assert np.allclose(H, D ** np.arange(n) * b, rtol=1e-14, atol=0.0)
+            break
+        expect_F = np.zeros(n)
+        expect_F[nxt] = D ** nxt * b
+        assert np.allclose(F, expect_F, rtol=1e-14, atol=0.0), (cyc, tile)
+        expect_H = np.array([D ** k * b if k < nxt else 0.0 for k in range(n)])
+        assert np.allclose(H, expect_H, rtol=1e-14, atol=0.0), (cyc, tile)
+        pos = nxt
+    else:
+        raise AssertionError("the packet was not absorbed")
