@@ -84,7 +84,7 @@ def parse_args():
     p.add_argument("--serve-seconds", type=float, default=6.0,
                    help="length of each serving phase")
     p.add_argument("--serve-kmax", type=int, default=16)
-    p.add_argument("--window-cfg", default=None, metavar="TILE,HUBS,GRID",
+    p.add_argument("--window-cfg", default=None, metavar="TILE,HUBS,GRID[,ROUNDS]",
                    help="pin the window configuration of the headline graph instead of tuning it "
                         "(for profiler runs, whose timing would steer the tuner)")
     p.add_argument("--calibration-copy", action="store_true",
@@ -664,8 +664,8 @@ def main():
     g = di.Graph(n, src, dst)
     del src, dst
     if args.window_cfg:
-        tile, hubs, grid = (int(v) for v in args.window_cfg.split(","))
-        if di.di_graph_set_window(g.handle, tile, hubs, grid) != di.DI_OK:
+        vals = [int(v) for v in args.window_cfg.split(",")]
+        if di.di_graph_set_window(g.handle, *vals) != di.DI_OK:
             raise RuntimeError(di.di_last_error())
     X = torch.empty(n, dtype=torch.float64, device="cuda")
     opts = di.di_opts_default()

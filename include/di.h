@@ -103,8 +103,12 @@ enum {
   DI_KERNEL_WINDOW = 3 /* one launch per cycle selects and pushes a tile of
                          nodes: links within 512 ids into an LDS window, the
                          far links into LDS hub rows or device-scope atomics;
-                         reads only the links it moves. Atomic order varies,
-                         so results agree with the pull to rounding */
+                         reads only the links it moves. For DI_SOP it runs
+                         two rounds a cycle over each tile by default (see
+                         di_graph_tuning): the second diffuses, against the
+                         cycle's r, what the first moved inside the tile, so
+                         its cycles are not the pull's. Atomic order varies,
+                         so results agree with the oracle to rounding */
 };
 
 typedef struct di_graph di_graph;
@@ -196,30 +200,36 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
  * configuration (also used by DI_KERNEL_WINDOW): *kernel DI_KERNEL_WINDOW or
  * DI_KERNEL_PULL; *tile nodes per tile (1024, 2048 or 4096), *hubs active
  * hub rows (far links into the nodes with the most far in-links, summed per
- * block in LDS; at most 1024), *grid the largest number of blocks. *tuned is
- * 1 once the tuner has picked them and 0 for the defaults (the window with
- * 2048-node tiles and 256 hub rows). The tuner runs on the graph's first
- * DI_KERNEL_AUTO DI-SOP solve (unless DI_FLAG_NO_TUNE): it times ten
- * cycles of the PageRank right-hand side per candidate (the three tile
- * shapes, then hub counts, then smaller grids, then the select + pull pair)
- * and keeps the fastest; a graph of the same n, L and largest in- and
- * out-degree reuses the process's earlier choice. *us_default, *us_tuned
- * and *us_pull receive its measured time per cycle of the default window
- * configuration, of the best one, and of the pull (0 before tuning). Any
- * output pointer may be NULL. */
+ * block in LDS; at most 1024), *grid the largest number of blocks, *rounds
+ * the DI-SOP diffusion rounds per cycle over each tile (2: a second round
+ * diffuses, against the same r, the fluid the first round moved inside the
+ * tile; 1: the frontier-synchronous cycle). *tuned is 1 once the tuner has
+ * picked them and 0 for the defaults (2048-node tiles, 256 hub rows, two
+ * rounds). The tuner runs on the graph's first DI_KERNEL_AUTO DI-SOP solve
+ * (unless DI_FLAG_NO_TUNE): per candidate (the three tile shapes, then hub
+ * counts, then smaller grids, then the select + pull pair) it times eleven
+ * cycles from the PageRank right-hand side and divides by the decades the
+ * residual fell in them, and keeps the fastest; a graph of the same n, L
+ * and largest in- and out-degree reuses the process's earlier choice.
+ * *us_default, *us_tuned and *us_pull receive those times (microseconds per
+ * tenfold cut of the residual) of the default window configuration, of the
+ * best one and of the pull (0 before tuning). Any output pointer may be
+ * NULL. */
 di_status di_graph_tuning(const di_graph* g, int32_t* kernel, int32_t* tile, int32_t* hubs,
-                          int32_t* grid, int32_t* tuned, double* us_default, double* us_tuned,
-                          double* us_pull);
+                          int32_t* grid, int32_t* rounds, int32_t* tuned, double* us_default,
+                          double* us_tuned, double* us_pull);
 
 /* Sets the graph's window-push configuration instead of tuning it: tile
  * nodes per tile (1024, 2048 or 4096, a shape the graph allows), hubs active
  * hub rows (0 to the graph's ranked hubs, at most 1024), grid_cap the largest
- * number of blocks (1 to 1024). DI_KERNEL_AUTO then runs DI-SOP with this
- * window configuration (no tuning, no pull), as does DI_KERNEL_WINDOW.
- * For profiling and reproducible timing. DI_E_INVAL for a value outside
- * those ranges, with nothing changed. Not to be called while a solve on the
- * graph runs. */
-di_status di_graph_set_window(di_graph* g, int32_t tile, int32_t hubs, int32_t grid_cap);
+ * number of blocks (1 to 1024), rounds 1 or 2 (as in di_graph_tuning).
+ * DI_KERNEL_AUTO then runs DI-SOP with this window configuration (no
+ * tuning, no pull), as does DI_KERNEL_WINDOW. For profiling, reproducible
+ * timing and the frontier-synchronous cycle (rounds 1). DI_E_INVAL for a
+ * value outside those ranges, with nothing changed. Not to be called while
+ * a solve on the graph runs. */
+di_status di_graph_set_window(di_graph* g, int32_t tile, int32_t hubs, int32_t grid_cap,
+                              int32_t rounds);
 
 /* Frees the graph and its device memory. NULL is ignored. */
 void di_graph_destroy(di_graph* g);

@@ -83,6 +83,7 @@ struct WinCfg {
   int shape = 1;
   int hubs = 256;
   int grid_cap = kWinMaxGrid;
+  int rounds = 2;  // DI-SOP diffusion rounds per cycle over each tile
 };
 
 // stride of the two far-accumulator copies (whole 256-byte lines, so that

@@ -486,11 +486,21 @@ std::map<TuneKey, TuneEntry>& tune_cache() {
   return m;
 }
 
-constexpr int kTuneCycles = 10;  // timed cycles per candidate
+constexpr int kTuneCycles = 10;  // timed cycles per candidate (plus one)
 
-// Time per cycle of one window configuration: kTuneCycles DI-SOP cycles
-// from the PageRank right-hand side (after one untimed cycle), timed with
-// events on the solve's stream. Leaves the workspace's state undefined.
+// A candidate's time for one tenfold cut of the residual: us for the
+// timed cycles over the decades r fell in them (the cycle's own cost and
+// how far a cycle gets both count: a larger tile's two rounds cut r
+// further).
+double per_decade(double us, double r_before, double r_after) {
+  if (r_after > 0.0 && r_before > r_after) return us / std::log10(r_before / r_after);
+  return us;
+}
+
+// One window configuration's time per tenfold cut of the residual over the
+// first kTuneCycles + 1 DI-SOP cycles from the PageRank right-hand side,
+// timed with events on the solve's stream. Leaves the workspace's state
+// undefined.
 template <typename T>
 di_status time_window_cfg(di_graph* g, Workspace* ws, hipStream_t stream, double d,
                           const WinCfg& c, double* us) {
@@ -511,18 +521,22 @@ di_status time_window_cfg(di_graph* g, Workspace* ws, hipStream_t stream, double
   DI_TRY(ensure_events(ws, 2));
   DI_HIP(launch_reset_ctl(a));
   DI_HIP(launch_wstart<T>(a, nullptr, (1.0 - d) / (double)g->n));
-  DI_HIP(launch_wcycle<T>(a, 0, nullptr, nullptr));
+  // cycles 0 .. kTuneCycles timed; the launch after them decides r of the
+  // next cycle (the control block then holds r of cycle 0 and that r)
   DI_HIP(hipEventRecord(ws->events[0], stream));
-  for (int cyc = 1; cyc <= kTuneCycles; ++cyc) DI_HIP(launch_wcycle<T>(a, cyc, nullptr, nullptr));
+  for (int cyc = 0; cyc <= kTuneCycles; ++cyc) DI_HIP(launch_wcycle<T>(a, cyc, nullptr, nullptr));
   DI_HIP(hipEventRecord(ws->events[1], stream));
-  DI_HIP(hipEventSynchronize(ws->events[1]));
+  DI_HIP(launch_wcycle<T>(a, kTuneCycles + 1, nullptr, nullptr));
+  DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  DI_HIP(hipStreamSynchronize(stream));
   float ms = 0.f;
   DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
-  *us = 1e3 * ms / kTuneCycles;
+  const Ctl& h = ws->host_ctl[(kTuneCycles + 2) & 1];
+  *us = per_decade(1e3 * ms, h.r_first, h.r);
   return DI_OK;
 }
 
-// Time per cycle of the select + pull pair, measured as for the window.
+// The same for the select + pull pair.
 template <typename T>
 di_status time_pull(di_graph* g, Workspace* ws, hipStream_t stream, double d, double* us) {
   CycleArgs a{};
@@ -541,28 +555,30 @@ di_status time_pull(di_graph* g, Workspace* ws, hipStream_t stream, double d, do
   DI_TRY(ensure_events(ws, 2));
   DI_HIP(launch_reset_ctl(a));
   DI_HIP(launch_start<T>(a, nullptr, (1.0 - d) / (double)g->n));
-  DI_HIP(launch_select<T>(a, 0, 1));
-  DI_HIP(launch_move<T>(a, 0, nullptr, nullptr));
-  DI_HIP(launch_select<T>(a, 1, 0));
   DI_HIP(hipEventRecord(ws->events[0], stream));
-  for (int cyc = 1; cyc <= kTuneCycles; ++cyc) {
+  DI_HIP(launch_select<T>(a, 0, 1));
+  for (int cyc = 0; cyc <= kTuneCycles; ++cyc) {
     DI_HIP(launch_move<T>(a, cyc, nullptr, nullptr));
-    DI_HIP(launch_select<T>(a, cyc + 1, 0));
+    if (cyc < kTuneCycles) DI_HIP(launch_select<T>(a, cyc + 1, 0));
   }
   DI_HIP(hipEventRecord(ws->events[1], stream));
-  DI_HIP(hipEventSynchronize(ws->events[1]));
+  DI_HIP(launch_select<T>(a, kTuneCycles + 1, 0));
+  DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+  DI_HIP(hipStreamSynchronize(stream));
   float ms = 0.f;
   DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
-  *us = 1e3 * ms / kTuneCycles;
+  const Ctl& h = ws->host_ctl[(kTuneCycles + 2) & 1];
+  *us = per_decade(1e3 * ms, h.r_first, h.r);
   return DI_OK;
 }
 
 // Picks the graph's window configuration by timing candidates, greedily:
 // the tile shapes at the default hub count, then the hub counts at the best
-// shape, then smaller grids; and whether the select + pull pair is faster
-// still (small graphs, where each launch's own latency dominates). Or takes
-// the choice made for a graph of the same shape (n, L, largest in- and
-// out-degree) earlier in the process.
+// shape, then smaller grids, with one and with two rounds a cycle; and
+// whether the select + pull pair is faster still (small graphs, where each
+// launch's own latency dominates). Candidates compare by time per tenfold
+// cut of the residual. Or takes the choice made for a graph of the same
+// shape (n, L, largest in- and out-degree) earlier in the process.
 template <typename T>
 di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) {
   {
@@ -585,40 +601,58 @@ di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) 
     }
   }
   const WinCfg def = default_window_cfg(g);
-  WinCfg best = def;
-  double best_us = 0.0, def_us = 0.0;
+  double def_us = 0.0;
   DI_TRY(time_window_cfg<T>(g, ws, stream, d, def, &def_us));
-  best_us = def_us;
-  auto consider = [&](const WinCfg& c) -> di_status {
-    double us = 0.0;
-    DI_TRY(time_window_cfg<T>(g, ws, stream, d, c, &us));
-    if (us < best_us) {
-      best_us = us;
-      best = c;
+  WinCfg best = def;
+  double best_us = def_us;
+  // a greedy search from a timed start: the tile shapes, then the hub
+  // counts at the best shape, then smaller grids
+  auto search = [&](const WinCfg& start, double start_us) -> di_status {
+    WinCfg local = start;
+    double local_us = start_us;
+    auto consider = [&](const WinCfg& c) -> di_status {
+      double us = 0.0;
+      DI_TRY(time_window_cfg<T>(g, ws, stream, d, c, &us));
+      if (us < local_us) {
+        local_us = us;
+        local = c;
+      }
+      return DI_OK;
+    };
+    for (int sh = 0; sh < kWinShapes; ++sh)
+      if (sh != start.shape && g->window_ok[sh]) {
+        WinCfg c = start;
+        c.shape = sh;
+        DI_TRY(consider(c));
+      }
+    const WinCfg shaped = local;
+    for (int h : {0, 64, 128, 256, 512, 1024}) {
+      const int hh = (int)std::min<int64_t>(h, g->n_hubs);
+      if (hh == shaped.hubs) continue;
+      WinCfg c = shaped;
+      c.hubs = hh;
+      DI_TRY(consider(c));
+    }
+    const WinCfg hubbed = local;
+    for (int cap : {256, 512})
+      if (cap < g->n_wtiles[hubbed.shape]) {
+        WinCfg c = hubbed;
+        c.grid_cap = cap;
+        DI_TRY(consider(c));
+      }
+    if (local_us < best_us) {
+      best_us = local_us;
+      best = local;
     }
     return DI_OK;
   };
-  for (int sh = 0; sh < kWinShapes; ++sh)
-    if (sh != def.shape && g->window_ok[sh]) {
-      WinCfg c = def;
-      c.shape = sh;
-      DI_TRY(consider(c));
-    }
-  const WinCfg shaped = best;
-  for (int h : {0, 64, 128, 512, 1024}) {
-    const int hh = (int)std::min<int64_t>(h, g->n_hubs);
-    if (hh == shaped.hubs) continue;
-    WinCfg c = shaped;
-    c.hubs = hh;
-    DI_TRY(consider(c));
-  }
-  const WinCfg hubbed = best;
-  for (int cap : {256, 512})
-    if (cap < g->n_wtiles[hubbed.shape]) {
-      WinCfg c = hubbed;
-      c.grid_cap = cap;
-      DI_TRY(consider(c));
-    }
+  // with the default rounds a cycle, then with the other number
+  DI_TRY(search(def, def_us));
+  WinCfg other = def;
+  other.rounds = 3 - def.rounds;
+  double other_us = 0.0;
+  DI_TRY(time_window_cfg<T>(g, ws, stream, d, other, &other_us));
+  DI_TRY(search(other, other_us));
   double pull_us = 0.0;
   DI_TRY(time_pull<T>(g, ws, stream, d, &pull_us));
   const bool use_pull = pull_us < best_us;
@@ -1296,8 +1330,8 @@ di_status di_residual_dev(const di_graph* g, const double* B_dev, double d, cons
 }
 
 di_status di_graph_tuning(const di_graph* gc, int32_t* kernel, int32_t* tile, int32_t* hubs,
-                          int32_t* grid, int32_t* tuned, double* us_default, double* us_tuned,
-                          double* us_pull) {
+                          int32_t* grid, int32_t* rounds, int32_t* tuned, double* us_default,
+                          double* us_tuned, double* us_pull) {
   if (!gc) {
     di::set_error("di_graph_tuning: graph is NULL");
     return DI_E_INVAL;
@@ -1309,6 +1343,7 @@ di_status di_graph_tuning(const di_graph* gc, int32_t* kernel, int32_t* tile, in
   if (tile) *tile = di::kWinTileOf[c.shape];
   if (hubs) *hubs = c.hubs;
   if (grid) *grid = di::win_grid(g, c);
+  if (rounds) *rounds = c.rounds;
   if (tuned) *tuned = g->win_tuned ? 1 : 0;
   if (us_default) *us_default = g->win_us_default;
   if (us_tuned) *us_tuned = g->win_us_tuned;
@@ -1316,7 +1351,8 @@ di_status di_graph_tuning(const di_graph* gc, int32_t* kernel, int32_t* tile, in
   return DI_OK;
 }
 
-di_status di_graph_set_window(di_graph* g, int32_t tile, int32_t hubs, int32_t grid_cap) {
+di_status di_graph_set_window(di_graph* g, int32_t tile, int32_t hubs, int32_t grid_cap,
+                              int32_t rounds) {
   if (!g) {
     di::set_error("di_graph_set_window: graph is NULL");
     return DI_E_INVAL;
@@ -1329,14 +1365,15 @@ di_status di_graph_set_window(di_graph* g, int32_t tile, int32_t hubs, int32_t g
     return DI_E_INVAL;
   }
   if (hubs < 0 || hubs > std::min<int64_t>(g->n_hubs, di::kWinHubMax) || grid_cap < 1 ||
-      grid_cap > di::kWinMaxGrid) {
-    di::set_error("di_graph_set_window: hubs or grid_cap out of range");
+      grid_cap > di::kWinMaxGrid || rounds < 1 || rounds > 2) {
+    di::set_error("di_graph_set_window: hubs, grid_cap or rounds out of range");
     return DI_E_INVAL;
   }
   std::lock_guard<std::mutex> lock(g->mu);
   g->win_cfg.shape = shape;
   g->win_cfg.hubs = hubs;
   g->win_cfg.grid_cap = grid_cap;
+  g->win_cfg.rounds = rounds;
   g->win_use_pull = false;
   g->win_us_default = g->win_us_tuned = g->pull_us = 0.0;
   g->win_tuned = true;

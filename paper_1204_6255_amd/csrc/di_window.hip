@@ -84,6 +84,7 @@ struct WinState {
   T* hub_cur;
   T* hub_next;
   int64_t hub_gs;
+  int rounds;  // diffusion rounds per cycle over each tile (DI-SOP), 1 or 2
 };
 
 // The tile's ranked hubs: their ids ascending (s_hnode) and, when `add`,
@@ -170,19 +171,25 @@ __device__ inline T start_value(const WinState<T>& S, T f, int64_t i, int64_t ti
 
 // One link i -> code of a push: links into an active hub (code = -1 - r,
 // r < K) into the block's hub accumulators, near links (|code - i| <= W)
-// into the window, other far links into the next far accumulator.
-template <typename T>
-__device__ inline void push_link(const WinState<T>& S, int32_t code, int64_t i, int64_t win0, T s,
+// into the window, other far links into the next far accumulator. Returns
+// true when the amount landed in the tile's own part of the window (the
+// window's middle, which a second round of the cycle reads).
+template <typename T, int TILE>
+__device__ inline bool push_link(const WinState<T>& S, int32_t code, int64_t i, int64_t win0, T s,
                                  T* s_win, T* s_hub) {
   if (code < 0) {
     const int r = -1 - code;
     if (r < S.K) lds_add(&s_hub[r], s);
     else atomic_add(&S.A_next[S.hub_rank_node[r]], s);
-  } else if (code - i <= W && i - code <= W) {
-    lds_add(&s_win[code - win0], s);
-  } else {
-    atomic_add(&S.A_next[code], s);
+    return false;
   }
+  if (code - i <= W && i - code <= W) {
+    const int64_t k = code - win0;
+    lds_add(&s_win[k], s);
+    return k >= W && k < W + TILE;
+  }
+  atomic_add(&S.A_next[code], s);
+  return false;
 }
 
 // Four consecutive values of a node array, as one vector access when all
@@ -239,7 +246,7 @@ __device__ inline void wave_scan2(int& x, int& y) {
 // fluid (a fold pass ran after the last cycle).
 // At least four waves per SIMD (at most 128 VGPRs): two 512-thread blocks
 // per compute unit.
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, int ROUNDS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_wcycle(
     WinState<T> S, const Part* __restrict__ rec_in, int nrec_in, Part* __restrict__ rec_out,
     Ctl* __restrict__ ctl, int parity, int first, int folded, double d, double tol,
@@ -335,6 +342,43 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   double my_keep = 0.0, my_push = 0.0, my_e = 0.0;
   unsigned long long my_ops = 0;
   unsigned int my_sel = 0, my_front = 0;
+  // a second round of the cycle over each tile (DI-SOP's threshold only):
+  // the first round's amounts that stay in the tile are fluid the second
+  // round may diffuse again, so only the others count as pushed
+  const bool two = ROUNDS == 2 && mode == 0;
+
+  // push, parallel over the tile's moved links: thread tid moves links
+  // base + tid, base + tid + BLOCK, ..., kUnroll at a time. A link's sender
+  // is the last node whose first moved link is at or before it (that node
+  // has links): a search of fixed depth over the positions, the kUnroll
+  // searches side by side, then the kUnroll link loads in flight together.
+  // out_only: add to my_push only what leaves the tile's own window part.
+  auto push_pass = [&](int64_t a, int64_t win0, int total, bool out_only) {
+    for (int q0 = tid; q0 < total; q0 += kUnroll * BLOCK) {
+      int lo[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) lo[u] = 0;
+#pragma unroll
+      for (int step = TILE / 2; step > 0; step >>= 1) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (s_off[lo[u] + step] <= q0 + u * BLOCK) lo[u] += step;
+      }
+      int32_t code[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int q = q0 + u * BLOCK;
+        code[u] = q < total ? S.wp_col[ebase + s_rel[lo[u]] + (q - s_off[lo[u]])] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (q0 + u * BLOCK < total) {
+          const T sv = s_snd[lo[u]];
+          const bool in = push_link<T, TILE>(S, code[u], a + lo[u], win0, sv, s_win, s_hub);
+          if (out_only && !in) my_push += to_d(sv);
+        }
+    }
+  };
 
   for (;;) {
     const int64_t a = tile * TILE;
@@ -391,10 +435,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
           snd[m] = (T)(t[m] * d / (double)out);
           my_ops += (unsigned long long)np[m];
           ++my_front;
-          my_push += to_d(snd[m]) * (double)np[m];
+          if (!two) my_push += to_d(snd[m]) * (double)np[m];
         }
       }
-      my_keep += to_d(keep[m]);
+      if (!two) my_keep += to_d(keep[m]);
     }
     // the far accumulator entries read are cleared; the history of the
     // diffused nodes
@@ -402,7 +446,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const T zero[4] = {(T)0, (T)0, (T)0, (T)0};
       store4(S.A_cur, i0, S.n, zero);
     }
-    if (any_sel) store4(S.H, i0, S.n, hv);
+    // (with a second round, the history is stored after it)
+    if (any_sel && !two) store4(S.H, i0, S.n, hv);
     // the kept fluid starts the tile's part of the window, which the near
     // pushes then add to (the window was cleared before the last barrier)
 #pragma unroll
@@ -442,31 +487,75 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       npos += np[m];
     }
     __syncthreads();
-    // push, parallel over the tile's moved links: thread tid moves links
-    // tid, tid + BLOCK, ..., kUnroll at a time. A link's sender is the last
-    // node whose first moved link is at or before it (that node has links):
-    // a search of fixed depth over the positions, the kUnroll searches side
-    // by side, then the kUnroll link loads in flight together
-    for (int q0 = tid; q0 < total; q0 += kUnroll * BLOCK) {
-      int lo[kUnroll];
+    push_pass(a, win0, total, two);
+    if constexpr (ROUNDS == 2) if (two) {
+      // second round: every node of the tile against the same threshold,
+      // with its fluid now (kept + what the first round moved to it inside
+      // the tile); its pushes all count, and those that stay in the tile
+      // wait for the next cycle like every other
+      __syncthreads();
+      int nsum2 = 0;
+      double t2[4];
+      bool sel2[4], any_sel2 = false;
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) lo[u] = 0;
-#pragma unroll
-      for (int step = TILE / 2; step > 0; step >>= 1) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          if (s_off[lo[u] + step] <= q0 + u * BLOCK) lo[u] += step;
+      for (int m = 0; m < 4; ++m) {
+        const int64_t i = i0 + m;
+        const T f2 = s_win[W + l0 + m];
+        const double f = to_d(f2);
+        const int out = (int)(w[m] & kOutMask);
+        const bool loop = (w[m] & kLoopBit) != 0;
+        const int dg = out - (loop ? 1 : 0);
+        const double thr = out == 0 ? 0.0 : rl * (double)out;
+        const double af = fabs(f);
+        np[m] = 0;
+        snd[m] = (T)0;
+        t2[m] = 0.0;
+        T k2 = f2;
+        sel2[m] = i < S.n && af > 0.0 && af >= thr;
+        if (sel2[m]) {
+          any_sel2 = true;
+          t2[m] = loop ? f * (double)out / ((double)out - d) : f;
+          k2 = (T)0;
+          ++my_sel;
+          if (out == 0) {
+            my_e += t2[m];
+          } else if (dg > 0) {
+            np[m] = dg;
+            snd[m] = (T)(t2[m] * d / (double)out);
+            my_ops += (unsigned long long)np[m];
+            ++my_front;
+            my_push += to_d(snd[m]) * (double)np[m];
+          }
+          s_win[W + l0 + m] = (T)0;
+        }
+        my_keep += to_d(k2);
+        nsum2 += np[m];
       }
-      int32_t code[kUnroll];
+      if (any_sel || any_sel2) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int q = q0 + u * BLOCK;
-        code[u] = q < total ? S.wp_col[ebase + s_rel[lo[u]] + (q - s_off[lo[u]])] : 0;
+        for (int m = 0; m < 4; ++m)
+          if (sel2[m]) hv[m] = (T)(to_d(hv[m]) + t2[m]);
+        store4(S.H, i0, S.n, hv);
+      }
+      int dummy = 0, ninc2 = nsum2;
+      wave_scan2(dummy, ninc2);
+      if (lane == 63) s_wtot[NW + wave] = ninc2;
+      __syncthreads();
+      int npos2 = ninc2 - nsum2, total2 = 0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        const int y = s_wtot[NW + q];
+        if (q < wave) npos2 += y;
+        total2 += y;
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (q0 + u * BLOCK < total)
-          push_link(S, code[u], a + lo[u], win0, s_snd[lo[u]], s_win, s_hub);
+      for (int m = 0; m < 4; ++m) {
+        s_off[l0 + m] = npos2;
+        s_snd[l0 + m] = snd[m];
+        npos2 += np[m];
+      }
+      __syncthreads();
+      push_pass(a, win0, total2, false);
     }
     __syncthreads();
     // kept fluid plus the tile's own near pushes; the halos for the
@@ -626,6 +715,7 @@ WinState<T> win_state(const CycleArgs& a, int parity) {
   S.hub_cur = hub + (int64_t)parity * bsz;
   S.hub_next = hub + (int64_t)(parity ^ 1) * bsz;
   S.hub_gs = win_hub_rows(g->n_wtiles[0]);
+  S.rounds = a.method == DI_SOP ? a.wcfg.rounds : 1;
   return S;
 }
 
@@ -644,7 +734,7 @@ struct CycleLaunch {
   static hipError_t run(const CycleArgs& a, int G, hipEvent_t ev0, hipEvent_t ev1,
                         const WinState<T>& S, const Part* rec_in, int nrec_in, Part* rec_out,
                         int parity, int first, int folded) {
-    auto kern = k_wcycle<T, BLOCK>;
+    auto kern = S.rounds == 2 ? k_wcycle<T, BLOCK, 2> : k_wcycle<T, BLOCK, 1>;
     if (ev0 || ev1)
       hipExtLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), 0, a.stream, ev0, ev1, 0u, S, rec_in,
                             nrec_in, rec_out, a.ws->ctl, parity, first, folded, a.d, a.tol,

@@ -141,10 +141,10 @@ def lib():
     L.di_cycles_dev.restype = i32
     L.di_residual_dev.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
     L.di_residual_dev.restype = i32
-    L.di_graph_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(dbl), P(dbl),
-                                  P(dbl)]
+    L.di_graph_tuning.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32), P(dbl),
+                                  P(dbl), P(dbl)]
     L.di_graph_tuning.restype = i32
-    L.di_graph_set_window.argtypes = [vp, i32, i32, i32]
+    L.di_graph_set_window.argtypes = [vp, i32, i32, i32, i32]
     L.di_graph_set_window.restype = i32
     L.di_residual_dev_noalloc.argtypes = [vp, vp, dbl, vp, vp, P(dbl), vp]
     L.di_residual_dev_noalloc.restype = i32
@@ -286,20 +286,22 @@ def di_cycles_dev(h, d: float, method: int, F_dev, H_dev, cycles: int, e: float 
 
 def di_graph_tuning(h):
     """What DI_KERNEL_AUTO runs for DI-SOP on the graph and its window
-    configuration: dict(kernel, tile, hubs, grid, tuned, us_default,
-    us_tuned, us_pull)."""
-    v = [ctypes.c_int32() for _ in range(5)]
+    configuration: dict(kernel, tile, hubs, grid, rounds, tuned, and the
+    tuner's us_default, us_tuned, us_pull per tenfold cut of the
+    residual)."""
+    v = [ctypes.c_int32() for _ in range(6)]
     u = [ctypes.c_double() for _ in range(3)]
     _check(lib().di_graph_tuning(h, *[ctypes.byref(x) for x in v], *[ctypes.byref(x) for x in u]))
     return {"kernel": {DI_KERNEL_WINDOW: "window", DI_KERNEL_PULL: "pull"}[v[0].value],
-            "tile": v[1].value, "hubs": v[2].value, "grid": v[3].value, "tuned": bool(v[4].value),
-            "us_default": u[0].value, "us_tuned": u[1].value, "us_pull": u[2].value}
+            "tile": v[1].value, "hubs": v[2].value, "grid": v[3].value, "rounds": v[4].value,
+            "tuned": bool(v[5].value), "us_default": u[0].value, "us_tuned": u[1].value,
+            "us_pull": u[2].value}
 
 
-def di_graph_set_window(h, tile: int, hubs: int, grid_cap: int) -> int:
+def di_graph_set_window(h, tile: int, hubs: int, grid_cap: int, rounds: int = 2) -> int:
     """Pins the graph's window-push configuration (no tuning). Returns the
     status."""
-    return lib().di_graph_set_window(h, int(tile), int(hubs), int(grid_cap))
+    return lib().di_graph_set_window(h, int(tile), int(hubs), int(grid_cap), int(rounds))
 
 
 def di_residual_dev(h, B_dev, d: float, X_dev, R_dev=None, stream=None):

@@ -98,8 +98,9 @@ def test_batch_column_independence(torch_cuda):
     X1, st1, _ = batch(g, 1, B[3:4], tol[:1])
     assert np.abs(X1[0] - X[3]).sum() <= 2 * 1e-10 / (1 - D)
     assert abs(st1[0].cycles - st[3].cycles) <= 1
-    # and the single-RHS path agrees
-    Xs, sts = di.solve(g, B[3], D, 1e-10)
+    # and the single-RHS path agrees (the pull: the batch's frontier-
+    # synchronous schedule, so the same cycles)
+    Xs, sts = di.solve(g, B[3], D, 1e-10, kernel=di.DI_KERNEL_PULL)
     assert np.abs(Xs - X[3]).sum() <= 2 * 1e-10 / (1 - D)
     assert abs(sts["cycles"] - st[3].cycles) <= 1
 

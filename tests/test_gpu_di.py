@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from paper_1204_6255_amd import di, graphgen
+from tests._sched import schedule_of
 from tests._dense import dense_solve
 
 pytestmark = pytest.mark.gpu
@@ -211,13 +212,15 @@ def test_parity_10k_pagerank(torch_cuda, alpha, kernel):
     src, dst = web(n, alpha=alpha)
     B = graphgen.uniform_rhs(n, D)
     og, X_ref = oracle_ref(n, src, dst, B)
-    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), None, kernel=kernel)
+    g = di.Graph(n, src, dst)
+    X, st, _ = gpu_solve(torch_cuda, g, None, kernel=kernel)
     assert np.abs(X - X_ref).sum() <= 1e-9
     # sum |F| is the residual of H: recompute it from X with the oracle
     _, r_true = oracle.residual(og, B, D, X)
     assert abs(r_true - st.resid_l1) <= 1e-14
-    # the frontier-synchronous schedule does the oracle's sync-mode work
-    _, _, so = oracle.diter(og, B, D, oracle.SOP, oracle.SYNC, tol=TOL_PAR)
+    # the GPU's schedule does the work of the oracle's matching mode
+    sch, kw = schedule_of(g, kernel)
+    _, _, so = oracle.diter(og, B, D, oracle.SOP, sch, tol=TOL_PAR, **kw)
     assert abs(st.cycles - so.cycles) <= 1
     assert abs(st.nb_iter - so.nb_iter) <= 0.02 * so.nb_iter
 
@@ -248,9 +251,12 @@ def test_parity_1m_bench_configuration(torch_cuda):
     X2, _, _ = gpu_solve(torch_cuda, g, None, kernel=di.DI_KERNEL_PULL)
     assert np.array_equal(X2, Xq)
     assert np.abs(Xq - X_ref).sum() <= 1e-9
-    # the push and window directions differ from it only by the order of
-    # atomic additions
-    assert np.abs(X - Xq).sum() <= 1e-12 and st.cycles == stq.cycles
+    # the default's cycles are those of the oracle's matching schedule (two
+    # rounds a cycle over the window's tiles take fewer than the pull's)
+    sch, kw = schedule_of(g, di.DI_KERNEL_AUTO)
+    _, _, so = oracle.diter(og, B, D, oracle.SOP, sch, tol=TOL_PAR, **kw)
+    assert abs(st.cycles - so.cycles) <= 1
+    # the push differs from the pull only by the order of atomic additions
     Xp, stp, _ = gpu_solve(torch_cuda, g, None, kernel=di.DI_KERNEL_PUSH)
     assert np.abs(Xp - X_ref).sum() <= 1e-9
     assert np.abs(Xp - Xq).sum() <= 1e-12
@@ -284,15 +290,17 @@ def test_fp32_fluid_at_1m(torch_cuda, kernel):
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_paper_stop_same_cycle_as_oracle_sync(torch_cuda, kernel):
     """The paper's stop rule (sum F / (1 - d - d e) <= 1/N, Section 2.5.4):
-    the GPU stops on the same cycle as the oracle's frontier-synchronous run
-    and reports the same estimate to rounding."""
+    the GPU stops on the same cycle as the oracle's run in the matching
+    schedule (frontier-synchronous, or tiled for the window push) and
+    reports the same estimate to rounding."""
     n = 10000
     src, dst = web(n)
     B = graphgen.uniform_rhs(n, D)
     og = oracle.Graph(n, src, dst)
-    _, _, so = oracle.diter(og, B, D, oracle.SOP, oracle.SYNC, stop=oracle.STOP_PAPER, tol=1.0 / n)
-    X, st, _ = gpu_solve(torch_cuda, di.Graph(n, src, dst), None, tol=1.0 / n,
-                         stop=di.DI_STOP_PAPER, kernel=kernel)
+    g = di.Graph(n, src, dst)
+    X, st, _ = gpu_solve(torch_cuda, g, None, tol=1.0 / n, stop=di.DI_STOP_PAPER, kernel=kernel)
+    sch, kw = schedule_of(g, kernel)
+    _, _, so = oracle.diter(og, B, D, oracle.SOP, sch, stop=oracle.STOP_PAPER, tol=1.0 / n, **kw)
     assert st.cycles == so.cycles
     assert abs(st.paper_err - so.paper_err) <= 1e-12 * so.paper_err
     assert abs(st.e - so.e) <= 1e-12 * so.e
@@ -342,16 +350,24 @@ def test_signed_right_hand_side(torch_cuda):
 def test_max_cycles_stops_on_an_exact_prefix(torch_cuda, kernel):
     """A solve stopped by max_cycles returns the history of exactly that many
     cycles, at and around the host's read-back points (the first after 8
-    cycles), although the host keeps a cycle queued behind each read-back."""
+    cycles), although the host keeps a cycle queued behind each read-back:
+    the pull's bit for bit that of di_cycles_dev, the others' that of the
+    oracle's matching schedule to rounding."""
     torch = torch_cuda
     n = 10000
     src, dst = web(n)
     g = di.Graph(n, src, dst)
+    og = oracle.Graph(n, src, dst)
     B = graphgen.uniform_rhs(n, D)
     for m in (1, 2, 8, 9, 10, 23):
         X, st, status = gpu_solve(torch, g, None, tol=1e-15, allow=(di.DI_E_NOCONV,), max_cycles=m,
                                   kernel=kernel)
         assert status == di.DI_E_NOCONV and st.cycles == m, (m, st.cycles)
+        sch, kw = schedule_of(g, kernel)
+        if sch != oracle.SYNC:
+            Ho, _, so = oracle.diter(og, B, D, oracle.SOP, sch, tol=0.0, max_cycles=m, **kw)
+            assert so.cycles == m and np.abs(X - Ho).sum() <= 1e-13, m
+            continue
         F = torch.from_numpy(B.copy()).cuda()
         H = torch.zeros(n, dtype=torch.float64, device="cuda")
         status, _, stc = di.di_cycles_dev(g.handle, D, di.DI_SOP, F, H, m)

@@ -1,11 +1,14 @@
 """Per-cycle trace of a solve (di_solve_trace_dev): each record against the
-hand-worked cycles of the 4-node example and against the oracle's
-frontier-synchronous cycles (Section 2.5.5 selection, one r per cycle)."""
+hand-worked cycles of the 4-node example and against the oracle's cycles in
+the schedule the GPU runs (Section 2.5.5 selection, one r per cycle):
+frontier-synchronous, or tiled with two rounds for DI-SOP on the window
+push."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_1204_6255_amd import di, graphgen
+from tests._sched import schedule_of
 from tests.test_oracle_pins import _read_worked_example
 
 pytestmark = pytest.mark.gpu
@@ -47,7 +50,9 @@ def test_trace_worked_example(torch_cuda):
     g = di.Graph(n, src, dst)
     worked = runs["sync"]
     # a tolerance far below the worked cycles: the capacity cuts the trace
-    _, st, recs = traced(torch_cuda, g, B, len(worked), d=d, tol=1e-14)
+    # (the worked cycles are frontier-synchronous: the pull's schedule)
+    _, st, recs = traced(torch_cuda, g, B, len(worked), d=d, tol=1e-14,
+                         kernel=di.DI_KERNEL_PULL)
     assert st.cycles > len(worked)
     assert len(recs) == len(worked)
     F_prev = B
@@ -62,8 +67,8 @@ def test_trace_worked_example(torch_cuda):
 @pytest.mark.parametrize("alpha", [graphgen.ALPHA_L_MATCHED, graphgen.ALPHA_LITERAL])
 def test_trace_matches_oracle_cycles(torch_cuda, alpha, kernel):
     """Every record of a whole solve on a 10k web graph equals the oracle's
-    frontier-synchronous cycle from the same state: the same nodes diffused,
-    the same link operations, r to rounding."""
+    cycle in the same schedule from the same state: the same diffusions, the
+    same link operations, r to rounding."""
     n = 10000
     src, dst = graphgen.web_graph(n, seed=0, alpha=alpha, kmax=500)
     B = graphgen.uniform_rhs(n, D)
@@ -72,15 +77,18 @@ def test_trace_matches_oracle_cycles(torch_cuda, alpha, kernel):
     assert len(recs) == st.cycles > 10
     assert sum(r.links for r in recs) == st.edges_pushed
     og = oracle.Graph(n, src, dst)
+    sch, kw = schedule_of(g, kernel)
     # links each node moves when diffused (self-loops stay)
     moves = np.bincount(src[src != dst], minlength=n) > 0
     F, H, e = B.copy(), np.zeros(n), 0.0
     for c, rec in enumerate(recs):
-        cnt, sel, e, ops, r = oracle.di_cycle(og, F, H, D, oracle.SOP, oracle.SYNC, e)
+        cnt, sel, e, ops, r = oracle.di_cycle(og, F, H, D, oracle.SOP, sch, e, **kw)
         assert abs(rec.r - r) <= 1e-13 * r, (c, rec.r, r)
-        assert rec.selected == cnt == int(sel.sum()), c
+        assert rec.selected == cnt, c
         assert rec.links == ops, c
-        assert rec.senders == int(np.count_nonzero(sel & moves)), c
+        if sch == oracle.SYNC:  # one diffusion per node and cycle
+            assert cnt == int(sel.sum()), c
+            assert rec.senders == int(np.count_nonzero(sel & moves)), c
     # the solve stopped at the first cycle whose start is within tol
     assert np.abs(F).sum() <= TOL < recs[-1].r
 
@@ -111,17 +119,19 @@ def test_trace_dicyc_matches_oracle_cycles(torch_cuda, kernel):
 def test_trace_matches_oracle_cycles_at_1m(torch_cuda):
     """The benchmark's configuration (N = 1M web graph, uniform B, default
     options): every cycle of the whole solve diffuses exactly the oracle's
-    frontier-synchronous selection, with r to rounding."""
+    selections in the same schedule (the tuned window push: two rounds a
+    cycle over its tiles), with r to rounding."""
     n = 1_000_000
     src, dst = graphgen.web_graph(n, seed=0)
     B = graphgen.uniform_rhs(n, D)
     g = di.Graph(n, src, dst)
     _, st, recs = traced(torch_cuda, g, None, 4096)
-    assert len(recs) == st.cycles > 50
+    assert len(recs) == st.cycles > 40
     og = oracle.Graph(n, src, dst)
+    sch, kw = schedule_of(g, di.DI_KERNEL_AUTO)
     F, H, e = B.copy(), np.zeros(n), 0.0
     for c, rec in enumerate(recs):
-        cnt, sel, e, ops, r = oracle.di_cycle(og, F, H, D, oracle.SOP, oracle.SYNC, e)
+        cnt, sel, e, ops, r = oracle.di_cycle(og, F, H, D, oracle.SOP, sch, e, **kw)
         # the oracle adds N terms one after another: within (N - 1) u of the sum
         assert abs(rec.r - r) <= (n - 1) * 0.5 * np.finfo(float).eps * r, (c, rec.r, r)
         assert rec.selected == cnt and rec.links == ops, c
