@@ -204,12 +204,13 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
  * the DI-SOP diffusion rounds per cycle over each tile (2: a second round
  * diffuses, against the same r, the fluid the first round moved inside the
  * tile; 1: the frontier-synchronous cycle). *tuned is 1 once the tuner has
- * picked them and 0 for the defaults (2048-node tiles, 256 hub rows, two
+ * picked them and 0 for the defaults (2048-node tiles, 1024 hub rows, two
  * rounds). The tuner runs on the graph's first DI_KERNEL_AUTO DI-SOP solve
  * (unless DI_FLAG_NO_TUNE): per candidate (the three tile shapes, then hub
- * counts, then smaller grids, then the select + pull pair) it times eleven
- * cycles from the PageRank right-hand side and divides by the decades the
- * residual fell in them, and keeps the fastest; a graph of the same n, L
+ * counts, then smaller grids, each with one and with two rounds, then the
+ * select + pull pair) it times a solve from the PageRank right-hand side
+ * until the residual has fallen four decades (at most 400 cycles), divides
+ * by the decades it fell, and keeps the fastest; a graph of the same n, L
  * and largest in- and out-degree reuses the process's earlier choice.
  * *us_default, *us_tuned and *us_pull receive those times (microseconds per
  * tenfold cut of the residual) of the default window configuration, of the

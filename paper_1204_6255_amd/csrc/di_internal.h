@@ -81,7 +81,7 @@ static_assert(kWinHalo <= 1024, "a near link must land in the tile or a neighbou
 // ranked hubs) and the largest grid.
 struct WinCfg {
   int shape = 1;
-  int hubs = 256;
+  int hubs = kWinHubMax;
   int grid_cap = kWinMaxGrid;
   int rounds = 2;  // DI-SOP diffusion rounds per cycle over each tile
 };

@@ -455,7 +455,7 @@ WinCfg default_window_cfg(const di_graph* g) {
   if (!g->window_ok[c.shape])
     for (int sh = 0; sh < kWinShapes; ++sh)
       if (g->window_ok[sh]) c.shape = sh;
-  c.hubs = (int)std::min<int64_t>(256, g->n_hubs);
+  c.hubs = (int)std::min<int64_t>(kWinHubMax, g->n_hubs);
   c.grid_cap = kWinMaxGrid;
   return c;
 }
@@ -486,89 +486,75 @@ std::map<TuneKey, TuneEntry>& tune_cache() {
   return m;
 }
 
-constexpr int kTuneCycles = 10;  // timed cycles per candidate (plus one)
+// The tuner's timed run: the solve from the PageRank right-hand side until
+// the residual has fallen four decades (at most kTuneMaxCycles cycles), with
+// the solve's own cycle loop and read-backs. A whole run, not its first few
+// cycles, since the cycles differ along a solve (the first ones diffuse
+// most of the nodes) and the two-round cycle gains more in the later ones.
+constexpr double kTuneCut = 1e-4;
+constexpr int kTuneMaxCycles = 400;
 
-// A candidate's time for one tenfold cut of the residual: us for the
-// timed cycles over the decades r fell in them (the cycle's own cost and
-// how far a cycle gets both count: a larger tile's two rounds cut r
-// further).
+// A candidate's time for one tenfold cut of the residual: us over the
+// decades r fell.
 double per_decade(double us, double r_before, double r_after) {
   if (r_after > 0.0 && r_before > r_after) return us / std::log10(r_before / r_after);
   return us;
 }
 
-// One window configuration's time per tenfold cut of the residual over the
-// first kTuneCycles + 1 DI-SOP cycles from the PageRank right-hand side,
-// timed with events on the solve's stream. Leaves the workspace's state
-// undefined.
-template <typename T>
-di_status time_window_cfg(di_graph* g, Workspace* ws, hipStream_t stream, double d,
-                          const WinCfg& c, double* us) {
+CycleArgs tune_args(di_graph* g, Workspace* ws, hipStream_t stream, double d, int direction) {
   CycleArgs a{};
   a.g = g;
   a.ws = ws;
   a.d = d;
-  a.tol = 0.0;
-  a.tol_in = 0.0;
+  a.tol = (1.0 - d) * kTuneCut;  // Σ|B| = 1 - d at the start
+  a.tol_in = a.tol;
   a.tol_rel = -1.0;
   a.method = DI_SOP;
   a.stop = DI_STOP_RESID;
-  a.max_cycles = kTuneCycles + 2;
-  a.direction = kWindow;
+  a.max_cycles = kTuneMaxCycles;
+  a.direction = direction;
   a.stream = stream;
   a.first_parts = part_count(a) + 1;
+  return a;
+}
+
+// One window configuration's time per tenfold cut of the residual over the
+// tuner's timed run. Leaves the workspace's state undefined.
+template <typename T>
+di_status time_window_cfg(di_graph* g, Workspace* ws, hipStream_t stream, double d,
+                          const WinCfg& c, double* us) {
+  CycleArgs a = tune_args(g, ws, stream, d, kWindow);
   a.wcfg = c;
   DI_TRY(ensure_events(ws, 2));
+  // one untimed cycle first: a kernel's first launch in the process also
+  // loads its code
   DI_HIP(launch_reset_ctl(a));
   DI_HIP(launch_wstart<T>(a, nullptr, (1.0 - d) / (double)g->n));
-  // cycles 0 .. kTuneCycles timed; the launch after them decides r of the
-  // next cycle (the control block then holds r of cycle 0 and that r)
+  DI_HIP(launch_wcycle<T>(a, 0, nullptr, nullptr));
+  DI_HIP(launch_reset_ctl(a));
   DI_HIP(hipEventRecord(ws->events[0], stream));
-  for (int cyc = 0; cyc <= kTuneCycles; ++cyc) DI_HIP(launch_wcycle<T>(a, cyc, nullptr, nullptr));
-  DI_HIP(hipEventRecord(ws->events[1], stream));
-  DI_HIP(launch_wcycle<T>(a, kTuneCycles + 1, nullptr, nullptr));
-  DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-  DI_HIP(hipStreamSynchronize(stream));
-  float ms = 0.f;
-  DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
-  const Ctl& h = ws->host_ctl[(kTuneCycles + 2) & 1];
-  *us = per_decade(1e3 * ms, h.r_first, h.r);
+  DI_HIP(launch_wstart<T>(a, nullptr, (1.0 - d) / (double)g->n));
+  RunTimes rt;
+  DI_TRY(run_cycles<T>(a, false, ws->events[0], &rt));
+  *us = per_decade(1e6 * rt.seconds, rt.state.r_first, rt.state.r);
   return DI_OK;
 }
 
 // The same for the select + pull pair.
 template <typename T>
 di_status time_pull(di_graph* g, Workspace* ws, hipStream_t stream, double d, double* us) {
-  CycleArgs a{};
-  a.g = g;
-  a.ws = ws;
-  a.d = d;
-  a.tol = 0.0;
-  a.tol_in = 0.0;
-  a.tol_rel = -1.0;
-  a.method = DI_SOP;
-  a.stop = DI_STOP_RESID;
-  a.max_cycles = kTuneCycles + 2;
-  a.direction = kPull;
-  a.stream = stream;
-  a.first_parts = part_count(a) + 1;
+  CycleArgs a = tune_args(g, ws, stream, d, kPull);
   DI_TRY(ensure_events(ws, 2));
   DI_HIP(launch_reset_ctl(a));
   DI_HIP(launch_start<T>(a, nullptr, (1.0 - d) / (double)g->n));
-  DI_HIP(hipEventRecord(ws->events[0], stream));
   DI_HIP(launch_select<T>(a, 0, 1));
-  for (int cyc = 0; cyc <= kTuneCycles; ++cyc) {
-    DI_HIP(launch_move<T>(a, cyc, nullptr, nullptr));
-    if (cyc < kTuneCycles) DI_HIP(launch_select<T>(a, cyc + 1, 0));
-  }
-  DI_HIP(hipEventRecord(ws->events[1], stream));
-  DI_HIP(launch_select<T>(a, kTuneCycles + 1, 0));
-  DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost, stream));
-  DI_HIP(hipStreamSynchronize(stream));
-  float ms = 0.f;
-  DI_HIP(hipEventElapsedTime(&ms, ws->events[0], ws->events[1]));
-  const Ctl& h = ws->host_ctl[(kTuneCycles + 2) & 1];
-  *us = per_decade(1e3 * ms, h.r_first, h.r);
+  DI_HIP(launch_move<T>(a, 0, nullptr, nullptr));
+  DI_HIP(launch_reset_ctl(a));
+  DI_HIP(hipEventRecord(ws->events[0], stream));
+  DI_HIP(launch_start<T>(a, nullptr, (1.0 - d) / (double)g->n));
+  RunTimes rt;
+  DI_TRY(run_cycles<T>(a, false, ws->events[0], &rt));
+  *us = per_decade(1e6 * rt.seconds, rt.state.r_first, rt.state.r);
   return DI_OK;
 }
 
@@ -619,12 +605,17 @@ di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) 
       }
       return DI_OK;
     };
-    for (int sh = 0; sh < kWinShapes; ++sh)
-      if (sh != start.shape && g->window_ok[sh]) {
-        WinCfg c = start;
-        c.shape = sh;
-        DI_TRY(consider(c));
-      }
+    auto shapes = [&]() -> di_status {
+      const WinCfg from = local;
+      for (int sh = 0; sh < kWinShapes; ++sh)
+        if (sh != from.shape && g->window_ok[sh]) {
+          WinCfg c = from;
+          c.shape = sh;
+          DI_TRY(consider(c));
+        }
+      return DI_OK;
+    };
+    DI_TRY(shapes());
     const WinCfg shaped = local;
     for (int h : {0, 64, 128, 256, 512, 1024}) {
       const int hh = (int)std::min<int64_t>(h, g->n_hubs);
@@ -633,6 +624,8 @@ di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) 
       c.hubs = hh;
       DI_TRY(consider(c));
     }
+    // the shapes once more if the hub count changed
+    if (local.hubs != shaped.hubs) DI_TRY(shapes());
     const WinCfg hubbed = local;
     for (int cap : {256, 512})
       if (cap < g->n_wtiles[hubbed.shape]) {

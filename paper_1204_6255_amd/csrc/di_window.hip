@@ -175,21 +175,17 @@ __device__ inline T start_value(const WinState<T>& S, T f, int64_t i, int64_t ti
 // true when the amount landed in the tile's own part of the window (the
 // window's middle, which a second round of the cycle reads).
 template <typename T, int TILE>
-__device__ inline bool push_link(const WinState<T>& S, int32_t code, int64_t i, int64_t win0, T s,
+__device__ inline void push_link(const WinState<T>& S, int32_t code, int64_t i, int64_t win0, T s,
                                  T* s_win, T* s_hub) {
   if (code < 0) {
     const int r = -1 - code;
     if (r < S.K) lds_add(&s_hub[r], s);
     else atomic_add(&S.A_next[S.hub_rank_node[r]], s);
-    return false;
+  } else if (code - i <= W && i - code <= W) {
+    lds_add(&s_win[code - win0], s);
+  } else {
+    atomic_add(&S.A_next[code], s);
   }
-  if (code - i <= W && i - code <= W) {
-    const int64_t k = code - win0;
-    lds_add(&s_win[k], s);
-    return k >= W && k < W + TILE;
-  }
-  atomic_add(&S.A_next[code], s);
-  return false;
 }
 
 // Four consecutive values of a node array, as one vector access when all
@@ -244,10 +240,16 @@ __device__ inline void wave_scan2(int& x, int& y) {
 // they do not depend on; nothing is written before it. first: the records
 // are the start records and F is the whole fluid; folded: F is the whole
 // fluid (a fold pass ran after the last cycle).
-// At least four waves per SIMD (at most 128 VGPRs): two 512-thread blocks
-// per compute unit.
+// Waves per SIMD: as many as the block's LDS lets a compute unit hold, at
+// most four (at most 128 VGPRs): two 512-thread blocks or one 1024-thread
+// block; three 256-thread blocks in FP64 (up to 168 VGPRs), four in FP32.
+template <typename T, int BLOCK>
+constexpr int win_waves() {
+  return (sizeof(T) == 8 && BLOCK == 256) ? 3 : 4;
+}
 template <typename T, int BLOCK, int ROUNDS>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_wcycle(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(win_waves<T, BLOCK>())))
+void k_wcycle(
     WinState<T> S, const Part* __restrict__ rec_in, int nrec_in, Part* __restrict__ rec_out,
     Ctl* __restrict__ ctl, int parity, int first, int folded, double d, double tol,
     double tol_in, double tol_rel, int method, int stop, int max_cycles,
@@ -339,7 +341,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   const int mode = s_cyc;
   const double rl = s_r / (double)S.L;
 
-  double my_keep = 0.0, my_push = 0.0, my_e = 0.0;
+  // the fluid the next cycle starts with (kept + pushed), the absorbed fluid
+  double my_r = 0.0, my_e = 0.0;
   unsigned long long my_ops = 0;
   unsigned int my_sel = 0, my_front = 0;
   // a second round of the cycle over each tile (DI-SOP's threshold only):
@@ -352,8 +355,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   // is the last node whose first moved link is at or before it (that node
   // has links): a search of fixed depth over the positions, the kUnroll
   // searches side by side, then the kUnroll link loads in flight together.
-  // out_only: add to my_push only what leaves the tile's own window part.
-  auto push_pass = [&](int64_t a, int64_t win0, int total, bool out_only) {
+  auto push_pass = [&](int64_t a, int64_t win0, int total) {
     for (int q0 = tid; q0 < total; q0 += kUnroll * BLOCK) {
       int lo[kUnroll];
 #pragma unroll
@@ -372,11 +374,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
-        if (q0 + u * BLOCK < total) {
-          const T sv = s_snd[lo[u]];
-          const bool in = push_link<T, TILE>(S, code[u], a + lo[u], win0, sv, s_win, s_hub);
-          if (out_only && !in) my_push += to_d(sv);
-        }
+        if (q0 + u * BLOCK < total)
+          push_link<T, TILE>(S, code[u], a + lo[u], win0, s_snd[lo[u]], s_win, s_hub);
     }
   };
 
@@ -435,10 +434,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
           snd[m] = (T)(t[m] * d / (double)out);
           my_ops += (unsigned long long)np[m];
           ++my_front;
-          if (!two) my_push += to_d(snd[m]) * (double)np[m];
+          my_r += to_d(snd[m]) * (double)np[m];
         }
       }
-      if (!two) my_keep += to_d(keep[m]);
+      my_r += to_d(keep[m]);
     }
     // the far accumulator entries read are cleared; the history of the
     // diffused nodes
@@ -446,8 +445,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const T zero[4] = {(T)0, (T)0, (T)0, (T)0};
       store4(S.A_cur, i0, S.n, zero);
     }
-    // (with a second round, the history is stored after it)
-    if (any_sel && !two) store4(S.H, i0, S.n, hv);
+    if (any_sel) store4(S.H, i0, S.n, hv);
     // the kept fluid starts the tile's part of the window, which the near
     // pushes then add to (the window was cleared before the last barrier)
 #pragma unroll
@@ -487,12 +485,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       npos += np[m];
     }
     __syncthreads();
-    push_pass(a, win0, total, two);
+    push_pass(a, win0, total);
     if constexpr (ROUNDS == 2) if (two) {
       // second round: every node of the tile against the same threshold,
       // with its fluid now (kept + what the first round moved to it inside
-      // the tile); its pushes all count, and those that stay in the tile
-      // wait for the next cycle like every other
+      // the tile); what it moves waits for the next cycle like every other
+      // push. The first round counted its kept and pushed fluid whole;
+      // a node that diffuses again takes its fluid f out of that count and
+      // puts back what it pushes, so that the record still sums to the
+      // fluid the next cycle starts with. The node words and the history
+      // (stored by the first round) are read again rather than held
+      // through the first push.
+      uint32_t w2[4];
+      T h2[4];
+      load4(S.wp_info, i0, S.n, w2);
+      load4(S.H, i0, S.n, h2);
       __syncthreads();
       int nsum2 = 0;
       double t2[4];
@@ -502,20 +509,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         const int64_t i = i0 + m;
         const T f2 = s_win[W + l0 + m];
         const double f = to_d(f2);
-        const int out = (int)(w[m] & kOutMask);
-        const bool loop = (w[m] & kLoopBit) != 0;
+        const int out = (int)(w2[m] & kOutMask);
+        const bool loop = (w2[m] & kLoopBit) != 0;
         const int dg = out - (loop ? 1 : 0);
-        const double thr = out == 0 ? 0.0 : rl * (double)out;
+        // (the threshold from LDS again: not held through the first push)
+        const double thr = out == 0 ? 0.0 : s_r / (double)S.L * (double)out;
         const double af = fabs(f);
         np[m] = 0;
         snd[m] = (T)0;
         t2[m] = 0.0;
-        T k2 = f2;
         sel2[m] = i < S.n && af > 0.0 && af >= thr;
         if (sel2[m]) {
           any_sel2 = true;
           t2[m] = loop ? f * (double)out / ((double)out - d) : f;
-          k2 = (T)0;
+          my_r -= f;
           ++my_sel;
           if (out == 0) {
             my_e += t2[m];
@@ -524,18 +531,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             snd[m] = (T)(t2[m] * d / (double)out);
             my_ops += (unsigned long long)np[m];
             ++my_front;
-            my_push += to_d(snd[m]) * (double)np[m];
+            my_r += to_d(snd[m]) * (double)np[m];
           }
           s_win[W + l0 + m] = (T)0;
         }
-        my_keep += to_d(k2);
         nsum2 += np[m];
       }
-      if (any_sel || any_sel2) {
+      if (any_sel2) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-          if (sel2[m]) hv[m] = (T)(to_d(hv[m]) + t2[m]);
-        store4(S.H, i0, S.n, hv);
+          if (sel2[m]) h2[m] = (T)(to_d(h2[m]) + t2[m]);
+        store4(S.H, i0, S.n, h2);
       }
       int dummy = 0, ninc2 = nsum2;
       wave_scan2(dummy, ninc2);
@@ -555,7 +561,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         npos2 += np[m];
       }
       __syncthreads();
-      push_pass(a, win0, total2, false);
+      push_pass(a, win0, total2);
     }
     __syncthreads();
     // kept fluid plus the tile's own near pushes; the halos for the
@@ -579,7 +585,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     const T v = s_hub[k];
     if (v != (T)0) S.hub_next[(int64_t)k * S.hub_gs + blockIdx.x] = v;
   }
-  Part rec{my_keep + my_push, my_keep + my_push, my_e, my_ops, my_sel, my_front};
+  Part rec{my_r, my_r, my_e, my_ops, my_sel, my_front};
   rec = block_sum_part(rec, s_part);
   if (tid == 0) rec_out[blockIdx.x] = rec;
 }
