@@ -14,6 +14,19 @@ __device__ inline double to_d(float x) { return (double)x; }
 __device__ inline void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 __device__ inline void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 
+// A control block into pinned host memory, one 64-bit system-scope store
+// per word (written through to the host, not held in the device's caches):
+// the host reads it once the launch has completed, with no copy queued
+// behind the launch.
+static_assert(sizeof(Ctl) % 8 == 0, "the control block in whole 64-bit words");
+__device__ inline void store_ctl_host(Ctl* dst, const Ctl& c) {
+  const auto* src = reinterpret_cast<const unsigned long long*>(&c);
+  auto* out = reinterpret_cast<unsigned long long*>(dst);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(Ctl) / 8); ++k)
+    __hip_atomic_store(out + k, src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Lane exchanges by DPP, an operand modifier of the vector ALU (no LDS
 // round trip). Each control used here permutes lanes within groups of 2, 4,
 // 8 or 16, so every lane has a source; the whole wave must be active.

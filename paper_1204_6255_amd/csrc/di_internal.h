@@ -126,6 +126,9 @@ struct Ctl {
   // the first selection whose r, an L1 residual, was <= 1e-9 (0: not yet)
   unsigned long long t_start;
   unsigned long long t_1e9;
+  // launches of the run that decided this copy (the selection of cycle c
+  // writes c + 1): the host's check that its pinned copy is the new one
+  unsigned long long seq;
 };
 
 // Per select tile: what its nodes did in the cycle.
@@ -185,9 +188,11 @@ struct Workspace {
   int* wflag = nullptr;         // device flag (any negative right-hand side)
   int* host_flag = nullptr;     // pinned copy
   Ctl* ctl = nullptr;           // two copies (see Ctl)
-  Ctl* host_ctl = nullptr;      // pinned copy of both, for the stop check
+  // pinned host copies of both, for the stop check: the selection kernels
+  // (k_select, k_wcycle) store each new copy here too
+  Ctl* host_ctl = nullptr;
   double* Y64 = nullptr;        // refinement: d X_j / out_j
-  Part* host_part = nullptr;    // pinned copy of the records (residual norm)
+  Part* host_part = nullptr;    // pinned: the residual sums (pabs, psum) of k_sum_parts
   double* X64 = nullptr;        // host entry points: device copy of X
   double* B64 = nullptr;        // host entry points: device copy of B
   std::vector<hipEvent_t> events;
@@ -341,6 +346,9 @@ template <typename T>
 hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 hipError_t launch_h_to_x(const CycleArgs& a, double* X);
+// Sums |F| and F over the records blk_part[0, count) in a fixed order into
+// out->pabs and out->psum (pinned host or device memory).
+hipError_t launch_sum_parts(const CycleArgs& a, int count, Part* out);
 
 // ---- window push (di_window.hip) --------------------------------------------
 // Cycle c is one launch of the window kernel: its selection reads the

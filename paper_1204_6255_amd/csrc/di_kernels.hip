@@ -89,6 +89,7 @@ __global__ void k_reset_ctl(Ctl* ctl, double* __restrict__ hacc, int64_t n2) {
     c.sel_total = 0;
     c.t_start = 0;
     c.t_1e9 = 0;
+    c.seq = 0;
     ctl[threadIdx.x] = c;
   }
 }
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(BLOCK) void k_select(
     const int32_t* __restrict__ hc_seg0, const int32_t* __restrict__ hc_seg1,
     const int32_t* __restrict__ hc_off, const double* __restrict__ seg_val, int64_t n_heavy,
     int64_t n_hchunks, int heavy_atomic, T* __restrict__ hret, const double* __restrict__ hacc,
-    Ctl* __restrict__ ctl, int parity, int first, double d,
+    Ctl* __restrict__ ctl, Ctl* __restrict__ ctl_host, int parity, int first, double d,
     double tol, double tol_in, double tol_rel, int method, int stop, int max_cycles,
     di_cycle_rec* __restrict__ trace, int trace_cap) {
   constexpr int TILE = BLOCK * M;
@@ -285,9 +286,11 @@ __global__ __launch_bounds__(BLOCK) void k_select(
   }
   v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
   if (tid == 0) {
-    const Ctl c = next_ctl(c0, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
+    Ctl c = next_ctl(c0, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
+    c.seq = c0.seq + 1;
     if (blockIdx.x == 0) {
       ctl[parity ^ 1] = c;
+      if (ctl_host) store_ctl_host(&ctl_host[parity ^ 1], c);
       // the cycle just counted: the r its selection used and the statistics
       // of that selection (folded into the records)
       if (trace && !first && !c0.done && c.cycles - 1 < trace_cap)
@@ -663,6 +666,26 @@ __global__ __launch_bounds__(kPushBlock) void k_push(T* __restrict__ F,
     }
     const int32_t j = col[s_base[lo] + e];
     atomic_add(&F[j], s_val[lo]);
+  }
+}
+
+// Sums |F| and F over the records [0, count) in a fixed order (lane l the
+// records l, l + 64, ..., then the wave's fixed-order sum) and stores both
+// (out->pabs, out->psum) with system-scope stores, so that pinned host
+// memory receives them directly. One wave.
+__global__ __launch_bounds__(64) void k_sum_parts(const Part* __restrict__ parts, int count,
+                                                  Part* __restrict__ out) {
+  const int lane = threadIdx.x;
+  double s1 = 0.0, s2 = 0.0;
+  for (int k = lane; k < count; k += 64) {
+    s1 += parts[k].pabs;
+    s2 += parts[k].psum;
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (lane == 0) {
+    __hip_atomic_store(&out->pabs, s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&out->psum, s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -1058,7 +1081,8 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        (int64_t*)nullptr, (T*)nullptr, ws->tile_stat, (const Part*)ws->blk_part,
                        nparts, g->heavy_row, g->hc_seg0, g->hc_seg1, g->hc_off,
                        (const double*)ws->seg_val, g->n_heavy, g->n_hchunks, (int)g->heavy_atomic,
-                       (T*)ws->hret, (const double*)ws->hacc, ws->ctl, parity, first, a.d, a.tol,
+                       (T*)ws->hret, (const double*)ws->hacc, ws->ctl, ws->host_ctl, parity, first,
+                       a.d, a.tol,
                        a.tol_in, a.tol_rel, a.method, a.stop,
                        a.max_cycles, a.trace, a.trace_cap);
   } else {
@@ -1069,7 +1093,7 @@ hipError_t launch_select(const CycleArgs& a, int cycle, int first) {
                        (const Part*)ws->blk_part, nparts, (const int32_t*)nullptr,
                        (const int32_t*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr,
                        (const double*)nullptr, (int64_t)0, (int64_t)0, 0, (T*)nullptr,
-                       (const double*)nullptr, ws->ctl, parity, first,
+                       (const double*)nullptr, ws->ctl, ws->host_ctl, parity, first,
                        a.d, a.tol, a.tol_in, a.tol_rel, a.method, a.stop, a.max_cycles, a.trace,
                        a.trace_cap);
   }
@@ -1119,6 +1143,12 @@ hipError_t launch_move(const CycleArgs& a, int cycle, hipEvent_t ev0, hipEvent_t
   hipLaunchKernelGGL(k_reduce<T>, dim3(reduce_grid(g->n)), dim3(kReduceBlock), 0, a.stream,
                      (const T*)ws->F, g->n, (const SelStat*)ws->tile_stat, ntiles, ws->blk_part,
                      ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const CycleArgs& a, int count, Part* out) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, a.stream, (const Part*)a.ws->blk_part,
+                     count, out);
   return hipGetLastError();
 }
 

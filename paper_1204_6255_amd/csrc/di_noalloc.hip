@@ -47,16 +47,6 @@ di_status scratch_ptr(int dev, unsigned char** out) {
   return DI_OK;
 }
 
-// |R|_1 from the pass's records, added in record order (as the host does
-// for di_residual_dev), into *l1.
-__global__ void k_fold_records(const Part* __restrict__ part, int count, double* __restrict__ l1) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < count; ++k) s += part[k].pabs;
-    *l1 = s;
-  }
-}
-
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 di_status residual_noalloc(const di_graph* gc, const double* B_dev, double d, const double* X_dev,
@@ -107,9 +97,9 @@ di_status residual_noalloc(const di_graph* gc, const double* B_dev, double d, co
   a.stream = (hipStream_t)stream_v;
   DI_HIP(launch_refine<double>(a, const_cast<double*>(X_dev), (double*)nullptr, B_dev,
                                (1.0 - d) / (double)g->n, R));
-  hipLaunchKernelGGL(k_fold_records, dim3(1), dim3(64), 0, a.stream, (const Part*)ws.blk_part,
-                     grid + 1, l1_dev);
-  DI_HIP(hipGetLastError());
+  // |R|_1 from the pass's records in the order di_residual_dev sums them
+  // (its pabs, the record's first field, at l1_dev)
+  DI_HIP(launch_sum_parts(a, grid + 1, (Part*)l1_dev));
   double l1 = 0.0;
   DI_HIP(hipMemcpyAsync(&l1, l1_dev, sizeof(double), hipMemcpyDeviceToHost, a.stream));
   DI_HIP(hipStreamSynchronize(a.stream));

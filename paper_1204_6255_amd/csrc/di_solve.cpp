@@ -136,8 +136,7 @@ size_t window_bytes(const di_graph* g, int prec) {
 // Pinned host copy of the per-block records, allocated on first use.
 di_status ensure_host_part(Workspace* ws) {
   if (!ws->host_part) {
-    const size_t bytes = ((size_t)std::max(kPullMaxGrid, kReduceGrid) + 1) * sizeof(Part);
-    hipError_t err = hipHostMalloc((void**)&ws->host_part, bytes, hipHostMallocDefault);
+    hipError_t err = hipHostMalloc((void**)&ws->host_part, sizeof(Part), hipHostMallocDefault);
     if (err != hipSuccess) {
       ws->host_part = nullptr;
       set_error(std::string("hipHostMalloc: ") + hipGetErrorString(err));
@@ -153,21 +152,22 @@ di_status ensure_refine_buffers(const di_graph* g, Workspace* ws) {
   return ensure_host_part(ws);
 }
 
-// sum |R| of the records [0, count) of a residual pass, in record order
-// (waits for the stream)
-di_status residual_norm(const CycleArgs& a, int count, double* l1, double* sum) {
-  Workspace* ws = a.ws;
-  DI_HIP(hipMemcpyAsync(ws->host_part, ws->blk_part, (size_t)count * sizeof(Part),
-                        hipMemcpyDeviceToHost, a.stream));
-  DI_HIP(hipStreamSynchronize(a.stream));
-  double s1 = 0.0, s2 = 0.0;
-  for (int k = 0; k < count; ++k) {
-    s1 += ws->host_part[k].pabs;
-    s2 += ws->host_part[k].psum;
-  }
-  *l1 = s1;
-  if (sum) *sum = s2;
+// sum |R| (and sum R) of the records [0, count) of a residual pass, in
+// k_sum_parts' fixed order: residual_queue sums them on the device into
+// host_part[0]; residual_wait waits for the stream and reads the sums.
+di_status residual_queue(const CycleArgs& a, int count) {
+  DI_HIP(launch_sum_parts(a, count, a.ws->host_part));
   return DI_OK;
+}
+di_status residual_wait(const CycleArgs& a, double* l1, double* sum) {
+  DI_HIP(hipStreamSynchronize(a.stream));
+  *l1 = a.ws->host_part[0].pabs;
+  if (sum) *sum = a.ws->host_part[0].psum;
+  return DI_OK;
+}
+di_status residual_norm(const CycleArgs& a, int count, double* l1, double* sum) {
+  DI_TRY(residual_queue(a, count));
+  return residual_wait(a, l1, sum);
 }
 
 Workspace* acquire(di_graph* g, int prec, di_status* st) {
@@ -204,13 +204,30 @@ struct PoolGuard {
 // synchronization); the others time single pull/push launches and are only
 // read for their timestamps, so they skip the system-scope fence (a cache
 // writeback that would otherwise land inside the timed launch).
+// Timing events. None carries a system-scope fence: each such fence (cache
+// write-back and invalidation) held the stream for about 10 us on this
+// device, and the host reads nothing through them (the control block has
+// its own event, `copied`).
 di_status ensure_events(Workspace* ws, size_t count) {
   while (ws->events.size() < count) {
     hipEvent_t e;
-    if (ws->events.size() < 2) DI_HIP(hipEventCreate(&e));
-    else DI_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    DI_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     ws->events.push_back(e);
   }
+  return DI_OK;
+}
+
+// The control block that the selection of cycle `sel` decided (copy
+// (sel + 1) & 1), once an event after that selection has completed: the
+// pinned copy its kernel stored, or, should that copy not be the new one
+// (seq other than sel + 1), the device's copy.
+di_status read_ctl(const CycleArgs& a, int sel, Ctl* out) {
+  Workspace* ws = a.ws;
+  const int k = (sel + 1) & 1;
+  *out = ws->host_ctl[k];
+  if (out->seq == (unsigned long long)(sel + 1)) return DI_OK;
+  DI_HIP(hipMemcpyAsync(out, ws->ctl + k, sizeof(Ctl), hipMemcpyDeviceToHost, a.stream));
+  DI_HIP(hipStreamSynchronize(a.stream));
   return DI_OK;
 }
 
@@ -314,12 +331,15 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
   int at = 0;  // the selection the last read-back follows
   for (;;) {
     at = last_sel;
+    // the selection kernels also store the control block into host_ctl:
+    // once this event completes, host_ctl holds selection `at`'s copy
     DI_HIP(hipEventRecord(ev_end, a.stream));
-    DI_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost, a.stream));
     DI_HIP(hipEventRecord(ws->copied, a.stream));
     for (int q = 0; q < kLookahead && last_sel < a.max_cycles; ++q) DI_TRY(queue_cycle());
     DI_HIP(hipEventSynchronize(ws->copied));
-    const Ctl& h = ws->host_ctl[(at + 1) & 1];
+    Ctl h;
+    DI_TRY(read_ctl(a, at, &h));
+    rt->state = h;
     if (h.done) break;
     if (at >= a.max_cycles) {
       set_error("internal: the device did not stop after max_cycles");
@@ -330,7 +350,6 @@ di_status run_cycles(const CycleArgs& a, bool timing, hipEvent_t ev_begin, RunTi
     const int todo = std::min(chunk - (last_sel - at), a.max_cycles - last_sel);
     for (int q = 0; q < todo; ++q) DI_TRY(queue_cycle());
   }
-  rt->state = ws->host_ctl[(at + 1) & 1];
   if (rt->t_start == 0) rt->t_start = rt->state.t_start;
   if (rt->t_1e9 == 0) rt->t_1e9 = rt->state.t_1e9;
   float ms = 0.f;
@@ -836,10 +855,10 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   di_stats tmp;
   std::memset(&tmp, 0, sizeof(tmp));
   // window push: once a run has stopped at cycle c, its fluid (parity c & 1)
-  // is gathered into F and its residual summed exactly
-  auto window_finish = [&](const Ctl& h, double* r_exact) -> di_status {
+  // is gathered into F (and its exact residual summed, when `sum`)
+  auto window_finish = [&](const Ctl& h, bool sum) -> di_status {
     DI_HIP(launch_wfinal<T>(a, h.cycles & 1, (!a.folded && h.cycles > 0) ? 1 : 0));
-    return residual_norm(a, win_grid(g, a.wcfg), r_exact, nullptr);
+    return sum ? residual_queue(a, win_grid(g, a.wcfg)) : DI_OK;
   };
   auto elapsed = [&](double* sec) -> di_status {
     DI_HIP(hipEventRecord(ws->events[1], stream));
@@ -871,8 +890,12 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
       tot.done = h.done;
       tot.paper_err = h.paper_err;
       if (h.done == 3) return status_from_done(3);
+      DI_TRY(window_finish(h, true));
+      // X from the history while the host waits for the residual (a
+      // restart below writes it again)
+      DI_HIP(launch_h_to_x<T>(a, X_dev));
       double r_exact = 0.0;
-      DI_TRY(window_finish(h, &r_exact));
+      DI_TRY(residual_wait(a, &r_exact, nullptr));
       tot.final_r = r_exact;
       // the stop compared the kept-plus-pushed sum with tol; should rounding
       // leave the exact residual above tol, the solve goes on from the
@@ -886,14 +909,15 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
       }
       break;
     }
-    DI_HIP(launch_h_to_x<T>(a, X_dev));
     DI_TRY(elapsed(&rt.seconds));
     fill_stats(g, tot, d, (int)sizeof(T), a.direction, rt, 0, &tmp);
     if (st) *st = tmp;
     return status_from_done(tot.done);
   }
   // FP32 passes with FP64 residual passes between them: X accumulates the
-  // passes' histories; each pass solves for the correction of X.
+  // passes' histories; each pass solves for the correction of X. A signed
+  // right-hand side is not gathered after every cycle either (below).
+  a.folded = 0;
   DI_TRY(ensure_refine_buffers(g, ws));
   DI_HIP(hipMemsetAsync(X_dev, 0, (size_t)g->n * sizeof(double), stream));
   a.tol_in = 0.5 * tol;
@@ -914,15 +938,15 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
       break;
     }
     if (h.done == 3) return status_from_done(3);
-    if (window) {  // clears the far accumulators for the next pass
-      double r_pass = 0.0;
-      DI_TRY(window_finish(h, &r_pass));
-    }
+    if (window) DI_TRY(window_finish(h, false));  // clears the far accumulators
     // inner stop or max_cycles: fold H into X and recompute the residual
     DI_HIP(launch_refine<T>(a, X_dev, (T*)ws->H, B_dev, b_uniform, (T*)ws->F));
     ++refinements;
     a.first_parts = pull_grid(g) + 1;
-    a.folded = window ? 1 : 0;  // the residual is a signed fluid
+    // the residual is a signed fluid; an FP32 pass does not gather it after
+    // every cycle: its stop is an inner one, taken on the records' bound of
+    // sum |F| (|kept| + |pushed|), and the FP64 residual pass decides
+    a.folded = 0;
     if (h.done == 2 || refinements >= kMaxRefinements) {
       DI_TRY(residual_norm(a, a.first_parts, &tot.final_r, nullptr));
       result = tot.final_r <= tol ? DI_OK : DI_E_NOCONV;
@@ -1183,10 +1207,10 @@ di_status solo_first(SoloRun* r) {
   CycleArgs& a = r->a;
   r->last_sel = 0;
   r->chunk = 8;
+  // (the selection also stores the control block into host_ctl, which the
+  // caller reads once the stream's work so far has completed)
   if (r->window) DI_HIP(launch_wcycle<double>(a, 0, nullptr, nullptr));
   else DI_HIP(launch_select<double>(a, 0, 1));
-  DI_HIP(hipMemcpyAsync(r->ws->host_ctl, r->ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost,
-                        a.stream));
   return DI_OK;
 }
 
@@ -1222,7 +1246,8 @@ di_status solo_start(SoloRun* r, const double* B_dev, double b_uniform, double d
 
 di_status solo_next(SoloRun* r, int* done) {
   CycleArgs& a = r->a;
-  const Ctl& h = r->ws->host_ctl[(r->last_sel + 1) & 1];
+  Ctl h;
+  DI_TRY(read_ctl(a, r->last_sel, &h));
   *done = h.done;
   if (h.done) return DI_OK;
   if (r->last_sel >= a.max_cycles) {
@@ -1241,14 +1266,13 @@ di_status solo_next(SoloRun* r, int* done) {
     }
     r->last_sel = c + 1;
   }
-  DI_HIP(hipMemcpyAsync(r->ws->host_ctl, r->ws->ctl, 2 * sizeof(Ctl), hipMemcpyDeviceToHost,
-                        a.stream));
   return DI_OK;
 }
 
 di_status solo_finish(SoloRun* r, double* X_dev, di_stats* st, bool* again) {
   CycleArgs& a = r->a;
-  const Ctl h = r->ws->host_ctl[(r->last_sel + 1) & 1];
+  Ctl h;
+  DI_TRY(read_ctl(a, r->last_sel, &h));
   *again = false;
   Ctl tot = r->tot;
   add_run(&tot, h);

@@ -85,6 +85,7 @@ struct WinState {
   T* hub_next;
   int64_t hub_gs;
   int rounds;  // diffusion rounds per cycle over each tile (DI-SOP), 1 or 2
+  Ctl* ctl_host;  // pinned host copies of the control block (or null)
 };
 
 // The tile's ranked hubs: their ids ascending (s_hnode) and, when `add`,
@@ -318,9 +319,11 @@ void k_wcycle(
   for (int p = tid + BLOCK; p < nrec_in; p += BLOCK) part_add(v, rec_in[p]);
   v = block_sum_part_w0<NW>(v, s_part, blockIdx.x == 0);
   if (tid == 0) {
-    const Ctl c = next_ctl(s_ctl, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
+    Ctl c = next_ctl(s_ctl, v, first, d, tol, tol_in, tol_rel, method, stop, max_cycles);
+    c.seq = s_ctl.seq + 1;
     if (blockIdx.x == 0) {
       ctl[parity ^ 1] = c;
+      if (S.ctl_host) store_ctl_host(&S.ctl_host[parity ^ 1], c);
       if (trace && !first && !s_ctl.done && c.cycles - 1 < trace_cap)
         trace[c.cycles - 1] = di_cycle_rec{c.r_last, (int64_t)v.ops, (int32_t)v.sel,
                                            (int32_t)v.nfront};
@@ -341,7 +344,8 @@ void k_wcycle(
   const int mode = s_cyc;
   const double rl = s_r / (double)S.L;
 
-  // the fluid the next cycle starts with (kept + pushed), the absorbed fluid
+  // |kept| + |pushed|: the fluid the next cycle starts with when it stays
+  // nonnegative, a bound of its sum |F| otherwise; the absorbed fluid
   double my_r = 0.0, my_e = 0.0;
   unsigned long long my_ops = 0;
   unsigned int my_sel = 0, my_front = 0;
@@ -434,10 +438,10 @@ void k_wcycle(
           snd[m] = (T)(t[m] * d / (double)out);
           my_ops += (unsigned long long)np[m];
           ++my_front;
-          my_r += to_d(snd[m]) * (double)np[m];
+          my_r += fabs(to_d(snd[m])) * (double)np[m];
         }
       }
-      my_r += to_d(keep[m]);
+      my_r += fabs(to_d(keep[m]));
     }
     // the far accumulator entries read are cleared; the history of the
     // diffused nodes
@@ -491,9 +495,10 @@ void k_wcycle(
       // with its fluid now (kept + what the first round moved to it inside
       // the tile); what it moves waits for the next cycle like every other
       // push. The first round counted its kept and pushed fluid whole;
-      // a node that diffuses again takes its fluid f out of that count and
-      // puts back what it pushes, so that the record still sums to the
-      // fluid the next cycle starts with. The node words and the history
+      // a node that diffuses again takes |f| out of that count and puts
+      // back what it pushes, so that the record still sums to the fluid
+      // the next cycle starts with (bounds it, for a signed fluid: removing
+      // a node's f lowers sum |F| by exactly |f|). The node words and the history
       // (stored by the first round) are read again rather than held
       // through the first push.
       uint32_t w2[4];
@@ -522,7 +527,7 @@ void k_wcycle(
         if (sel2[m]) {
           any_sel2 = true;
           t2[m] = loop ? f * (double)out / ((double)out - d) : f;
-          my_r -= f;
+          my_r -= af;
           ++my_sel;
           if (out == 0) {
             my_e += t2[m];
@@ -531,7 +536,7 @@ void k_wcycle(
             snd[m] = (T)(t2[m] * d / (double)out);
             my_ops += (unsigned long long)np[m];
             ++my_front;
-            my_r += to_d(snd[m]) * (double)np[m];
+            my_r += fabs(to_d(snd[m])) * (double)np[m];
           }
           s_win[W + l0 + m] = (T)0;
         }
@@ -722,6 +727,7 @@ WinState<T> win_state(const CycleArgs& a, int parity) {
   S.hub_next = hub + (int64_t)(parity ^ 1) * bsz;
   S.hub_gs = win_hub_rows(g->n_wtiles[0]);
   S.rounds = a.method == DI_SOP ? a.wcfg.rounds : 1;
+  S.ctl_host = ws->host_ctl;
   return S;
 }
 
