@@ -196,7 +196,7 @@ struct Workspace {
   double* X64 = nullptr;        // host entry points: device copy of X
   double* B64 = nullptr;        // host entry points: device copy of B
   std::vector<hipEvent_t> events;
-  hipEvent_t copied = nullptr;  // after a control-block read-back (no timing)
+  hipEvent_t copied = nullptr;  // the control block is in host_ctl (no timing)
   di_cycle_rec* trace = nullptr;  // per-cycle records of a traced solve
   int trace_cap = 0;
 };

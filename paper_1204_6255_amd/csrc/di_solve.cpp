@@ -200,14 +200,11 @@ struct PoolGuard {
   }
 };
 
-// events[0] and [1] bracket a solve (the host reads them after a stream
-// synchronization); the others time single pull/push launches and are only
-// read for their timestamps, so they skip the system-scope fence (a cache
-// writeback that would otherwise land inside the timed launch).
-// Timing events. None carries a system-scope fence: each such fence (cache
-// write-back and invalidation) held the stream for about 10 us on this
-// device, and the host reads nothing through them (the control block has
-// its own event, `copied`).
+// Timing events: events[0] and [1] bracket a solve, the others time single
+// launches. None carries a system-scope fence (a cache write-back and
+// invalidation that held the stream for about 10 us on this device, or
+// landed inside the timed launch): the host reads only their timestamps.
+// The control block has its own event, `copied`, which keeps the fence.
 di_status ensure_events(Workspace* ws, size_t count) {
   while (ws->events.size() < count) {
     hipEvent_t e;
