@@ -210,7 +210,8 @@ di_status di_graph_create(int64_t n, int64_t m, const int32_t* src, const int32_
  * counts, then smaller grids, each with one and with two rounds, then the
  * select + pull pair) it times a solve from the PageRank right-hand side
  * until the residual has fallen four decades (at most 400 cycles), divides
- * by the decades it fell, and keeps the fastest; a graph of the same n, L
+ * by the decades it fell, and keeps the fastest (a candidate replaces the
+ * best so far only when 2% faster); a graph of the same n, L
  * and largest in- and out-degree reuses the process's earlier choice.
  * *us_default, *us_tuned and *us_pull receive those times (microseconds per
  * tenfold cut of the residual) of the default window configuration, of the

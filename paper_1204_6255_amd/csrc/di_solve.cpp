@@ -509,6 +509,10 @@ std::map<TuneKey, TuneEntry>& tune_cache() {
 // most of the nodes) and the two-round cycle gains more in the later ones.
 constexpr double kTuneCut = 1e-4;
 constexpr int kTuneMaxCycles = 400;
+// a candidate replaces the best so far only when at least 2% faster (runs
+// of one configuration differ by about 1%), so that near ties keep the
+// earlier, more common configuration
+constexpr double kTuneGain = 0.98;
 
 // A candidate's time for one tenfold cut of the residual: us over the
 // decades r fell.
@@ -615,7 +619,7 @@ di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) 
     auto consider = [&](const WinCfg& c) -> di_status {
       double us = 0.0;
       DI_TRY(time_window_cfg<T>(g, ws, stream, d, c, &us));
-      if (us < local_us) {
+      if (us < kTuneGain * local_us) {
         local_us = us;
         local = c;
       }
@@ -649,7 +653,7 @@ di_status tune_window(di_graph* g, Workspace* ws, hipStream_t stream, double d) 
         c.grid_cap = cap;
         DI_TRY(consider(c));
       }
-    if (local_us < best_us) {
+    if (local_us < kTuneGain * best_us) {
       best_us = local_us;
       best = local;
     }

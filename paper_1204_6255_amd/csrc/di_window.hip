@@ -237,8 +237,9 @@ __device__ inline void wave_scan2(int& x, int& y) {
 // One cycle: the stop test on the last cycle's records, then select, claim
 // and push every tile of the block (grid-stride). Thread tid holds the four
 // consecutive nodes a + 4 tid .. a + 4 tid + 3 of tile a. The first tile's
-// loads (and its hub rows' sums) are issued before the stop test, which
-// they do not depend on; nothing is written before it. first: the records
+// loads that the selection needs (and its hub rows' sums) are issued before
+// the stop test, which they do not depend on; nothing is written before
+// it. first: the records
 // are the start records and F is the whole fluid; folded: F is the whole
 // fluid (a fold pass ran after the last cycle).
 // Waves per SIMD: as many as the block's LDS lets a compute unit hold, at
@@ -281,8 +282,9 @@ void k_wcycle(
   const bool add = !first && !folded;
   const int l0 = 4 * tid;  // the thread's first node in the tile
 
-  // a tile's loads: kept fluid, far accumulator, history, node words, the
-  // halo values of the tile's first and last W nodes, the tile's first link
+  // a tile's loads: kept fluid, far accumulator, node words, the halo
+  // values of the tile's first and last W nodes, the tile's first link (the
+  // history hv is loaded later, at the top of the tile's work)
   T raw[4], av[4], hv[4], hl[4], hr[4];
   uint32_t w[4];
   int64_t ebase = 0;
@@ -291,7 +293,6 @@ void k_wcycle(
     const int64_t i0 = tile * TILE + l0;
     load4(S.F, i0, S.n, raw);
     load4(S.wp_info, i0, S.n, w);
-    load4(S.H, i0, S.n, hv);
     ebase = S.row_ptr[tile * TILE];
 #pragma unroll
     for (int m = 0; m < 4; ++m) av[m] = hl[m] = hr[m] = (T)0;
@@ -387,6 +388,10 @@ void k_wcycle(
     const int64_t a = tile * TILE;
     const int64_t i0 = a + l0;
     const int64_t win0 = a - W;
+    // the history, needed only once the tile's nodes are selected: loaded
+    // after the stop decision, so that the loads the decision and the
+    // selection wait for go out alone
+    load4(S.H, i0, S.n, hv);
     // fluid at the cycle's start: kept + far accumulator + halos + hubs
     T fv[4], keep[4], snd[4];
     double t[4];
