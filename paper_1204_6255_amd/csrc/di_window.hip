@@ -596,7 +596,7 @@ void k_wcycle(
     if (v != (T)0) S.hub_next[(int64_t)k * S.hub_gs + blockIdx.x] = v;
   }
   Part rec{my_r, my_r, my_e, my_ops, my_sel, my_front};
-  rec = block_sum_part(rec, s_part);
+  rec = block_sum_part_w0<NW>(rec, s_part, true);
   if (tid == 0) rec_out[blockIdx.x] = rec;
 }
 
