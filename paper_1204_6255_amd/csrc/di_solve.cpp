@@ -76,7 +76,9 @@ di_status alloc_workspace(const di_graph* g, int prec, Workspace** out) {
   if (st == DI_OK) st = dmalloc((void**)&ws->hacc, 2 * nh * sizeof(double));
   if (st == DI_OK) st = dmalloc((void**)&ws->ctl, 2 * sizeof(Ctl));
   if (st == DI_OK) {
-    hipError_t err = hipHostMalloc((void**)&ws->host_ctl, 2 * sizeof(Ctl), hipHostMallocDefault);
+    // coherent (fine-grained) pinned memory: the selection kernels store the
+    // control block straight into it
+    hipError_t err = hipHostMalloc((void**)&ws->host_ctl, 2 * sizeof(Ctl), hipHostMallocCoherent);
     if (err != hipSuccess) {
       ws->host_ctl = nullptr;
       set_error(std::string("hipHostMalloc: ") + hipGetErrorString(err));
@@ -136,7 +138,7 @@ size_t window_bytes(const di_graph* g, int prec) {
 // Pinned host copy of the per-block records, allocated on first use.
 di_status ensure_host_part(Workspace* ws) {
   if (!ws->host_part) {
-    hipError_t err = hipHostMalloc((void**)&ws->host_part, sizeof(Part), hipHostMallocDefault);
+    hipError_t err = hipHostMalloc((void**)&ws->host_part, sizeof(Part), hipHostMallocCoherent);
     if (err != hipSuccess) {
       ws->host_part = nullptr;
       set_error(std::string("hipHostMalloc: ") + hipGetErrorString(err));

@@ -172,10 +172,8 @@ __device__ inline T start_value(const WinState<T>& S, T f, int64_t i, int64_t ti
 
 // One link i -> code of a push: links into an active hub (code = -1 - r,
 // r < K) into the block's hub accumulators, near links (|code - i| <= W)
-// into the window, other far links into the next far accumulator. Returns
-// true when the amount landed in the tile's own part of the window (the
-// window's middle, which a second round of the cycle reads).
-template <typename T, int TILE>
+// into the window, other far links into the next far accumulator.
+template <typename T>
 __device__ inline void push_link(const WinState<T>& S, int32_t code, int64_t i, int64_t win0, T s,
                                  T* s_win, T* s_hub) {
   if (code < 0) {
@@ -350,9 +348,7 @@ void k_wcycle(
   double my_r = 0.0, my_e = 0.0;
   unsigned long long my_ops = 0;
   unsigned int my_sel = 0, my_front = 0;
-  // a second round of the cycle over each tile (DI-SOP's threshold only):
-  // the first round's amounts that stay in the tile are fluid the second
-  // round may diffuse again, so only the others count as pushed
+  // a second round of the cycle over each tile (DI-SOP's threshold only)
   const bool two = ROUNDS == 2 && mode == 0;
 
   // push, parallel over the tile's moved links: thread tid moves links
@@ -380,7 +376,7 @@ void k_wcycle(
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
         if (q0 + u * BLOCK < total)
-          push_link<T, TILE>(S, code[u], a + lo[u], win0, s_snd[lo[u]], s_win, s_hub);
+          push_link<T>(S, code[u], a + lo[u], win0, s_snd[lo[u]], s_win, s_hub);
     }
   };
 
