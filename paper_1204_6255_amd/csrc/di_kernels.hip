@@ -725,7 +725,10 @@ __global__ void k_refine_y(double* __restrict__ X, T* __restrict__ H,
 // seg_val for k_refine_heavy. Each block writes one record of its rows'
 // sum |R| and sum R.
 template <typename T>
-__global__ __launch_bounds__(kPullBlock) void k_refine_r(
+// (at most 64 VGPRs, like the pull: eight waves per SIMD keep more of the
+// random gathers of y in flight)
+__global__ __launch_bounds__(kPullBlock) __attribute__((amdgpu_waves_per_eu(DI_PULL_WAVES_PER_EU)))
+void k_refine_r(
     T* __restrict__ R, const double* __restrict__ X, const double* __restrict__ y,
     const double* __restrict__ B, double b_uniform, const uint32_t* __restrict__ info,
     const int64_t* __restrict__ csc_ptr, const int32_t* __restrict__ csc_idx,
