@@ -126,7 +126,7 @@ typedef struct di_opts {
   double inner_tol;   /* DI_FP32_REFINE: relative residual reduction asked
                          of each FP32 pass (<= 0: 1e-5). A refined solve
                          runs FP32 DI-SOP cycles until sum|F| <=
-                         max(tol/2, inner_tol * r_start), then folds H
+                         max(0.9 tol, inner_tol * r_start), then folds H
                          into an FP64 X and recomputes the fluid as the
                          FP64 residual B + P.X - X; it stops when that
                          residual is <= tol. DI_STOP_RESID only. */

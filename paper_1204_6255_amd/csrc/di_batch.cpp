@@ -217,7 +217,7 @@ di_status batch_group(di_graph* g, int k, const double* B_dev, double d, const d
       if (b.state == kBRun) {
         // cycles still needed from this column's contraction so far
         int nc = 16;
-        const double target = refine ? std::max(0.5 * b.tol, a.tol_rel * b.r_start) : b.tol;
+        const double target = refine ? std::max(kInnerStop * b.tol, a.tol_rel * b.r_start) : b.tol;
         if (b.pass_cycles >= 1 && b.r > 0.0 && b.r < b.r_start && target > 0.0) {
           const double rate = std::log(b.r / b.r_start) / (double)b.pass_cycles;
           const double est = std::log(target / b.r) / rate;

@@ -817,7 +817,7 @@ __global__ __launch_bounds__(kBBlock) void k_breduce(
     } else if (tol_rel >= 0.0) {
       // refined solve: the FP32 pass ends; convergence is decided on the
       // FP64 residual of the next pass
-      if (r <= fmax(0.5 * b.tol, tol_rel * b.r_start)) {
+      if (r <= fmax(kInnerStop * b.tol, tol_rel * b.r_start)) {
         b.state = kBInner;
         b.final_r = r;
       } else if (b.cycles >= max_cycles) {

@@ -100,6 +100,13 @@ inline int64_t win_hub_rows(int64_t tiles_of_smallest_shape) {
 // (the pull's heavy-row bit there) the ranked-hub flag
 constexpr uint32_t kHubBit = 0x40000000u;
 
+// FP32 passes of a refined solve (single, batched or served) stop once
+// their r is at most kInnerStop * tol (or the relative inner target): the
+// FP64 residual after the pass differs from that r by the FP32 rounding of
+// what the pass moved (about 1e-7 of it, far below 0.1 tol), and a pass
+// whose FP64 residual is still above tol is followed by another.
+constexpr double kInnerStop = 0.9;
+
 // Control block: two copies. The select kernel of cycle c reads copy c & 1
 // (the state after cycle c - 1) and its block 0 writes copy (c + 1) & 1; the
 // pull (or push) of cycle c reads copy (c + 1) & 1.

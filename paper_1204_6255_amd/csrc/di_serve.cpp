@@ -506,7 +506,7 @@ di_status launch_set(di_server* s, ColumnSet* cs) {
     if (cs->lanes[(size_t)c].ticket != 0 && b.state == kBIdle) need = std::max(need, 16);
     if (b.state != kBRun) continue;
     int nc = 16;
-    const double target = a.tol_rel >= 0.0 ? std::max(0.5 * b.tol, a.tol_rel * b.r_start) : b.tol;
+    const double target = a.tol_rel >= 0.0 ? std::max(kInnerStop * b.tol, a.tol_rel * b.r_start) : b.tol;
     if (b.pass_cycles >= 1 && b.r > 0.0 && b.r < b.r_start && target > 0.0) {
       const double rate = std::log(b.r / b.r_start) / (double)b.pass_cycles;
       const double est = std::log(target / b.r) / rate;

@@ -923,7 +923,7 @@ di_status solve_t(di_graph* g, const double* B_dev, double d, double tol, const 
   a.folded = 0;
   DI_TRY(ensure_refine_buffers(g, ws));
   DI_HIP(hipMemsetAsync(X_dev, 0, (size_t)g->n * sizeof(double), stream));
-  a.tol_in = 0.5 * tol;
+  a.tol_in = kInnerStop * tol;
   a.tol_rel = o.inner_tol > 0.0 ? o.inner_tol : 1e-5;
   Ctl tot{};
   int refinements = 0;

@@ -173,8 +173,8 @@ def test_trace_fp32_refine_numbers_passes_in_order(torch_cuda):
     # rise only where a pass starts from the FP64 residual
     rises = np.nonzero(r[1:] > r[:-1])[0] + 1
     assert len(rises) <= st.refinements
-    # no cycle started below the inner stop (half the tolerance)
-    assert r.min() > 0.5e-9
+    # no cycle started below the inner stop (0.9 of the tolerance)
+    assert r.min() > 0.9e-9
 
 
 def test_trace_pi_diffuses_every_node(torch_cuda):
