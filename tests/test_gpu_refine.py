@@ -169,6 +169,29 @@ def test_refined_solve_1m_bench_configuration(torch_cuda):
     assert st2.resid_l1 <= 1e-9 and st2.refinements <= st.refinements
 
 
+def test_refined_signed_1m_window(torch_cuda):
+    """A signed right-hand side at N = 1M on the window push: the FP32
+    passes take r from the records' bound of sum |F| (no gathering after
+    each cycle), and the FP64 residual passes still decide convergence: the
+    residual the oracle recomputes is within tol and X within tol / (1 - d)
+    of the oracle's."""
+    n = 1_000_000
+    src, dst = web(n)
+    og = oracle.Graph(n, src, dst)
+    B = np.random.default_rng(11).standard_normal(n) * (1.0 / n)
+    print("refined signed 1M: oracle solve", flush=True)
+    X_ref = oracle_solution(og, B)
+    g = di.Graph(n, src, dst)
+    print("refined signed 1M: GPU solve", flush=True)
+    tol = 1e-9
+    X, st, _ = refined(torch_cuda, g, B, tol, kernel=di.DI_KERNEL_WINDOW)
+    _, r_true = oracle.residual(og, B, D, X)
+    assert st.refinements >= 1
+    assert st.resid_l1 <= tol and r_true <= tol * (1 + 1e-6)
+    assert abs(r_true - st.resid_l1) <= 1e-15 + 1e-6 * st.resid_l1
+    assert np.abs(X - X_ref).sum() <= tol / (1 - D) + 1e-12
+
+
 def test_refined_edge_cases(torch_cuda):
     torch = torch_cuda
     # one node, no links: X = B / 1 after one pass
